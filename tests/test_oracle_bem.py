@@ -1,0 +1,205 @@
+"""Pins of the dense BEM oracle (oracle/bem.py) against facts fixed by the mathematics.
+
+  * the 4-point rule on 4 sub-triangles integrates all cubics exactly (reading of Sec. 2.2);
+  * closed-form self integrals: int_T 1/r from the centroid of an equilateral triangle equals
+    sqrt(3) a ln(2 + sqrt(3)); U_self equals a brute-force Duffy-transformed quadrature of U;
+    P_self equals a brute-force polar quadrature of P over the triangle minus a small disk (the
+    principal value), and vanishes for an equilateral triangle (symmetry);
+  * the discrete system reproduces a rigid translation (Dirichlet u = c gives t ~ 0);
+  * LU, the oracle's plain GMRES and scipy's GMRES agree on the rearranged system (eq. num2);
+  * the unit cube in uniaxial tension (Sec. 3 benchmark shape) reproduces the uniform stress at
+    interior points through eq. stress_1, converging under refinement.
+"""
+import numpy as np
+import pytest
+
+from oracle import bem as ob
+from oracle import direct as od
+from workloads import geometry as geo
+
+G = 1.0
+NU = 0.3
+K = od.moduli(G, NU)
+
+
+def test_quadrature_exact_for_cubics():
+    rng = np.random.default_rng(0)
+    tri = rng.normal(size=(1, 3, 3))
+    pts, nrm, w = ob.quadrature(tri)[:3]
+    area = ob.tri_geometry(tri)[2][0]
+    # barycentric coordinates of the points
+    Tm = np.stack([tri[0, 0] - tri[0, 2], tri[0, 1] - tri[0, 2]], axis=1)
+    lam01 = np.linalg.lstsq(Tm, (pts - tri[0, 2]).T, rcond=None)[0].T
+    lam = np.column_stack([lam01, 1 - lam01.sum(1)])
+    from math import factorial
+    for a in range(4):
+        for b in range(4 - a):
+            for c in range(4 - a - b):
+                exact = 2 * area * factorial(a) * factorial(b) * factorial(c) / factorial(a + b + c + 2)
+                approx = np.sum(w * lam[:, 0] ** a * lam[:, 1] ** b * lam[:, 2] ** c)
+                assert abs(approx - exact) < 1e-13 * max(1, abs(exact))
+    assert abs(w.sum() - area) < 1e-14 * area
+
+
+def _equilateral(a=1.0):
+    return np.array([[0, 0, 0], [a, 0, 0], [a / 2, a * np.sqrt(3) / 2, 0]], float)
+
+
+def _int_inv_r(tri):
+    Us, _ = ob.self_integrals(tri, K, G)
+    c = 1.0 / (16 * np.pi * (1 - NU) * G)
+    return np.trace(Us) / (c * (3 * (3 - 4 * NU) + 1))
+
+
+def test_inv_r_equilateral_closed_form():
+    for a in (1.0, 0.37):
+        assert abs(_int_inv_r(_equilateral(a)) - np.sqrt(3) * a * np.log(2 + np.sqrt(3))) < 1e-13
+
+
+def _subtris(tri):
+    xi = tri.mean(0)
+    return xi, [(tri[e], tri[(e + 1) % 3]) for e in range(3)]
+
+
+def _duffy_U(tri, n=40):
+    """Brute force int_T U(xi, x) dS by the Duffy map on the 3 sub-triangles (xi, a, b)."""
+    g, gw = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1); gw = 0.5 * gw
+    xi, sub = _subtris(tri)
+    nrm = np.cross(tri[1] - tri[0], tri[2] - tri[0]); nrm /= np.linalg.norm(nrm)
+    total = np.zeros((3, 3))
+    for a, b in sub:
+        J = np.linalg.norm(np.cross(a - xi, b - a))
+        U_, V_ = np.meshgrid(g, g, indexing="ij")
+        W = np.outer(gw, gw) * U_ * J
+        X = xi[None] + U_.reshape(-1, 1) * (a - xi)[None] + (U_ * V_).reshape(-1, 1) * (b - a)[None]
+        Uk = od.pair_kernels(np.repeat(xi[None], X.shape[0], 0), X, np.repeat(nrm[None], X.shape[0], 0), K, G)[0]
+        total += np.einsum("p,pij->ij", W.reshape(-1), Uk)
+    return total
+
+
+def _polar_P(tri, n_th=96, n_s=24, eps_frac=0.05):
+    """Brute force PV int_T P(xi, x) dS: polar quadrature over T minus a disk of radius eps about xi.
+
+    The excluded disk contributes nothing to the principal value (the in-plane kernel is odd in r_hat).
+    """
+    xi, sub = _subtris(tri)
+    nrm = np.cross(tri[1] - tri[0], tri[2] - tri[0]); nrm /= np.linalg.norm(nrm)
+    e1 = (tri[0] - xi) / np.linalg.norm(tri[0] - xi); e2 = np.cross(nrm, e1)
+    gt, gtw = np.polynomial.legendre.leggauss(n_th)
+    gs, gsw = np.polynomial.legendre.leggauss(n_s)
+    gs = 0.5 * (gs + 1); gsw = 0.5 * gsw
+    inr = min(abs(np.dot(np.cross(b - a, xi - a), nrm)) / np.linalg.norm(b - a) for a, b in sub)
+    eps = eps_frac * inr
+    total = np.zeros((3, 3))
+    for a, b in sub:
+        ta = np.arctan2(np.dot(a - xi, e2), np.dot(a - xi, e1))
+        tb = np.arctan2(np.dot(b - xi, e2), np.dot(b - xi, e1))
+        if tb < ta:
+            tb += 2 * np.pi
+        th = ta + (tb - ta) * 0.5 * (gt + 1); thw = (tb - ta) * 0.5 * gtw
+        for t, tw in zip(th, thw):
+            d = np.cos(t) * e1 + np.sin(t) * e2
+            # distance to edge (a,b) along d
+            m = np.cross(b - a, nrm)
+            R = np.dot(a - xi, m) / np.dot(d, m)
+            rho = eps * (R / eps) ** gs
+            wts = tw * gsw * rho * rho * np.log(R / eps)
+            X = xi[None] + rho[:, None] * d[None]
+            Pk = od.pair_kernels(np.repeat(xi[None], len(rho), 0), X, np.repeat(nrm[None], len(rho), 0), K, G)[1]
+            total += np.einsum("p,pij->ij", wts, Pk)
+    return total
+
+
+@pytest.mark.parametrize("which", ["equilateral", "voxel", "random"])
+def test_self_blocks_match_brute_force(which):
+    if which == "equilateral":
+        tri = _equilateral(0.8)
+    elif which == "voxel":
+        tri = geo.cube_mesh(1)["tri"][1]
+    else:
+        tri = np.random.default_rng(4).normal(size=(3, 3))
+    Us, Ps = ob.self_integrals(tri, K, G)
+    Ub = _duffy_U(tri)
+    assert np.abs(Us - Ub).max() < 1e-11 * np.abs(Ub).max()
+    Pb = _polar_P(tri)
+    assert np.abs(Ps - Pb).max() < 1e-9 * max(1e-3, np.abs(Pb).max())
+    if which == "equilateral":
+        assert np.abs(Ps).max() < 1e-14
+    else:
+        assert np.abs(Ps).max() > 1e-6  # the antisymmetric coupling is present
+
+
+@pytest.fixture(scope="module")
+def tension2():
+    p = geo.cube_tension_problem(2)
+    return ob.DenseBEM(p["tri"], p["bc_type"], p["bc_val"], K, G)
+
+
+def _refine(t):
+    v0, v1, v2 = t[:, 0], t[:, 1], t[:, 2]
+    m01, m12, m20 = (v0 + v1) / 2, (v1 + v2) / 2, (v2 + v0) / 2
+    return np.concatenate([np.stack(s, 1) for s in [(v0, m01, m20), (m01, v1, m12), (m20, m12, v2),
+                                                      (m01, m12, m20)]])
+
+
+def test_rigid_translation_identity():
+    """(1/2 I + P^D) c = 0 for a constant c on a closed surface (eq. BIE with u = c, t = 0).
+
+    With the 16-point rule the residual is the near-singular quadrature error of the neighbours
+    (Sec. 2.2 notes this limitation); evaluating the same integrals with refined quadrature drives it
+    to zero, which pins the assembly, the self blocks and the free term.
+    """
+    tri = geo.cube_mesh(3)["tri"]
+    T = tri.shape[0]
+    c = np.array([0.3, -0.7, 0.2])
+    sysm = ob.DenseBEM(tri, np.zeros((T, 3), np.int8), np.zeros((T, 3)), K, G)
+    r0 = np.abs(sysm.H @ np.tile(c, T)).max()
+    assert r0 < 1e-2 * np.linalg.norm(c)
+    cen = ob.tri_geometry(tri)[0]
+    res = []
+    for lev in (1, 2, 3):
+        sub, parent = tri.copy(), np.arange(T)
+        for _ in range(lev):
+            sub, parent = _refine(sub), np.concatenate([parent] * 4)
+        qp, qn, qw, qe = ob.quadrature(sub)
+        _, Pm = od.quad_blocks(cen, qp, qn, qw, parent[qe], T, K, G)
+        for k in range(T):
+            Pm[3 * k:3 * k + 3, 3 * k:3 * k + 3] = ob.self_integrals(tri[k], K, G)[1]
+        res.append(np.abs((Pm + 0.5 * np.eye(3 * T)) @ np.tile(c, T)).max())
+    assert res[0] < r0 and res[1] < res[0] and res[2] < res[1]
+    assert res[2] < 1e-6 * np.linalg.norm(c)
+
+
+def test_lu_gmres_scipy_agree(tension2):
+    import scipy.sparse.linalg as sla
+    A, b = tension2.A, tension2.b
+    x_lu = np.linalg.solve(A, b)
+    x_g, it, ok, rr = ob.gmres(lambda v: A @ v, b, tol=1e-12, restart=30, max_iter=2000)
+    assert ok and rr <= 1e-12
+    assert np.linalg.norm(x_g - x_lu) <= 1e-9 * np.linalg.norm(x_lu)
+    x_s, info = sla.gmres(A, b, rtol=1e-12, restart=30, maxiter=200)
+    assert info == 0
+    assert np.linalg.norm(x_s - x_lu) <= 1e-8 * np.linalg.norm(x_lu)
+    # warm start from the solution: zero iterations
+    _, it0, ok0, _ = ob.gmres(lambda v: A @ v, b, x0=x_lu, tol=1e-10)
+    assert ok0 and it0 == 0
+
+
+def test_uniaxial_tension_interior_stress():
+    errs = []
+    for N in (2, 4):
+        p = geo.cube_tension_problem(N)
+        sys = ob.DenseBEM(p["tri"], p["bc_type"], p["bc_val"], K, G)
+        u, t = sys.split(sys.solve_lu())
+        qp, qn, qw, qe = ob.quadrature(sys.tri)
+        a = t[qe]; b = -u[qe]
+        xi = np.array([[0.5, 0.5, 0.5], [0.3, 0.6, 0.4]])
+        s = od.direct(od.STRESS, xi, qp, qw, a=a, b=b, nrm=qn, K=K, G=G)
+        ref = np.array([1.0, 0, 0, 0, 0, 0])
+        errs.append(np.abs(s - ref[None]).max())
+        # displacement along x on the loaded face ~ 1/E
+        E = 2 * G * (1 + NU)
+        loaded = (p["bc_val"][:, 0] == 1.0)
+        assert abs(u[loaded, 0].mean() - 1.0 / E) < 0.1 / E
+    assert errs[1] < errs[0] and errs[1] < 0.05
