@@ -1,0 +1,154 @@
+/*
+ * kfmm.h -- C ABI of the MI355X kernel-independent fast multipole library for 3D isotropic
+ * elastostatics (Kelvin kernels) and the collocation BEM it drives.
+ *
+ * Paper: Ostanin, Tsybulin, Litsarev, Oseledets, Zorin, "What lies beneath the surface:
+ * topological-shape optimization with the kernel-independent fast multipole method"
+ * (arXiv:1612.04082).  Section references below are to that paper.
+ *
+ * Conventions for every entry point
+ *  - Pointers are DEVICE pointers unless marked (host).  Floating-point I/O is FP64, row-major,
+ *    array-of-structures: a point is 3 consecutive doubles (x, y, z).
+ *  - All device work is enqueued on the HIP stream passed as `stream` (a hipStream_t; NULL means
+ *    the default stream).  fmm_eval returns without waiting for the GPU; fmm_plan, bem_solve and the
+ *    ws_* training call synchronise the stream because they need sizes or residuals on the host.
+ *  - A plan copies what it needs during fmm_plan and keeps no pointer to caller memory.  The caller
+ *    owns every input and output buffer.  A plan must not be used from two streams at once.
+ *  - Errors: a negative status is returned; outputs are then undefined (except KFMM_E_NOCONV, which
+ *    leaves the best iterate and filled statistics).  kfmm_last_error() returns a message for the
+ *    last failing call on the calling thread.
+ *  - Elastic moduli are the bulk modulus K and shear modulus G (Sec. 2, eq. elast); internally
+ *    nu = (3K - 2G) / (2 (3K + G)).  K <= 0, G <= 0 or non-finite moduli are KFMM_E_ARG.
+ */
+#ifndef KFMM_H
+#define KFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KFMM_OK = 0,
+  KFMM_E_ARG = -1,    /* invalid argument (sizes, moduli, non-finite coordinates, ...) */
+  KFMM_E_OOM = -2,    /* device allocation failed or exceeds opts.mem_limit */
+  KFMM_E_HIP = -3,    /* a HIP runtime call failed */
+  KFMM_E_NOCONV = -4, /* GMRES did not reach the tolerance within max_iter */
+  KFMM_E_STATE = -5   /* object used in a wrong state (e.g. destroyed plan) */
+};
+
+/* Internal arithmetic of fmm_eval. */
+enum {
+  KFMM_FP64 = 0,          /* everything in FP64 (near field, far field, translations) */
+  KFMM_FP32 = 1,          /* near field, check/equivalent evaluations and M2L in FP32; pseudo-inverse
+                             and M2M/L2L translations in FP64 */
+  KFMM_FP32_M2L_BF16 = 2  /* as KFMM_FP32 but M2L in BF16 on the matrix cores, FP32 accumulation */
+};
+
+/* Target kind of fmm_eval. */
+enum {
+  KFMM_DISP = 0,  /* displacement: 3 components per target */
+  KFMM_STRESS = 1 /* stress: 6 components per target, order xx, yy, zz, yz, xz, xy */
+};
+
+typedef struct {
+  double K, G;        /* bulk and shear modulus */
+  int p;              /* equivalent-surface order: p points per cube edge, 6(p-1)^2+2 points; 0 -> 6 */
+  int leaf_max;       /* a box is split while it holds more than leaf_max sources + targets; 0 -> 64 */
+  int precision;      /* KFMM_FP64, KFMM_FP32 or KFMM_FP32_M2L_BF16 */
+  double svd_eps;     /* relative singular-value cutoff of the check-to-equivalent pseudo-inverse; 0 -> 1e-8 */
+  int max_depth;      /* deepest octree level; 0 -> 16 */
+  size_t mem_limit;   /* bytes of device memory the plan may use; 0 = no limit */
+} fmm_opts;
+
+typedef struct kfmm_plan* kfmm_plan_t;
+
+/*
+ * fmm_plan -- build the octree, interaction lists and translation operators for a fixed set of
+ * sources (points y_j with normals n_j and weights w_j) and targets x_i (Sec. 2.2, "Kernel-independent
+ * fast multipole method": octree, upward/downward passes, near field; eq. fmm_summation).
+ *
+ *   src_xyz  N x 3  source points                       (device, FP64)
+ *   src_nrm  N x 3  unit normals at the sources, or NULL (then only single-layer densities may be used)
+ *   src_w    N      source weights (area x quadrature weight), or NULL for all ones
+ *   n_src    N >= 0
+ *   trg_xyz  M x 3  target points, or NULL: targets are the sources themselves (M must equal N)
+ *   n_trg    M >= 0
+ *   batch_src, batch_trg  (host) offsets of n_batch independent geometries, n_batch + 1 entries each,
+ *            starting at 0 and ending at N (resp. M); or NULL with n_batch <= 1 for one geometry.
+ *            Geometries never interact: each has its own root box.
+ *   opts     (host) options; see fmm_opts.
+ * Coordinates must be finite (checked on the device; KFMM_E_ARG otherwise).  A source that coincides
+ * exactly with a target contributes nothing to that target.
+ */
+int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w, int64_t n_src,
+             const double* trg_xyz, int64_t n_trg, const int64_t* batch_src, const int64_t* batch_trg,
+             int32_t n_batch, const fmm_opts* opts, void* stream);
+
+/*
+ * fmm_eval -- fast evaluation of the boundary integrals at the plan's targets (eq. fmm_summation):
+ *   KFMM_DISP  : out_i   = sum_j U(x_i, y_j) w_j a_j + P(x_i, y_j, n_j) w_j b_j        (eqs. disp_1, disp_2)
+ *   KFMM_STRESS: out_i,kl = sum_j D_mkl(x_i, y_j) w_j a_j,m + S_mkl(x_i, y_j, n_j) w_j b_j,m  (eqs. stress_2, stress_3)
+ * With a = t and b = -u these are the right-hand sides of eq. BIE and eq. stress_1.
+ *   a_sl  N x 3 single-layer density (device, FP64) or NULL (zero)
+ *   b_dl  N x 3 double-layer density (device, FP64) or NULL (zero); needs normals in the plan
+ *   out   M x 3 (DISP) or M x 6 (STRESS), overwritten (device, FP64), targets in the caller's order.
+ */
+int fmm_eval(kfmm_plan_t plan, int kind, const double* a_sl, const double* b_dl, double* out, void* stream);
+
+/* Sizes and counters of a plan (host struct). */
+typedef struct {
+  int64_t n_src, n_trg, n_box, n_leaf;
+  int32_t depth, n_eq;
+  int64_t n_u_pairs;   /* near-field source-target point pairs (P2P) */
+  int64_t n_v_pairs;   /* M2L box pairs */
+  int64_t n_w_pairs, n_x_pairs;
+  double plan_seconds;
+  size_t device_bytes;
+} fmm_info;
+int fmm_plan_info(kfmm_plan_t plan, fmm_info* info /* host */);
+
+/*
+ * Phase timing.  fmm_profile(plan, 1) makes every following fmm_eval record HIP events between its
+ * phases on the caller's stream and wait for them at the end of the call (so profiled calls are
+ * synchronous); fmm_profile(plan, 0) stops it.  fmm_phase_times writes, for each phase, the summed
+ * milliseconds over the profiled calls (host array of KFMM_N_PHASES doubles) and their number.
+ * Enabling resets the sums.
+ */
+enum {
+  KFMM_PH_PERMUTE = 0, /* densities into tree order */
+  KFMM_PH_S2M,         /* sources -> upward check potentials of leaves */
+  KFMM_PH_UC2UE,       /* upward check -> equivalent densities of leaves */
+  KFMM_PH_M2M,         /* upward translations, all levels */
+  KFMM_PH_M2L_PREP,    /* clearing and converting for the M2L */
+  KFMM_PH_M2L,         /* M2L contraction (matrix cores), all levels */
+  KFMM_PH_S2L,         /* X list: sources -> downward check potentials */
+  KFMM_PH_DOWN,        /* downward check -> equivalent, L2L, all levels */
+  KFMM_PH_LEAF,        /* L2T + W list + near field at the target leaves */
+  KFMM_N_PHASES
+};
+int fmm_profile(kfmm_plan_t plan, int enable);
+int fmm_phase_times(kfmm_plan_t plan, double* ms /* host, KFMM_N_PHASES */, int64_t* calls /* host */);
+
+/* Release the plan and its device memory.  NULL is a no-op. */
+int fmm_plan_destroy(kfmm_plan_t plan);
+
+/*
+ * Test hook: one launch of the batched gather/scatter GEMM used by every translation,
+ *   Y[:, out[j]] (=, +=, atomic +=) scale[j] * A[op[j]] * X[:, in[j]]
+ * precision 0: A, X, Y FP64; 1: FP32; 2: A, X bfloat16 and Y FP32.  A holds NC x NC row-major operators,
+ * X and Y hold NC-vectors (stride NC).  op, in, out, scale (scale may be NULL) are HOST arrays of ncols
+ * entries with op non-decreasing; NC must be a multiple of 96.  Synchronises the stream.
+ */
+int kfmm_selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,
+                       const int* out, const double* scale, int ncols, int mode, void* stream);
+
+/* Last error message of the calling thread ("" if none); valid until the next call on this thread. */
+const char* kfmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFMM_H */

@@ -1,0 +1,146 @@
+// C-ABI entry points (include/kfmm.h): argument validation, status codes and thread-local errors.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/kfmm.h"
+#include "common.h"
+#include "plan.h"
+
+namespace kfmm {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace kfmm
+
+struct kfmm_plan {
+  kfmm::Plan* impl;
+};
+
+using namespace kfmm;
+
+template <typename F>
+static int guarded(F&& f) {
+  try {
+    set_last_error("");
+    f();
+    return KFMM_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return KFMM_E_OOM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return KFMM_E_HIP;
+  }
+}
+
+static void check_moduli(double K, double G) {
+  KFMM_REQUIRE(std::isfinite(K) && std::isfinite(G) && K > 0 && G > 0, "moduli K and G must be finite and positive");
+}
+
+extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w,
+                        int64_t n_src, const double* trg_xyz, int64_t n_trg, const int64_t* batch_src,
+                        const int64_t* batch_trg, int32_t n_batch, const fmm_opts* opts, void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    KFMM_REQUIRE(opts != nullptr, "opts is NULL");
+    check_moduli(opts->K, opts->G);
+    KFMM_REQUIRE(n_src >= 0 && n_trg >= 0, "negative size");
+    KFMM_REQUIRE(n_src < (int64_t)1 << 31 && n_trg < (int64_t)1 << 31, "too many points (max 2^31 - 1)");
+    KFMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "src_xyz is NULL");
+    if (trg_xyz == nullptr) KFMM_REQUIRE(n_trg == n_src, "aliased targets need n_trg == n_src");
+    KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_M2L_BF16, "unknown precision");
+    KFMM_REQUIRE(opts->p == 0 || (opts->p >= 3 && opts->p <= 12), "p must be in [3, 12]");
+    KFMM_REQUIRE(opts->leaf_max >= 0 && opts->max_depth >= 0, "negative leaf_max or max_depth");
+    KFMM_REQUIRE(n_batch >= 0 && n_batch <= 128, "n_batch must be in [0, 128]");
+    std::vector<int64_t> bs, bt;
+    if (n_batch <= 1 || batch_src == nullptr) {
+      KFMM_REQUIRE(n_batch <= 1, "batch offsets are NULL");
+      bs = {0, n_src};
+      bt = {0, trg_xyz ? n_trg : n_src};
+    } else {
+      KFMM_REQUIRE(batch_trg != nullptr || trg_xyz == nullptr, "batch_trg is NULL");
+      bs.assign(batch_src, batch_src + n_batch + 1);
+      bt = trg_xyz ? std::vector<int64_t>(batch_trg, batch_trg + n_batch + 1) : bs;
+      KFMM_REQUIRE(bs.front() == 0 && bs.back() == n_src && bt.front() == 0 && bt.back() == (trg_xyz ? n_trg : n_src),
+                   "batch offsets must start at 0 and end at the point counts");
+      for (int g = 0; g < n_batch; ++g)
+        KFMM_REQUIRE(bs[g + 1] >= bs[g] && bt[g + 1] >= bt[g], "batch offsets must be non-decreasing");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Plan* p = plan_create(src_xyz, src_nrm, src_w, n_src, trg_xyz, trg_xyz ? n_trg : n_src, bs, bt, *opts, s);
+    *out = new kfmm_plan{p};
+  });
+}
+
+extern "C" int fmm_eval(kfmm_plan_t plan, int kind, const double* a_sl, const double* b_dl, double* out,
+                        void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr, "plan is NULL");
+    KFMM_REQUIRE(kind == KFMM_DISP || kind == KFMM_STRESS, "kind must be KFMM_DISP or KFMM_STRESS");
+    Plan& P = *plan->impl;
+    KFMM_REQUIRE(out != nullptr || P.n_trg == 0, "out is NULL");
+    KFMM_REQUIRE(b_dl == nullptr || P.has_nrm || P.n_src == 0, "double-layer density needs normals in the plan");
+    plan_eval(P, kind, a_sl, b_dl, out, (hipStream_t)stream);
+  });
+}
+
+extern "C" int fmm_plan_info(kfmm_plan_t plan, fmm_info* info) {
+  return guarded([&] {
+    KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr && info != nullptr, "NULL argument");
+    Plan& P = *plan->impl;
+    std::memset(info, 0, sizeof(*info));
+    info->n_src = P.n_src;
+    info->n_trg = P.n_trg;
+    info->n_box = P.tree.n_box;
+    info->n_leaf = P.n_leaf;
+    info->depth = P.tree.depth;
+    info->n_eq = P.n_eq;
+    info->n_u_pairs = P.n_u_pairs;
+    info->n_v_pairs = P.n_v_pairs;
+    info->n_w_pairs = P.n_w_pairs;
+    info->n_x_pairs = P.n_x_pairs;
+    info->plan_seconds = P.plan_seconds;
+    info->device_bytes = P.arena.bytes;
+  });
+}
+
+extern "C" int fmm_profile(kfmm_plan_t plan, int enable) {
+  return guarded([&] {
+    KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr, "plan is NULL");
+    plan_profile(*plan->impl, enable != 0);
+  });
+}
+
+extern "C" int fmm_phase_times(kfmm_plan_t plan, double* ms, int64_t* calls) {
+  return guarded([&] {
+    KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr && ms != nullptr, "NULL argument");
+    for (int i = 0; i < KFMM_N_PHASES; ++i) ms[i] = plan->impl->phase_ms[i];
+    if (calls) *calls = plan->impl->prof_calls;
+  });
+}
+
+extern "C" int fmm_plan_destroy(kfmm_plan_t plan) {
+  return guarded([&] {
+    if (!plan) return;
+    delete plan->impl;
+    plan->impl = nullptr;
+    delete plan;
+  });
+}
+
+extern "C" int kfmm_selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op,
+                                  const int* in, const int* out, const double* scale, int ncols, int mode,
+                                  void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(precision >= 0 && precision <= 2 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
+    KFMM_REQUIRE(NC > 0 && NC % kGemmBM == 0, "NC must be a positive multiple of 96");
+    for (int i = 1; i < ncols; ++i) KFMM_REQUIRE(op[i] >= op[i - 1], "columns must be sorted by op");
+    selftest_gemm(precision, A, NC, X, Y, op, in, out, scale, ncols, mode, (hipStream_t)stream);
+  });
+}
+
+extern "C" const char* kfmm_last_error(void) { return g_last_error.c_str(); }

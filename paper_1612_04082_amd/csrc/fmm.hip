@@ -1,0 +1,789 @@
+// KIFMM evaluation of the Kelvin elastostatic boundary integrals on one GPU (Sec. 2.2).
+//
+// fmm_eval pipeline (all on one stream):
+//   permute-in   densities w*a, w*b gathered into tree (Morton) order
+//   S2M          sources of every leaf -> displacement at its upward check surface (source kernel U/P)
+//   UC2UE        phi_up = r_l * UC2UE * q                                (FP64 MFMA)
+//   M2M          level by level: T = M2M_c * phi_up(child); phi_up(parent) = sum over children
+//   M2L          qhat(B) += M2L_d * phi_up(A) for V pairs, grouped by offset d over all levels (MFMA)
+//   S2L (X)      qhat(B) += r_l * (sources of coarse adjacent leaves at B's downward check surface)
+//   DC2DE, L2L   phi_dn = DC2DE * qhat + L2L_c * phi_dn(parent), top-down  (FP64 MFMA)
+//   leaf eval    per target leaf: L2T (phi_dn), M2T over W, direct sum over U; result written in the
+//                caller's order (U or D kernel for far fields; U+P or D+S near field)
+// Coordinates are stored relative to the leaf centre; box-centre offsets are exact dyadic numbers
+// (power-of-two root), which keeps FP32 near-field differences accurate.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+
+#include "../../include/kfmm.h"
+#include "common.h"
+#include "gemm.h"
+#include "operators.h"
+#include "plan.h"
+#include "tree.h"
+
+namespace kfmm {
+
+// ------------------------------------------------------------------------ process-wide operator cache
+
+struct DeviceOps {
+  int device = -1;
+  int p = 0, n = 0, NC = 0, n_eq = 0;
+  double *uc2ue = nullptr, *dc2de = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l64 = nullptr;
+  float* m2l32 = nullptr;
+  __hip_bfloat16* m2l16 = nullptr;
+  double* surf = nullptr;  // n_eq x 3
+  std::vector<int> m2l_index;
+  Arena arena;
+};
+
+static std::mutex g_ops_mutex;
+static std::map<std::tuple<int, int, double, double, double>, std::shared_ptr<DeviceOps>> g_ops;
+
+static std::vector<double> pad_square(const std::vector<double>& M, int n, int NC) {
+  std::vector<double> out((size_t)NC * NC, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[(size_t)i * NC + j] = M[(size_t)i * n + j];
+  return out;
+}
+
+static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, int precision, hipStream_t s) {
+  int dev = 0;
+  KFMM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_ops_mutex);
+  auto key = std::make_tuple(dev, p, el.nu, el.G, eps);
+  std::shared_ptr<DeviceOps> d;
+  auto it = g_ops.find(key);
+  if (it != g_ops.end()) d = it->second;
+  if (!d) {
+    Operators op = build_operators(p, el, eps);
+    d = std::make_shared<DeviceOps>();
+    d->device = dev;
+    d->p = p;
+    d->n = op.n;
+    d->n_eq = op.n_eq;
+    d->NC = round_up(op.n, kGemmBM);
+    d->m2l_index = op.m2l_index;
+    const int NC = d->NC;
+    auto up = [&](const std::vector<double>& v) {
+      double* ptr = d->arena.get<double>(v.size());
+      KFMM_HIP(hipMemcpy(ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
+      return ptr;
+    };
+    d->uc2ue = up(pad_square(op.uc2ue, op.n, NC));
+    d->dc2de = up(pad_square(op.dc2de, op.n, NC));
+    std::vector<double> cat;
+    for (int c = 0; c < 8; ++c) {
+      auto v = pad_square(op.m2m[c], op.n, NC);
+      cat.insert(cat.end(), v.begin(), v.end());
+    }
+    d->m2m = up(cat);
+    cat.clear();
+    for (int c = 0; c < 8; ++c) {
+      auto v = pad_square(op.l2l[c], op.n, NC);
+      cat.insert(cat.end(), v.begin(), v.end());
+    }
+    d->l2l = up(cat);
+    d->surf = up(op.surf);
+    // M2L operators in the requested precisions are uploaded lazily below
+    std::vector<double> m2l_all;
+    m2l_all.reserve(op.m2l.size() * (size_t)NC * NC);
+    for (auto& m : op.m2l) {
+      auto v = pad_square(m, op.n, NC);
+      m2l_all.insert(m2l_all.end(), v.begin(), v.end());
+    }
+    // keep host copy only as long as needed: convert now for every precision
+    d->m2l64 = up(m2l_all);
+    {
+      std::vector<float> f(m2l_all.size());
+      for (size_t i = 0; i < f.size(); ++i) f[i] = (float)m2l_all[i];
+      d->m2l32 = d->arena.get<float>(f.size());
+      KFMM_HIP(hipMemcpy(d->m2l32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+      std::vector<__hip_bfloat16> h(m2l_all.size());
+      for (size_t i = 0; i < h.size(); ++i) h[i] = __float2bfloat16((float)m2l_all[i]);
+      d->m2l16 = d->arena.get<__hip_bfloat16>(h.size());
+      KFMM_HIP(hipMemcpy(d->m2l16, h.data(), h.size() * sizeof(__hip_bfloat16), hipMemcpyHostToDevice));
+    }
+    g_ops[key] = d;
+  }
+  return d;
+}
+
+// ------------------------------------------------------------------------------------ small kernels
+
+__device__ __forceinline__ void box_offset(const int* level, const int* ix, const int* iy, const int* iz,
+                                           const int* geom, const double* root_R, int A, int B, double* o) {
+  int la = level[A], lb = level[B];
+  int L = la > lb ? la : lb;
+  double R = root_R[geom[B]];
+  double sc = ldexp(R, -L);
+  long na[3] = {ix[A], iy[A], iz[A]}, nb[3] = {ix[B], iy[B], iz[B]};
+  for (int d = 0; d < 3; ++d) {
+    long num = ((2 * na[d] + 1) << (L - la)) - ((2 * nb[d] + 1) << (L - lb));
+    o[d] = (double)num * sc;
+  }
+}
+
+__device__ __forceinline__ double box_half(const int* level, const int* geom, const double* root_R, int B) {
+  return ldexp(root_R[geom[B]], -level[B]);
+}
+
+__device__ __forceinline__ void box_center(const int* level, const int* ix, const int* iy, const int* iz,
+                                           const int* geom, const double* root_c, const double* root_R, int B,
+                                           double* c) {
+  int g = geom[B];
+  double R = root_R[g];
+  double r = ldexp(R, -level[B]);
+  int q[3] = {ix[B], iy[B], iz[B]};
+  for (int d = 0; d < 3; ++d) c[d] = root_c[3 * g + d] - R + (2.0 * q[d] + 1.0) * r;
+}
+
+// Local (leaf-relative) coordinates and normals of the sorted points.
+template <typename T>
+__global__ void k_local_points(int64_t n, const int* perm, const int* leaf_of, const double* xyz, const double* nrm,
+                               const double* w, TreeView tv, T* pos4, T* nrm4, double* w_sorted) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = perm[i];
+  int leaf = leaf_of[i];
+  double c[3];
+  box_center(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_c, tv.root_R, leaf, c);
+  for (int d = 0; d < 3; ++d) pos4[4 * i + d] = (T)(xyz[3 * o + d] - c[d]);
+  pos4[4 * i + 3] = T(0);
+  if (nrm4) {
+    for (int d = 0; d < 3; ++d) nrm4[4 * i + d] = nrm ? (T)nrm[3 * o + d] : T(0);
+    nrm4[4 * i + 3] = T(0);
+  }
+  if (w_sorted) w_sorted[i] = w ? w[o] : 1.0;
+}
+
+template <typename T>
+__global__ void k_permute_in(int64_t n, const int* perm, const double* w_sorted, const double* a, const double* b,
+                             T* dens8) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = perm[i];
+  double w = w_sorted[i];
+  for (int d = 0; d < 3; ++d) {
+    dens8[8 * i + d] = a ? (T)(w * a[3 * o + d]) : T(0);
+    dens8[8 * i + 4 + d] = b ? (T)(w * b[3 * o + d]) : T(0);
+  }
+  dens8[8 * i + 3] = T(0);
+  dens8[8 * i + 7] = T(0);
+}
+
+template <typename TI, typename TO>
+__global__ void k_convert(int64_t n, const TI* in, TO* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (TO)in[i];
+}
+
+template <>
+__global__ void k_convert<double, __hip_bfloat16>(int64_t n, const double* in, __hip_bfloat16* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = __float2bfloat16((float)in[i]);
+}
+
+// phi_up(parent) = sum over children with sources of T(child)
+__global__ void k_m2m_reduce(const int* parents, int n_par, const int* child_first, const int* child_count,
+                             const int* src_b, const int* src_e, const double* T, double* phi, int NC) {
+  int pi = blockIdx.x;
+  if (pi >= n_par) return;
+  int P = parents[pi];
+  int f = child_first[P], nc = child_count[P];
+  for (int c = threadIdx.x; c < NC; c += blockDim.x) {
+    double acc = 0;
+    for (int k = 0; k < nc; ++k) {
+      int C = f + k;
+      if (src_e[C] > src_b[C]) acc += T[(size_t)C * NC + c];
+    }
+    phi[(size_t)P * NC + c] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ check-surface evaluations (S2M, X)
+
+constexpr int kStage = 256;  // points staged in LDS per round
+
+// Evaluate the sources of a list of leaves at the check surface of box B (displacement, U and/or P).
+//   S2M: B's own sources at its upward check surface (radius r_up_check), written to q (FP64).
+//   S2L: sources of X(B) at B's downward check surface (radius r_dn_check), r_B * value added to qhat.
+template <typename T, typename TQ, bool SL, bool DL, bool S2M>
+__global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ boxes, TreeView tv,
+                                                    const int* __restrict__ list_off,
+                                                    const int* __restrict__ list_idx, const T* __restrict__ spos4,
+                                                    const T* __restrict__ snrm4, const T* __restrict__ dens8,
+                                                    const double* __restrict__ surf, int n_eq, double radius, int NC,
+                                                    KConst<T> kc, TQ* __restrict__ out) {
+  __shared__ T sp[kStage][4];
+  __shared__ T sn[kStage][4];
+  __shared__ T sd[kStage][8];
+  const int B = boxes[blockIdx.x];
+  const int tid = threadIdx.x;
+  const double rB = box_half(tv.level, tv.geom, tv.root_R, B);
+  T x[3] = {0, 0, 0};
+  if (tid < n_eq)
+    for (int d = 0; d < 3; ++d) x[d] = (T)(radius * rB * surf[3 * tid + d]);
+  T vU[3] = {0, 0, 0}, vP[3] = {0, 0, 0};
+  int fill = 0;
+  auto flush = [&](int n) {
+    __syncthreads();
+    if (tid < n_eq) {
+      for (int j = 0; j < n; ++j) {
+        T dx = sp[j][0] - x[0], dy = sp[j][1] - x[1], dz = sp[j][2] - x[2];
+        T r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == T(0)) continue;
+        disp_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, vU, vP);
+      }
+    }
+    __syncthreads();
+  };
+  const int nl = S2M ? 1 : list_off[B + 1] - list_off[B];
+  for (int li = 0; li < nl; ++li) {
+    const int A = S2M ? B : list_idx[list_off[B] + li];
+    double o[3] = {0, 0, 0};
+    if (!S2M) box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
+    const int s0 = tv.src_b[A], ns = tv.src_e[A] - s0;
+    for (int base = 0; base < ns; base += kStage) {
+      int cnt = min(kStage, ns - base);
+      if (fill + cnt > kStage) {
+        flush(fill);
+        fill = 0;
+      }
+      for (int i = tid; i < cnt; i += blockDim.x) {
+        int64_t g = s0 + base + i;
+        for (int d = 0; d < 3; ++d) {
+          sp[fill + i][d] = (T)o[d] + spos4[4 * g + d];
+          sn[fill + i][d] = snrm4[4 * g + d];
+        }
+        for (int d = 0; d < 8; ++d) sd[fill + i][d] = dens8[8 * g + d];
+      }
+      fill += cnt;
+    }
+  }
+  flush(fill);
+  if (tid < n_eq) {
+    for (int d = 0; d < 3; ++d) {
+      double v = (double)(kc.cU * vU[d] - kc.cP * vP[d]);
+      if (S2M)
+        out[(size_t)B * NC + 3 * tid + d] = (TQ)v;
+      else
+        out[(size_t)B * NC + 3 * tid + d] += (TQ)(rB * v);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------- leaf evaluation
+
+// One workgroup per target leaf B.  Lanes are split into S slices over the staged points; slice
+// partial sums are reduced in LDS at the end.  KIND 0 = displacement (3), 1 = stress (6).
+template <typename T, int KIND, bool SL, bool DL>
+__global__ __launch_bounds__(256) void k_leaf_eval(
+    const int* __restrict__ leaves, TreeView tv, const int* __restrict__ u_off, const int* __restrict__ u_idx,
+    const int* __restrict__ w_off, const int* __restrict__ w_idx, const T* __restrict__ spos4,
+    const T* __restrict__ snrm4, const T* __restrict__ dens8, const T* __restrict__ tpos4,
+    const int* __restrict__ perm_trg, const T* __restrict__ phi_dn, const T* __restrict__ phi_up,
+    const double* __restrict__ surf, int n_eq, double r_up_equiv, double r_dn_equiv, int NC, int far_field,
+    KConst<T> kc, double* __restrict__ out) {
+  constexpr int NO = KIND == 0 ? 3 : 6;
+  __shared__ T sp[kStage][4];
+  __shared__ T sn[kStage][4];
+  __shared__ T sd[kStage][8];
+  __shared__ double red[256][NO];
+  const int B = leaves[blockIdx.x];
+  const int tid = threadIdx.x;
+  const double rB = box_half(tv.level, tv.geom, tv.root_R, B);
+  const int t0 = tv.trg_b[B], nt_all = tv.trg_e[B] - t0;
+  for (int tc = 0; tc < nt_all; tc += 256) {
+    const int nt = min(256, nt_all - tc);
+    const int S = 256 / nt;
+    const int t = tid % nt, sl = tid / nt;
+    const bool act = sl < S;
+    T x[3];
+    for (int d = 0; d < 3; ++d) x[d] = tpos4[4 * (int64_t)(t0 + tc + t) + d];
+    T aU[NO], aP[NO];
+    for (int c = 0; c < NO; ++c) aU[c] = aP[c] = T(0);
+    int fill = 0;
+    // far-field points carry only a single-layer density (in sd[0..2])
+    auto flush = [&](int n, bool near) {
+      __syncthreads();
+      if (act) {
+        for (int j = sl; j < n; j += S) {
+          T dx = sp[j][0] - x[0], dy = sp[j][1] - x[1], dz = sp[j][2] - x[2];
+          T r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == T(0)) continue;
+          if (near) {
+            if (KIND == 0)
+              disp_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU, aP);
+            else
+              stress_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU, aP);
+          } else {
+            if (KIND == 0)
+              disp_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU, aP);
+            else
+              stress_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU, aP);
+          }
+        }
+      }
+      __syncthreads();
+    };
+    if (far_field) {
+      // L2T: B's downward equivalent surface, then M2T over W(B) (upward equivalent surfaces)
+      const int nw = w_off[B + 1] - w_off[B];
+      for (int li = -1; li < nw; ++li) {
+        const int A = li < 0 ? B : w_idx[w_off[B] + li];
+        double o[3] = {0, 0, 0};
+        if (li >= 0) box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
+        const double rad = li < 0 ? r_dn_equiv * rB : r_up_equiv * box_half(tv.level, tv.geom, tv.root_R, A);
+        const T* phi = li < 0 ? phi_dn : phi_up;
+        for (int base = 0; base < n_eq; base += kStage) {
+          const int cnt = min(kStage, n_eq - base);
+          if (fill + cnt > kStage) {
+            flush(fill, false);
+            fill = 0;
+          }
+          for (int i = tid; i < cnt; i += blockDim.x) {
+            const int e = base + i;
+            for (int d = 0; d < 3; ++d) {
+              sp[fill + i][d] = (T)(o[d] + rad * surf[3 * e + d]);
+              sd[fill + i][d] = phi[(size_t)A * NC + 3 * e + d];
+            }
+          }
+          fill += cnt;
+        }
+      }
+      flush(fill, false);
+      fill = 0;
+    }
+    // near field: U(B)
+    for (int li = u_off[B]; li < u_off[B + 1]; ++li) {
+      const int A = u_idx[li];
+      double o[3];
+      box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
+      const int s0 = tv.src_b[A], ns = tv.src_e[A] - s0;
+      for (int base = 0; base < ns; base += kStage) {
+        int cnt = min(kStage, ns - base);
+        if (fill + cnt > kStage) {
+          flush(fill, true);
+          fill = 0;
+        }
+        for (int i = tid; i < cnt; i += blockDim.x) {
+          int64_t g = s0 + base + i;
+          for (int d = 0; d < 3; ++d) {
+            sp[fill + i][d] = (T)o[d] + spos4[4 * g + d];
+            sn[fill + i][d] = snrm4[4 * g + d];
+          }
+          for (int d = 0; d < 8; ++d) sd[fill + i][d] = dens8[8 * g + d];
+        }
+        fill += cnt;
+      }
+    }
+    flush(fill, true);
+    // combine prefactors, reduce the slices
+    for (int c = 0; c < NO; ++c) {
+      double v;
+      if (KIND == 0)
+        v = (double)kc.cU * (double)aU[c] - (double)kc.cP * (double)aP[c];
+      else
+        v = (double)kc.cD * (double)aU[c] + (double)kc.cS * (double)aP[c];
+      red[tid][c] = act ? v : 0.0;
+    }
+    __syncthreads();
+    if (tid < nt) {
+      double acc[NO];
+      for (int c = 0; c < NO; ++c) acc[c] = 0;
+      for (int s2 = 0; s2 < S; ++s2)
+        for (int c = 0; c < NO; ++c) acc[c] += red[s2 * nt + tid][c];
+      int o = perm_trg[t0 + tc + tid];
+      for (int c = 0; c < NO; ++c) out[(size_t)o * NO + c] = acc[c];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------ plan
+
+static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s) {
+  GemmJob job;
+  const int n = (int)cols.op.size();
+  if (n == 0) return job;
+  // tiles: consecutive columns with the same op, <= kGemmBN each (columns must be grouped by op)
+  std::vector<int4> tiles;
+  int i = 0;
+  while (i < n) {
+    int j = i;
+    while (j < n && cols.op[j] == cols.op[i] && j - i < kGemmBN) ++j;
+    tiles.push_back(make_int4(cols.op[i], i, j - i, 0));
+    i = j;
+  }
+  job.n_tiles = (int)tiles.size();
+  job.tiles = a.get<int4>(tiles.size());
+  KFMM_HIP(hipMemcpyAsync(job.tiles, tiles.data(), tiles.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  job.in_idx = a.get<int>(n);
+  job.out_idx = a.get<int>(n);
+  job.scale = a.get<double>(n);
+  KFMM_HIP(hipMemcpyAsync(job.in_idx, cols.in.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  KFMM_HIP(hipMemcpyAsync(job.out_idx, cols.out.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  KFMM_HIP(hipMemcpyAsync(job.scale, cols.scale.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  return job;
+}
+
+// Sort columns by op (stable) so that tiles share one operator.
+static GemmCols sorted_by_op(const GemmCols& c) {
+  std::vector<int> order(c.op.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c.op[a] < c.op[b]; });
+  GemmCols o;
+  for (int i : order) o.add(c.op[i], c.in[i], c.out[i], c.scale[i]);
+  return o;
+}
+
+template <typename T>
+static T* upload_vec(Arena& a, const std::vector<T>& h, hipStream_t s) {
+  T* d = a.get<T>(h.empty() ? 1 : h.size());
+  if (!h.empty()) KFMM_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return d;
+}
+
+Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t n_src, const double* trg,
+                  int64_t n_trg, const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, const fmm_opts& o,
+                  hipStream_t s) {
+  auto t_start = std::chrono::steady_clock::now();
+  std::unique_ptr<Plan> P(new Plan());
+  P->opts = o;
+  P->el = Elastic::make(o.K, o.G);
+  P->prec = o.precision;
+  P->n_src = n_src;
+  P->alias = trg == nullptr;
+  P->n_trg = P->alias ? n_src : n_trg;
+  P->has_nrm = nrm != nullptr;
+  P->arena.limit = o.mem_limit;
+  const int p = o.p > 0 ? o.p : 6;
+  const int leaf_max = o.leaf_max > 0 ? o.leaf_max : 64;
+  const int max_depth = std::min(o.max_depth > 0 ? o.max_depth : 16, kMortonBits - 1);
+  // relative cutoff of the pseudo-inverse: 1e-8 minimised the measured error for p = 4..10
+  double eps = o.svd_eps > 0 ? o.svd_eps : 1e-8;
+  P->ops = get_ops(p, P->el, eps, o.precision, s);
+  const DeviceOps& D = *P->ops;
+  P->NC = D.NC;
+  P->n_eq = D.n_eq;
+  if (n_src == 0 || P->n_trg == 0) {
+    P->empty = true;
+    P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return P.release();
+  }
+  Tree& t = P->tree;
+  build_tree(t, P->arena, src, n_src, trg, n_trg, bs, bt, leaf_max, max_depth, s);
+  build_lists(t, P->arena, s);
+  P->tv = TreeView{t.level, t.ix, t.iy, t.iz, t.geom, t.root_c, t.root_R, t.src_b, t.src_e, t.trg_b, t.trg_e};
+  const int nb = t.n_box, NC = P->NC;
+  // ---- sorted local point data
+  const bool f64 = o.precision == KFMM_FP64;
+  const size_t ts = f64 ? 8 : 4;
+  P->spos = P->arena.alloc(ts * 4 * n_src);
+  P->snrm = P->arena.alloc(ts * 4 * n_src);
+  P->sw = P->arena.get<double>(n_src);
+  P->tpos = P->alias ? P->spos : P->arena.alloc(ts * 4 * P->n_trg);
+  P->dens = P->arena.alloc(ts * 8 * n_src);
+  unsigned gb = (unsigned)((n_src + 255) / 256), gt = (unsigned)((P->n_trg + 255) / 256);
+  if (f64) {
+    hipLaunchKernelGGL(k_local_points<double>, dim3(gb), dim3(256), 0, s, n_src, t.perm_src, t.leaf_of_src, src, nrm,
+                       w, P->tv, (double*)P->spos, (double*)P->snrm, P->sw);
+    if (!P->alias)
+      hipLaunchKernelGGL(k_local_points<double>, dim3(gt), dim3(256), 0, s, P->n_trg, t.perm_trg, t.leaf_of_trg, trg,
+                         (const double*)nullptr, (const double*)nullptr, P->tv, (double*)P->tpos, (double*)nullptr,
+                         (double*)nullptr);
+  } else {
+    hipLaunchKernelGGL(k_local_points<float>, dim3(gb), dim3(256), 0, s, n_src, t.perm_src, t.leaf_of_src, src, nrm,
+                       w, P->tv, (float*)P->spos, (float*)P->snrm, P->sw);
+    if (!P->alias)
+      hipLaunchKernelGGL(k_local_points<float>, dim3(gt), dim3(256), 0, s, P->n_trg, t.perm_trg, t.leaf_of_trg, trg,
+                         (const double*)nullptr, (const double*)nullptr, P->tv, (float*)P->tpos, (float*)nullptr,
+                         (double*)nullptr);
+  }
+  KFMM_HIP(hipGetLastError());
+  // ---- work lists
+  std::vector<int> leaves_src, leaves_trg, x_boxes;
+  for (int b = 0; b < nb; ++b) {
+    bool hs = t.h_src_e[b] > t.h_src_b[b], ht = t.h_trg_e[b] > t.h_trg_b[b];
+    if (t.h_is_leaf[b] && hs) leaves_src.push_back(b);
+    if (t.h_is_leaf[b] && ht) leaves_trg.push_back(b);
+    if (t.h_x_off[b + 1] > t.h_x_off[b]) x_boxes.push_back(b);
+  }
+  P->n_leaves_src = (int)leaves_src.size();
+  P->n_leaves_trg = (int)leaves_trg.size();
+  P->n_x_boxes = (int)x_boxes.size();
+  P->leaves_src = upload_vec(P->arena, leaves_src, s);
+  P->leaves_trg = upload_vec(P->arena, leaves_trg, s);
+  P->x_boxes = upload_vec(P->arena, x_boxes, s);
+  auto half = [&](int b) { return std::ldexp(t.h_root_R[t.h_geom[b]], -t.h_level[b]); };
+  auto octant = [&](int b) { return (t.h_ix[b] & 1) | ((t.h_iy[b] & 1) << 1) | ((t.h_iz[b] & 1) << 2); };
+  auto hs = [&](int b) { return t.h_src_e[b] > t.h_src_b[b]; };
+  auto ht = [&](int b) { return t.h_trg_e[b] > t.h_trg_b[b]; };
+  // UC2UE over source leaves
+  {
+    GemmCols c;
+    for (int b : leaves_src) c.add(0, b, b, half(b));
+    P->job_uc2ue = upload_job(P->arena, c, s);
+  }
+  // M2M per level (deepest first): children with sources, grouped by octant; parents reduce
+  P->up_levels.clear();
+  for (int l = t.depth; l >= 1; --l) {
+    GemmCols c;
+    std::vector<int> parents;
+    for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
+      if (hs(b)) c.add(octant(b), b, b);
+    for (int b = t.level_start[l - 1]; b < t.level_start[l]; ++b)
+      if (!t.h_is_leaf[b] && hs(b)) parents.push_back(b);
+    if (c.op.empty()) continue;
+    UpLevel U;
+    U.job = upload_job(P->arena, sorted_by_op(c), s);
+    U.n_par = (int)parents.size();
+    U.parents = upload_vec(P->arena, parents, s);
+    P->up_levels.push_back(U);
+  }
+  // M2L: V pairs grouped by compact offset index
+  {
+    GemmCols c;
+    for (size_t i = 0; i < t.h_v_trg.size(); ++i) {
+      int oi = D.m2l_index[t.h_v_off[i]];
+      if (oi < 0) throw Error(-5, "internal: V pair with a near offset");
+      c.add(oi, t.h_v_src[i], t.h_v_trg[i]);
+    }
+    P->job_m2l = upload_job(P->arena, sorted_by_op(c), s);
+    P->n_v_pairs = (int64_t)c.op.size();
+  }
+  // DC2DE over all boxes with targets at level >= 2; L2L per level >= 3
+  {
+    GemmCols c;
+    for (int b = 0; b < nb; ++b)
+      if (t.h_level[b] >= 2 && ht(b)) c.add(0, b, b);
+    P->job_dc2de = upload_job(P->arena, c, s);
+    P->dn_levels.clear();
+    for (int l = 3; l <= t.depth; ++l) {
+      GemmCols cl;
+      for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
+        if (ht(b)) cl.add(octant(b), t.h_parent[b], b);
+      if (cl.op.empty()) continue;
+      P->dn_levels.push_back(upload_job(P->arena, sorted_by_op(cl), s));
+    }
+  }
+  // ---- counters
+  int64_t up = 0;
+  for (int b : leaves_trg)
+    for (int k = t.h_u_off[b]; k < t.h_u_off[b + 1]; ++k) {
+      int A = t.h_u_idx[k];
+      up += (int64_t)(t.h_trg_e[b] - t.h_trg_b[b]) * (t.h_src_e[A] - t.h_src_b[A]);
+    }
+  P->n_u_pairs = up;
+  P->n_w_pairs = (int64_t)t.h_w_idx.size();
+  P->n_x_pairs = (int64_t)t.h_x_idx.size();
+  P->n_leaf = 0;
+  for (int b = 0; b < nb; ++b) P->n_leaf += t.h_is_leaf[b];
+  // ---- work buffers (zeroed once; padding rows stay zero)
+  auto zalloc = [&](size_t bytes) {
+    void* p = P->arena.alloc(bytes);
+    KFMM_HIP(hipMemsetAsync(p, 0, bytes, s));
+    return p;
+  };
+  const size_t nbc = (size_t)nb * NC;
+  P->q_up = (double*)zalloc(nbc * 8);
+  P->phi_up = (double*)zalloc(nbc * 8);
+  P->phi_dn = (double*)zalloc(nbc * 8);
+  P->tmp = (double*)zalloc(nbc * 8);
+  if (!f64) {
+    P->phi_up_lo = zalloc(nbc * 4);
+    P->phi_dn_lo = zalloc(nbc * 4);
+    P->qhat_lo = zalloc(nbc * 4);
+    if (o.precision == KFMM_FP32_M2L_BF16) P->phi_up_bf = zalloc(nbc * 2);
+  }
+  KFMM_HIP(hipStreamSynchronize(s));
+  P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return P.release();
+}
+
+// ------------------------------------------------------------------------------------------ eval
+
+template <typename T>
+static void eval_t(Plan& P, int kind, const double* a, const double* b, double* out, hipStream_t s) {
+  const Tree& t = P.tree;
+  const DeviceOps& D = *P.ops;
+  const int NC = P.NC, nb = t.n_box, n_eq = P.n_eq;
+  const size_t nbc = (size_t)nb * NC;
+  const bool SLa = a != nullptr, DLa = b != nullptr;
+  KConst<T> kc(P.el);
+  auto mark = [&](int i) {
+    if (P.prof) KFMM_HIP(hipEventRecord(P.ev[i], s));
+  };
+  mark(KFMM_PH_PERMUTE);
+  // densities
+  hipLaunchKernelGGL(k_permute_in<T>, dim3((unsigned)((P.n_src + 255) / 256)), dim3(256), 0, s, P.n_src,
+                     t.perm_src, P.sw, a, b, (T*)P.dens);
+  const T* spos = (const T*)P.spos;
+  const T* snrm = (const T*)P.snrm;
+  const T* dens = (const T*)P.dens;
+  const bool far = nb > 1;
+  // one thread per check point (n_eq <= 1024 for p <= 12)
+  const int check_block = std::max(64, round_up(n_eq, 64));
+  mark(KFMM_PH_S2M);
+  if (far) {
+    // S2M
+    auto s2m = [&](auto sl, auto dl) {
+      constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
+      hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
+                         P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
+                         2.95, NC, kc, P.q_up);
+    };
+    if (SLa && DLa)
+      s2m(std::true_type(), std::true_type());
+    else if (SLa)
+      s2m(std::true_type(), std::false_type());
+    else
+      s2m(std::false_type(), std::true_type());
+    KFMM_HIP(hipGetLastError());
+    mark(KFMM_PH_UC2UE);
+    gemm_f64(P.job_uc2ue, D.uc2ue, NC, P.q_up, P.phi_up, kStore, s);
+    mark(KFMM_PH_M2M);
+    for (const UpLevel& U : P.up_levels) {
+      gemm_f64(U.job, D.m2m, NC, P.phi_up, P.tmp, kStore, s);
+      if (U.n_par)
+        hipLaunchKernelGGL(k_m2m_reduce, dim3(U.n_par), dim3(256), 0, s, U.parents, U.n_par, t.child_first,
+                           t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
+    }
+    KFMM_HIP(hipGetLastError());
+    // M2L into qhat
+    mark(KFMM_PH_M2L_PREP);
+    void* qhat;
+    if (P.prec == KFMM_FP64) {
+      qhat = P.q_up;  // reuse: S2M potentials are consumed
+      KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 8, s));
+      mark(KFMM_PH_M2L);
+      gemm_f64(P.job_m2l, D.m2l64, NC, P.phi_up, (double*)qhat, kAtomicAdd, s);
+    } else {
+      qhat = P.qhat_lo;
+      KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 4, s));
+      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                         (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
+      if (P.prec == KFMM_FP32) {
+        mark(KFMM_PH_M2L);
+        gemm_f32(P.job_m2l, D.m2l32, NC, (const float*)P.phi_up_lo, (float*)qhat, kAtomicAdd, s);
+      } else {
+        hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                           (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
+        mark(KFMM_PH_M2L);
+        gemm_bf16(P.job_m2l, D.m2l16, NC, (const __hip_bfloat16*)P.phi_up_bf, (float*)qhat, kAtomicAdd, s);
+      }
+    }
+    KFMM_HIP(hipGetLastError());
+    mark(KFMM_PH_S2L);
+    // X list
+    if (P.n_x_boxes) {
+      using TQ = typename std::conditional<sizeof(T) == 8, double, float>::type;
+      auto s2l = [&](auto sl, auto dl) {
+        constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
+        hipLaunchKernelGGL((k_check_eval<T, TQ, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, s, P.x_boxes, P.tv,
+                           t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, (TQ*)qhat);
+      };
+      if (SLa && DLa)
+        s2l(std::true_type(), std::true_type());
+      else if (SLa)
+        s2l(std::true_type(), std::false_type());
+      else
+        s2l(std::false_type(), std::true_type());
+      KFMM_HIP(hipGetLastError());
+    }
+    // downward pass in FP64
+    mark(KFMM_PH_DOWN);
+    const double* q64 = (const double*)qhat;
+    if (P.prec != KFMM_FP64) {
+      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                         (int64_t)nbc, (const float*)qhat, P.tmp);
+      q64 = P.tmp;
+    }
+    gemm_f64(P.job_dc2de, D.dc2de, NC, q64, P.phi_dn, kStore, s);
+    for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, NC, P.phi_dn, P.phi_dn, kAdd, s);
+    if (P.prec != KFMM_FP64)
+      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                         (int64_t)nbc, P.phi_dn, (float*)P.phi_dn_lo);
+    KFMM_HIP(hipGetLastError());
+  }
+  if (!far) {  // no far field: empty intermediate phases
+    for (int ph = KFMM_PH_UC2UE; ph <= KFMM_PH_DOWN; ++ph) mark(ph);
+  }
+  mark(KFMM_PH_LEAF);
+  const T* phi_dn = P.prec == KFMM_FP64 ? (const T*)P.phi_dn : (const T*)P.phi_dn_lo;
+  const T* phi_up = P.prec == KFMM_FP64 ? (const T*)P.phi_up : (const T*)P.phi_up_lo;
+  auto leaf = [&](auto kd, auto sl, auto dl) {
+    constexpr int KIND = decltype(kd)::value;
+    constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
+    hipLaunchKernelGGL((k_leaf_eval<T, KIND, SL, DL>), dim3(P.n_leaves_trg), dim3(256), 0, s, P.leaves_trg, P.tv,
+                       t.u_off, t.u_idx, t.w_off, t.w_idx, spos, snrm, dens, (const T*)P.tpos, t.perm_trg, phi_dn,
+                       phi_up, D.surf, n_eq, 1.05, 2.95, NC, far ? 1 : 0, kc, out);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  if (kind == KFMM_DISP) {
+    if (SLa && DLa)
+      leaf(I0(), std::true_type(), std::true_type());
+    else if (SLa)
+      leaf(I0(), std::true_type(), std::false_type());
+    else
+      leaf(I0(), std::false_type(), std::true_type());
+  } else {
+    if (SLa && DLa)
+      leaf(I1(), std::true_type(), std::true_type());
+    else if (SLa)
+      leaf(I1(), std::true_type(), std::false_type());
+    else
+      leaf(I1(), std::false_type(), std::true_type());
+  }
+  KFMM_HIP(hipGetLastError());
+  mark(KFMM_N_PHASES);
+  if (P.prof) {
+    KFMM_HIP(hipEventSynchronize(P.ev[KFMM_N_PHASES]));
+    for (int ph = 0; ph < KFMM_N_PHASES; ++ph) {
+      float ms = 0;
+      KFMM_HIP(hipEventElapsedTime(&ms, P.ev[ph], P.ev[ph + 1]));
+      P.phase_ms[ph] += ms;
+    }
+    P.prof_calls++;
+  }
+}
+
+Plan::~Plan() {
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+void plan_profile(Plan& P, bool enable) {
+  if (enable && !P.ev[0])
+    for (auto& e : P.ev) KFMM_HIP(hipEventCreate(&e));
+  P.prof = enable;
+  if (enable) {
+    for (double& v : P.phase_ms) v = 0;
+    P.prof_calls = 0;
+  }
+}
+
+void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out, hipStream_t s) {
+  const int no = kind == KFMM_DISP ? 3 : 6;
+  if (P.n_trg == 0) return;
+  if (P.empty || (!a && !b)) {
+    KFMM_HIP(hipMemsetAsync(out, 0, sizeof(double) * no * P.n_trg, s));
+    return;
+  }
+  if (P.prec == KFMM_FP64)
+    eval_t<double>(P, kind, a, b, out, s);
+  else
+    eval_t<float>(P, kind, a, b, out, s);
+}
+
+}  // namespace kfmm

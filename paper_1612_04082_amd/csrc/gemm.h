@@ -1,0 +1,53 @@
+// Batched gather/scatter GEMM on the CDNA matrix cores for every KIFMM translation.
+//
+//   Y[:, out_idx[j]] (=, +=, atomic +=)  scale[j] * A_op(j) * X[:, in_idx[j]]
+//
+// A_op are NC x NC row-major operators (op index per tile, stride NC*NC), X and Y hold one
+// NC-vector per box (box-major, stride NC).  Columns are grouped in tiles of <= 64 that share one
+// operator.  A workgroup of 4 waves computes a (16*TM) x 64 block: every wave owns 16 columns and
+// all rows; A and X tiles are staged in LDS, products use v_mfma_*_16x16x4 (FP64/FP32) or
+// v_mfma_f32_16x16x32_bf16 (BF16 inputs, FP32 accumulation).
+#pragma once
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+namespace kfmm {
+
+enum GemmMode { kStore = 0, kAdd = 1, kAtomicAdd = 2 };
+
+constexpr int kGemmBN = 64;     // columns per tile
+constexpr int kGemmTM = 6;      // 16-row MFMA tiles per wave
+constexpr int kGemmBM = 16 * kGemmTM;  // 96 rows per workgroup; NC is a multiple of this
+
+struct GemmJob {  // device arrays describing one launch
+  int n_tiles = 0;
+  int4* tiles = nullptr;    // {op, first column, column count, unused}
+  int* in_idx = nullptr;    // per column: source box (X column)
+  int* out_idx = nullptr;   // per column: destination box (Y column)
+  double* scale = nullptr;  // per column factor or nullptr
+};
+
+// Host-side description: (op, in, out, scale) per column, grouped by op into tiles.
+struct GemmCols {
+  std::vector<int> op, in, out;
+  std::vector<double> scale;
+  void add(int o, int i, int u, double s = 1.0) {
+    op.push_back(o);
+    in.push_back(i);
+    out.push_back(u);
+    scale.push_back(s);
+  }
+};
+
+void gemm_f64(const GemmJob& job, const double* A, int NC, const double* X, double* Y, int mode, hipStream_t s);
+void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, float* Y, int mode, hipStream_t s);
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, float* Y, int mode,
+               hipStream_t s);
+
+// Runs one gather/scatter GEMM launch from host column descriptors (test hook).
+void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,
+                   const int* out, const double* scale, int ncols, int mode, hipStream_t s);
+
+}  // namespace kfmm

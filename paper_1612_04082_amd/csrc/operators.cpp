@@ -1,0 +1,312 @@
+// Host-side FP64 precompute of the KIFMM translation operators (Sec. 2.2, "Kernel-independent fast
+// multipole method": far and local fields are densities on equivalent surfaces; M2M, M2L and L2L are
+// matrices computed from the kernel alone).
+//
+// Surfaces are cube surfaces with p points per edge (6(p-1)^2+2 points) around a box of half-width r:
+//   upward equivalent 1.05 r, upward check 2.95 r, downward check 1.05 r, downward equivalent 2.95 r.
+// The equivalent density is always a single-layer (Kelvin U) density.  Because U is homogeneous of
+// degree -1, every operator below is computed once at unit half-width and is level-invariant:
+//   UC2UE  = pinv(U[uc <- ue])                      leaf:   phi_up = r_l * UC2UE * q_check
+//   M2M_c  = UC2UE * U[parent uc <- child c ue]     parent: phi_up = sum_c M2M_c * phi_up(child c)
+//   M2L_d  = U[dc <- ue shifted by 2d]              qhat(B) += M2L_d * phi_up(A),  d = index offset A - B
+//   DC2DE  = pinv(U[dc <- de]) = UC2UE^T            phi_down = DC2DE * qhat
+//   L2L_c  = DC2DE * U[child c dc <- parent de]     phi_down(child) += L2L_c * phi_down(parent)
+// where qhat = r_l * (downward check potential).  U is symmetric and reciprocal, so U[dc<-de] is the
+// transpose of U[uc<-ue] and one SVD serves both pseudo-inverses.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+#include "operators.h"
+
+namespace kfmm {
+
+std::vector<double> cube_surface(int p) {
+  std::vector<double> pts;
+  for (int k = 0; k < p; ++k)
+    for (int j = 0; j < p; ++j)
+      for (int i = 0; i < p; ++i) {
+        if (i != 0 && i != p - 1 && j != 0 && j != p - 1 && k != 0 && k != p - 1) continue;
+        pts.push_back(-1.0 + 2.0 * i / (p - 1));
+        pts.push_back(-1.0 + 2.0 * j / (p - 1));
+        pts.push_back(-1.0 + 2.0 * k / (p - 1));
+      }
+  return pts;
+}
+
+// Dense U-kernel matrix, row-major (3 nx) x (3 ny): entry [3a+i][3b+j] = U_ij(x_a, y_b)  (eq. disp_1).
+static void kernel_matrix_U(const Elastic& e, const double* X, int nx, const double* Y, int ny, double* out) {
+  const int ld = 3 * ny;
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b) {
+      double d[3] = {Y[3 * b] - X[3 * a], Y[3 * b + 1] - X[3 * a + 1], Y[3 * b + 2] - X[3 * a + 2]};
+      double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double rr = d[i] * d[j] / (r * r);
+          out[(size_t)(3 * a + i) * ld + 3 * b + j] = e.cU / r * ((i == j ? (3.0 - 4.0 * e.nu) : 0.0) + rr);
+        }
+    }
+}
+
+// Pseudo-inverse of a square n x n row-major matrix by one-sided (Hestenes) Jacobi SVD in FP64,
+// singular values below eps * s_max discarded.  Columns are processed in a round-robin ordering so
+// that the n/2 rotations of one round touch disjoint column pairs and run on several threads.
+static std::vector<double> pinv_jacobi(const std::vector<double>& A, int n, double eps, int* rank_out) {
+  // column-major working copies: W = A V, V
+  std::vector<double> W((size_t)n * n), V((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) W[(size_t)j * n + i] = A[(size_t)i * n + j];
+  for (int j = 0; j < n; ++j) V[(size_t)j * n + j] = 1.0;
+  const int m = n + (n & 1);  // even number of slots for the tournament
+  std::vector<int> slot(m);
+  for (int i = 0; i < m; ++i) slot[i] = i;
+  unsigned hw = std::thread::hardware_concurrency();
+  int nthreads = (int)std::max(1u, std::min(hw == 0 ? 1u : hw, 16u));
+  const double tol = 1e-15;
+  // persistent workers; a sense-reversing spin barrier separates the rounds of the tournament
+  std::atomic<int> arrived{0};
+  std::atomic<int> sense{0};
+  auto barrier = [&](int& local_sense) {
+    local_sense ^= 1;
+    if (arrived.fetch_add(1) == nthreads - 1) {
+      arrived.store(0);
+      sense.store(local_sense);
+    } else {
+      while (sense.load() != local_sense) std::this_thread::yield();
+    }
+  };
+  std::vector<int> rotated(nthreads, 0);
+  std::atomic<bool> done{false};
+  auto worker = [&](int tid) {
+    int ls = 0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      for (int round = 0; round < m - 1; ++round) {
+        for (int k = tid; k < m / 2; k += nthreads) {
+          int p = slot[k], q = slot[m - 1 - k];
+          if (p >= n || q >= n) continue;
+          if (p > q) std::swap(p, q);
+          double* wp = &W[(size_t)p * n];
+          double* wq = &W[(size_t)q * n];
+          double al = 0, be = 0, ga = 0;
+          for (int i = 0; i < n; ++i) {
+            al += wp[i] * wp[i];
+            be += wq[i] * wq[i];
+            ga += wp[i] * wq[i];
+          }
+          if (ga == 0.0 || std::fabs(ga) <= tol * std::sqrt(al * be)) continue;
+          rotated[tid]++;
+          double zeta = (be - al) / (2.0 * ga);
+          double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+          for (int i = 0; i < n; ++i) {
+            double a = wp[i], b = wq[i];
+            wp[i] = c * a - s * b;
+            wq[i] = s * a + c * b;
+          }
+          double* vp = &V[(size_t)p * n];
+          double* vq = &V[(size_t)q * n];
+          for (int i = 0; i < n; ++i) {
+            double a = vp[i], b = vq[i];
+            vp[i] = c * a - s * b;
+            vq[i] = s * a + c * b;
+          }
+        }
+        barrier(ls);
+        if (tid == 0) {  // rotate the tournament (slot 0 fixed)
+          int last = slot[m - 1];
+          for (int i = m - 1; i > 1; --i) slot[i] = slot[i - 1];
+          slot[1] = last;
+        }
+        barrier(ls);
+      }
+      if (tid == 0) {
+        int tot = 0;
+        for (int& r : rotated) {
+          tot += r;
+          r = 0;
+        }
+        done.store(tot == 0);
+      }
+      barrier(ls);
+      if (done.load()) break;
+      barrier(ls);
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int t = 1; t < nthreads; ++t) th.emplace_back(worker, t);
+    worker(0);
+    for (auto& t : th) t.join();
+  }
+  std::vector<double> sig(n);
+  double smax = 0;
+  for (int j = 0; j < n; ++j) {
+    double s = 0;
+    for (int i = 0; i < n; ++i) s += W[(size_t)j * n + i] * W[(size_t)j * n + i];
+    sig[j] = std::sqrt(s);
+    smax = std::max(smax, sig[j]);
+  }
+  // pinv = V diag(1/s) U^T with U_j = W_j / s_j  ->  pinv[i][k] = sum_j V[i][j] W[k][j] / s_j^2
+  std::vector<double> P((size_t)n * n, 0.0);
+  int rank = 0;
+  std::vector<double> scaled((size_t)n * n, 0.0);  // column j: W_j / s_j^2 (kept columns only)
+  std::vector<int> keep;
+  for (int j = 0; j < n; ++j)
+    if (sig[j] > eps * smax) {
+      keep.push_back(j);
+      ++rank;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      double acc = 0;
+      for (int j : keep) acc += V[(size_t)j * n + i] * W[(size_t)j * n + k] / (sig[j] * sig[j]);
+      P[(size_t)i * n + k] = acc;
+    }
+  if (rank_out) *rank_out = rank;
+  return P;
+}
+
+// C = A B for n x n row-major FP64 matrices.
+static std::vector<double> matmul(const std::vector<double>& A, const std::vector<double>& B, int n) {
+  std::vector<double> C((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double* c = &C[(size_t)i * n];
+    for (int k = 0; k < n; ++k) {
+      double a = A[(size_t)i * n + k];
+      const double* b = &B[(size_t)k * n];
+      for (int j = 0; j < n; ++j) c[j] += a * b[j];
+    }
+  }
+  return C;
+}
+
+static std::string cache_path(int p, const Elastic& e, double eps) {
+  const char* dir = std::getenv("KFMM_CACHE_DIR");
+  std::string d;
+  if (dir && *dir) {
+    d = dir;
+  } else {
+    const char* home = std::getenv("HOME");
+    d = std::string(home ? home : "/tmp") + "/.cache/kfmm";
+  }
+  char name[256];
+  std::snprintf(name, sizeof(name), "/uc2ue_p%d_nu%.17g_G%.17g_eps%.3g_r1.05_2.95.bin", p, e.nu, e.G, eps);
+  return d + name;
+}
+
+static bool load_cache(const std::string& path, int n, std::vector<double>& P) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return false;
+  int nn = 0;
+  f.read((char*)&nn, sizeof(int));
+  if (nn != n) return false;
+  P.resize((size_t)n * n);
+  f.read((char*)P.data(), sizeof(double) * P.size());
+  uint64_t chk = 0, ref = 0;
+  f.read((char*)&ref, sizeof(ref));
+  if (!f) return false;
+  for (double v : P) {
+    uint64_t u;
+    std::memcpy(&u, &v, 8);
+    chk = chk * 1099511628211ull ^ u;
+  }
+  return chk == ref;
+}
+
+static void save_cache(const std::string& path, int n, const std::vector<double>& P) {
+  std::string dir = path.substr(0, path.rfind('/'));
+  std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
+  if (std::system(cmd.c_str()) != 0) return;
+  std::string tmp = path + ".tmp" + std::to_string((long)std::rand());
+  std::ofstream f(tmp, std::ios::binary);
+  if (!f) return;
+  f.write((const char*)&n, sizeof(int));
+  f.write((const char*)P.data(), sizeof(double) * P.size());
+  uint64_t chk = 0;
+  for (double v : P) {
+    uint64_t u;
+    std::memcpy(&u, &v, 8);
+    chk = chk * 1099511628211ull ^ u;
+  }
+  f.write((const char*)&chk, sizeof(chk));
+  f.close();
+  std::rename(tmp.c_str(), path.c_str());
+}
+
+Operators build_operators(int p, const Elastic& e, double svd_eps) {
+  Operators op;
+  op.p = p;
+  op.n_eq = surface_count(p);
+  const int n = 3 * op.n_eq;
+  op.n = n;
+  std::vector<double> S = cube_surface(p);
+  op.surf = S;
+  auto scaled = [&](double a, double ox, double oy, double oz) {
+    std::vector<double> v(S.size());
+    for (int i = 0; i < op.n_eq; ++i) {
+      v[3 * i] = ox + a * S[3 * i];
+      v[3 * i + 1] = oy + a * S[3 * i + 1];
+      v[3 * i + 2] = oz + a * S[3 * i + 2];
+    }
+    return v;
+  };
+  const double RE_UP = 1.05, RC_UP = 2.95, RC_DN = 1.05, RE_DN = 2.95;
+  op.r_up_equiv = RE_UP;
+  op.r_up_check = RC_UP;
+  op.r_dn_check = RC_DN;
+  op.r_dn_equiv = RE_DN;
+  std::vector<double> uc = scaled(RC_UP, 0, 0, 0), ue = scaled(RE_UP, 0, 0, 0);
+  std::vector<double> K((size_t)n * n);
+  kernel_matrix_U(e, uc.data(), op.n_eq, ue.data(), op.n_eq, K.data());
+  std::string path = cache_path(p, e, svd_eps);
+  if (!load_cache(path, n, op.uc2ue)) {
+    op.uc2ue = pinv_jacobi(K, n, svd_eps, &op.rank);
+    save_cache(path, n, op.uc2ue);
+  }
+  op.dc2de.resize((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) op.dc2de[(size_t)i * n + j] = op.uc2ue[(size_t)j * n + i];
+  // M2M and L2L per child octant c (bit0 x, bit1 y, bit2 z; child centre = parent centre + 0.5 o r_parent)
+  op.m2m.resize(8);
+  op.l2l.resize(8);
+  for (int c = 0; c < 8; ++c) {
+    double o[3] = {(c & 1) ? 1.0 : -1.0, (c & 2) ? 1.0 : -1.0, (c & 4) ? 1.0 : -1.0};
+    // parent frame (unit parent half-width): child upward equivalent surface
+    std::vector<double> che = scaled(0.5 * RE_UP, 0.5 * o[0], 0.5 * o[1], 0.5 * o[2]);
+    std::vector<double> Kc((size_t)n * n);
+    kernel_matrix_U(e, uc.data(), op.n_eq, che.data(), op.n_eq, Kc.data());
+    op.m2m[c] = matmul(op.uc2ue, Kc, n);
+    // child frame (unit child half-width): parent downward equivalent surface at -o with half-width 2*RE_DN
+    std::vector<double> cdc = scaled(RC_DN, 0, 0, 0);
+    std::vector<double> pde = scaled(2.0 * RE_DN, -o[0], -o[1], -o[2]);
+    std::vector<double> Kl((size_t)n * n);
+    kernel_matrix_U(e, cdc.data(), op.n_eq, pde.data(), op.n_eq, Kl.data());
+    op.l2l[c] = matmul(op.dc2de, Kl, n);
+  }
+  // M2L for every index offset d in [-3,3]^3 with max |d_i| >= 2 (316 offsets)
+  std::vector<double> dc = scaled(RC_DN, 0, 0, 0);
+  op.m2l_index.assign(343, -1);
+  for (int dz = -3; dz <= 3; ++dz)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) < 2) continue;
+        int idx = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+        op.m2l_index[idx] = (int)op.m2l.size();
+        std::vector<double> se = scaled(RE_UP, 2.0 * dx, 2.0 * dy, 2.0 * dz);
+        std::vector<double> Km((size_t)n * n);
+        kernel_matrix_U(e, dc.data(), op.n_eq, se.data(), op.n_eq, Km.data());
+        op.m2l.push_back(std::move(Km));
+      }
+  return op;
+}
+
+}  // namespace kfmm

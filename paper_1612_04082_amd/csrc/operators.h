@@ -1,0 +1,23 @@
+// Level-invariant KIFMM translation operators (host, FP64); see operators.cpp.
+#pragma once
+#include <vector>
+
+#include "common.h"
+
+namespace kfmm {
+
+struct Operators {
+  int p = 0, n_eq = 0, n = 0, rank = 0;  // n = 3 n_eq coefficients per box
+  double r_up_equiv = 0, r_up_check = 0, r_dn_check = 0, r_dn_equiv = 0;
+  std::vector<double> surf;                 // n_eq x 3 unit cube-surface points
+  std::vector<double> uc2ue, dc2de;         // n x n
+  std::vector<std::vector<double>> m2m;     // 8 x (n x n)
+  std::vector<std::vector<double>> l2l;     // 8 x (n x n)
+  std::vector<std::vector<double>> m2l;     // 316 x (n x n)
+  std::vector<int> m2l_index;               // 343 -> compact index (or -1), key (dx+3)+7(dy+3)+49(dz+3)
+};
+
+std::vector<double> cube_surface(int p);
+Operators build_operators(int p, const Elastic& e, double svd_eps);
+
+}  // namespace kfmm

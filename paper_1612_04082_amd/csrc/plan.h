@@ -1,0 +1,68 @@
+// FMM plan object: tree, lists, operator handles, work buffers and per-pass launch descriptors.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "../../include/kfmm.h"
+#include "common.h"
+#include "gemm.h"
+#include "tree.h"
+
+namespace kfmm {
+
+struct DeviceOps;
+
+// Read-only device view of the box arrays passed to kernels by value.
+struct TreeView {
+  const int *level, *ix, *iy, *iz, *geom;
+  const double *root_c, *root_R;
+  const int *src_b, *src_e, *trg_b, *trg_e;
+};
+
+struct UpLevel {
+  GemmJob job;          // T(child) = M2M_octant(child) * phi_up(child), children of one level
+  int n_par = 0;        // parents (non-leaf boxes with sources) of that level
+  int* parents = nullptr;
+};
+
+struct Plan {
+  fmm_opts opts{};
+  Elastic el{};
+  int prec = 0;
+  bool alias = false, has_nrm = false, empty = false;
+  int64_t n_src = 0, n_trg = 0;
+  int NC = 0, n_eq = 0;
+  std::shared_ptr<DeviceOps> ops;
+  Arena arena;
+  Tree tree;
+  TreeView tv{};
+  // sorted, leaf-local point data (precision-dependent element type)
+  void *spos = nullptr, *snrm = nullptr, *tpos = nullptr, *dens = nullptr;
+  double* sw = nullptr;
+  // launch lists
+  int n_leaves_src = 0, n_leaves_trg = 0, n_x_boxes = 0;
+  int *leaves_src = nullptr, *leaves_trg = nullptr, *x_boxes = nullptr;
+  GemmJob job_uc2ue, job_m2l, job_dc2de;
+  std::vector<UpLevel> up_levels;
+  std::vector<GemmJob> dn_levels;
+  // per-box coefficient buffers (n_box x NC)
+  double *q_up = nullptr, *phi_up = nullptr, *phi_dn = nullptr, *tmp = nullptr;
+  void *phi_up_lo = nullptr, *phi_dn_lo = nullptr, *qhat_lo = nullptr, *phi_up_bf = nullptr;
+  // optional phase timing with HIP events (see fmm_profile)
+  bool prof = false;
+  hipEvent_t ev[KFMM_N_PHASES + 1] = {};
+  double phase_ms[KFMM_N_PHASES] = {};
+  int64_t prof_calls = 0;
+  // counters
+  int64_t n_leaf = 0, n_u_pairs = 0, n_v_pairs = 0, n_w_pairs = 0, n_x_pairs = 0;
+  double plan_seconds = 0;
+  ~Plan();
+};
+
+Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t n_src, const double* trg,
+                  int64_t n_trg, const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, const fmm_opts& o,
+                  hipStream_t s);
+void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out, hipStream_t s);
+void plan_profile(Plan& P, bool enable);
+
+}  // namespace kfmm
