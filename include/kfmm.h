@@ -135,6 +135,69 @@ int fmm_phase_times(kfmm_plan_t plan, double* ms /* host, KFMM_N_PHASES */, int6
 /* Release the plan and its device memory.  NULL is a no-op. */
 int fmm_plan_destroy(kfmm_plan_t plan);
 
+/* ---------------------------------------------------------------------------------------------------
+ * Collocation BEM (Sec. 2.2, "Discretization of BIE", "Matrix-vector products"; eqs. BIE, num, coef, num2).
+ * Flat triangles with piecewise-constant displacement and traction, collocation at centroids (free term
+ * 1/2 I), 16 quadrature points per triangle (4 midpoint sub-triangles x symmetric 4-point rule), closed-form
+ * self integrals in the local pass, unknowns per element and component: u where the traction is prescribed,
+ * t where the displacement is prescribed.
+ */
+typedef struct {
+  int64_t n_tri;          /* T > 0 */
+  const double* tri_xyz;  /* T x 3 x 3 vertices (device), counter-clockwise seen from outside the body */
+  const int8_t* bc_type;  /* T x 3 (device): 0 = displacement prescribed, 1 = traction prescribed */
+  const double* bc_val;   /* T x 3 (device): prescribed displacement or traction */
+  double K, G;            /* moduli */
+} bem_problem;
+
+typedef struct {
+  double tol;      /* stop when ||b - A x|| / ||b|| <= tol (true residual) */
+  int restart;     /* GMRES restart length m (1..500) */
+  int max_iter;    /* maximum number of Arnoldi steps (matrix-vector products); 0 evaluates x0 only */
+  fmm_opts fmm;    /* options of the fast summation behind every product (K, G are taken from the problem) */
+} bem_opts;
+
+typedef struct {   /* host */
+  int iters, restarts, converged;
+  int64_t n_matvec;
+  double rel_res;      /* true relative residual of the returned x */
+  double rel_res0;     /* true relative residual of x0 */
+  double res_estimate; /* last GMRES estimate */
+  double b_norm;
+  double t_setup_s, t_solve_s;
+} bem_stats;
+
+/*
+ * bem_solve -- solve A x = B y (eq. num2) by restarted GMRES, every product through fmm_eval plus the local
+ * pass.  x0 (device, T x 3) or NULL for zero, and x (device, T x 3), hold the unknowns in physical units
+ * (inside the solver traction unknowns are scaled by -l/G, l = mean edge length; residuals refer to that system).  u_full, t_full (device, T x 3, may be NULL) receive the complete
+ * boundary displacement and traction.  stats (host) may be NULL.  Returns KFMM_E_NOCONV (x and stats filled)
+ * if the tolerance is not reached within max_iter.  Synchronises the stream.
+ */
+int bem_solve(const bem_problem* prob, const bem_opts* opts, const double* x0, double* x, double* u_full,
+              double* t_full, bem_stats* stats, void* stream);
+
+/*
+ * bem_stress -- interior stress from a boundary solution (eq. stress_1): sigma = int D t - int S u, with the
+ * same 16-point quadrature.  u_full, t_full: T x 3 (device); trg: M x 3 (device); out: M x 6 (device, xx, yy,
+ * zz, yz, xz, xy).  Builds and destroys a plan internally.  Synchronises the stream.
+ */
+int bem_stress(const bem_problem* prob, const double* u_full, const double* t_full, const double* trg, int64_t M,
+               double* out, const fmm_opts* fmm, void* stream);
+
+/*
+ * bem_matvec -- one product of the discrete system, as used inside bem_solve:
+ *   which = 0: y = A x   (x in solver units: traction unknowns scaled by -l/G),
+ *   which = 1: y = B y_prescribed (right-hand side; x ignored).
+ * x, y: T x 3 (device).  Builds a plan internally.  Synchronises the stream.
+ */
+int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const double* x, double* y, void* stream);
+
+/* bem_quadrature -- the 16 quadrature points per triangle (device, 16T x 3), their normals (16T x 3),
+ * weights (16T) and the collocation points (T x 3).  Synchronises the stream. */
+int bem_quadrature(int64_t n_tri, const double* tri_xyz, double* qp, double* qn, double* qw, double* colloc,
+                   void* stream);
+
 /*
  * Test hook: one launch of the batched gather/scatter GEMM used by every translation,
  *   Y[:, out[j]] (=, +=, atomic +=) scale[j] * A[op[j]] * X[:, in[j]]

@@ -15,7 +15,9 @@ Readings where the paper is silent (all listed with the design notes):
     barycentric (3/5, 1/5, 1/5) with weight 25/48);
   * "analytic" self integrals are done fully in closed form in polar coordinates about the
     centroid (radial integral exact, angular integral exact per edge);
-  * traction unknowns are column-scaled by G / l (l = mean element edge) for conditioning;
+  * traction unknowns are column-scaled by -G / l (l = mean element edge): the magnitude balances the
+    single-layer columns against the 1/2 I + P columns, the sign turns the columns -U (negative
+    definite) into +U so that the spectrum lies in the right half-plane (GMRES stalls otherwise);
   * GMRES stops on the true relative residual ||b - A x|| / ||b||.
 
 The matrices come from oracle.direct.quad_blocks (plain FP64 sums, coincident pairs skipped).
@@ -134,7 +136,7 @@ class DenseBEM:
             Pm[3 * k:3 * k + 3, 3 * k:3 * k + 3] = Ps
         self.H = Pm + 0.5 * np.eye(3 * self.T)
         self.Gm = Um
-        self.scale_t = G / mean_edge(self.tri)
+        self.scale_t = -G / mean_edge(self.tri)
         flat = self.bc_type.reshape(-1)
         self.u_unknown = flat == 1  # traction prescribed -> displacement unknown
         self.t_unknown = flat == 0

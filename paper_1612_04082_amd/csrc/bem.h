@@ -1,0 +1,47 @@
+// Collocation BEM system on the device (see bem.hip).
+#pragma once
+#include <memory>
+
+#include "../../include/kfmm.h"
+#include "common.h"
+#include "plan.h"
+#include "tree.h"
+
+namespace kfmm {
+
+struct BemSystem {
+  hipStream_t stream;
+  int64_t T = 0, n = 0;
+  Elastic el{};
+  const double* tri = nullptr;
+  const int8_t* bc_type = nullptr;
+  const double* bc_val = nullptr;
+  double mean_edge = 0, scale_t = 1;
+  Arena arena;
+  double *qp = nullptr, *qn = nullptr, *qw = nullptr, *cen = nullptr;  // quadrature sources, collocation points
+  double *dU = nullptr, *dP = nullptr;                                 // local-pass blocks (T x 3 x 3)
+  double *a16 = nullptr, *b16 = nullptr, *ae = nullptr, *be = nullptr, *fmm_out = nullptr;
+  double* partial = nullptr;
+  std::unique_ptr<Plan> plan;
+  int64_t n_apply = 0;
+
+  BemSystem(const bem_problem& p, const fmm_opts& fo, hipStream_t s);
+  ~BemSystem();
+  void apply(int mode, const double* x, double* out);  // 0: A x, 1: B y
+  double dot(const double* x, const double* y);
+  void split(const double* x, double* u, double* t);
+  bem_stats gmres(const double* x0, double* x, double tol, int m, int max_iter);
+  double* scratch_partial();
+};
+
+// Multiplies the traction entries of an unknown vector by factor (scale_t: solver units -> physical).
+void scale_traction_unknowns(BemSystem& sys, double* x, double factor);
+
+// Interior stress (eq. stress_1) from boundary u, t through a fresh plan with the lattice as targets.
+void stress_from_boundary(const bem_problem& p, const double* u, const double* t, const double* trg, int64_t M,
+                          double* out, const fmm_opts& fo, hipStream_t s);
+
+// Quadrature expansion only (16 points per triangle, normals, weights, centroids).
+void bem_expand(int64_t T, const double* tri, double* qp, double* qn, double* qw, double* cen, hipStream_t s);
+
+}  // namespace kfmm

@@ -1,10 +1,12 @@
 // C-ABI entry points (include/kfmm.h): argument validation, status codes and thread-local errors.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
 
 #include "../../include/kfmm.h"
 #include "common.h"
+#include "bem.h"
 #include "plan.h"
 
 namespace kfmm {
@@ -129,6 +131,70 @@ extern "C" int fmm_plan_destroy(kfmm_plan_t plan) {
     delete plan->impl;
     plan->impl = nullptr;
     delete plan;
+  });
+}
+
+static void check_problem(const bem_problem* p) {
+  KFMM_REQUIRE(p != nullptr, "problem is NULL");
+  KFMM_REQUIRE(p->n_tri > 0 && p->n_tri < ((int64_t)1 << 27), "n_tri must be in [1, 2^27)");
+  KFMM_REQUIRE(p->tri_xyz && p->bc_type && p->bc_val, "problem arrays are NULL");
+  check_moduli(p->K, p->G);
+}
+
+extern "C" int bem_solve(const bem_problem* prob, const bem_opts* opts, const double* x0, double* x, double* u_full,
+                         double* t_full, bem_stats* stats, void* stream) {
+  int rc = KFMM_OK;
+  int code = guarded([&] {
+    check_problem(prob);
+    KFMM_REQUIRE(opts != nullptr && x != nullptr, "opts or x is NULL");
+    KFMM_REQUIRE(opts->tol > 0 && opts->restart >= 1 && opts->restart <= 500 && opts->max_iter >= 0,
+                 "tol > 0, restart in [1, 500], max_iter >= 0 required");
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    BemSystem sys(*prob, opts->fmm, s);
+    double t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bem_stats st = sys.gmres(x0, x, opts->tol, opts->restart, opts->max_iter);
+    st.t_setup_s = t_setup;
+    // traction unknowns back to physical units
+    sys.split(x, u_full, t_full);
+    scale_traction_unknowns(sys, x, sys.scale_t);
+    KFMM_HIP(hipStreamSynchronize(s));
+    if (stats) *stats = st;
+    if (!st.converged) rc = KFMM_E_NOCONV;
+  });
+  if (code != KFMM_OK) return code;
+  if (rc != KFMM_OK) set_last_error("GMRES did not reach the tolerance within max_iter");
+  return rc;
+}
+
+extern "C" int bem_stress(const bem_problem* prob, const double* u_full, const double* t_full, const double* trg,
+                          int64_t M, double* out, const fmm_opts* fmm, void* stream) {
+  return guarded([&] {
+    check_problem(prob);
+    KFMM_REQUIRE(u_full && t_full && fmm, "NULL argument");
+    KFMM_REQUIRE(M >= 0 && (M == 0 || (trg && out)), "bad targets");
+    if (M == 0) return;
+    stress_from_boundary(*prob, u_full, t_full, trg, M, out, *fmm, (hipStream_t)stream);
+  });
+}
+
+extern "C" int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const double* x, double* y,
+                          void* stream) {
+  return guarded([&] {
+    check_problem(prob);
+    KFMM_REQUIRE(fmm && y && (which == 1 || (which == 0 && x)), "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    BemSystem sys(*prob, *fmm, s);
+    sys.apply(which, x, y);
+    KFMM_HIP(hipStreamSynchronize(s));
+  });
+}
+
+extern "C" int bem_quadrature(int64_t n_tri, const double* tri_xyz, double* qp, double* qn, double* qw,
+                              double* colloc, void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(n_tri >= 0 && (n_tri == 0 || (tri_xyz && qp && qn && qw && colloc)), "bad arguments");
+    if (n_tri) bem_expand(n_tri, tri_xyz, qp, qn, qw, colloc, (hipStream_t)stream);
   });
 }
 

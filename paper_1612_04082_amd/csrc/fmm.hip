@@ -602,7 +602,6 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   if (!f64) {
     P->phi_up_lo = zalloc(nbc * 4);
     P->phi_dn_lo = zalloc(nbc * 4);
-    P->qhat_lo = zalloc(nbc * 4);
     if (o.precision == KFMM_FP32_M2L_BF16) P->phi_up_bf = zalloc(nbc * 2);
   }
   KFMM_HIP(hipStreamSynchronize(s));
@@ -661,32 +660,31 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     KFMM_HIP(hipGetLastError());
     // M2L into qhat
     mark(KFMM_PH_M2L_PREP);
-    void* qhat;
+    // qhat is FP64 in every precision: the atomic scatter of the M2L then perturbs it only at FP64
+    // rounding, so repeated products of one operator agree to ~1e-16 (GMRES sees a fixed operator).
+    double* qhat = P.q_up;  // reuse: S2M potentials are consumed
+    KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 8, s));
     if (P.prec == KFMM_FP64) {
-      qhat = P.q_up;  // reuse: S2M potentials are consumed
-      KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 8, s));
       mark(KFMM_PH_M2L);
-      gemm_f64(P.job_m2l, D.m2l64, NC, P.phi_up, (double*)qhat, kAtomicAdd, s);
+      gemm_f64(P.job_m2l, D.m2l64, NC, P.phi_up, qhat, kAtomicAdd, s);
     } else {
-      qhat = P.qhat_lo;
-      KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 4, s));
       hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                          (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
       if (P.prec == KFMM_FP32) {
         mark(KFMM_PH_M2L);
-        gemm_f32(P.job_m2l, D.m2l32, NC, (const float*)P.phi_up_lo, (float*)qhat, kAtomicAdd, s);
+        gemm_f32(P.job_m2l, D.m2l32, NC, (const float*)P.phi_up_lo, qhat, kAtomicAdd, s);
       } else {
         hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                            (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
         mark(KFMM_PH_M2L);
-        gemm_bf16(P.job_m2l, D.m2l16, NC, (const __hip_bfloat16*)P.phi_up_bf, (float*)qhat, kAtomicAdd, s);
+        gemm_bf16(P.job_m2l, D.m2l16, NC, (const __hip_bfloat16*)P.phi_up_bf, qhat, kAtomicAdd, s);
       }
     }
     KFMM_HIP(hipGetLastError());
     mark(KFMM_PH_S2L);
     // X list
     if (P.n_x_boxes) {
-      using TQ = typename std::conditional<sizeof(T) == 8, double, float>::type;
+      using TQ = double;
       auto s2l = [&](auto sl, auto dl) {
         constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
         hipLaunchKernelGGL((k_check_eval<T, TQ, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, s, P.x_boxes, P.tv,
@@ -702,13 +700,7 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     }
     // downward pass in FP64
     mark(KFMM_PH_DOWN);
-    const double* q64 = (const double*)qhat;
-    if (P.prec != KFMM_FP64) {
-      hipLaunchKernelGGL((k_convert<float, double>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
-                         (int64_t)nbc, (const float*)qhat, P.tmp);
-      q64 = P.tmp;
-    }
-    gemm_f64(P.job_dc2de, D.dc2de, NC, q64, P.phi_dn, kStore, s);
+    gemm_f64(P.job_dc2de, D.dc2de, NC, qhat, P.phi_dn, kStore, s);
     for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, NC, P.phi_dn, P.phi_dn, kAdd, s);
     if (P.prec != KFMM_FP64)
       hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,

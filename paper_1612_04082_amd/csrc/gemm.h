@@ -43,7 +43,10 @@ struct GemmCols {
 
 void gemm_f64(const GemmJob& job, const double* A, int NC, const double* X, double* Y, int mode, hipStream_t s);
 void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, float* Y, int mode, hipStream_t s);
+void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, double* Y, int mode, hipStream_t s);
 void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, float* Y, int mode,
+               hipStream_t s);
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, double* Y, int mode,
                hipStream_t s);
 
 // Runs one gather/scatter GEMM launch from host column descriptors (test hook).

@@ -25,12 +25,13 @@ __device__ __forceinline__ void store_out(T* p, T v, int mode) {
     unsafeAtomicAdd(p, v);
 }
 
-// FP64 / FP32 variant: BK = 16 per LDS stage, 4 MFMA k-steps of 4.
-template <typename T>
+// FP64 / FP32 variant: BK = 16 per LDS stage, 4 MFMA k-steps of 4.  Outputs of type TY (FP32 products
+// may be accumulated into FP64 so that atomic scatter order does not change the result beyond FP64 rounding).
+template <typename T, typename TY>
 __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC, const int4* __restrict__ tiles,
                                                 const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                 const double* __restrict__ scale, const T* __restrict__ X,
-                                                T* __restrict__ Y, int mode) {
+                                                TY* __restrict__ Y, int mode) {
   constexpr int BK = 16, BM = kGemmBM, BN = kGemmBN, TM = kGemmTM;
   __shared__ T As[BK][BM + 1];
   __shared__ T Bs[BK][BN + 1];
@@ -96,22 +97,23 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC,
   const int c = wave * 16 + (lane & 15);
   if (c >= tile.z) return;
   const int col = tile.y + c;
-  T* ycol = Y + (size_t)out_idx[col] * NC + r0;
-  const T sc = scale ? (T)scale[col] : T(1);
+  TY* ycol = Y + (size_t)out_idx[col] * NC + r0;
+  const TY sc = scale ? (TY)scale[col] : TY(1);
 #pragma unroll
   for (int t = 0; t < TM; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = sizeof(T) == 8 ? t * 16 + (lane >> 4) + 4 * v : t * 16 + 4 * (lane >> 4) + v;
-      store_out(ycol + row, sc * acc[t][v], mode);
+      store_out(ycol + row, sc * (TY)acc[t][v], mode);
     }
 }
 
 // BF16 inputs, FP32 accumulation: BK = 32 per LDS stage, one MFMA k-step.
+template <typename TY>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A, int NC, const int4* __restrict__ tiles,
                                                    const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                    const double* __restrict__ scale, const __bf16* __restrict__ X,
-                                                   float* __restrict__ Y, int mode) {
+                                                   TY* __restrict__ Y, int mode) {
   constexpr int BK = 32, BM = kGemmBM, BN = kGemmBN, TM = kGemmTM, PAD = 8;
   __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][BK + PAD];
@@ -169,12 +171,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
   const int c = wave * 16 + (lane & 15);
   if (c >= tile.z) return;
   const int col = tile.y + c;
-  float* ycol = Y + (size_t)out_idx[col] * NC + r0;
-  const float sc = scale ? (float)scale[col] : 1.0f;
+  TY* ycol = Y + (size_t)out_idx[col] * NC + r0;
+  const TY sc = scale ? (TY)scale[col] : TY(1);
 #pragma unroll
   for (int t = 0; t < TM; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) store_out(ycol + t * 16 + 4 * (lane >> 4) + v, sc * acc[t][v], mode);
+    for (int v = 0; v < 4; ++v) store_out(ycol + t * 16 + 4 * (lane >> 4) + v, sc * (TY)acc[t][v], mode);
 }
 
 static void check_job(const GemmJob& job, int NC) {
@@ -184,26 +186,42 @@ static void check_job(const GemmJob& job, int NC) {
 void gemm_f64(const GemmJob& job, const double* A, int NC, const double* X, double* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
   check_job(job, NC);
-  hipLaunchKernelGGL(k_gemm_f<double>, dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC, job.tiles,
+  hipLaunchKernelGGL((k_gemm_f<double, double>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC, job.tiles,
                      job.in_idx, job.out_idx, job.scale, X, Y, mode);
   KFMM_HIP(hipGetLastError());
 }
 
-void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, float* Y, int mode, hipStream_t s) {
+template <typename TY>
+static void gemm_f32_t(const GemmJob& job, const float* A, int NC, const float* X, TY* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
   check_job(job, NC);
-  hipLaunchKernelGGL(k_gemm_f<float>, dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC, job.tiles, job.in_idx,
-                     job.out_idx, job.scale, X, Y, mode);
+  hipLaunchKernelGGL((k_gemm_f<float, TY>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC, job.tiles,
+                     job.in_idx, job.out_idx, job.scale, X, Y, mode);
   KFMM_HIP(hipGetLastError());
 }
+void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, float* Y, int mode, hipStream_t s) {
+  gemm_f32_t(job, A, NC, X, Y, mode, s);
+}
+void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, double* Y, int mode, hipStream_t s) {
+  gemm_f32_t(job, A, NC, X, Y, mode, s);
+}
 
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, float* Y, int mode,
-               hipStream_t s) {
+template <typename TY>
+static void gemm_bf16_t(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, TY* Y, int mode,
+                        hipStream_t s) {
   if (job.n_tiles == 0) return;
   check_job(job, NC);
-  hipLaunchKernelGGL(k_gemm_bf16, dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, (const __bf16*)A, NC, job.tiles,
-                     job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
+  hipLaunchKernelGGL((k_gemm_bf16<TY>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, (const __bf16*)A, NC,
+                     job.tiles, job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
   KFMM_HIP(hipGetLastError());
+}
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, float* Y, int mode,
+               hipStream_t s) {
+  gemm_bf16_t(job, A, NC, X, Y, mode, s);
+}
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, double* Y, int mode,
+               hipStream_t s) {
+  gemm_bf16_t(job, A, NC, X, Y, mode, s);
 }
 
 }  // namespace kfmm

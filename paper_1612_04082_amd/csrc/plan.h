@@ -47,7 +47,7 @@ struct Plan {
   std::vector<GemmJob> dn_levels;
   // per-box coefficient buffers (n_box x NC)
   double *q_up = nullptr, *phi_up = nullptr, *phi_dn = nullptr, *tmp = nullptr;
-  void *phi_up_lo = nullptr, *phi_dn_lo = nullptr, *qhat_lo = nullptr, *phi_up_bf = nullptr;
+  void *phi_up_lo = nullptr, *phi_dn_lo = nullptr, *phi_up_bf = nullptr;
   // optional phase timing with HIP events (see fmm_profile)
   bool prof = false;
   hipEvent_t ev[KFMM_N_PHASES + 1] = {};

@@ -38,6 +38,22 @@ class FmmInfo(ctypes.Structure):
                 ("n_x_pairs", ctypes.c_int64), ("plan_seconds", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
 
 
+class BemProblem(ctypes.Structure):
+    _fields_ = [("n_tri", ctypes.c_int64), ("tri_xyz", ctypes.c_void_p), ("bc_type", ctypes.c_void_p),
+                ("bc_val", ctypes.c_void_p), ("K", ctypes.c_double), ("G", ctypes.c_double)]
+
+
+class BemOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("fmm", FmmOpts)]
+
+
+class BemStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
+                ("res_estimate", ctypes.c_double), ("b_norm", ctypes.c_double), ("t_setup_s", ctypes.c_double),
+                ("t_solve_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -63,6 +79,15 @@ def load_library():
     L.fmm_profile.restype = ctypes.c_int
     L.fmm_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     L.fmm_phase_times.restype = ctypes.c_int
+    L.bem_solve.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(BemOpts), vp, vp, vp, vp,
+                            ctypes.POINTER(BemStats), vp]
+    L.bem_solve.restype = ctypes.c_int
+    L.bem_stress.argtypes = [ctypes.POINTER(BemProblem), vp, vp, vp, i64, vp, ctypes.POINTER(FmmOpts), vp]
+    L.bem_stress.restype = ctypes.c_int
+    L.bem_matvec.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(FmmOpts), ctypes.c_int, vp, vp, vp]
+    L.bem_matvec.restype = ctypes.c_int
+    L.bem_quadrature.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    L.bem_quadrature.restype = ctypes.c_int
     ip = ctypes.POINTER(ctypes.c_int)
     L.kfmm_selftest_gemm.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, vp, ip, ip, ip,
                                      ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int, vp]
@@ -168,3 +193,76 @@ def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0)
     check(L.kfmm_selftest_gemm(precision, ctypes.c_void_p(A.data_ptr()), NC, ctypes.c_void_p(X.data_ptr()),
                                ctypes.c_void_p(Y.data_ptr()), ia(op), ia(cols_in), ia(cols_out), sc, n, mode,
                                _stream()))
+
+
+def _problem(tri, bc_type, bc_val, K, G):
+    if not (bc_type.is_cuda and bc_type.dtype == torch.int8 and bc_type.is_contiguous()):
+        raise TypeError("bc_type must be a contiguous int8 CUDA tensor")
+    T = int(tri.shape[0])
+    return BemProblem(T, _dptr(tri, "tri").value, ctypes.c_void_p(bc_type.data_ptr()).value,
+                      _dptr(bc_val, "bc_val", 3).value, K, G)
+
+
+def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_iter=2000, x0=None, p=8,
+              leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False):
+    """bem_solve on torch tensors: tri (T,3,3) f64, bc_type (T,3) int8, bc_val (T,3) f64, all on the GPU.
+
+    Returns (x, u, t, stats) with x the unknowns (physical units) and u, t the full boundary data."""
+    L = load_library()
+    if K is None:
+        K = moduli(G, 0.3)
+    prob = _problem(tri, bc_type, bc_val, K, G)
+    opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0))
+    T = int(tri.shape[0])
+    x = torch.empty((T, 3), dtype=torch.float64, device=tri.device)
+    u = torch.empty_like(x) if want_full else None
+    t = torch.empty_like(x) if want_full else None
+    st = BemStats()
+    rc = L.bem_solve(ctypes.byref(prob), ctypes.byref(opts), _dptr(x0, "x0", 3), _dptr(x, "x", 3),
+                     _dptr(u, "u", 3), _dptr(t, "t", 3), ctypes.byref(st), _stream())
+    stats = {k: getattr(st, k) for k, _ in BemStats._fields_}
+    if rc == -4 and allow_noconv:
+        return x, u, t, stats
+    check(rc)
+    return x, u, t, stats
+
+
+def bem_stress(tri, bc_type, bc_val, u, t, trg, K=None, G=1.0, p=8, leaf_max=128, precision=FP32, svd_eps=0.0):
+    """Interior stress (M,6) from boundary u, t (eq. stress_1) at trg (M,3)."""
+    L = load_library()
+    if K is None:
+        K = moduli(G, 0.3)
+    prob = _problem(tri, bc_type, bc_val, K, G)
+    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0)
+    M = int(trg.shape[0])
+    out = torch.empty((M, 6), dtype=torch.float64, device=trg.device)
+    check(L.bem_stress(ctypes.byref(prob), _dptr(u, "u", 3), _dptr(t, "t", 3), _dptr(trg, "trg", 3), M,
+                       _dptr(out, "out", 6), ctypes.byref(fo), _stream()))
+    return out
+
+
+def bem_quadrature(tri):
+    """16 quadrature points per triangle, normals, weights and collocation points (device tensors)."""
+    L = load_library()
+    T = int(tri.shape[0])
+    dev = tri.device
+    qp = torch.empty((16 * T, 3), dtype=torch.float64, device=dev)
+    qn = torch.empty_like(qp)
+    qw = torch.empty((16 * T,), dtype=torch.float64, device=dev)
+    cen = torch.empty((T, 3), dtype=torch.float64, device=dev)
+    check(L.bem_quadrature(T, _dptr(tri, "tri"), _dptr(qp, "qp"), _dptr(qn, "qn"), _dptr(qw, "qw"),
+                           _dptr(cen, "cen"), _stream()))
+    return qp, qn, qw, cen
+
+
+def bem_matvec(tri, bc_type, bc_val, x=None, which=0, K=None, G=1.0, p=8, leaf_max=128, precision=FP32,
+               svd_eps=0.0):
+    """y = A x (which=0, x in solver units) or the right-hand side B y (which=1)."""
+    L = load_library()
+    if K is None:
+        K = moduli(G, 0.3)
+    prob = _problem(tri, bc_type, bc_val, K, G)
+    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0)
+    y = torch.empty((int(tri.shape[0]), 3), dtype=torch.float64, device=tri.device)
+    check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3), _dptr(y, "y", 3), _stream()))
+    return y

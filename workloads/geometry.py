@@ -137,22 +137,25 @@ def box_beam_cloud(seed=2, L=120.0, W=20.0, n_w=11):
 # ----------------------------------------------------------------------------- cantilever with holes
 
 
-def cantilever_voxels(L=32.0, Wd=4.0, h=2.0 / 9.0, n_holes=64, r_lo=0.3, r_hi=0.8, seed=3, max_tries=200000):
+def cantilever_voxels(L=32.0, Wd=4.0, h=2.0 / 9.0, n_holes=64, r_lo=0.3, r_hi=0.8, seed=3, max_tries=200000,
+                      margin=None):
     """Beam [0,L]x[0,Wd]^2 voxelised at spacing h, with random non-overlapping spherical holes.
 
-    Hole centres lie in x in [2+r+2h, L-2-r-2h], y,z in [r+2h, Wd-r-2h]; a candidate is rejected if
-    within r_i + r_j + 2h of an accepted hole.  Voxels whose centre lies inside a hole are empty.
+    With m = margin (default 2h): hole centres lie in x in [2+r+m, L-2-r-m], y,z in [r+m, Wd-r-m]; a
+    candidate is rejected if within r_i + r_j + m of an accepted hole.  Voxels whose centre lies inside a
+    hole are empty.
     """
     rng = np.random.default_rng(seed)
+    m = 2 * h if margin is None else margin
     nx, ny = int(round(L / h)), int(round(Wd / h))
     holes = []
     tries = 0
     while len(holes) < n_holes and tries < max_tries:
         tries += 1
         r = rng.uniform(r_lo, r_hi)
-        c = np.array([rng.uniform(2 + r + 2 * h, L - 2 - r - 2 * h),
-                      rng.uniform(r + 2 * h, Wd - r - 2 * h), rng.uniform(r + 2 * h, Wd - r - 2 * h)])
-        if all(np.linalg.norm(c - c2) >= r + r2 + 2 * h for (c2, r2) in holes):
+        c = np.array([rng.uniform(2 + r + m, L - 2 - r - m),
+                      rng.uniform(r + m, Wd - r - m), rng.uniform(r + m, Wd - r - m)])
+        if all(np.linalg.norm(c - c2) >= r + r2 + m for (c2, r2) in holes):
             holes.append((c, r))
     xs = (np.arange(nx) + 0.5) * h
     ys = (np.arange(ny) + 0.5) * h
