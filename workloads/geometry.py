@@ -250,8 +250,12 @@ def cell_batch(n_cells=64, seed_base=4000, lo=20000, hi=200000, seed=4):
         target = rng.uniform(lo, hi)
         # a full cube at n voxels has 6 n^2 faces * 64 points
         n_vox = int(np.clip(round(np.sqrt(target / 384.0)), 7, 22))
-        M, h = cell_voxels(g, n_vox, seed_base)
-        surf = surface_from_voxels(M, h)
+        while True:  # inclusions add surface: step the resolution down until the cell is within [lo, hi]
+            M, h = cell_voxels(g, n_vox, seed_base)
+            surf = surface_from_voxels(M, h)
+            if surf["tri"].shape[0] * 16 <= hi or n_vox <= 7:
+                break
+            n_vox -= 1
         pts, nrm, w = quadrature_cloud(surf["tri"])
         r2 = np.random.default_rng(seed * 100000 + g)
         out.append(dict(src=pts, nrm=nrm, w=w, a=r2.normal(size=pts.shape), b=r2.normal(size=pts.shape)))
