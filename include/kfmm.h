@@ -155,10 +155,14 @@ typedef struct {
   int restart;     /* GMRES restart length m (1..500) */
   int max_iter;    /* maximum number of Arnoldi steps (matrix-vector products); 0 evaluates x0 only */
   fmm_opts fmm;    /* options of the fast summation behind every product (K, G are taken from the problem) */
+  const double* x0_alt; /* optional second start (device, T x 3, physical units): the start with the smaller
+                           true residual is used (one extra product); NULL for none */
 } bem_opts;
 
 typedef struct {   /* host */
   int iters, restarts, converged;
+  int used_alt;        /* 1 if x0_alt was the better start */
+  double rel_res_alt;  /* true relative residual of x0_alt (if given) */
   int64_t n_matvec;
   double rel_res;      /* true relative residual of the returned x */
   double rel_res0;     /* true relative residual of x0 */
@@ -197,6 +201,50 @@ int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const do
  * weights (16T) and the collocation points (T x 3).  Synchronises the stream. */
 int bem_quadrature(int64_t n_tri, const double* tri_xyz, double* qp, double* qn, double* qw, double* colloc,
                    void* stream);
+
+/* ---------------------------------------------------------------------------------------------------
+ * Learned GMRES warm start.  The paper suggests reusing the previous iteration's boundary solution when the
+ * boundary changes little (Sec. 5, fast update of the boundary solution); here a point-wise MLP
+ * (16 -> 128 -> 128 -> 3, SiLU) learns, online, the correction from the previous solution mapped onto the
+ * new surface to the new solution.  Inference uses BF16 matrix cores; training FP32 with Adam.  The solve's
+ * accuracy never depends on the network: GMRES runs to the same residual from whatever start it is given.
+ */
+#define KFMM_WS_DIN 16
+typedef struct ws_net* ws_net_t;
+
+/* Create a network (d_in must be KFMM_WS_DIN, width 128); weights drawn from a counter-based generator. */
+int ws_create(ws_net_t* out, int d_in, int width, uint64_t seed);
+int ws_destroy(ws_net_t net);
+
+/*
+ * ws_features -- per element of `next`: the nearest element of `prev` (by centroid, exact matches at
+ * distance 0), the previous solution mapped into next's unknown layout (x_mapped, T' x 3, device: the
+ * previous t where next prescribes u, the previous u where it prescribes t) and KFMM_WS_DIN features
+ * (feat, T' x 16, device FP32).  u_prev, t_prev: previous full boundary solution (T x 3, device).
+ * *scale (host) receives the RMS of x_mapped used to normalise features and targets.  Synchronises.
+ */
+int ws_features(const bem_problem* prev, const double* u_prev, const double* t_prev, const bem_problem* next,
+                float* feat, double* x_mapped, double* scale, void* stream);
+
+/* ws_predict -- x0 = x_mapped + scale * net(feat)   (device, n x 3). */
+int ws_predict(ws_net_t net, const float* feat, int64_t n, const double* x_mapped, double scale, double* x0,
+               void* stream);
+
+/* ws_train -- `epochs` full-batch Adam steps (learning rate lr) on the target (x_target - x_mapped) / scale;
+ * *loss (host) receives the last mean squared error.  Synchronises. */
+int ws_train(ws_net_t net, const float* feat, const double* x_mapped, const double* x_target, int64_t n,
+             double scale, int epochs, float lr, float* loss, void* stream);
+
+/* Parameters as one host FP32 vector: W1 (16x128, [in][out]), b1, W2 (128x128), b2, W3 (128x3), b3. */
+int ws_num_params(ws_net_t net, int64_t* n);
+int ws_get_params(ws_net_t net, float* host);
+int ws_set_params(ws_net_t net, const float* host);
+/* Test hook: loss and gradient (host, ws_num_params entries) for features X and residual targets R
+ * (device FP32, n x 16 and n x 3). */
+int ws_loss_grad(ws_net_t net, const float* X, const float* R, int64_t n, float* loss, float* grad, void* stream);
+/* Save / load parameters and Adam state (host path). */
+int ws_save(ws_net_t net, const char* path);
+int ws_load(ws_net_t net, const char* path);
 
 /*
  * Test hook: one launch of the batched gather/scatter GEMM used by every translation,

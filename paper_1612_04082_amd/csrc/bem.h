@@ -30,7 +30,7 @@ struct BemSystem {
   void apply(int mode, const double* x, double* out);  // 0: A x, 1: B y
   double dot(const double* x, const double* y);
   void split(const double* x, double* u, double* t);
-  bem_stats gmres(const double* x0, double* x, double tol, int m, int max_iter);
+  bem_stats gmres(const double* x0, const double* x0_alt, double* x, double tol, int m, int max_iter);
   double* scratch_partial();
 };
 

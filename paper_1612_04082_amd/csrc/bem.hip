@@ -393,7 +393,7 @@ void BemSystem::split(const double* x, double* u, double* t) {
 }
 
 // Restarted GMRES(m) with CGS2 Arnoldi (see file header).  Returns the stats; x holds the best iterate.
-bem_stats BemSystem::gmres(const double* x0, double* x, double tol, int m, int max_iter) {
+bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, double tol, int m, int max_iter) {
   hipStream_t s = stream;
   bem_stats st{};
   auto t0 = std::chrono::steady_clock::now();
@@ -432,6 +432,21 @@ bem_stats BemSystem::gmres(const double* x0, double* x, double tol, int m, int m
     st.rel_res = 0;
     return st;
   }
+  // guard: a second start is kept if its true residual is smaller (one extra product)
+  double* xa = nullptr;
+  double* ra = nullptr;
+  double rel_alt = INFINITY;
+  if (x0_alt) {
+    xa = arena.get<double>(n);
+    ra = arena.get<double>(n);
+    KFMM_HIP(hipMemcpyAsync(xa, x0_alt, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    scale_traction_unknowns(*this, xa, 1.0 / scale_t);
+    apply(0, xa, ra);
+    hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, b, -1.0, ra);
+    rel_alt = std::sqrt(dot(ra, ra)) / bnorm;
+    if (!std::isfinite(rel_alt)) rel_alt = INFINITY;
+    st.rel_res_alt = rel_alt;
+  }
   int it = 0, stalled = 0;
   double rel = 0, prev_rel = INFINITY;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
@@ -441,7 +456,16 @@ bem_stats BemSystem::gmres(const double* x0, double* x, double tol, int m, int m
     hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, b, -1.0, r);  // r = b - A x
     double beta = std::sqrt(dot(r, r));
     rel = beta / bnorm;
-    if (st.iters == 0 && it == 0) st.rel_res0 = rel;
+    if (it == 0 && st.restarts == 0) {
+      st.rel_res0 = rel;
+      if (xa && (rel_alt < rel || !std::isfinite(rel))) {
+        KFMM_HIP(hipMemcpyAsync(x, xa, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        KFMM_HIP(hipMemcpyAsync(r, ra, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        rel = rel_alt;
+        beta = rel * bnorm;
+        st.used_alt = 1;
+      }
+    }
     if (rel <= tol || it >= max_iter || !std::isfinite(rel)) break;
     // stagnation (operator noise floor): five restarts in a row without a 1% decrease of the true residual
     stalled = (it > 0 && rel > 0.99 * prev_rel) ? stalled + 1 : 0;

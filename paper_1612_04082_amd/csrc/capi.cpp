@@ -1,12 +1,15 @@
 // C-ABI entry points (include/kfmm.h): argument validation, status codes and thread-local errors.
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <vector>
 #include <cstring>
 #include <string>
 
 #include "../../include/kfmm.h"
 #include "common.h"
 #include "bem.h"
+#include "learn.h"
 #include "plan.h"
 
 namespace kfmm {
@@ -153,7 +156,7 @@ extern "C" int bem_solve(const bem_problem* prob, const bem_opts* opts, const do
     auto t0 = std::chrono::steady_clock::now();
     BemSystem sys(*prob, opts->fmm, s);
     double t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    bem_stats st = sys.gmres(x0, x, opts->tol, opts->restart, opts->max_iter);
+    bem_stats st = sys.gmres(x0, opts->x0_alt, x, opts->tol, opts->restart, opts->max_iter);
     st.t_setup_s = t_setup;
     // traction unknowns back to physical units
     sys.split(x, u_full, t_full);
@@ -195,6 +198,136 @@ extern "C" int bem_quadrature(int64_t n_tri, const double* tri_xyz, double* qp, 
   return guarded([&] {
     KFMM_REQUIRE(n_tri >= 0 && (n_tri == 0 || (tri_xyz && qp && qn && qw && colloc)), "bad arguments");
     if (n_tri) bem_expand(n_tri, tri_xyz, qp, qn, qw, colloc, (hipStream_t)stream);
+  });
+}
+
+struct ws_net {
+  kfmm::WsNet* impl;
+};
+
+static WsNet& net_of(ws_net_t n) {
+  KFMM_REQUIRE(n != nullptr && n->impl != nullptr, "network is NULL");
+  return *n->impl;
+}
+
+extern "C" int ws_create(ws_net_t* out, int d_in, int width, uint64_t seed) {
+  return guarded([&] {
+    KFMM_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    *out = new ws_net{new WsNet(d_in, width, seed)};
+  });
+}
+
+extern "C" int ws_destroy(ws_net_t net) {
+  return guarded([&] {
+    if (!net) return;
+    delete net->impl;
+    delete net;
+  });
+}
+
+extern "C" int ws_features(const bem_problem* prev, const double* u_prev, const double* t_prev,
+                           const bem_problem* next, float* feat, double* x_mapped, double* scale, void* stream) {
+  return guarded([&] {
+    check_problem(prev);
+    check_problem(next);
+    KFMM_REQUIRE(u_prev && t_prev && feat && x_mapped && scale, "NULL argument");
+    *scale = ws_make_features(*prev, u_prev, t_prev, *next, feat, x_mapped, (hipStream_t)stream);
+  });
+}
+
+extern "C" int ws_predict(ws_net_t net, const float* feat, int64_t n, const double* x_mapped, double scale,
+                          double* x0, void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(n >= 0 && (n == 0 || (feat && x_mapped && x0)), "bad arguments");
+    KFMM_REQUIRE(std::isfinite(scale) && scale > 0, "scale must be positive");
+    net_of(net).predict(feat, n, x_mapped, scale, x0, (hipStream_t)stream);
+  });
+}
+
+extern "C" int ws_train(ws_net_t net, const float* feat, const double* x_mapped, const double* x_target, int64_t n,
+                        double scale, int epochs, float lr, float* loss, void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(n > 0 && feat && x_mapped && x_target && epochs >= 0 && lr > 0, "bad arguments");
+    KFMM_REQUIRE(std::isfinite(scale) && scale > 0, "scale must be positive");
+    float L = net_of(net).train(feat, x_mapped, x_target, n, scale, epochs, lr, (hipStream_t)stream);
+    if (loss) *loss = L;
+  });
+}
+
+extern "C" int ws_num_params(ws_net_t net, int64_t* n) {
+  return guarded([&] {
+    KFMM_REQUIRE(n != nullptr, "NULL argument");
+    *n = net_of(net).np;
+  });
+}
+
+extern "C" int ws_get_params(ws_net_t net, float* host) {
+  return guarded([&] {
+    KFMM_REQUIRE(host != nullptr, "NULL argument");
+    WsNet& w = net_of(net);
+    KFMM_HIP(hipMemcpy(host, w.params, sizeof(float) * w.np, hipMemcpyDeviceToHost));
+  });
+}
+
+extern "C" int ws_set_params(ws_net_t net, const float* host) {
+  return guarded([&] {
+    KFMM_REQUIRE(host != nullptr, "NULL argument");
+    WsNet& w = net_of(net);
+    KFMM_HIP(hipMemcpy(w.params, host, sizeof(float) * w.np, hipMemcpyHostToDevice));
+    w.bf_dirty = true;
+  });
+}
+
+extern "C" int ws_loss_grad(ws_net_t net, const float* X, const float* R, int64_t n, float* loss, float* grad,
+                            void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(n > 0 && X && R, "bad arguments");
+    WsNet& w = net_of(net);
+    hipStream_t s = (hipStream_t)stream;
+    float L = w.loss_grad(X, R, n, s);
+    if (loss) *loss = L;
+    if (grad) {
+      KFMM_HIP(hipMemcpyAsync(grad, w.grads, sizeof(float) * w.np, hipMemcpyDeviceToHost, s));
+      KFMM_HIP(hipStreamSynchronize(s));
+    }
+  });
+}
+
+extern "C" int ws_save(ws_net_t net, const char* path) {
+  return guarded([&] {
+    KFMM_REQUIRE(path != nullptr, "path is NULL");
+    WsNet& w = net_of(net);
+    std::vector<float> buf(3 * (size_t)w.np);
+    KFMM_HIP(hipMemcpy(buf.data(), w.params, sizeof(float) * w.np, hipMemcpyDeviceToHost));
+    KFMM_HIP(hipMemcpy(buf.data() + w.np, w.m1, sizeof(float) * w.np, hipMemcpyDeviceToHost));
+    KFMM_HIP(hipMemcpy(buf.data() + 2 * w.np, w.m2, sizeof(float) * w.np, hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    KFMM_REQUIRE(f != nullptr, std::string("cannot open ") + path);
+    int64_t hdr[4] = {0x6b666d6d77730001LL, w.din, w.width, w.step};
+    bool ok = std::fwrite(hdr, sizeof(hdr), 1, f) == 1 && std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    std::fclose(f);
+    KFMM_REQUIRE(ok, "write failed");
+  });
+}
+
+extern "C" int ws_load(ws_net_t net, const char* path) {
+  return guarded([&] {
+    KFMM_REQUIRE(path != nullptr, "path is NULL");
+    WsNet& w = net_of(net);
+    FILE* f = std::fopen(path, "rb");
+    KFMM_REQUIRE(f != nullptr, std::string("cannot open ") + path);
+    int64_t hdr[4];
+    std::vector<float> buf(3 * (size_t)w.np);
+    bool ok = std::fread(hdr, sizeof(hdr), 1, f) == 1 && hdr[0] == 0x6b666d6d77730001LL && hdr[1] == w.din &&
+              hdr[2] == w.width && std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    std::fclose(f);
+    KFMM_REQUIRE(ok, "not a network file of this shape");
+    KFMM_HIP(hipMemcpy(w.params, buf.data(), sizeof(float) * w.np, hipMemcpyHostToDevice));
+    KFMM_HIP(hipMemcpy(w.m1, buf.data() + w.np, sizeof(float) * w.np, hipMemcpyHostToDevice));
+    KFMM_HIP(hipMemcpy(w.m2, buf.data() + 2 * w.np, sizeof(float) * w.np, hipMemcpyHostToDevice));
+    w.step = hdr[3];
+    w.bf_dirty = true;
   });
 }
 

@@ -54,6 +54,10 @@ void build_tree(Tree& t, Arena& arena, const double* src, int64_t n_src, const d
                 const std::vector<int64_t>& batch_src, const std::vector<int64_t>& batch_trg, int leaf_max,
                 int max_depth, hipStream_t s);
 
+// Sorts (key, idx) pairs on the device: n valid entries in arrays of n_pad (a power of two >= 2048)
+// elements; the padding is filled with the largest key.
+void sort_keys(uint64_t* key, int* idx, int64_t n, int64_t n_pad, hipStream_t s);
+
 // Builds the U, V, W, X lists of the tree.
 void build_lists(Tree& t, Arena& arena, hipStream_t s);
 

@@ -206,6 +206,20 @@ static void bitonic_sort(uint64_t* key, int* idx, int64_t n_pad, hipStream_t s) 
   KFMM_HIP(hipGetLastError());
 }
 
+__global__ void k_pad_keys(uint64_t* key, int* idx, int64_t n, int64_t n_pad) {
+  int64_t i = n + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_pad) {
+    key[i] = ~0ull;
+    idx[i] = 0x7fffffff;
+  }
+}
+
+void sort_keys(uint64_t* key, int* idx, int64_t n, int64_t n_pad, hipStream_t s) {
+  if (n_pad > n)
+    hipLaunchKernelGGL(k_pad_keys, dim3((unsigned)((n_pad - n + 255) / 256)), dim3(256), 0, s, key, idx, n, n_pad);
+  bitonic_sort(key, idx, n_pad, s);
+}
+
 // ------------------------------------------------------------------------------------ tree levels
 
 struct LevelBoxes {  // boxes of one level, device

@@ -44,12 +44,13 @@ class BemProblem(ctypes.Structure):
 
 
 class BemOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("fmm", FmmOpts)]
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("fmm", FmmOpts),
+                ("x0_alt", ctypes.c_void_p)]
 
 
 class BemStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
-                ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
+                ("used_alt", ctypes.c_int), ("rel_res_alt", ctypes.c_double), ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
                 ("res_estimate", ctypes.c_double), ("b_norm", ctypes.c_double), ("t_setup_s", ctypes.c_double),
                 ("t_solve_s", ctypes.c_double)]
 
@@ -88,6 +89,23 @@ def load_library():
     L.bem_matvec.restype = ctypes.c_int
     L.bem_quadrature.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     L.bem_quadrature.restype = ctypes.c_int
+    fp = ctypes.c_void_p
+    L.ws_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
+    L.ws_destroy.argtypes = [vp]
+    L.ws_features.argtypes = [ctypes.POINTER(BemProblem), vp, vp, ctypes.POINTER(BemProblem), fp, vp,
+                              ctypes.POINTER(ctypes.c_double), vp]
+    L.ws_predict.argtypes = [vp, fp, i64, vp, ctypes.c_double, vp, vp]
+    L.ws_train.argtypes = [vp, fp, vp, vp, i64, ctypes.c_double, ctypes.c_int, ctypes.c_float,
+                           ctypes.POINTER(ctypes.c_float), vp]
+    L.ws_num_params.argtypes = [vp, ctypes.POINTER(i64)]
+    L.ws_get_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.ws_set_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    L.ws_loss_grad.argtypes = [vp, fp, fp, i64, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), vp]
+    L.ws_save.argtypes = [vp, ctypes.c_char_p]
+    L.ws_load.argtypes = [vp, ctypes.c_char_p]
+    for f in ("ws_create", "ws_destroy", "ws_features", "ws_predict", "ws_train", "ws_num_params", "ws_get_params",
+              "ws_set_params", "ws_loss_grad", "ws_save", "ws_load"):
+        getattr(L, f).restype = ctypes.c_int
     ip = ctypes.POINTER(ctypes.c_int)
     L.kfmm_selftest_gemm.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, vp, ip, ip, ip,
                                      ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int, vp]
@@ -204,7 +222,7 @@ def _problem(tri, bc_type, bc_val, K, G):
 
 
 def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_iter=2000, x0=None, p=8,
-              leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False):
+              leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False, x0_alt=None):
     """bem_solve on torch tensors: tri (T,3,3) f64, bc_type (T,3) int8, bc_val (T,3) f64, all on the GPU.
 
     Returns (x, u, t, stats) with x the unknowns (physical units) and u, t the full boundary data."""
@@ -212,7 +230,9 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
     if K is None:
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G)
-    opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0))
+    alt = _dptr(x0_alt, "x0_alt", 3)
+    opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0),
+                   alt.value if alt is not None else None)
     T = int(tri.shape[0])
     x = torch.empty((T, 3), dtype=torch.float64, device=tri.device)
     u = torch.empty_like(x) if want_full else None
@@ -266,3 +286,94 @@ def bem_matvec(tri, bc_type, bc_val, x=None, which=0, K=None, G=1.0, p=8, leaf_m
     y = torch.empty((int(tri.shape[0]), 3), dtype=torch.float64, device=tri.device)
     check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3), _dptr(y, "y", 3), _stream()))
     return y
+
+
+def _fptr(t, name, last=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if last is not None and t.shape[-1] != last:
+        raise ValueError(f"{name} must have last dimension {last}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+WS_DIN = 16
+
+
+class WarmStartNet:
+    """ws_* entry points: features, BF16 inference and FP32 Adam training of the warm-start MLP."""
+
+    def __init__(self, seed=0, width=128):
+        self._h = ctypes.c_void_p()
+        check(load_library().ws_create(ctypes.byref(self._h), WS_DIN, width, seed))
+
+    def num_params(self):
+        n = ctypes.c_int64()
+        check(load_library().ws_num_params(self._h, ctypes.byref(n)))
+        return n.value
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.num_params(), dtype=np.float32)
+        check(load_library().ws_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_params(self, p):
+        import numpy as np
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.num_params()
+        check(load_library().ws_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def loss_grad(self, X, R):
+        import numpy as np
+        g = np.empty(self.num_params(), dtype=np.float32)
+        loss = ctypes.c_float()
+        check(load_library().ws_loss_grad(self._h, _fptr(X, "X", WS_DIN), _fptr(R, "R", 3), int(X.shape[0]),
+                                          ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          _stream()))
+        return loss.value, g
+
+    def predict(self, feat, x_mapped, scale):
+        x0 = torch.empty_like(x_mapped)
+        check(load_library().ws_predict(self._h, _fptr(feat, "feat", WS_DIN), int(feat.shape[0]),
+                                        _dptr(x_mapped, "x_mapped", 3), float(scale), _dptr(x0, "x0", 3), _stream()))
+        return x0
+
+    def train(self, feat, x_mapped, x_target, scale, epochs=50, lr=1e-3):
+        loss = ctypes.c_float()
+        check(load_library().ws_train(self._h, _fptr(feat, "feat", WS_DIN), _dptr(x_mapped, "x_mapped", 3),
+                                      _dptr(x_target, "x_target", 3), int(feat.shape[0]), float(scale), int(epochs),
+                                      float(lr), ctypes.byref(loss), _stream()))
+        return loss.value
+
+    def save(self, path):
+        check(load_library().ws_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        check(load_library().ws_load(self._h, str(path).encode()))
+
+    def close(self):
+        if self._h:
+            check(load_library().ws_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ws_features(prev, u_prev, t_prev, nxt):
+    """prev / nxt: dicts of device tensors tri, bc_type, bc_val; returns (feat, x_mapped, scale)."""
+    L = load_library()
+    K = moduli(1.0, 0.3)
+    pp = _problem(prev["tri"], prev["bc_type"], prev["bc_val"], K, 1.0)
+    pn = _problem(nxt["tri"], nxt["bc_type"], nxt["bc_val"], K, 1.0)
+    T = int(nxt["tri"].shape[0])
+    dev = nxt["tri"].device
+    feat = torch.empty((T, WS_DIN), dtype=torch.float32, device=dev)
+    xm = torch.empty((T, 3), dtype=torch.float64, device=dev)
+    scale = ctypes.c_double()
+    check(L.ws_features(ctypes.byref(pp), _dptr(u_prev, "u_prev", 3), _dptr(t_prev, "t_prev", 3), ctypes.byref(pn),
+                        _fptr(feat, "feat", WS_DIN), _dptr(xm, "x_mapped", 3), ctypes.byref(scale), _stream()))
+    return feat, xm, scale.value
