@@ -156,12 +156,14 @@ typedef struct {
   int max_iter;    /* maximum number of Arnoldi steps (matrix-vector products); 0 evaluates x0 only */
   fmm_opts fmm;    /* options of the fast summation behind every product (K, G are taken from the problem) */
   const double* x0_alt; /* optional second start (device, T x 3, physical units): the start with the smaller
-                           true residual is used (one extra product); NULL for none */
+                           true residual is used (one extra product); NULL for none.  A given start whose
+                           residual exceeds that of zero is replaced by zero. */
 } bem_opts;
 
 typedef struct {   /* host */
   int iters, restarts, converged;
   int used_alt;        /* 1 if x0_alt was the better start */
+  int used_zero;       /* 1 if both given starts were worse than zero and zero was used */
   double rel_res_alt;  /* true relative residual of x0_alt (if given) */
   int64_t n_matvec;
   double rel_res;      /* true relative residual of the returned x */
@@ -201,6 +203,13 @@ int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const do
  * weights (16T) and the collocation points (T x 3).  Synchronises the stream. */
 int bem_quadrature(int64_t n_tri, const double* tri_xyz, double* qp, double* qn, double* qw, double* colloc,
                    void* stream);
+
+/*
+ * kfmm_topological_derivative -- pointwise topological derivative of the compliance (Sec. 2, eq. deriv):
+ *   D = 3 (1 - nu) / (4 E (7 - 5 nu)) [10 (1 + nu) sig:sig - (1 + 5 nu) (tr sig)^2]
+ * sig6: M x 6 stresses (xx, yy, zz, yz, xz, xy, device FP64), td: M (device FP64).  E, nu from (K, G).
+ */
+int kfmm_topological_derivative(const double* sig6, int64_t M, double K, double G, double* td, void* stream);
 
 /* ---------------------------------------------------------------------------------------------------
  * Learned GMRES warm start.  The paper suggests reusing the previous iteration's boundary solution when the

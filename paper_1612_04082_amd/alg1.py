@@ -1,0 +1,175 @@
+"""Algorithm 1 (Sec. 2.3): hard-kill topology optimisation on voxels, driven through the library's C ABI.
+
+Per iteration: boundary of the material voxels -> 4 triangles per face (geometry.cantilever_problem),
+BEM solve (bem_solve), stress at the filled voxel centres (bem_stress, eq. stress_1), topological
+derivative (kfmm_topological_derivative, eq. deriv), removal of the voxels below
+D_min + C (D_max - D_min), post-processing, volume ratio alpha and compliance Psi.
+
+Readings where the paper is silent: the first and last voxel layers along the beam (clamped and loaded
+ends) are protected from removal; post-processing keeps the voxels face-connected to both protected
+layers (a floating piece would make the elastic problem singular).
+
+The warm-start study (`warm_start_study`) re-solves the systems of a fixed sequence with three starting
+points -- zero, the previous solution mapped onto the new surface, and the learned network (with the
+residual guard) -- and reports GMRES iterations and times.
+"""
+import time
+
+import numpy as np
+import torch
+
+from workloads import geometry as geo
+
+
+def _dev(x, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+
+
+def postprocess(M):
+    """Keep the voxels face-connected to both end layers (x = 0 and x = nx - 1)."""
+    from scipy import ndimage
+    lab, n = ndimage.label(M)
+    if n == 0:
+        return M
+    lo = set(np.unique(lab[0][lab[0] > 0]))
+    hi = set(np.unique(lab[-1][lab[-1] > 0]))
+    keep = sorted(lo & hi)
+    return np.isin(lab, keep) & M
+
+
+def voxel_centres(M, h):
+    idx = np.argwhere(M)
+    return (idx + 0.5) * h, idx
+
+
+class Problem:
+    """Surface problem of a voxel set on the device."""
+
+    def __init__(self, M, h, load):
+        p = geo.cantilever_problem(M, h, load)
+        self.host = p
+        self.T = p["tri"].shape[0]
+        self.dev = dict(tri=_dev(p["tri"]), bc_type=_dev(p["bc_type"], torch.int8), bc_val=_dev(p["bc_val"]))
+
+    def args(self):
+        return (self.dev["tri"], self.dev["bc_type"], self.dev["bc_val"])
+
+
+class Optimiser:
+    def __init__(self, M0, h=1.0, load=(0.0, 0.0, -1.0), C=0.02, G=1.0, nu=0.3, tol=1e-8, restart=200, p=8,
+                 leaf_max=128, precision=0, max_iter=5000):
+        from paper_1612_04082_amd import kfmm
+        self.kfmm = kfmm
+        self.M0 = np.asarray(M0, bool)
+        self.h, self.load, self.C = h, load, C
+        self.G, self.nu = G, nu
+        self.K = kfmm.moduli(G, nu)
+        self.E = 2 * G * (1 + nu)
+        self.solve_kw = dict(K=self.K, G=G, tol=tol, restart=restart, p=p, leaf_max=leaf_max, precision=precision,
+                             max_iter=max_iter)
+        self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=precision)
+
+    def solve(self, prob, x0=None, x0_alt=None, **over):
+        kw = dict(self.solve_kw)
+        kw.update(over)
+        return self.kfmm.bem_solve(*prob.args(), x0=x0, x0_alt=x0_alt, allow_noconv=True, **kw)
+
+    def evaluate(self, M, prob, u, t):
+        """Stress, topological derivative and energy density at the filled voxel centres."""
+        trg, idx = voxel_centres(M, self.h)
+        sig = self.kfmm.bem_stress(*prob.args(), u, t, _dev(trg), **self.fmm_kw)
+        td = self.kfmm.topological_derivative(sig, K=self.K, G=self.G).cpu().numpy()
+        s = sig.cpu().numpy()
+        ss = (s[:, :3] ** 2).sum(1) + 2 * (s[:, 3:] ** 2).sum(1)
+        tr = s[:, :3].sum(1)
+        energy = 0.5 * ((1 + self.nu) * ss - self.nu * tr * tr) / self.E
+        return idx, td, energy
+
+    def remove(self, M, idx, td):
+        lo, hi = td.min(), td.max()
+        kill = td < lo + self.C * (hi - lo)
+        kill &= (idx[:, 0] > 0) & (idx[:, 0] < M.shape[0] - 1)  # protected end layers
+        M2 = M.copy()
+        M2[tuple(idx[kill].T)] = False
+        return postprocess(M2)
+
+    def run(self, n_iter, alpha_c=0.0, callback=None):
+        M = self.M0.copy()
+        hist = []
+        for k in range(n_iter):
+            prob = Problem(M, self.h, self.load)
+            x, u, t, st = self.solve(prob)
+            idx, td, energy = self.evaluate(M, prob, u, t)
+            alpha = M.sum() / self.M0.sum()
+            psi = energy.sum() * self.h ** 3
+            hist.append(dict(iter=k + 1, alpha=float(alpha), psi=float(psi), T=prob.T, gmres=st["iters"],
+                             rel_res=st["rel_res"]))
+            if callback:
+                callback(k, M, prob, x, u, t, st)
+            if alpha < alpha_c:
+                break
+            M_next = self.remove(M, idx, td)
+            if not M_next.any():  # the rule would disconnect the supports: stop with the last design
+                break
+            M = M_next
+        return M, hist
+
+
+def warm_start_study(M0, n_iter=20, train_from=2, measure_from=11, h=1.0, C=0.02, tol_seq=1e-8, tol=1e-6,
+                     epochs=200, lr=1e-3, seed=0, log=print, **kw):
+    """Drive Algorithm 1 with tight solves; re-solve the measured systems from three starts.
+
+    Returns a list of per-iteration records (iterations and seconds for x0 = 0, previous, network)."""
+    from paper_1612_04082_amd import kfmm
+    opt = Optimiser(M0, h=h, C=C, tol=tol_seq, **kw)
+    net = kfmm.WarmStartNet(seed=seed)
+    rec = []
+    state = {}
+
+    def sync():
+        torch.cuda.synchronize()
+
+    def cb(k, M, prob, x, u, t, st):
+        r = dict(iter=k + 1, T=prob.T, seq_iters=st["iters"])
+        if "prev" in state:
+            pv = state["prev"]
+            sync()
+            t0 = time.time()
+            feat, xm, scale = kfmm.ws_features(pv["prob"].dev, pv["u"], pv["t"], prob.dev)
+            sync()
+            t_feat = time.time() - t0
+            if k + 1 >= measure_from:
+                for mode in ("zero", "prev", "net"):
+                    sync()
+                    t0 = time.time()
+                    if mode == "zero":
+                        _, _, _, s2 = opt.solve(prob, tol=tol)
+                        extra = 0.0
+                    elif mode == "prev":
+                        _, _, _, s2 = opt.solve(prob, x0=xm, tol=tol)
+                        extra = t_feat
+                    else:
+                        t1 = time.time()
+                        x0 = net.predict(feat, xm, scale)
+                        sync()
+                        extra = t_feat + (time.time() - t1)
+                        _, _, _, s2 = opt.solve(prob, x0=x0, x0_alt=xm, tol=tol)
+                    sync()
+                    r[mode] = dict(iters=s2["iters"], seconds=time.time() - t0 + extra, rel_res0=s2["rel_res0"],
+                                   converged=s2["converged"], used_alt=s2.get("used_alt", 0),
+                                   used_zero=s2.get("used_zero", 0))
+            if k + 1 >= train_from:
+                sync()
+                t0 = time.time()
+                r["train_loss"] = net.train(feat, xm, x, scale, epochs=epochs, lr=lr)
+                sync()
+                r["train_seconds"] = time.time() - t0
+        state["prev"] = dict(prob=prob, u=u.clone(), t=t.clone())
+        rec.append(r)
+        log(r)
+
+    _, hist = opt.run(n_iter, callback=cb)
+    for r, hh in zip(rec, hist):
+        r.update(alpha=hh["alpha"], psi=hh["psi"])
+    net.close()
+    return rec

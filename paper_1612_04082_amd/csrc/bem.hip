@@ -465,6 +465,14 @@ bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, do
         beta = rel * bnorm;
         st.used_alt = 1;
       }
+      // a given start whose residual exceeds the zero start's (relative residual 1) is replaced by zero
+      if ((x0 || xa) && !(rel <= 1.0)) {
+        KFMM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+        KFMM_HIP(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        rel = 1.0;
+        beta = bnorm;
+        st.used_zero = 1;
+      }
     }
     if (rel <= tol || it >= max_iter || !std::isfinite(rel)) break;
     // stagnation (operator noise floor): five restarts in a row without a 1% decrease of the true residual
@@ -577,6 +585,28 @@ void stress_from_boundary(const bem_problem& p, const double* u, const double* t
   std::unique_ptr<Plan> plan(plan_create(qp, qn, qw, NQ, trg, M, bs, bt, o, s));
   plan_eval(*plan, KFMM_STRESS, da, db, out, s);
   KFMM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace kfmm
+
+namespace kfmm {
+
+// Topological derivative of the compliance at a point with stress sig (eq. deriv; "tr sigma^2" read as the
+// square of the trace).
+__global__ void k_topo_derivative(const double* __restrict__ sig, int64_t M, double E, double nu,
+                                  double* __restrict__ td) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const double* s = sig + 6 * i;
+  double ss = s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+  double tr = s[0] + s[1] + s[2];
+  td[i] = 3.0 * (1.0 - nu) / (4.0 * E * (7.0 - 5.0 * nu)) * (10.0 * (1.0 + nu) * ss - (1.0 + 5.0 * nu) * tr * tr);
+}
+
+void topological_derivative(const double* sig, int64_t M, const Elastic& el, double* td, hipStream_t s) {
+  const double E = 9.0 * el.K * el.G / (3.0 * el.K + el.G);
+  hipLaunchKernelGGL(k_topo_derivative, dim3(nblk(M)), dim3(256), 0, s, sig, M, E, el.nu, td);
+  KFMM_HIP(hipGetLastError());
 }
 
 }  // namespace kfmm

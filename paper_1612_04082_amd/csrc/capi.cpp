@@ -201,6 +201,15 @@ extern "C" int bem_quadrature(int64_t n_tri, const double* tri_xyz, double* qp, 
   });
 }
 
+extern "C" int kfmm_topological_derivative(const double* sig6, int64_t M, double K, double G, double* td,
+                                           void* stream) {
+  return guarded([&] {
+    check_moduli(K, G);
+    KFMM_REQUIRE(M >= 0 && (M == 0 || (sig6 && td)), "bad arguments");
+    if (M) topological_derivative(sig6, M, Elastic::make(K, G), td, (hipStream_t)stream);
+  });
+}
+
 struct ws_net {
   kfmm::WsNet* impl;
 };

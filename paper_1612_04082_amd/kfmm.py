@@ -50,7 +50,8 @@ class BemOpts(ctypes.Structure):
 
 class BemStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
-                ("used_alt", ctypes.c_int), ("rel_res_alt", ctypes.c_double), ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
+                ("used_alt", ctypes.c_int), ("used_zero", ctypes.c_int), ("rel_res_alt", ctypes.c_double),
+                ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
                 ("res_estimate", ctypes.c_double), ("b_norm", ctypes.c_double), ("t_setup_s", ctypes.c_double),
                 ("t_solve_s", ctypes.c_double)]
 
@@ -89,6 +90,8 @@ def load_library():
     L.bem_matvec.restype = ctypes.c_int
     L.bem_quadrature.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     L.bem_quadrature.restype = ctypes.c_int
+    L.kfmm_topological_derivative.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
+    L.kfmm_topological_derivative.restype = ctypes.c_int
     fp = ctypes.c_void_p
     L.ws_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_uint64]
     L.ws_destroy.argtypes = [vp]
@@ -377,3 +380,13 @@ def ws_features(prev, u_prev, t_prev, nxt):
     check(L.ws_features(ctypes.byref(pp), _dptr(u_prev, "u_prev", 3), _dptr(t_prev, "t_prev", 3), ctypes.byref(pn),
                         _fptr(feat, "feat", WS_DIN), _dptr(xm, "x_mapped", 3), ctypes.byref(scale), _stream()))
     return feat, xm, scale.value
+
+
+def topological_derivative(sig6, K=None, G=1.0):
+    """Pointwise topological derivative (eq. deriv) of (M,6) stresses on the GPU."""
+    if K is None:
+        K = moduli(G, 0.3)
+    td = torch.empty((int(sig6.shape[0]),), dtype=torch.float64, device=sig6.device)
+    check(load_library().kfmm_topological_derivative(_dptr(sig6, "sig6", 6), int(sig6.shape[0]), K, G,
+                                                     _dptr(td, "td"), _stream()))
+    return td
