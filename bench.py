@@ -34,10 +34,20 @@ def main():
     ap.add_argument("--leaf", type=int, default=128)
     ap.add_argument("--sample", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--svd-eps", type=float, default=0.0, help="pseudo-inverse cutoff (0: library default)")
+    ap.add_argument("--rows", type=int, default=2000, help="oracle sample for the cantilever workload")
+    ap.add_argument("--iters", type=int, default=20, help="Algorithm 1 iterations for the warmstart workload")
+    ap.add_argument("--measure-from", type=int, default=11)
+    ap.add_argument("--workload", choices=["beam", "sphere", "cells", "cantilever", "warmstart"], default="beam",
+                    help="beam: the headline line; the others measure the remaining configurations")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "beam":
+        import bench_configs
+        bench_configs.run(args)
+        return
 
     import numpy as np
     import torch

@@ -124,6 +124,7 @@ enum {
   KFMM_PH_M2M,         /* upward translations, all levels */
   KFMM_PH_M2L_PREP,    /* clearing and converting for the M2L */
   KFMM_PH_M2L,         /* M2L contraction (matrix cores), all levels */
+  KFMM_PH_M2L_RED,     /* sum of the per-pair M2L outputs of every target box (fixed order) */
   KFMM_PH_S2L,         /* X list: sources -> downward check potentials */
   KFMM_PH_DOWN,        /* downward check -> equivalent, L2L, all levels */
   KFMM_PH_LEAF,        /* L2T + W list + near field at the target leaves */
@@ -154,7 +155,8 @@ typedef struct {
   double tol;      /* stop when ||b - A x|| / ||b|| <= tol (true residual) */
   int restart;     /* GMRES restart length m (1..500) */
   int max_iter;    /* maximum number of Arnoldi steps (matrix-vector products); 0 evaluates x0 only */
-  fmm_opts fmm;    /* options of the fast summation behind every product (K, G are taken from the problem) */
+  fmm_opts fmm;    /* options of the fast summation behind every product (K, G are taken from the problem;
+                      svd_eps 0 means 1e-7 here: smaller equivalent densities, lower rounding floor) */
   const double* x0_alt; /* optional second start (device, T x 3, physical units): the start with the smaller
                            true residual is used (one extra product); NULL for none.  A given start whose
                            residual exceeds that of zero is replaced by zero. */

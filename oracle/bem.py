@@ -206,3 +206,31 @@ def gmres(matvec, b, x0=None, tol=1e-6, restart=50, max_iter=2000):
                 break
         y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
         x = x + V[:k].T @ y
+
+
+def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0):
+    """Rows of A x (eq. num2, solver units as in DenseBEM) by direct FP64 sums, for large meshes.
+
+    For each collocation row t: the quadrature sum over every element's 16 points (coincident pair
+    skipped), with the element's own quadrature terms replaced by its closed-form self block, plus the
+    free term 1/2 u.  Unknown layout as DenseBEM: u where the traction is prescribed, t / scale_t where the
+    displacement is prescribed, scale_t = -G / l.
+    """
+    tri = np.ascontiguousarray(tri, dtype=np.float64)
+    T = tri.shape[0]
+    bc = np.asarray(bc_type).reshape(T, 3)
+    x = np.asarray(x, dtype=np.float64).reshape(T, 3)
+    scale_t = -G / mean_edge(tri)
+    t_unk = bc == 0
+    a_el = np.where(t_unk, -scale_t * x, 0.0)   # -t for traction unknowns
+    b_el = np.where(t_unk, 0.0, x)              #  u for displacement unknowns
+    qp, qn, qw, qe = quadrature(tri)
+    cen = tri_geometry(tri)[0]
+    rows = np.asarray(rows)
+    out = od.direct(od.DISP, cen[rows], qp, qw, a=a_el[qe], b=b_el[qe], nrm=qn, K=K, G=G, nthreads=nthreads)
+    for i, r in enumerate(rows):
+        sl = slice(16 * r, 16 * r + 16)
+        own = od.direct(od.DISP, cen[r:r + 1], qp[sl], qw[sl], a=a_el[qe[sl]], b=b_el[qe[sl]], nrm=qn[sl], K=K, G=G)
+        Us, Ps = self_integrals(tri[r], K, G)
+        out[i] += -own[0] + Us @ a_el[r] + Ps @ b_el[r] + 0.5 * b_el[r]
+    return out

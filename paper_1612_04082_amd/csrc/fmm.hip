@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -190,6 +192,19 @@ template <>
 __global__ void k_convert<double, __hip_bfloat16>(int64_t n, const double* in, __hip_bfloat16* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = __float2bfloat16((float)in[i]);
+}
+
+// qhat(box) = sum of the box's M2L slots in a fixed order (FP64 accumulation)
+template <typename TS>
+__global__ void k_slot_reduce(const int* __restrict__ boxes, const int* __restrict__ off, const int* __restrict__ idx,
+                              const TS* __restrict__ slots, double* __restrict__ qhat, int NC) {
+  const int i = blockIdx.x;
+  const int B = boxes[i];
+  for (int c = threadIdx.x; c < NC; c += blockDim.x) {
+    double acc = 0;
+    for (int k = off[i]; k < off[i + 1]; ++k) acc += (double)slots[(size_t)idx[k] * NC + c];
+    qhat[(size_t)B * NC + c] = acc;
+  }
 }
 
 // phi_up(parent) = sum over children with sources of T(child)
@@ -411,16 +426,17 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
 
 // ------------------------------------------------------------------------------------------ plan
 
-static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s) {
+static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int tile_cols = kGemmBN) {
   GemmJob job;
+  job.cols_per_tile = tile_cols;
   const int n = (int)cols.op.size();
   if (n == 0) return job;
-  // tiles: consecutive columns with the same op, <= kGemmBN each (columns must be grouped by op)
+  // tiles: consecutive columns with the same op, <= tile_cols each (columns must be grouped by op)
   std::vector<int4> tiles;
   int i = 0;
   while (i < n) {
     int j = i;
-    while (j < n && cols.op[j] == cols.op[i] && j - i < kGemmBN) ++j;
+    while (j < n && cols.op[j] == cols.op[i] && j - i < tile_cols) ++j;
     tiles.push_back(make_int4(cols.op[i], i, j - i, 0));
     i = j;
   }
@@ -558,8 +574,51 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       if (oi < 0) throw Error(-5, "internal: V pair with a near offset");
       c.add(oi, t.h_v_src[i], t.h_v_trg[i]);
     }
-    P->job_m2l = upload_job(P->arena, sorted_by_op(c), s);
+    GemmCols sc = sorted_by_op(c);
+    // Every pair writes its own slot, then each target box sums its slots in a fixed order: repeated
+    // products are bitwise identical (atomic accumulation would let the order, and so the rounding, vary
+    // between calls, which GMRES on ill-conditioned systems sees as operator noise), and the plain stores
+    // are cheaper than FP64 atomics.
+    const int np_ = (int)sc.op.size();
+    std::vector<std::vector<int>> slots(nb);
+    for (int j = 0; j < np_; ++j) {
+      slots[sc.out[j]].push_back(j);
+      sc.out[j] = j;
+    }
+    std::vector<int> boxes, off = {0}, idx;
+    for (int b2 = 0; b2 < nb; ++b2)
+      if (!slots[b2].empty()) {
+        boxes.push_back(b2);
+        idx.insert(idx.end(), slots[b2].begin(), slots[b2].end());
+        off.push_back((int)idx.size());
+      }
+    P->m2l_red_n = (int)boxes.size();
+    P->m2l_red_box = upload_vec(P->arena, boxes, s);
+    P->m2l_red_off = upload_vec(P->arena, off, s);
+    P->m2l_red_idx = upload_vec(P->arena, idx, s);
+    P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * D.NC) * (o.precision == KFMM_FP64 ? 8 : 4));
+    P->job_m2l = upload_job(P->arena, sc, s, o.precision == KFMM_FP32 ? 2 * kGemmBN : kGemmBN);
     P->n_v_pairs = (int64_t)c.op.size();
+    if (std::getenv("KFMM_DEBUG_STATS")) {  // occupancy of target-box blocks x offsets (design statistics)
+      for (int bs : {16, 32, 64}) {
+        std::vector<int> tb;  // target boxes with V lists, in tree order
+        std::vector<std::vector<int>> offs(nb);
+        for (size_t i = 0; i < t.h_v_trg.size(); ++i) offs[t.h_v_trg[i]].push_back(D.m2l_index[t.h_v_off[i]]);
+        for (int b2 = 0; b2 < nb; ++b2)
+          if (!offs[b2].empty()) tb.push_back(b2);
+        long cells = 0;
+        for (size_t i = 0; i < tb.size(); i += bs) {
+          std::vector<char> u(316, 0);
+          for (size_t j = i; j < std::min(tb.size(), i + bs); ++j)
+            for (int o2 : offs[tb[j]]) u[o2] = 1;
+          int cnt = 0;
+          for (char x2 : u) cnt += x2;
+          cells += (long)cnt * bs;
+        }
+        std::fprintf(stderr, "[kfmm stats] V pairs %zu, target boxes %zu, block %d: offset-union cells %ld, fill %.3f\n",
+                     t.h_v_trg.size(), tb.size(), bs, cells, (double)t.h_v_trg.size() / std::max(1L, cells));
+      }
+    }
   }
   // DC2DE over all boxes with targets at level >= 2; L2L per level >= 3
   {
@@ -666,19 +725,26 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 8, s));
     if (P.prec == KFMM_FP64) {
       mark(KFMM_PH_M2L);
-      gemm_f64(P.job_m2l, D.m2l64, NC, P.phi_up, qhat, kAtomicAdd, s);
+      gemm_f64(P.job_m2l, D.m2l64, NC, P.phi_up, (double*)P.m2l_slots, kStore, s);
+      if (P.m2l_red_n)
+        hipLaunchKernelGGL(k_slot_reduce<double>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
+                           P.m2l_red_idx, (const double*)P.m2l_slots, qhat, NC);
     } else {
       hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                          (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
       if (P.prec == KFMM_FP32) {
         mark(KFMM_PH_M2L);
-        gemm_f32(P.job_m2l, D.m2l32, NC, (const float*)P.phi_up_lo, qhat, kAtomicAdd, s);
+        gemm_f32(P.job_m2l, D.m2l32, NC, (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);
       } else {
         hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                            (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
         mark(KFMM_PH_M2L);
-        gemm_bf16(P.job_m2l, D.m2l16, NC, (const __hip_bfloat16*)P.phi_up_bf, qhat, kAtomicAdd, s);
+        gemm_bf16(P.job_m2l, D.m2l16, NC, (const __hip_bfloat16*)P.phi_up_bf, (float*)P.m2l_slots, kStore, s);
       }
+      mark(KFMM_PH_M2L_RED);
+      if (P.m2l_red_n)
+        hipLaunchKernelGGL(k_slot_reduce<float>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
+                           P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
     }
     KFMM_HIP(hipGetLastError());
     mark(KFMM_PH_S2L);

@@ -23,6 +23,7 @@ constexpr int kGemmBM = 16 * kGemmTM;  // 96 rows per workgroup; NC is a multipl
 
 struct GemmJob {  // device arrays describing one launch
   int n_tiles = 0;
+  int cols_per_tile = 64;   // 64 or 128 (wide tiles: FP32 only)
   int4* tiles = nullptr;    // {op, first column, column count, unused}
   int* in_idx = nullptr;    // per column: source box (X column)
   int* out_idx = nullptr;   // per column: destination box (Y column)

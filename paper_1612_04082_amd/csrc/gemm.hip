@@ -25,51 +25,69 @@ __device__ __forceinline__ void store_out(T* p, T v, int mode) {
     unsafeAtomicAdd(p, v);
 }
 
-// FP64 / FP32 variant: BK = 16 per LDS stage, 4 MFMA k-steps of 4.  Outputs of type TY (FP32 products
-// may be accumulated into FP64 so that atomic scatter order does not change the result beyond FP64 rounding).
-template <typename T, typename TY>
+// FP64 / FP32 variant.  Workgroup tile (16*TM) x (64*TN): wave w owns columns [16*TN*w, 16*TN*(w+1))
+// and all rows; the K dimension advances BK per LDS stage (register-prefetched, one stage in flight).
+// Outputs of type TY (FP32 products may be accumulated into FP64).
+template <typename T, typename TY, int TN, int BK>
 __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC, const int4* __restrict__ tiles,
                                                 const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                 const double* __restrict__ scale, const T* __restrict__ X,
                                                 TY* __restrict__ Y, int mode) {
-  constexpr int BK = 16, BM = kGemmBM, BN = kGemmBN, TM = kGemmTM;
-  __shared__ T As[BK][BM + 1];
+  constexpr int TM = kGemmTM, BM = 16 * TM, BN = 64 * TN;
+  constexpr int VA = 16 / sizeof(T);  // elements per 16-byte global load
+  constexpr int A_VEC = BM * BK / VA / 256;  // vector loads per thread for the A tile
+  constexpr int B_THR_PER_COL = 256 / BN;    // threads sharing one column of the X tile
+  constexpr int B_ELEMS = BK / B_THR_PER_COL;
+  static_assert(BM * BK % (VA * 256) == 0, "A tile must split into 16-byte loads");
+  static_assert(B_ELEMS % VA == 0, "B tile must split into 16-byte loads");
+  __shared__ T As[BM][BK + 1];
   __shared__ T Bs[BK][BN + 1];
   const int4 tile = tiles[blockIdx.x];
   const int r0 = blockIdx.y * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T* Aop = A + (size_t)tile.x * NC * NC;
-  // global -> register staging: A tile BM x BK (row-major rows of 16), B tile BK x BN (column gathers)
-  constexpr int A_ELEMS = BM * BK / 256;  // 6 per thread
-  constexpr int B_ELEMS = BK * BN / 256;  // 4 per thread
-  T ra[A_ELEMS], rb[B_ELEMS];
-  // B: thread -> (column c = tid / 4, k-quad q = tid % 4)
-  const int bc = tid >> 2, bq = tid & 3;
+  typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type vec_t;
+  vec_t ra[A_VEC], rb[B_ELEMS / VA];
+  const int bc = tid / B_THR_PER_COL, bq = tid % B_THR_PER_COL;
   const int col_ok = bc < tile.z;
   const T* xcol = X + (size_t)(col_ok ? in_idx[tile.y + bc] : 0) * NC;
   auto load = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < A_ELEMS; ++e) {
-      int lin = tid + 256 * e;  // over BM*BK, row-major in the tile
-      int row = lin / BK, kk = lin % BK;
-      ra[e] = Aop[(size_t)(r0 + row) * NC + k0 + kk];
+    for (int e = 0; e < A_VEC; ++e) {
+      int lin = tid + 256 * e;  // vector index in the tile, row-major
+      int row = lin / (BK / VA), kv = lin % (BK / VA);
+      ra[e] = *(const vec_t*)(Aop + (size_t)(r0 + row) * NC + k0 + kv * VA);
     }
 #pragma unroll
-    for (int e = 0; e < B_ELEMS; ++e) rb[e] = col_ok ? xcol[k0 + 4 * bq + e] : T(0);
+    for (int e = 0; e < B_ELEMS / VA; ++e) {
+      if (col_ok)
+        rb[e] = *(const vec_t*)(xcol + k0 + bq * B_ELEMS + e * VA);
+      else
+        rb[e] = vec_t{};
+    }
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int e = 0; e < A_ELEMS; ++e) {
+    for (int e = 0; e < A_VEC; ++e) {
       int lin = tid + 256 * e;
-      As[lin % BK][lin / BK] = ra[e];
+      int row = lin / (BK / VA), kv = lin % (BK / VA);
+      const T* v = (const T*)&ra[e];
+#pragma unroll
+      for (int q = 0; q < VA; ++q) As[row][kv * VA + q] = v[q];
     }
 #pragma unroll
-    for (int e = 0; e < B_ELEMS; ++e) Bs[4 * bq + e][bc] = rb[e];
+    for (int e = 0; e < B_ELEMS / VA; ++e) {
+      const T* v = (const T*)&rb[e];
+#pragma unroll
+      for (int q = 0; q < VA; ++q) Bs[bq * B_ELEMS + e * VA + q][bc] = v[q];
+    }
   };
   typedef typename std::conditional<sizeof(T) == 8, double4_t, float4_t>::type acc_t;
-  acc_t acc[TM];
+  acc_t acc[TM][TN];
 #pragma unroll
-  for (int t = 0; t < TM; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  for (int t = 0; t < TM; ++t)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[t][u] = acc_t{0, 0, 0, 0};
   const int nk = NC / BK;
   load(0);
   stash();
@@ -78,14 +96,19 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC,
     if (kt + 1 < nk) load((kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
-      T b = Bs[ks * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+      T b[TN];
+#pragma unroll
+      for (int u = 0; u < TN; ++u) b[u] = Bs[ks * 4 + (lane >> 4)][(wave * TN + u) * 16 + (lane & 15)];
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        T a = As[ks * 4 + (lane >> 4)][t * 16 + (lane & 15)];
-        if constexpr (sizeof(T) == 8)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-        else
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        T a = As[t * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+#pragma unroll
+        for (int u = 0; u < TN; ++u) {
+          if constexpr (sizeof(T) == 8)
+            acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[u], acc[t][u], 0, 0, 0);
+          else
+            acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[u], acc[t][u], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -94,18 +117,21 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC,
       __syncthreads();
     }
   }
-  const int c = wave * 16 + (lane & 15);
-  if (c >= tile.z) return;
-  const int col = tile.y + c;
-  TY* ycol = Y + (size_t)out_idx[col] * NC + r0;
-  const TY sc = scale ? (TY)scale[col] : TY(1);
 #pragma unroll
-  for (int t = 0; t < TM; ++t)
+  for (int u = 0; u < TN; ++u) {
+    const int c = (wave * TN + u) * 16 + (lane & 15);
+    if (c >= tile.z) continue;
+    const int col = tile.y + c;
+    TY* ycol = Y + (size_t)out_idx[col] * NC + r0;
+    const TY sc = scale ? (TY)scale[col] : TY(1);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = sizeof(T) == 8 ? t * 16 + (lane >> 4) + 4 * v : t * 16 + 4 * (lane >> 4) + v;
-      store_out(ycol + row, sc * (TY)acc[t][v], mode);
-    }
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = sizeof(T) == 8 ? t * 16 + (lane >> 4) + 4 * v : t * 16 + 4 * (lane >> 4) + v;
+        store_out(ycol + row, sc * (TY)acc[t][u][v], mode);
+      }
+  }
 }
 
 // BF16 inputs, FP32 accumulation: BK = 32 per LDS stage, one MFMA k-step.
@@ -186,8 +212,8 @@ static void check_job(const GemmJob& job, int NC) {
 void gemm_f64(const GemmJob& job, const double* A, int NC, const double* X, double* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
   check_job(job, NC);
-  hipLaunchKernelGGL((k_gemm_f<double, double>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC, job.tiles,
-                     job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  hipLaunchKernelGGL((k_gemm_f<double, double, 1, 16>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC,
+                     job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
   KFMM_HIP(hipGetLastError());
 }
 
@@ -195,8 +221,12 @@ template <typename TY>
 static void gemm_f32_t(const GemmJob& job, const float* A, int NC, const float* X, TY* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
   check_job(job, NC);
-  hipLaunchKernelGGL((k_gemm_f<float, TY>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC, job.tiles,
-                     job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  if (job.cols_per_tile > kGemmBN)
+    hipLaunchKernelGGL((k_gemm_f<float, TY, 2, 32>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC,
+                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  else
+    hipLaunchKernelGGL((k_gemm_f<float, TY, 1, 32>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC,
+                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
   KFMM_HIP(hipGetLastError());
 }
 void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, float* Y, int mode, hipStream_t s) {
@@ -232,14 +262,16 @@ void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y,
                    const int* out, const double* scale, int ncols, int mode, hipStream_t s) {
   Arena a;
   std::vector<int4> tiles;
+  const int tile_cols = precision == 1 ? 2 * kGemmBN : kGemmBN;  // FP32 runs the wide tiles used by the M2L
   int i = 0;
   while (i < ncols) {
     int j = i;
-    while (j < ncols && op[j] == op[i] && j - i < kGemmBN) ++j;
+    while (j < ncols && op[j] == op[i] && j - i < tile_cols) ++j;
     tiles.push_back(make_int4(op[i], i, j - i, 0));
     i = j;
   }
   GemmJob job;
+  job.cols_per_tile = tile_cols;
   job.n_tiles = (int)tiles.size();
   job.tiles = a.get<int4>(tiles.size() + 1);
   job.in_idx = a.get<int>(ncols + 1);

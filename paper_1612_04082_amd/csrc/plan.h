@@ -43,6 +43,10 @@ struct Plan {
   int n_leaves_src = 0, n_leaves_trg = 0, n_x_boxes = 0;
   int *leaves_src = nullptr, *leaves_trg = nullptr, *x_boxes = nullptr;
   GemmJob job_uc2ue, job_m2l, job_dc2de;
+  // M2L: per-pair output slots (FP64 or FP32) and their fixed-order reduction per target box
+  void* m2l_slots = nullptr;
+  int m2l_red_n = 0;
+  int *m2l_red_box = nullptr, *m2l_red_off = nullptr, *m2l_red_idx = nullptr;
   std::vector<UpLevel> up_levels;
   std::vector<GemmJob> dn_levels;
   // per-box coefficient buffers (n_box x NC)

@@ -203,3 +203,13 @@ def test_uniaxial_tension_interior_stress():
         loaded = (p["bc_val"][:, 0] == 1.0)
         assert abs(u[loaded, 0].mean() - 1.0 / E) < 0.1 / E
     assert errs[1] < errs[0] and errs[1] < 0.05
+
+
+def test_matvec_rows_equals_dense():
+    p = geo.cube_tension_problem(2)
+    s = ob.DenseBEM(p["tri"], p["bc_type"], p["bc_val"], K, G)
+    x = np.random.default_rng(1).normal(size=s.A.shape[0])
+    rows = np.array([0, 5, 17, 40, 95])
+    got = ob.matvec_rows(p["tri"], p["bc_type"], x, rows, K, G)
+    ref = (s.A @ x).reshape(-1, 3)[rows]
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(s.A @ x).max()
