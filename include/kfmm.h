@@ -61,6 +61,8 @@ typedef struct {
   double svd_eps;     /* relative singular-value cutoff of the check-to-equivalent pseudo-inverse; 0 -> 1e-8 */
   int max_depth;      /* deepest octree level; 0 -> 16 */
   size_t mem_limit;   /* bytes of device memory the plan may use; 0 = no limit */
+  double m2l_tol;     /* KFMM_FP32 only: > 0 compresses the M2L operators onto one shared basis, keeping the
+                         singular directions above m2l_tol (relative) of sum_o K_o K_o^T's square root; 0 = dense */
 } fmm_opts;
 
 typedef struct kfmm_plan* kfmm_plan_t;
@@ -107,6 +109,7 @@ typedef struct {
   int64_t n_w_pairs, n_x_pairs;
   double plan_seconds;
   size_t device_bytes;
+  int32_t m2l_rank;    /* rank of the compressed M2L (0: dense) */
 } fmm_info;
 int fmm_plan_info(kfmm_plan_t plan, fmm_info* info /* host */);
 
@@ -157,16 +160,19 @@ typedef struct {
   int max_iter;    /* maximum number of Arnoldi steps (matrix-vector products); 0 evaluates x0 only */
   fmm_opts fmm;    /* options of the fast summation behind every product (K, G are taken from the problem;
                       svd_eps 0 means 1e-7 here: smaller equivalent densities, lower rounding floor) */
-  const double* x0_alt; /* optional second start (device, T x 3, physical units): the start with the smaller
-                           true residual is used (one extra product); NULL for none.  A given start whose
-                           residual exceeds that of zero is replaced by zero. */
+  const double* x0_alt; /* optional second start (device, T x 3, physical units), NULL for none.  GMRES starts
+                           from the minimal-residual combination a x0 + c x0_alt (a alone without x0_alt),
+                           from the products A x0, A x0_alt (one extra product); a start still worse than
+                           zero is replaced by zero. */
 } bem_opts;
 
 typedef struct {   /* host */
   int iters, restarts, converged;
-  int used_alt;        /* 1 if x0_alt was the better start */
+  int used_alt;        /* 1 if x0_alt entered the start (c != 0) */
   int used_zero;       /* 1 if both given starts were worse than zero and zero was used */
   double rel_res_alt;  /* true relative residual of x0_alt (if given) */
+  double rel_res_start; /* relative residual of the minimal-residual start */
+  double start_coef[2]; /* the coefficients a, c of the start */
   int64_t n_matvec;
   double rel_res;      /* true relative residual of the returned x */
   double rel_res0;     /* true relative residual of x0 */

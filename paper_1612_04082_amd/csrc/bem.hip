@@ -402,6 +402,10 @@ bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, do
   bem_stats st{};
   auto t0 = std::chrono::steady_clock::now();
   m = std::max(1, std::min(m, 500));
+  if (!x0 && x0_alt) {  // a single start given as the alternative
+    x0 = x0_alt;
+    x0_alt = nullptr;
+  }
   double* b = arena.get<double>(n);
   double* r = arena.get<double>(n);
   double* w = arena.get<double>(n);
@@ -462,14 +466,42 @@ bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, do
     rel = beta / bnorm;
     if (it == 0 && st.restarts == 0) {
       st.rel_res0 = rel;
-      if (xa && (rel_alt < rel || !std::isfinite(rel))) {
-        KFMM_HIP(hipMemcpyAsync(x, xa, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        KFMM_HIP(hipMemcpyAsync(r, ra, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        rel = rel_alt;
-        beta = rel * bnorm;
-        st.used_alt = 1;
+      if (x0 && std::isfinite(rel)) {
+        // minimal-residual start in span{x0, x0_alt}: with u = A x0 = b - r, v = A xa = b - ra, minimise
+        // ||b - a u - c v|| (2 x 2 normal equations); without xa only the scale a.  Both products were
+        // computed already, so the projection costs dot products only.
+        hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, b, -1.0, r);  // r <- A x0
+        const double uu = dot(r, r), ub = dot(r, b);
+        double a = uu > 0 ? ub / uu : 0.0, c = 0.0;
+        if (xa && std::isfinite(rel_alt)) {
+          hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, b, -1.0, ra);  // ra <- A xa
+          const double vv = dot(ra, ra), uv = dot(r, ra), vb = dot(ra, b);
+          const double det = uu * vv - uv * uv;
+          if (det > 1e-14 * uu * vv) {
+            a = (ub * vv - vb * uv) / det;
+            c = (vb * uu - ub * uv) / det;
+          } else if (vv > 0 && vb * vb / vv > ub * ub / std::max(uu, 1e-300)) {
+            a = 0.0;
+            c = vb / vv;
+          }
+        }
+        // x <- a x0 + c xa,  r <- b - a A x0 - c A xa
+        hipLaunchKernelGGL(k_scale_copy, dim3(nblk(n)), dim3(256), 0, s, n, a, x, x);
+        hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, -a, r, 0.0, r);
+        if (c != 0.0) {
+          hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, c, xa, 1.0, x);
+          hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, -c, ra, 1.0, r);
+          st.used_alt = 1;
+        }
+        hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, b, 1.0, r);
+        KFMM_HIP(hipGetLastError());
+        st.start_coef[0] = a;
+        st.start_coef[1] = c;
+        beta = std::sqrt(dot(r, r));
+        rel = beta / bnorm;
+        st.rel_res_start = rel;
       }
-      // a given start whose residual exceeds the zero start's (relative residual 1) is replaced by zero
+      // a start whose residual exceeds the zero start's (relative residual 1) is replaced by zero
       if ((x0 || xa) && !(rel <= 1.0)) {
         KFMM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, s));
         KFMM_HIP(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));

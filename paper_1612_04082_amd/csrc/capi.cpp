@@ -60,6 +60,7 @@ extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* s
     KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_M2L_BF16, "unknown precision");
     KFMM_REQUIRE(opts->p == 0 || (opts->p >= 3 && opts->p <= 12), "p must be in [3, 12]");
     KFMM_REQUIRE(opts->leaf_max >= 0 && opts->max_depth >= 0, "negative leaf_max or max_depth");
+    KFMM_REQUIRE(opts->m2l_tol >= 0 && opts->m2l_tol < 1, "m2l_tol must be in [0, 1)");
     KFMM_REQUIRE(n_batch >= 0 && n_batch <= 128, "n_batch must be in [0, 128]");
     std::vector<int64_t> bs, bt;
     if (n_batch <= 1 || batch_src == nullptr) {
@@ -110,6 +111,7 @@ extern "C" int fmm_plan_info(kfmm_plan_t plan, fmm_info* info) {
     info->n_x_pairs = P.n_x_pairs;
     info->plan_seconds = P.plan_seconds;
     info->device_bytes = P.arena.bytes;
+    info->m2l_rank = plan_m2l_rank(P);
   });
 }
 

@@ -36,6 +36,21 @@ namespace kfmm {
 
 // ------------------------------------------------------------------------ process-wide operator cache
 
+static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int tile_cols);
+
+// Shared-basis compression of the M2L operators: K_o ~ U C_o U^T with one orthonormal basis U (n x r)
+// for every offset o.  U spans the dominant left singular space of [K_1 ... K_316]: the eigenvectors of
+// sum_o K_o K_o^T above a relative singular-value cutoff.  The U kernel is even and symmetric, so
+// K_{-o} = K_o^T and the right singular space is the same; C_{-o} = C_o^T.
+struct CompressedM2L {
+  double tol = 0;
+  int r = 0, NCr = 0;
+  double* Ut64 = nullptr;  // NCr x NC row-major (row k = k-th basis vector, rows >= r zero)
+  double* U64 = nullptr;   // NC x NCr row-major
+  float* Ut32 = nullptr;   // NCr x NC
+  float* C32 = nullptr;    // 316 x NCr x NCr row-major
+};
+
 struct DeviceOps {
   int device = -1;
   int p = 0, n = 0, NC = 0, n_eq = 0;
@@ -44,6 +59,7 @@ struct DeviceOps {
   __hip_bfloat16* m2l16 = nullptr;
   double* surf = nullptr;  // n_eq x 3
   std::vector<int> m2l_index;
+  std::map<double, std::shared_ptr<CompressedM2L>> comp;  // by relative cutoff
   Arena arena;
 };
 
@@ -224,6 +240,79 @@ __global__ void k_m2m_reduce(const int* parents, int n_par, const int* child_fir
   }
 }
 
+static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_ops_mutex);
+  auto it = d.comp.find(tol);
+  if (it != d.comp.end()) return it->second;
+  const int NC = d.NC, n = d.n, nops = 316;
+  auto c = std::make_shared<CompressedM2L>();
+  c->tol = tol;
+  Arena tmp;
+  // Gram matrix G = sum_o K_o K_o^T: column j of K_o K_o^T is K_o times row j of K_o (one launch per o,
+  // fixed order, so the basis is reproducible)
+  double* gram = tmp.get<double>((size_t)NC * NC);
+  KFMM_HIP(hipMemsetAsync(gram, 0, sizeof(double) * NC * NC, s));
+  for (int o = 0; o < nops; ++o) {
+    GemmCols cols;
+    for (int j = 0; j < n; ++j) cols.add(o, o * NC + j, j);
+    Arena ja;
+    GemmJob job = upload_job(ja, cols, s, kGemmBN);
+    gemm_f64(job, d.m2l64, GemmDims::Sq(NC), d.m2l64, gram, kAdd, s);
+    KFMM_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<double> hg((size_t)NC * NC), G((size_t)n * n);
+  KFMM_HIP(hipMemcpy(hg.data(), gram, sizeof(double) * NC * NC, hipMemcpyDeviceToHost));
+  for (int j = 0; j < n; ++j)  // stored by columns; G is symmetric
+    for (int i = 0; i < n; ++i) G[(size_t)i * n + j] = 0.5 * (hg[(size_t)j * NC + i] + hg[(size_t)i * NC + j]);
+  std::vector<double> lam, vecs;
+  sym_eig_psd(G, n, lam, vecs);
+  int r = 0;
+  while (r < n && lam[r] > 0 && std::sqrt(lam[r] / lam[0]) > tol) ++r;
+  r = std::max(r, 1);
+  c->r = r;
+  c->NCr = round_up(r, kGemmBM);
+  const int NCr = c->NCr;
+  std::vector<double> Ut((size_t)NCr * NC, 0.0), U((size_t)NC * NCr, 0.0);
+  for (int k = 0; k < r; ++k)
+    for (int i = 0; i < n; ++i) {
+      Ut[(size_t)k * NC + i] = vecs[(size_t)k * n + i];
+      U[(size_t)i * NCr + k] = vecs[(size_t)k * n + i];
+    }
+  c->Ut64 = d.arena.get<double>(Ut.size());
+  c->U64 = d.arena.get<double>(U.size());
+  KFMM_HIP(hipMemcpy(c->Ut64, Ut.data(), sizeof(double) * Ut.size(), hipMemcpyHostToDevice));
+  KFMM_HIP(hipMemcpy(c->U64, U.data(), sizeof(double) * U.size(), hipMemcpyHostToDevice));
+  std::vector<float> Ut32(Ut.begin(), Ut.end());
+  c->Ut32 = d.arena.get<float>(Ut32.size());
+  KFMM_HIP(hipMemcpy(c->Ut32, Ut32.data(), sizeof(float) * Ut32.size(), hipMemcpyHostToDevice));
+  // T_o = K_o U (columns j < r), then C_o(:, j) = U^T T_o(:, j) written as row j of C_{-o}
+  double* T = tmp.get<double>((size_t)nops * r * NC);
+  double* C64 = tmp.get<double>((size_t)nops * NCr * NCr);
+  KFMM_HIP(hipMemsetAsync(C64, 0, sizeof(double) * nops * NCr * NCr, s));
+  std::vector<int> neg(nops, -1);
+  for (int k343 = 0; k343 < 343; ++k343)
+    if (d.m2l_index[k343] >= 0) neg[d.m2l_index[k343]] = d.m2l_index[342 - k343];
+  {
+    GemmCols c1, c2;
+    for (int o = 0; o < nops; ++o)
+      for (int j = 0; j < r; ++j) {
+        c1.add(o, j, o * r + j);
+        c2.add(0, o * r + j, neg[o] * NCr + j);
+      }
+    GemmJob j1 = upload_job(tmp, c1, s, kGemmBN), j2 = upload_job(tmp, c2, s, kGemmBN);
+    gemm_f64(j1, d.m2l64, GemmDims::Sq(NC), c->Ut64, T, kStore, s);
+    gemm_f64(j2, c->Ut64, GemmDims{NCr, NC, NC, NCr}, T, C64, kStore, s);
+  }
+  c->C32 = d.arena.get<float>((size_t)nops * NCr * NCr);
+  const int64_t nc = (int64_t)nops * NCr * NCr;
+  hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc,
+                     (const double*)C64, c->C32);
+  KFMM_HIP(hipGetLastError());
+  KFMM_HIP(hipStreamSynchronize(s));
+  d.comp[tol] = c;
+  return c;
+}
+
 // ------------------------------------------------------------------ check-surface evaluations (S2M, X)
 
 constexpr int kStage = 256;  // points staged in LDS per round
@@ -298,7 +387,8 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
 
 // ------------------------------------------------------------------------------- leaf evaluation
 
-// One workgroup per target leaf B.  Lanes are split into S slices over the staged points; slice
+// One workgroup per target leaf B.  Every lane owns two targets (register blocking: each staged point is
+// read from LDS once per two targets) and the lanes are split into S slices over the staged points; slice
 // partial sums are reduced in LDS at the end.  KIND 0 = displacement (3), 1 = stress (6).
 template <typename T, int KIND, bool SL, bool DL>
 __global__ __launch_bounds__(256) void k_leaf_eval(
@@ -309,42 +399,57 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
     const double* __restrict__ surf, int n_eq, double r_up_equiv, double r_dn_equiv, int NC, int far_field,
     KConst<T> kc, double* __restrict__ out) {
   constexpr int NO = KIND == 0 ? 3 : 6;
+  constexpr int TPL = 2;  // targets per lane
   __shared__ T sp[kStage][4];
   __shared__ T sn[kStage][4];
   __shared__ T sd[kStage][8];
-  __shared__ double red[256][NO];
+  __shared__ double red[256][TPL * NO];
   const int B = leaves[blockIdx.x];
   const int tid = threadIdx.x;
   const double rB = box_half(tv.level, tv.geom, tv.root_R, B);
   const int t0 = tv.trg_b[B], nt_all = tv.trg_e[B] - t0;
-  for (int tc = 0; tc < nt_all; tc += 256) {
-    const int nt = min(256, nt_all - tc);
-    const int S = 256 / nt;
-    const int t = tid % nt, sl = tid / nt;
+  for (int tc = 0; tc < nt_all; tc += 256 * TPL) {
+    const int nt = min(256 * TPL, nt_all - tc);
+    const int ntp = (nt + TPL - 1) / TPL;  // lanes per slice
+    const int S = 256 / ntp;
+    const int tp = tid % ntp, sl = tid / ntp;
     const bool act = sl < S;
-    T x[3];
-    for (int d = 0; d < 3; ++d) x[d] = tpos4[4 * (int64_t)(t0 + tc + t) + d];
-    T aU[NO], aP[NO];
-    for (int c = 0; c < NO; ++c) aU[c] = aP[c] = T(0);
+    T x[TPL][3];
+    bool valid[TPL];
+    for (int q = 0; q < TPL; ++q) {
+      const int t = TPL * tp + q;
+      valid[q] = t < nt;
+      const int64_t g = t0 + tc + (valid[q] ? t : 0);
+      for (int d = 0; d < 3; ++d) x[q][d] = tpos4[4 * g + d];
+    }
+    T aU[TPL][NO], aP[TPL][NO];
+    for (int q = 0; q < TPL; ++q)
+      for (int c = 0; c < NO; ++c) aU[q][c] = aP[q][c] = T(0);
     int fill = 0;
     // far-field points carry only a single-layer density (in sd[0..2])
     auto flush = [&](int n, bool near) {
       __syncthreads();
       if (act) {
         for (int j = sl; j < n; j += S) {
-          T dx = sp[j][0] - x[0], dy = sp[j][1] - x[1], dz = sp[j][2] - x[2];
-          T r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == T(0)) continue;
-          if (near) {
-            if (KIND == 0)
-              disp_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU, aP);
-            else
-              stress_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU, aP);
-          } else {
-            if (KIND == 0)
-              disp_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU, aP);
-            else
-              stress_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU, aP);
+          const T px = sp[j][0], py = sp[j][1], pz = sp[j][2];
+#pragma unroll
+          for (int q = 0; q < TPL; ++q) {
+            if (!valid[q]) continue;
+            T dx = px - x[q][0], dy = py - x[q][1], dz = pz - x[q][2];
+            T r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == T(0)) continue;
+            if (near) {
+              if (KIND == 0)
+                disp_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU[q], aP[q]);
+              else
+                stress_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU[q],
+                                       aP[q]);
+            } else {
+              if (KIND == 0)
+                disp_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
+              else
+                stress_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
+            }
           }
         }
       }
@@ -403,21 +508,23 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
     }
     flush(fill, true);
     // combine prefactors, reduce the slices
-    for (int c = 0; c < NO; ++c) {
-      double v;
-      if (KIND == 0)
-        v = (double)kc.cU * (double)aU[c] - (double)kc.cP * (double)aP[c];
-      else
-        v = (double)kc.cD * (double)aU[c] + (double)kc.cS * (double)aP[c];
-      red[tid][c] = act ? v : 0.0;
-    }
+    for (int q = 0; q < TPL; ++q)
+      for (int c = 0; c < NO; ++c) {
+        double v;
+        if (KIND == 0)
+          v = (double)kc.cU * (double)aU[q][c] - (double)kc.cP * (double)aP[q][c];
+        else
+          v = (double)kc.cD * (double)aU[q][c] + (double)kc.cS * (double)aP[q][c];
+        red[tid][q * NO + c] = act ? v : 0.0;
+      }
     __syncthreads();
-    if (tid < nt) {
+    for (int t = tid; t < nt; t += blockDim.x) {
       double acc[NO];
       for (int c = 0; c < NO; ++c) acc[c] = 0;
+      const int lt = t / TPL, q = t % TPL;
       for (int s2 = 0; s2 < S; ++s2)
-        for (int c = 0; c < NO; ++c) acc[c] += red[s2 * nt + tid][c];
-      int o = perm_trg[t0 + tc + tid];
+        for (int c = 0; c < NO; ++c) acc[c] += red[s2 * ntp + lt][q * NO + c];
+      int o = perm_trg[t0 + tc + t];
       for (int c = 0; c < NO; ++c) out[(size_t)o * NO + c] = acc[c];
     }
     __syncthreads();
@@ -449,6 +556,7 @@ static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int til
   KFMM_HIP(hipMemcpyAsync(job.in_idx, cols.in.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
   KFMM_HIP(hipMemcpyAsync(job.out_idx, cols.out.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
   KFMM_HIP(hipMemcpyAsync(job.scale, cols.scale.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  KFMM_HIP(hipStreamSynchronize(s));  // host vectors may be released after return
   return job;
 }
 
@@ -465,7 +573,10 @@ static GemmCols sorted_by_op(const GemmCols& c) {
 template <typename T>
 static T* upload_vec(Arena& a, const std::vector<T>& h, hipStream_t s) {
   T* d = a.get<T>(h.empty() ? 1 : h.size());
-  if (!h.empty()) KFMM_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  if (!h.empty()) {
+    KFMM_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    KFMM_HIP(hipStreamSynchronize(s));
+  }
   return d;
 }
 
@@ -541,6 +652,8 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   P->leaves_trg = upload_vec(P->arena, leaves_trg, s);
   P->x_boxes = upload_vec(P->arena, x_boxes, s);
   auto half = [&](int b) { return std::ldexp(t.h_root_R[t.h_geom[b]], -t.h_level[b]); };
+  // 128-column tiles once a launch has enough columns to fill the chip with them
+  auto wide = [](const GemmCols& c) { return c.op.size() >= 4096 ? 2 * kGemmBN : kGemmBN; };
   auto octant = [&](int b) { return (t.h_ix[b] & 1) | ((t.h_iy[b] & 1) << 1) | ((t.h_iz[b] & 1) << 2); };
   auto hs = [&](int b) { return t.h_src_e[b] > t.h_src_b[b]; };
   auto ht = [&](int b) { return t.h_trg_e[b] > t.h_trg_b[b]; };
@@ -548,7 +661,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   {
     GemmCols c;
     for (int b : leaves_src) c.add(0, b, b, half(b));
-    P->job_uc2ue = upload_job(P->arena, c, s);
+    P->job_uc2ue = upload_job(P->arena, c, s, wide(c));
   }
   // M2M per level (deepest first): children with sources, grouped by octant; parents reduce
   P->up_levels.clear();
@@ -561,7 +674,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       if (!t.h_is_leaf[b] && hs(b)) parents.push_back(b);
     if (c.op.empty()) continue;
     UpLevel U;
-    U.job = upload_job(P->arena, sorted_by_op(c), s);
+    U.job = upload_job(P->arena, sorted_by_op(c), s, wide(c));
     U.n_par = (int)parents.size();
     U.parents = upload_vec(P->arena, parents, s);
     P->up_levels.push_back(U);
@@ -596,7 +709,21 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->m2l_red_box = upload_vec(P->arena, boxes, s);
     P->m2l_red_off = upload_vec(P->arena, off, s);
     P->m2l_red_idx = upload_vec(P->arena, idx, s);
-    P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * D.NC) * (o.precision == KFMM_FP64 ? 8 : 4));
+    int slot_len = D.NC;
+    if (o.precision == KFMM_FP32 && o.m2l_tol > 0) {
+      // compressed M2L: phi~ = U^T phi for every source box, r x r contractions per pair, q = U q~ per target
+      P->comp = get_compressed(*P->ops, o.m2l_tol, s);
+      slot_len = P->comp->NCr;
+      GemmCols cu, ce;
+      for (int b2 = 0; b2 < nb; ++b2)
+        if (t.h_src_e[b2] > t.h_src_b[b2]) cu.add(0, b2, b2);
+      for (int b2 : boxes) ce.add(0, b2, b2);
+      P->job_ut = upload_job(P->arena, cu, s, 2 * kGemmBN);
+      P->job_uexp = upload_job(P->arena, ce, s, kGemmBN);
+      P->phi_t = P->arena.get<float>((size_t)nb * slot_len);
+      P->q_t = P->arena.get<double>((size_t)nb * slot_len);
+    }
+    P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
     P->job_m2l = upload_job(P->arena, sc, s, o.precision == KFMM_FP32 ? 2 * kGemmBN : kGemmBN);
     P->n_v_pairs = (int64_t)c.op.size();
     if (std::getenv("KFMM_DEBUG_STATS")) {  // occupancy of target-box blocks x offsets (design statistics)
@@ -625,14 +752,14 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     GemmCols c;
     for (int b = 0; b < nb; ++b)
       if (t.h_level[b] >= 2 && ht(b)) c.add(0, b, b);
-    P->job_dc2de = upload_job(P->arena, c, s);
+    P->job_dc2de = upload_job(P->arena, c, s, wide(c));
     P->dn_levels.clear();
     for (int l = 3; l <= t.depth; ++l) {
       GemmCols cl;
       for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
         if (ht(b)) cl.add(octant(b), t.h_parent[b], b);
       if (cl.op.empty()) continue;
-      P->dn_levels.push_back(upload_job(P->arena, sorted_by_op(cl), s));
+      P->dn_levels.push_back(upload_job(P->arena, sorted_by_op(cl), s, wide(cl)));
     }
   }
   // ---- counters
@@ -708,10 +835,10 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       s2m(std::false_type(), std::true_type());
     KFMM_HIP(hipGetLastError());
     mark(KFMM_PH_UC2UE);
-    gemm_f64(P.job_uc2ue, D.uc2ue, NC, P.q_up, P.phi_up, kStore, s);
+    gemm_f64(P.job_uc2ue, D.uc2ue, GemmDims::Sq(NC), P.q_up, P.phi_up, kStore, s);
     mark(KFMM_PH_M2M);
     for (const UpLevel& U : P.up_levels) {
-      gemm_f64(U.job, D.m2m, NC, P.phi_up, P.tmp, kStore, s);
+      gemm_f64(U.job, D.m2m, GemmDims::Sq(NC), P.phi_up, P.tmp, kStore, s);
       if (U.n_par)
         hipLaunchKernelGGL(k_m2m_reduce, dim3(U.n_par), dim3(256), 0, s, U.parents, U.n_par, t.child_first,
                            t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
@@ -725,26 +852,39 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 8, s));
     if (P.prec == KFMM_FP64) {
       mark(KFMM_PH_M2L);
-      gemm_f64(P.job_m2l, D.m2l64, NC, P.phi_up, (double*)P.m2l_slots, kStore, s);
+      gemm_f64(P.job_m2l, D.m2l64, GemmDims::Sq(NC), P.phi_up, (double*)P.m2l_slots, kStore, s);
       if (P.m2l_red_n)
         hipLaunchKernelGGL(k_slot_reduce<double>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
                            P.m2l_red_idx, (const double*)P.m2l_slots, qhat, NC);
     } else {
       hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                          (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
-      if (P.prec == KFMM_FP32) {
+      if (P.prec == KFMM_FP32 && P.comp) {
+        const CompressedM2L& C = *P.comp;
+        const int NCr = C.NCr;
+        gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
         mark(KFMM_PH_M2L);
-        gemm_f32(P.job_m2l, D.m2l32, NC, (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);
+        gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
+        mark(KFMM_PH_M2L_RED);
+        if (P.m2l_red_n)
+          hipLaunchKernelGGL(k_slot_reduce<float>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
+                             P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
+        gemm_f64(P.job_uexp, C.U64, GemmDims{NC, NCr, NCr, NC}, P.q_t, qhat, kStore, s);
+      } else if (P.prec == KFMM_FP32) {
+        mark(KFMM_PH_M2L);
+        gemm_f32(P.job_m2l, D.m2l32, GemmDims::Sq(NC), (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);
       } else {
         hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                            (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
         mark(KFMM_PH_M2L);
-        gemm_bf16(P.job_m2l, D.m2l16, NC, (const __hip_bfloat16*)P.phi_up_bf, (float*)P.m2l_slots, kStore, s);
+        gemm_bf16(P.job_m2l, D.m2l16, GemmDims::Sq(NC), (const __hip_bfloat16*)P.phi_up_bf, (float*)P.m2l_slots, kStore, s);
       }
-      mark(KFMM_PH_M2L_RED);
-      if (P.m2l_red_n)
-        hipLaunchKernelGGL(k_slot_reduce<float>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
-                           P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
+      if (!P.comp) {
+        mark(KFMM_PH_M2L_RED);
+        if (P.m2l_red_n)
+          hipLaunchKernelGGL(k_slot_reduce<float>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
+                             P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
+      }
     }
     KFMM_HIP(hipGetLastError());
     mark(KFMM_PH_S2L);
@@ -766,8 +906,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     }
     // downward pass in FP64
     mark(KFMM_PH_DOWN);
-    gemm_f64(P.job_dc2de, D.dc2de, NC, qhat, P.phi_dn, kStore, s);
-    for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, NC, P.phi_dn, P.phi_dn, kAdd, s);
+    gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
+    for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, GemmDims::Sq(NC), P.phi_dn, P.phi_dn, kAdd, s);
     if (P.prec != KFMM_FP64)
       hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                          (int64_t)nbc, P.phi_dn, (float*)P.phi_dn_lo);
@@ -820,6 +960,8 @@ Plan::~Plan() {
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
 }
+
+int plan_m2l_rank(const Plan& P) { return P.comp ? P.comp->r : 0; }
 
 void plan_profile(Plan& P, bool enable) {
   if (enable && !P.ev[0])

@@ -42,12 +42,20 @@ struct GemmCols {
   }
 };
 
-void gemm_f64(const GemmJob& job, const double* A, int NC, const double* X, double* Y, int mode, hipStream_t s);
-void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, float* Y, int mode, hipStream_t s);
-void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, double* Y, int mode, hipStream_t s);
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, float* Y, int mode,
+// Shape of one launch: operators are M x K row-major (leading dimension K, stride M*K between
+// operators), X vectors have K entries at stride ldx, Y vectors M entries at stride ldy.  M must be a
+// multiple of 96 and K of 32.  Sq(NC) is the square case used by the translations.
+struct GemmDims {
+  int M, K, ldx, ldy;
+  static GemmDims Sq(int NC) { return GemmDims{NC, NC, NC, NC}; }
+};
+
+void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, double* Y, int mode, hipStream_t s);
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, float* Y, int mode, hipStream_t s);
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, double* Y, int mode, hipStream_t s);
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, float* Y, int mode,
                hipStream_t s);
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, double* Y, int mode,
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, double* Y, int mode,
                hipStream_t s);
 
 // Runs one gather/scatter GEMM launch from host column descriptors (test hook).

@@ -29,7 +29,7 @@ __device__ __forceinline__ void store_out(T* p, T v, int mode) {
 // and all rows; the K dimension advances BK per LDS stage (register-prefetched, one stage in flight).
 // Outputs of type TY (FP32 products may be accumulated into FP64).
 template <typename T, typename TY, int TN, int BK>
-__global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC, const int4* __restrict__ tiles,
+__global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
                                                 const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                 const double* __restrict__ scale, const T* __restrict__ X,
                                                 TY* __restrict__ Y, int mode) {
@@ -45,18 +45,18 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC,
   const int4 tile = tiles[blockIdx.x];
   const int r0 = blockIdx.y * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const T* Aop = A + (size_t)tile.x * NC * NC;
+  const T* Aop = A + (size_t)tile.x * dm.M * dm.K;
   typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type vec_t;
   vec_t ra[A_VEC], rb[B_ELEMS / VA];
   const int bc = tid / B_THR_PER_COL, bq = tid % B_THR_PER_COL;
   const int col_ok = bc < tile.z;
-  const T* xcol = X + (size_t)(col_ok ? in_idx[tile.y + bc] : 0) * NC;
+  const T* xcol = X + (size_t)(col_ok ? in_idx[tile.y + bc] : 0) * dm.ldx;
   auto load = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < A_VEC; ++e) {
       int lin = tid + 256 * e;  // vector index in the tile, row-major
       int row = lin / (BK / VA), kv = lin % (BK / VA);
-      ra[e] = *(const vec_t*)(Aop + (size_t)(r0 + row) * NC + k0 + kv * VA);
+      ra[e] = *(const vec_t*)(Aop + (size_t)(r0 + row) * dm.K + k0 + kv * VA);
     }
 #pragma unroll
     for (int e = 0; e < B_ELEMS / VA; ++e) {
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC,
   for (int t = 0; t < TM; ++t)
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = acc_t{0, 0, 0, 0};
-  const int nk = NC / BK;
+  const int nk = dm.K / BK;
   load(0);
   stash();
   __syncthreads();
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC,
     const int c = (wave * TN + u) * 16 + (lane & 15);
     if (c >= tile.z) continue;
     const int col = tile.y + c;
-    TY* ycol = Y + (size_t)out_idx[col] * NC + r0;
+    TY* ycol = Y + (size_t)out_idx[col] * dm.ldy + r0;
     const TY sc = scale ? (TY)scale[col] : TY(1);
 #pragma unroll
     for (int t = 0; t < TM; ++t)
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, int NC,
 
 // BF16 inputs, FP32 accumulation: BK = 32 per LDS stage, one MFMA k-step.
 template <typename TY>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A, int NC, const int4* __restrict__ tiles,
+__global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
                                                    const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                    const double* __restrict__ scale, const __bf16* __restrict__ X,
                                                    TY* __restrict__ Y, int mode) {
@@ -146,12 +146,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
   const int4 tile = tiles[blockIdx.x];
   const int r0 = blockIdx.y * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const __bf16* Aop = A + (size_t)tile.x * NC * NC;
+  const __bf16* Aop = A + (size_t)tile.x * dm.M * dm.K;
   // A tile: BM rows x 32 bf16 = BM*4 chunks of 8 (16 bytes); B tile: 64 columns x 4 chunks
   constexpr int A_CH = BM * BK / 8 / 256;  // 1.5 -> use 2 with guard
   const int bc = tid >> 2, bq = tid & 3;
   const int col_ok = bc < tile.z;
-  const __bf16* xcol = X + (size_t)(col_ok ? in_idx[tile.y + bc] : 0) * NC;
+  const __bf16* xcol = X + (size_t)(col_ok ? in_idx[tile.y + bc] : 0) * dm.ldx;
   uint4 ra[2], rb;
   auto load = [&](int k0) {
 #pragma unroll
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
       int lin = tid + 256 * e;
       if (lin < BM * 4) {
         int row = lin >> 2, q = lin & 3;
-        ra[e] = *(const uint4*)(Aop + (size_t)(r0 + row) * NC + k0 + 8 * q);
+        ra[e] = *(const uint4*)(Aop + (size_t)(r0 + row) * dm.K + k0 + 8 * q);
       }
     }
     rb = col_ok ? *(const uint4*)(xcol + k0 + 8 * bq) : make_uint4(0, 0, 0, 0);
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
   float4_t acc[TM];
 #pragma unroll
   for (int t = 0; t < TM; ++t) acc[t] = float4_t{0, 0, 0, 0};
-  const int nk = NC / BK;
+  const int nk = dm.K / BK;
   load(0);
   stash();
   __syncthreads();
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
   const int c = wave * 16 + (lane & 15);
   if (c >= tile.z) return;
   const int col = tile.y + c;
-  TY* ycol = Y + (size_t)out_idx[col] * NC + r0;
+  TY* ycol = Y + (size_t)out_idx[col] * dm.ldy + r0;
   const TY sc = scale ? (TY)scale[col] : TY(1);
 #pragma unroll
   for (int t = 0; t < TM; ++t)
@@ -205,53 +205,58 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
     for (int v = 0; v < 4; ++v) store_out(ycol + t * 16 + 4 * (lane >> 4) + v, sc * (TY)acc[t][v], mode);
 }
 
-static void check_job(const GemmJob& job, int NC) {
-  if (NC % kGemmBM != 0) throw Error(-1, "gemm: NC must be a multiple of the row block");
+static void check_dims(const GemmDims& d) {
+  if (d.M % kGemmBM != 0 || d.K % 32 != 0) throw Error(-1, "gemm: M must be a multiple of 96 and K of 32");
 }
 
-void gemm_f64(const GemmJob& job, const double* A, int NC, const double* X, double* Y, int mode, hipStream_t s) {
+void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, double* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
-  check_job(job, NC);
-  hipLaunchKernelGGL((k_gemm_f<double, double, 1, 16>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC,
-                     job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
-  KFMM_HIP(hipGetLastError());
-}
-
-template <typename TY>
-static void gemm_f32_t(const GemmJob& job, const float* A, int NC, const float* X, TY* Y, int mode, hipStream_t s) {
-  if (job.n_tiles == 0) return;
-  check_job(job, NC);
+  check_dims(d);
   if (job.cols_per_tile > kGemmBN)
-    hipLaunchKernelGGL((k_gemm_f<float, TY, 2, 32>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC,
+    hipLaunchKernelGGL((k_gemm_f<double, double, 2, 16>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
                        job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
   else
-    hipLaunchKernelGGL((k_gemm_f<float, TY, 1, 32>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, A, NC,
+    hipLaunchKernelGGL((k_gemm_f<double, double, 1, 16>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
                        job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
   KFMM_HIP(hipGetLastError());
 }
-void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, float* Y, int mode, hipStream_t s) {
-  gemm_f32_t(job, A, NC, X, Y, mode, s);
+
+template <typename TY>
+static void gemm_f32_t(const GemmJob& job, const float* A, GemmDims d, const float* X, TY* Y, int mode,
+                       hipStream_t s) {
+  if (job.n_tiles == 0) return;
+  check_dims(d);
+  if (job.cols_per_tile > kGemmBN)
+    hipLaunchKernelGGL((k_gemm_f<float, TY, 2, 32>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
+                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  else
+    hipLaunchKernelGGL((k_gemm_f<float, TY, 1, 32>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
+                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  KFMM_HIP(hipGetLastError());
 }
-void gemm_f32(const GemmJob& job, const float* A, int NC, const float* X, double* Y, int mode, hipStream_t s) {
-  gemm_f32_t(job, A, NC, X, Y, mode, s);
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, float* Y, int mode, hipStream_t s) {
+  gemm_f32_t(job, A, d, X, Y, mode, s);
+}
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, double* Y, int mode, hipStream_t s) {
+  gemm_f32_t(job, A, d, X, Y, mode, s);
 }
 
 template <typename TY>
-static void gemm_bf16_t(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, TY* Y, int mode,
-                        hipStream_t s) {
+static void gemm_bf16_t(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, TY* Y,
+                        int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
-  check_job(job, NC);
-  hipLaunchKernelGGL((k_gemm_bf16<TY>), dim3(job.n_tiles, NC / kGemmBM), dim3(256), 0, s, (const __bf16*)A, NC,
+  check_dims(d);
+  hipLaunchKernelGGL((k_gemm_bf16<TY>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, (const __bf16*)A, d,
                      job.tiles, job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
   KFMM_HIP(hipGetLastError());
 }
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, float* Y, int mode,
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, float* Y, int mode,
                hipStream_t s) {
-  gemm_bf16_t(job, A, NC, X, Y, mode, s);
+  gemm_bf16_t(job, A, d, X, Y, mode, s);
 }
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, int NC, const __hip_bfloat16* X, double* Y, int mode,
+void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, double* Y, int mode,
                hipStream_t s) {
-  gemm_bf16_t(job, A, NC, X, Y, mode, s);
+  gemm_bf16_t(job, A, d, X, Y, mode, s);
 }
 
 }  // namespace kfmm
@@ -262,7 +267,9 @@ void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y,
                    const int* out, const double* scale, int ncols, int mode, hipStream_t s) {
   Arena a;
   std::vector<int4> tiles;
-  const int tile_cols = precision == 1 ? 2 * kGemmBN : kGemmBN;  // FP32 runs the wide tiles used by the M2L
+  // FP32 runs the wide tiles used by the M2L; FP64 runs wide tiles when op == 0 only (as in large launches)
+  const int tile_cols = (precision == 1 || (precision == 0 && ncols > 0 && op[ncols - 1] == 0)) ? 2 * kGemmBN
+                                                                                                  : kGemmBN;
   int i = 0;
   while (i < ncols) {
     int j = i;
@@ -281,12 +288,13 @@ void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y,
   KFMM_HIP(hipMemcpyAsync(job.in_idx, in, ncols * sizeof(int), hipMemcpyHostToDevice, s));
   KFMM_HIP(hipMemcpyAsync(job.out_idx, out, ncols * sizeof(int), hipMemcpyHostToDevice, s));
   if (scale) KFMM_HIP(hipMemcpyAsync(job.scale, scale, ncols * sizeof(double), hipMemcpyHostToDevice, s));
+  const GemmDims d = GemmDims::Sq(NC);
   if (precision == 0)
-    gemm_f64(job, (const double*)A, NC, (const double*)X, (double*)Y, mode, s);
+    gemm_f64(job, (const double*)A, d, (const double*)X, (double*)Y, mode, s);
   else if (precision == 1)
-    gemm_f32(job, (const float*)A, NC, (const float*)X, (float*)Y, mode, s);
+    gemm_f32(job, (const float*)A, d, (const float*)X, (float*)Y, mode, s);
   else
-    gemm_bf16(job, (const __hip_bfloat16*)A, NC, (const __hip_bfloat16*)X, (float*)Y, mode, s);
+    gemm_bf16(job, (const __hip_bfloat16*)A, d, (const __hip_bfloat16*)X, (float*)Y, mode, s);
   KFMM_HIP(hipStreamSynchronize(s));
 }
 }  // namespace kfmm

@@ -57,12 +57,14 @@ static void kernel_matrix_U(const Elastic& e, const double* X, int nx, const dou
     }
 }
 
-// Pseudo-inverse of a square n x n row-major matrix by one-sided (Hestenes) Jacobi SVD in FP64,
-// singular values below eps * s_max discarded.  Columns are processed in a round-robin ordering so
-// that the n/2 rotations of one round touch disjoint column pairs and run on several threads.
-static std::vector<double> pinv_jacobi(const std::vector<double>& A, int n, double eps, int* rank_out) {
-  // column-major working copies: W = A V, V
-  std::vector<double> W((size_t)n * n), V((size_t)n * n, 0.0);
+// One-sided (Hestenes) Jacobi SVD of a square n x n row-major matrix A in FP64: on return W = A V has
+// mutually orthogonal columns (column-major, W_j = s_j u_j), V is orthogonal (column-major) and sig holds
+// the column norms s_j.  Columns are processed in a round-robin ordering so that the n/2 rotations of one
+// round touch disjoint column pairs and run on several threads.
+static void jacobi_svd(const std::vector<double>& A, int n, std::vector<double>& W, std::vector<double>& V,
+                       std::vector<double>& sig) {
+  W.assign((size_t)n * n, 0.0);
+  V.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) W[(size_t)j * n + i] = A[(size_t)i * n + j];
   for (int j = 0; j < n; ++j) V[(size_t)j * n + j] = 1.0;
@@ -147,14 +149,20 @@ static std::vector<double> pinv_jacobi(const std::vector<double>& A, int n, doub
     worker(0);
     for (auto& t : th) t.join();
   }
-  std::vector<double> sig(n);
-  double smax = 0;
+  sig.assign(n, 0.0);
   for (int j = 0; j < n; ++j) {
     double s = 0;
     for (int i = 0; i < n; ++i) s += W[(size_t)j * n + i] * W[(size_t)j * n + i];
     sig[j] = std::sqrt(s);
-    smax = std::max(smax, sig[j]);
   }
+}
+
+// Pseudo-inverse of a square n x n row-major matrix, singular values below eps * s_max discarded.
+static std::vector<double> pinv_jacobi(const std::vector<double>& A, int n, double eps, int* rank_out) {
+  std::vector<double> W, V, sig;
+  jacobi_svd(A, n, W, V, sig);
+  double smax = 0;
+  for (double v : sig) smax = std::max(smax, v);
   // pinv = V diag(1/s) U^T with U_j = W_j / s_j  ->  pinv[i][k] = sum_j V[i][j] W[k][j] / s_j^2
   std::vector<double> P((size_t)n * n, 0.0);
   int rank = 0;
@@ -307,6 +315,23 @@ Operators build_operators(int p, const Elastic& e, double svd_eps) {
         op.m2l.push_back(std::move(Km));
       }
   return op;
+}
+
+// Eigen-decomposition of a symmetric positive semi-definite n x n matrix (row-major): eigenvalues in
+// decreasing order and the matching unit eigenvectors (column-major n x n).  For such a matrix the one-sided
+// Jacobi iteration converges to W = A V = V diag(lambda), so the column norms are the eigenvalues.
+void sym_eig_psd(const std::vector<double>& A, int n, std::vector<double>& lambda, std::vector<double>& vecs) {
+  std::vector<double> W, V, sig;
+  jacobi_svd(A, n, W, V, sig);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return sig[a] > sig[b]; });
+  lambda.resize(n);
+  vecs.assign((size_t)n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    lambda[k] = sig[order[k]];
+    for (int i = 0; i < n; ++i) vecs[(size_t)k * n + i] = V[(size_t)order[k] * n + i];
+  }
 }
 
 }  // namespace kfmm

@@ -19,5 +19,6 @@ struct Operators {
 
 std::vector<double> cube_surface(int p);
 Operators build_operators(int p, const Elastic& e, double svd_eps);
+void sym_eig_psd(const std::vector<double>& A, int n, std::vector<double>& lambda, std::vector<double>& vecs);
 
 }  // namespace kfmm

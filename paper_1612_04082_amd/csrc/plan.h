@@ -11,6 +11,7 @@
 namespace kfmm {
 
 struct DeviceOps;
+struct CompressedM2L;
 
 // Read-only device view of the box arrays passed to kernels by value.
 struct TreeView {
@@ -43,6 +44,11 @@ struct Plan {
   int n_leaves_src = 0, n_leaves_trg = 0, n_x_boxes = 0;
   int *leaves_src = nullptr, *leaves_trg = nullptr, *x_boxes = nullptr;
   GemmJob job_uc2ue, job_m2l, job_dc2de;
+  // compressed M2L (FP32 with opts.m2l_tol > 0)
+  std::shared_ptr<CompressedM2L> comp;
+  GemmJob job_ut, job_uexp;
+  float* phi_t = nullptr;   // U^T phi_up per box (n_box x NCr)
+  double* q_t = nullptr;    // reduced compressed check potentials (n_box x NCr)
   // M2L: per-pair output slots (FP64 or FP32) and their fixed-order reduction per target box
   void* m2l_slots = nullptr;
   int m2l_red_n = 0;
@@ -68,5 +74,6 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
                   hipStream_t s);
 void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out, hipStream_t s);
 void plan_profile(Plan& P, bool enable);
+int plan_m2l_rank(const Plan& P);
 
 }  // namespace kfmm

@@ -28,14 +28,15 @@ class KfmmError(RuntimeError):
 class FmmOpts(ctypes.Structure):
     _fields_ = [("K", ctypes.c_double), ("G", ctypes.c_double), ("p", ctypes.c_int), ("leaf_max", ctypes.c_int),
                 ("precision", ctypes.c_int), ("svd_eps", ctypes.c_double), ("max_depth", ctypes.c_int),
-                ("mem_limit", ctypes.c_size_t)]
+                ("mem_limit", ctypes.c_size_t), ("m2l_tol", ctypes.c_double)]
 
 
 class FmmInfo(ctypes.Structure):
     _fields_ = [("n_src", ctypes.c_int64), ("n_trg", ctypes.c_int64), ("n_box", ctypes.c_int64),
                 ("n_leaf", ctypes.c_int64), ("depth", ctypes.c_int32), ("n_eq", ctypes.c_int32),
                 ("n_u_pairs", ctypes.c_int64), ("n_v_pairs", ctypes.c_int64), ("n_w_pairs", ctypes.c_int64),
-                ("n_x_pairs", ctypes.c_int64), ("plan_seconds", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+                ("n_x_pairs", ctypes.c_int64), ("plan_seconds", ctypes.c_double), ("device_bytes", ctypes.c_size_t),
+                ("m2l_rank", ctypes.c_int32)]
 
 
 class BemProblem(ctypes.Structure):
@@ -51,7 +52,7 @@ class BemOpts(ctypes.Structure):
 class BemStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("used_alt", ctypes.c_int), ("used_zero", ctypes.c_int), ("rel_res_alt", ctypes.c_double),
-                ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
+                ("rel_res_start", ctypes.c_double), ("start_coef", ctypes.c_double * 2), ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
                 ("res_estimate", ctypes.c_double), ("b_norm", ctypes.c_double), ("t_setup_s", ctypes.c_double),
                 ("t_solve_s", ctypes.c_double)]
 
@@ -147,12 +148,12 @@ class FmmPlan:
     """fmm_plan / fmm_eval / fmm_plan_destroy on torch tensors (FP64, on the current CUDA device)."""
 
     def __init__(self, src, nrm=None, w=None, trg=None, K=None, G=1.0, p=6, leaf_max=64, precision=FP32,
-                 svd_eps=0.0, max_depth=0, mem_limit=0, batch_src=None, batch_trg=None):
+                 svd_eps=0.0, max_depth=0, mem_limit=0, batch_src=None, batch_trg=None, m2l_tol=0.0):
         L = load_library()
         self._h = ctypes.c_void_p()
         if K is None:
             K = moduli(G, 0.3)
-        self.opts = FmmOpts(K, G, p, leaf_max, precision, svd_eps, max_depth, mem_limit)
+        self.opts = FmmOpts(K, G, p, leaf_max, precision, svd_eps, max_depth, mem_limit, m2l_tol)
         self.n_src = int(src.shape[0])
         self.n_trg = int(trg.shape[0]) if trg is not None else self.n_src
         self._keep = (src, nrm, w, trg)
@@ -234,7 +235,7 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G)
     alt = _dptr(x0_alt, "x0_alt", 3)
-    opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0),
+    opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0),
                    alt.value if alt is not None else None)
     T = int(tri.shape[0])
     x = torch.empty((T, 3), dtype=torch.float64, device=tri.device)
@@ -244,6 +245,7 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
     rc = L.bem_solve(ctypes.byref(prob), ctypes.byref(opts), _dptr(x0, "x0", 3), _dptr(x, "x", 3),
                      _dptr(u, "u", 3), _dptr(t, "t", 3), ctypes.byref(st), _stream())
     stats = {k: getattr(st, k) for k, _ in BemStats._fields_}
+    stats["start_coef"] = list(st.start_coef)
     if rc == -4 and allow_noconv:
         return x, u, t, stats
     check(rc)
@@ -256,7 +258,7 @@ def bem_stress(tri, bc_type, bc_val, u, t, trg, K=None, G=1.0, p=8, leaf_max=128
     if K is None:
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G)
-    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0)
+    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
     M = int(trg.shape[0])
     out = torch.empty((M, 6), dtype=torch.float64, device=trg.device)
     check(L.bem_stress(ctypes.byref(prob), _dptr(u, "u", 3), _dptr(t, "t", 3), _dptr(trg, "trg", 3), M,
@@ -285,7 +287,7 @@ def bem_matvec(tri, bc_type, bc_val, x=None, which=0, K=None, G=1.0, p=8, leaf_m
     if K is None:
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G)
-    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0)
+    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
     y = torch.empty((int(tri.shape[0]), 3), dtype=torch.float64, device=tri.device)
     check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3), _dptr(y, "y", 3), _stream()))
     return y

@@ -42,7 +42,7 @@ def test_warm_start_study_small(cuda):
     for r in meas:
         for mode in ("zero", "prev", "net"):
             assert r[mode]["converged"] == 1
-        # the guard never starts from a point worse than zero, so the warm starts cost at most one extra
-        # product and a few Arnoldi steps more than the zero start
-        assert r["prev"]["iters"] <= r["zero"]["iters"] + 3
-        assert r["net"]["iters"] <= r["zero"]["iters"] + 3
+        # the start is never worse than zero in residual (minimal-residual projection, then the zero guard);
+        # GMRES step counts are not monotone in the starting residual, hence the slack
+        assert r["prev"]["iters"] <= 1.25 * r["zero"]["iters"] + 5
+        assert r["net"]["iters"] <= 1.25 * r["zero"]["iters"] + 5

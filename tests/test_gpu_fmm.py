@@ -83,3 +83,25 @@ def test_double_layer_jump_through_fmm(cuda):
         err = np.abs(got + e[None]).max()
         print(f"jump identity component {k}: max err {err:.3e}")
         assert err < 1e-5
+
+
+@pytest.mark.parametrize("tol,slack", [(1e-7, 1.05), (1e-6, 1.5)])
+def test_compressed_m2l(cuda, tol, slack):
+    """Shared-basis M2L compression (FP32): the rank is reported and the error stays at the dense level
+    (the far-field truncation at p = 8, ~3e-5 here with a random double layer on the sphere)."""
+    from tests.fmm_cases import to_dev, K, G
+    from paper_1612_04082_amd import kfmm
+    c = geo.sphere_cloud(4096, seed=1)
+    rng = np.random.default_rng(8)
+    b = rng.normal(size=c["src"].shape)
+    ref = run_oracle(c["src"], c["nrm"], c["w"], c["a"], b, od.DISP)
+    dense = run_fmm(c["src"], c["nrm"], c["w"], c["a"], b, od.DISP, precision=1, p=8)
+    plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G, p=8, leaf_max=64,
+                        precision=1, m2l_tol=tol)
+    got = plan.eval(od.DISP, to_dev(c["a"]), to_dev(b)).cpu().numpy()
+    rank = plan.info()["m2l_rank"]
+    plan.close()
+    e_c, e_d = rel_l2(got, ref), rel_l2(dense, ref)
+    print(f"m2l_tol {tol:.0e}: rank {rank} of 888, compressed err {e_c:.2e}, dense err {e_d:.2e}")
+    assert 0 < rank < 888
+    assert e_c <= slack * e_d + 1e-7 and e_c < 5e-5

@@ -11,10 +11,10 @@ import torch
 pytestmark = pytest.mark.gpu
 
 
-def _case(precision, mode, seed=0):
+def _case(precision, mode, seed=0, n_ops=3):
     from paper_1612_04082_amd import kfmm
     rng = np.random.default_rng(seed)
-    NC, n_ops, n_box, ncols = 192, 3, 90, 150
+    NC, n_box, ncols = 192, 90, 150
     A = rng.normal(size=(n_ops, NC, NC))
     X = rng.normal(size=(n_box, NC))
     op = np.sort(rng.integers(0, n_ops, size=ncols))
@@ -54,3 +54,10 @@ def test_gemm_matches_reference(cuda, precision, tol, mode):
     err = _case(precision, mode)
     print(f"precision={precision} mode={mode} rel err {err:.3e}")
     assert err < tol
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_gemm_single_operator_wide_tiles(cuda, mode):
+    """One operator for every column: the FP64 launch then uses the 128-column tiles."""
+    err = _case(0, mode, seed=3, n_ops=1)
+    assert err < 1e-13
