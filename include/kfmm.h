@@ -116,7 +116,9 @@ int fmm_plan_info(kfmm_plan_t plan, fmm_info* info /* host */);
 /*
  * Phase timing.  fmm_profile(plan, 1) makes every following fmm_eval record HIP events between its
  * phases on the caller's stream and wait for them at the end of the call (so profiled calls are
- * synchronous); fmm_profile(plan, 0) stops it.  fmm_phase_times writes, for each phase, the summed
+ * synchronous); fmm_profile(plan, 0) stops it.  Unprofiled calls run the near field on a second
+ * stream of the plan, concurrently with the far-field passes; profiled calls run every phase in turn
+ * on the caller's stream.  fmm_phase_times writes, for each phase, the summed
  * milliseconds over the profiled calls (host array of KFMM_N_PHASES doubles) and their number.
  * Enabling resets the sums.
  */
@@ -130,7 +132,8 @@ enum {
   KFMM_PH_M2L_RED,     /* sum of the per-pair M2L outputs of every target box (fixed order) */
   KFMM_PH_S2L,         /* X list: sources -> downward check potentials */
   KFMM_PH_DOWN,        /* downward check -> equivalent, L2L, all levels */
-  KFMM_PH_LEAF,        /* L2T + W list + near field at the target leaves */
+  KFMM_PH_NEAR,        /* near field (U list) at the target leaves */
+  KFMM_PH_LEAF,        /* far field at the target leaves: L2T + W list */
   KFMM_N_PHASES
 };
 int fmm_profile(kfmm_plan_t plan, int enable);
@@ -269,6 +272,8 @@ int ws_load(ws_net_t net, const char* path);
  * precision 0: A, X, Y FP64; 1: FP32; 2: A, X bfloat16 and Y FP32.  A holds NC x NC row-major operators,
  * X and Y hold NC-vectors (stride NC).  op, in, out, scale (scale may be NULL) are HOST arrays of ncols
  * entries with op non-decreasing; NC must be a multiple of 96.  Synchronises the stream.
+ * precision + 16 * k selects the FP64 / FP32 kernel: k = 0 as the library chooses, 1 the LDS-tiled
+ * kernel, 2 the split-K kernel used for launches with few columns.
  */
 int kfmm_selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,
                        const int* out, const double* scale, int ncols, int mode, void* stream);

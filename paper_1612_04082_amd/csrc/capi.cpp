@@ -346,10 +346,13 @@ extern "C" int kfmm_selftest_gemm(int precision, const void* A, int NC, const vo
                                   const int* in, const int* out, const double* scale, int ncols, int mode,
                                   void* stream) {
   return guarded([&] {
+    const int kernel = precision >> 4;
+    precision &= 15;
     KFMM_REQUIRE(precision >= 0 && precision <= 2 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
+    KFMM_REQUIRE(kernel >= 0 && kernel <= 2 && (kernel == 0 || precision <= 1), "bad kernel selector");
     KFMM_REQUIRE(NC > 0 && NC % kGemmBM == 0, "NC must be a positive multiple of 96");
     for (int i = 1; i < ncols; ++i) KFMM_REQUIRE(op[i] >= op[i - 1], "columns must be sorted by op");
-    selftest_gemm(precision, A, NC, X, Y, op, in, out, scale, ncols, mode, (hipStream_t)stream);
+    selftest_gemm(precision, A, NC, X, Y, op, in, out, scale, ncols, mode, kernel, (hipStream_t)stream);
   });
 }
 

@@ -96,9 +96,11 @@ static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, 
       KFMM_HIP(hipMemcpy(ptr, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice));
       return ptr;
     };
-    d->uc2ue = up(pad_square(op.uc2ue, op.n, NC));
-    d->dc2de = up(pad_square(op.dc2de, op.n, NC));
-    std::vector<double> cat;
+    std::vector<double> cat = pad_square(op.uc2ue, op.n, NC);
+    d->uc2ue = up(cat);
+    cat = pad_square(op.dc2de, op.n, NC);
+    d->dc2de = up(cat);
+    cat.clear();
     for (int c = 0; c < 8; ++c) {
       auto v = pad_square(op.m2m[c], op.n, NC);
       cat.insert(cat.end(), v.begin(), v.end());
@@ -210,34 +212,78 @@ __global__ void k_convert<double, __hip_bfloat16>(int64_t n, const double* in, _
   if (i < n) out[i] = __float2bfloat16((float)in[i]);
 }
 
-// qhat(box) = sum of the box's M2L slots in a fixed order (FP64 accumulation)
+// Sums of NC-vectors in a fixed order (FP64 accumulation), 16 bytes per lane and per load, four loads in
+// flight.  NC is a multiple of 32.
 template <typename TS>
-__global__ void k_slot_reduce(const int* __restrict__ boxes, const int* __restrict__ off, const int* __restrict__ idx,
-                              const TS* __restrict__ slots, double* __restrict__ qhat, int NC) {
+struct Vec16 {
+  static constexpr int V = 16 / sizeof(TS);
+  TS v[V];
+};
+
+template <typename TS>
+__device__ __forceinline__ Vec16<TS> load16(const TS* p) {
+  return *(const Vec16<TS>*)p;
+}
+
+// out(box) = sum of the box's M2L slots in list order
+template <typename TS, typename TO>
+__global__ __launch_bounds__(256) void k_slot_reduce(const int* __restrict__ boxes, const int* __restrict__ off,
+                                                     const int* __restrict__ idx, const TS* __restrict__ slots,
+                                                     TO* __restrict__ out, int NC) {
+  constexpr int V = Vec16<TS>::V;
   const int i = blockIdx.x;
-  const int B = boxes[i];
-  for (int c = threadIdx.x; c < NC; c += blockDim.x) {
-    double acc = 0;
-    for (int k = off[i]; k < off[i + 1]; ++k) acc += (double)slots[(size_t)idx[k] * NC + c];
-    qhat[(size_t)B * NC + c] = acc;
+  const int B = boxes[i], k0 = off[i], k1 = off[i + 1];
+  for (int c = threadIdx.x * V; c < NC; c += blockDim.x * V) {
+    double acc[V] = {};
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      Vec16<TS> v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = load16(slots + (size_t)idx[k + u] * NC + c);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] += (double)v[u].v[e];
+    }
+    for (; k < k1; ++k) {
+      Vec16<TS> v = load16(slots + (size_t)idx[k] * NC + c);
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[e] += (double)v.v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < V; ++e) out[(size_t)B * NC + c + e] = (TO)acc[e];
   }
 }
 
-// phi_up(parent) = sum over children with sources of T(child)
-__global__ void k_m2m_reduce(const int* parents, int n_par, const int* child_first, const int* child_count,
-                             const int* src_b, const int* src_e, const double* T, double* phi, int NC) {
+// phi_up(parent) = sum over children with sources of T(child), children in order
+template <typename T>
+__global__ __launch_bounds__(256) void k_m2m_reduce(const int* parents, int n_par, const int* child_first,
+                                                    const int* child_count, const int* src_b, const int* src_e,
+                                                    const T* __restrict__ tmp, T* __restrict__ phi, int NC) {
+  constexpr int V = Vec16<T>::V;
   int pi = blockIdx.x;
   if (pi >= n_par) return;
   int P = parents[pi];
   int f = child_first[P], nc = child_count[P];
-  for (int c = threadIdx.x; c < NC; c += blockDim.x) {
-    double acc = 0;
+  for (int c = threadIdx.x * V; c < NC; c += blockDim.x * V) {
+    double acc[V] = {};
     for (int k = 0; k < nc; ++k) {
       int C = f + k;
-      if (src_e[C] > src_b[C]) acc += T[(size_t)C * NC + c];
+      if (src_e[C] > src_b[C]) {
+        Vec16<T> v = load16(tmp + (size_t)C * NC + c);
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] += (double)v.v[e];
+      }
     }
-    phi[(size_t)P * NC + c] = acc;
+#pragma unroll
+    for (int e = 0; e < V; ++e) phi[(size_t)P * NC + c + e] = (T)acc[e];
   }
+}
+
+// threads for one vector sum over NC entries of type T (16 bytes per lane)
+template <typename T>
+static int reduce_block(int NC) {
+  return std::min(256, round_up(NC / Vec16<T>::V, 64));
 }
 
 static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, hipStream_t s) {
@@ -390,14 +436,18 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
 // One workgroup per target leaf B.  Every lane owns two targets (register blocking: each staged point is
 // read from LDS once per two targets) and the lanes are split into S slices over the staged points; slice
 // partial sums are reduced in LDS at the end.  KIND 0 = displacement (3), 1 = stress (6).
+// far_field: L2T from B's downward equivalent surface, plus the W(B) contributions computed by k_w_eval
+// (one output slot per W pair, summed here in list order); near_field: U(B) directly; accumulate: add
+// to out instead of storing.
 template <typename T, int KIND, bool SL, bool DL>
 __global__ __launch_bounds__(256) void k_leaf_eval(
     const int* __restrict__ leaves, TreeView tv, const int* __restrict__ u_off, const int* __restrict__ u_idx,
-    const int* __restrict__ w_off, const int* __restrict__ w_idx, const T* __restrict__ spos4,
+    const int* __restrict__ w_off, const int64_t* __restrict__ wslot_off, const double* __restrict__ wslot,
+    const T* __restrict__ spos4,
     const T* __restrict__ snrm4, const T* __restrict__ dens8, const T* __restrict__ tpos4,
     const int* __restrict__ perm_trg, const T* __restrict__ phi_dn, const T* __restrict__ phi_up,
     const double* __restrict__ surf, int n_eq, double r_up_equiv, double r_dn_equiv, int NC, int far_field,
-    KConst<T> kc, double* __restrict__ out) {
+    int near_field, int accumulate, KConst<T> kc, double* __restrict__ out) {
   constexpr int NO = KIND == 0 ? 3 : 6;
   constexpr int TPL = 2;  // targets per lane
   __shared__ T sp[kStage][4];
@@ -456,35 +506,29 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
       __syncthreads();
     };
     if (far_field) {
-      // L2T: B's downward equivalent surface, then M2T over W(B) (upward equivalent surfaces)
-      const int nw = w_off[B + 1] - w_off[B];
-      for (int li = -1; li < nw; ++li) {
-        const int A = li < 0 ? B : w_idx[w_off[B] + li];
-        double o[3] = {0, 0, 0};
-        if (li >= 0) box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
-        const double rad = li < 0 ? r_dn_equiv * rB : r_up_equiv * box_half(tv.level, tv.geom, tv.root_R, A);
-        const T* phi = li < 0 ? phi_dn : phi_up;
-        for (int base = 0; base < n_eq; base += kStage) {
-          const int cnt = min(kStage, n_eq - base);
-          if (fill + cnt > kStage) {
-            flush(fill, false);
-            fill = 0;
-          }
-          for (int i = tid; i < cnt; i += blockDim.x) {
-            const int e = base + i;
-            for (int d = 0; d < 3; ++d) {
-              sp[fill + i][d] = (T)(o[d] + rad * surf[3 * e + d]);
-              sd[fill + i][d] = phi[(size_t)A * NC + 3 * e + d];
-            }
-          }
-          fill += cnt;
+      // L2T: B's downward equivalent surface
+      const double rad = r_dn_equiv * rB;
+      for (int base = 0; base < n_eq; base += kStage) {
+        const int cnt = min(kStage, n_eq - base);
+        if (fill + cnt > kStage) {
+          flush(fill, false);
+          fill = 0;
         }
+        for (int i = tid; i < cnt; i += blockDim.x) {
+          const int e = base + i;
+          for (int d = 0; d < 3; ++d) {
+            sp[fill + i][d] = (T)(rad * surf[3 * e + d]);
+            sd[fill + i][d] = phi_dn[(size_t)B * NC + 3 * e + d];
+          }
+        }
+        fill += cnt;
       }
       flush(fill, false);
       fill = 0;
     }
     // near field: U(B)
-    for (int li = u_off[B]; li < u_off[B + 1]; ++li) {
+    const int u_end = near_field ? u_off[B + 1] : u_off[B];
+    for (int li = u_off[B]; li < u_end; ++li) {
       const int A = u_idx[li];
       double o[3];
       box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
@@ -524,8 +568,97 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
       const int lt = t / TPL, q = t % TPL;
       for (int s2 = 0; s2 < S; ++s2)
         for (int c = 0; c < NO; ++c) acc[c] += red[s2 * ntp + lt][q * NO + c];
+      if (far_field)  // W(B) slots in list order
+        for (int k = w_off[B]; k < w_off[B + 1]; ++k)
+          for (int c = 0; c < NO; ++c) acc[c] += wslot[wslot_off[k] + (int64_t)(tc + t) * NO + c];
       int o = perm_trg[t0 + tc + t];
-      for (int c = 0; c < NO; ++c) out[(size_t)o * NO + c] = acc[c];
+      if (accumulate)
+        for (int c = 0; c < NO; ++c) out[(size_t)o * NO + c] += acc[c];
+      else
+        for (int c = 0; c < NO; ++c) out[(size_t)o * NO + c] = acc[c];
+    }
+    __syncthreads();
+  }
+}
+
+// M2T over the W lists, one workgroup per pair (B, A): A's upward equivalent surface evaluated at the
+// targets of leaf B, stored in the pair's slot (nt(B) x NO, prefactors applied).  One pair per workgroup
+// keeps the work even: a leaf next to a finely refined region can have tens of W boxes.
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) void k_w_eval(const int* __restrict__ pair_b, const int* __restrict__ pair_a,
+                                                const int64_t* __restrict__ slot_off, TreeView tv,
+                                                const T* __restrict__ tpos4, const T* __restrict__ phi_up,
+                                                const double* __restrict__ surf, int n_eq, double r_up_equiv, int NC,
+                                                KConst<T> kc, double* __restrict__ wslot) {
+  constexpr int NO = KIND == 0 ? 3 : 6;
+  constexpr int TPL = 2;
+  __shared__ T sp[kStage][4];
+  __shared__ T sd[kStage][4];
+  __shared__ double red[256][TPL * NO];
+  const int B = pair_b[blockIdx.x], A = pair_a[blockIdx.x];
+  const int tid = threadIdx.x;
+  double o[3];
+  box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
+  const double rad = r_up_equiv * box_half(tv.level, tv.geom, tv.root_R, A);
+  double* out = wslot + slot_off[blockIdx.x];
+  const int t0 = tv.trg_b[B], nt_all = tv.trg_e[B] - t0;
+  for (int tc = 0; tc < nt_all; tc += 256 * TPL) {
+    const int nt = min(256 * TPL, nt_all - tc);
+    const int ntp = (nt + TPL - 1) / TPL;
+    const int S = 256 / ntp;
+    const int tp = tid % ntp, sl = tid / ntp;
+    const bool act = sl < S;
+    T x[TPL][3];
+    bool valid[TPL];
+    for (int q = 0; q < TPL; ++q) {
+      const int t = TPL * tp + q;
+      valid[q] = t < nt;
+      const int64_t g = t0 + tc + (valid[q] ? t : 0);
+      for (int d = 0; d < 3; ++d) x[q][d] = tpos4[4 * g + d];
+    }
+    T aU[TPL][NO], aP[TPL][NO];
+    for (int q = 0; q < TPL; ++q)
+      for (int c = 0; c < NO; ++c) aU[q][c] = aP[q][c] = T(0);
+    for (int base = 0; base < n_eq; base += kStage) {
+      const int cnt = min(kStage, n_eq - base);
+      __syncthreads();
+      for (int i = tid; i < cnt; i += blockDim.x) {
+        const int e = base + i;
+        for (int d = 0; d < 3; ++d) {
+          sp[i][d] = (T)(o[d] + rad * surf[3 * e + d]);
+          sd[i][d] = phi_up[(size_t)A * NC + 3 * e + d];
+        }
+      }
+      __syncthreads();
+      if (act)
+        for (int j = sl; j < cnt; j += S) {
+          const T px = sp[j][0], py = sp[j][1], pz = sp[j][2];
+#pragma unroll
+          for (int q = 0; q < TPL; ++q) {
+            if (!valid[q]) continue;
+            T dx = px - x[q][0], dy = py - x[q][1], dz = pz - x[q][2];
+            T r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == T(0)) continue;
+            if (KIND == 0)
+              disp_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
+            else
+              stress_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
+          }
+        }
+    }
+    for (int q = 0; q < TPL; ++q)
+      for (int c = 0; c < NO; ++c) {
+        double v = KIND == 0 ? (double)kc.cU * (double)aU[q][c] : (double)kc.cD * (double)aU[q][c];
+        red[tid][q * NO + c] = act ? v : 0.0;
+      }
+    __syncthreads();
+    for (int t = tid; t < nt; t += blockDim.x) {
+      double acc[NO];
+      for (int c = 0; c < NO; ++c) acc[c] = 0;
+      const int lt = t / TPL, q = t % TPL;
+      for (int s2 = 0; s2 < S; ++s2)
+        for (int c = 0; c < NO; ++c) acc[c] += red[s2 * ntp + lt][q * NO + c];
+      for (int c = 0; c < NO; ++c) out[(int64_t)(tc + t) * NO + c] = acc[c];
     }
     __syncthreads();
   }
@@ -663,9 +796,10 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     for (int b : leaves_src) c.add(0, b, b, half(b));
     P->job_uc2ue = upload_job(P->arena, c, s, wide(c));
   }
-  // M2M per level (deepest first): children with sources, grouped by octant; parents reduce
+  // M2M per level (deepest first): children with sources, grouped by octant; parents reduce.  Parents
+  // at levels 0 and 1 are skipped: V and W lists only hold boxes of level >= 2.
   P->up_levels.clear();
-  for (int l = t.depth; l >= 1; --l) {
+  for (int l = t.depth; l >= 3; --l) {
     GemmCols c;
     std::vector<int> parents;
     for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
@@ -762,6 +896,24 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       P->dn_levels.push_back(upload_job(P->arena, sorted_by_op(cl), s, wide(cl)));
     }
   }
+  // W pairs and their output slots
+  {
+    std::vector<int> pb, pa;
+    std::vector<int64_t> off;
+    int64_t tot = 0;
+    for (int b = 0; b < nb; ++b)
+      for (int k = t.h_w_off[b]; k < t.h_w_off[b + 1]; ++k) {
+        pb.push_back(b);
+        pa.push_back(t.h_w_idx[k]);
+        off.push_back(tot);
+        tot += (int64_t)(t.h_trg_e[b] - t.h_trg_b[b]) * 6;
+      }
+    P->n_wp = (int)pb.size();
+    P->wp_b = upload_vec(P->arena, pb, s);
+    P->wp_a = upload_vec(P->arena, pa, s);
+    P->wslot_off = upload_vec(P->arena, off, s);
+    P->wslot = P->arena.get<double>(std::max<int64_t>(tot, 1));
+  }
   // ---- counters
   int64_t up = 0;
   for (int b : leaves_trg)
@@ -790,6 +942,9 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->phi_dn_lo = zalloc(nbc * 4);
     if (o.precision == KFMM_FP32_M2L_BF16) P->phi_up_bf = zalloc(nbc * 2);
   }
+  KFMM_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
+  KFMM_HIP(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+  KFMM_HIP(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
   KFMM_HIP(hipStreamSynchronize(s));
   P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return P.release();
@@ -816,6 +971,57 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   const T* snrm = (const T*)P.snrm;
   const T* dens = (const T*)P.dens;
   const bool far = nb > 1;
+  const T* phi_dn = P.prec == KFMM_FP64 ? (const T*)P.phi_dn : (const T*)P.phi_dn_lo;
+  const T* phi_up = P.prec == KFMM_FP64 ? (const T*)P.phi_up : (const T*)P.phi_up_lo;
+  // leaf evaluation: parts = 1 far field, 2 near field, 3 both
+  auto leaf_eval = [&](int parts, int accumulate, hipStream_t st) {
+    auto launch = [&](auto kd, auto sl, auto dl) {
+      constexpr int KIND = decltype(kd)::value;
+      constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
+      hipLaunchKernelGGL((k_leaf_eval<T, KIND, SL, DL>), dim3(P.n_leaves_trg), dim3(256), 0, st, P.leaves_trg, P.tv,
+                         t.u_off, t.u_idx, t.w_off, P.wslot_off, P.wslot, spos, snrm, dens, (const T*)P.tpos,
+                         t.perm_trg, phi_dn, phi_up, D.surf, n_eq, 1.05, 2.95, NC, parts & 1, (parts >> 1) & 1,
+                         accumulate, kc, out);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    if (kind == KFMM_DISP) {
+      if (SLa && DLa)
+        launch(I0(), std::true_type(), std::true_type());
+      else if (SLa)
+        launch(I0(), std::true_type(), std::false_type());
+      else
+        launch(I0(), std::false_type(), std::true_type());
+    } else {
+      if (SLa && DLa)
+        launch(I1(), std::true_type(), std::true_type());
+      else if (SLa)
+        launch(I1(), std::true_type(), std::false_type());
+      else
+        launch(I1(), std::false_type(), std::true_type());
+    }
+    KFMM_HIP(hipGetLastError());
+  };
+  auto w_eval = [&](hipStream_t st) {
+    if (!P.n_wp) return;
+    if (kind == KFMM_DISP)
+      hipLaunchKernelGGL((k_w_eval<T, 0>), dim3(P.n_wp), dim3(256), 0, st, P.wp_b, P.wp_a, P.wslot_off, P.tv,
+                         (const T*)P.tpos, phi_up, D.surf, n_eq, 1.05, NC, kc, P.wslot);
+    else
+      hipLaunchKernelGGL((k_w_eval<T, 1>), dim3(P.n_wp), dim3(256), 0, st, P.wp_b, P.wp_a, P.wslot_off, P.tv,
+                         (const T*)P.tpos, phi_up, D.surf, n_eq, 1.05, NC, kc, P.wslot);
+    KFMM_HIP(hipGetLastError());
+  };
+  // The near field only needs the densities: without profiling it runs on the plan's second stream
+  // while the far-field passes (many small, latency-bound launches) run here, and is joined before the
+  // far-field leaf evaluation adds to its output.
+  const bool overlap = far && !P.prof;
+  if (overlap) {
+    KFMM_HIP(hipEventRecord(P.fork_ev, s));
+    KFMM_HIP(hipStreamWaitEvent(P.near_stream, P.fork_ev, 0));
+    leaf_eval(2, 0, P.near_stream);
+    KFMM_HIP(hipEventRecord(P.join_ev, P.near_stream));
+  }
   // one thread per check point (n_eq <= 1024 for p <= 12)
   const int check_block = std::max(64, round_up(n_eq, 64));
   mark(KFMM_PH_S2M);
@@ -840,22 +1046,23 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     for (const UpLevel& U : P.up_levels) {
       gemm_f64(U.job, D.m2m, GemmDims::Sq(NC), P.phi_up, P.tmp, kStore, s);
       if (U.n_par)
-        hipLaunchKernelGGL(k_m2m_reduce, dim3(U.n_par), dim3(256), 0, s, U.parents, U.n_par, t.child_first,
-                           t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
+        hipLaunchKernelGGL(k_m2m_reduce<double>, dim3(U.n_par), dim3(reduce_block<double>(NC)), 0, s, U.parents,
+                           U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
     }
     KFMM_HIP(hipGetLastError());
     // M2L into qhat
     mark(KFMM_PH_M2L_PREP);
-    // qhat is FP64 in every precision: the atomic scatter of the M2L then perturbs it only at FP64
-    // rounding, so repeated products of one operator agree to ~1e-16 (GMRES sees a fixed operator).
+    // qhat is FP64 here in every precision; each box's M2L slots are summed in a fixed order, so repeated
+    // products of one operator are bitwise identical (GMRES sees a fixed operator).
     double* qhat = P.q_up;  // reuse: S2M potentials are consumed
     KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 8, s));
     if (P.prec == KFMM_FP64) {
       mark(KFMM_PH_M2L);
       gemm_f64(P.job_m2l, D.m2l64, GemmDims::Sq(NC), P.phi_up, (double*)P.m2l_slots, kStore, s);
+      mark(KFMM_PH_M2L_RED);
       if (P.m2l_red_n)
-        hipLaunchKernelGGL(k_slot_reduce<double>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
-                           P.m2l_red_idx, (const double*)P.m2l_slots, qhat, NC);
+        hipLaunchKernelGGL((k_slot_reduce<double, double>), dim3(P.m2l_red_n), dim3(reduce_block<double>(NC)), 0, s,
+                           P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const double*)P.m2l_slots, qhat, NC);
     } else {
       hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                          (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
@@ -867,8 +1074,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
         gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
         mark(KFMM_PH_M2L_RED);
         if (P.m2l_red_n)
-          hipLaunchKernelGGL(k_slot_reduce<float>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
-                             P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
+          hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
+                             P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
         gemm_f64(P.job_uexp, C.U64, GemmDims{NC, NCr, NCr, NC}, P.q_t, qhat, kStore, s);
       } else if (P.prec == KFMM_FP32) {
         mark(KFMM_PH_M2L);
@@ -882,19 +1089,18 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       if (!P.comp) {
         mark(KFMM_PH_M2L_RED);
         if (P.m2l_red_n)
-          hipLaunchKernelGGL(k_slot_reduce<float>, dim3(P.m2l_red_n), dim3(256), 0, s, P.m2l_red_box, P.m2l_red_off,
-                             P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
+          hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NC)), 0, s,
+                             P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
       }
     }
     KFMM_HIP(hipGetLastError());
     mark(KFMM_PH_S2L);
     // X list
     if (P.n_x_boxes) {
-      using TQ = double;
       auto s2l = [&](auto sl, auto dl) {
         constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
-        hipLaunchKernelGGL((k_check_eval<T, TQ, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, s, P.x_boxes, P.tv,
-                           t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, (TQ*)qhat);
+        hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, s,
+                           P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, qhat);
       };
       if (SLa && DLa)
         s2l(std::true_type(), std::true_type());
@@ -916,34 +1122,23 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   if (!far) {  // no far field: empty intermediate phases
     for (int ph = KFMM_PH_UC2UE; ph <= KFMM_PH_DOWN; ++ph) mark(ph);
   }
-  mark(KFMM_PH_LEAF);
-  const T* phi_dn = P.prec == KFMM_FP64 ? (const T*)P.phi_dn : (const T*)P.phi_dn_lo;
-  const T* phi_up = P.prec == KFMM_FP64 ? (const T*)P.phi_up : (const T*)P.phi_up_lo;
-  auto leaf = [&](auto kd, auto sl, auto dl) {
-    constexpr int KIND = decltype(kd)::value;
-    constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
-    hipLaunchKernelGGL((k_leaf_eval<T, KIND, SL, DL>), dim3(P.n_leaves_trg), dim3(256), 0, s, P.leaves_trg, P.tv,
-                       t.u_off, t.u_idx, t.w_off, t.w_idx, spos, snrm, dens, (const T*)P.tpos, t.perm_trg, phi_dn,
-                       phi_up, D.surf, n_eq, 1.05, 2.95, NC, far ? 1 : 0, kc, out);
-  };
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  if (kind == KFMM_DISP) {
-    if (SLa && DLa)
-      leaf(I0(), std::true_type(), std::true_type());
-    else if (SLa)
-      leaf(I0(), std::true_type(), std::false_type());
-    else
-      leaf(I0(), std::false_type(), std::true_type());
+  if (overlap) {
+    mark(KFMM_PH_NEAR);
+    mark(KFMM_PH_LEAF);
+    w_eval(s);
+    KFMM_HIP(hipStreamWaitEvent(s, P.join_ev, 0));
+    leaf_eval(1, 1, s);
+  } else if (far) {
+    mark(KFMM_PH_NEAR);
+    leaf_eval(2, 0, s);
+    mark(KFMM_PH_LEAF);
+    w_eval(s);
+    leaf_eval(1, 1, s);
   } else {
-    if (SLa && DLa)
-      leaf(I1(), std::true_type(), std::true_type());
-    else if (SLa)
-      leaf(I1(), std::true_type(), std::false_type());
-    else
-      leaf(I1(), std::false_type(), std::true_type());
+    mark(KFMM_PH_NEAR);
+    leaf_eval(2, 0, s);
+    mark(KFMM_PH_LEAF);
   }
-  KFMM_HIP(hipGetLastError());
   mark(KFMM_N_PHASES);
   if (P.prof) {
     KFMM_HIP(hipEventSynchronize(P.ev[KFMM_N_PHASES]));
@@ -959,6 +1154,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
 Plan::~Plan() {
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  if (fork_ev) (void)hipEventDestroy(fork_ev);
+  if (join_ev) (void)hipEventDestroy(join_ev);
+  if (near_stream) (void)hipStreamDestroy(near_stream);
 }
 
 int plan_m2l_rank(const Plan& P) { return P.comp ? P.comp->r : 0; }

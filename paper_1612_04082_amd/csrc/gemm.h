@@ -50,9 +50,15 @@ struct GemmDims {
   static GemmDims Sq(int NC) { return GemmDims{NC, NC, NC, NC}; }
 };
 
-void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, double* Y, int mode, hipStream_t s);
-void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, float* Y, int mode, hipStream_t s);
-void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, double* Y, int mode, hipStream_t s);
+// kernel: kGemmAuto picks the tiled kernel, or the split-K kernel for launches too small to fill the
+// chip; the other values force one of them (test hook).
+enum GemmKernel { kGemmAuto = 0, kGemmTiled = 1, kGemmSplitK = 2 };
+void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, double* Y, int mode, hipStream_t s,
+              int kernel = kGemmAuto);
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, float* Y, int mode, hipStream_t s,
+              int kernel = kGemmAuto);
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, double* Y, int mode, hipStream_t s,
+              int kernel = kGemmAuto);
 void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, float* Y, int mode,
                hipStream_t s);
 void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, double* Y, int mode,
@@ -60,6 +66,6 @@ void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __
 
 // Runs one gather/scatter GEMM launch from host column descriptors (test hook).
 void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,
-                   const int* out, const double* scale, int ncols, int mode, hipStream_t s);
+                   const int* out, const double* scale, int ncols, int mode, int kernel, hipStream_t s);
 
 }  // namespace kfmm

@@ -134,6 +134,110 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
   }
 }
 
+// Split-K variant for launches with few columns (the upper levels of the M2M / L2L passes), where the
+// tiled kernel above cannot fill the chip.  A workgroup computes a (16*TM) x 16 block; its four waves
+// take contiguous quarters of the K range and read A and X straight from global memory (there is no
+// reuse to stage through LDS), keeping PD chunks of loads in flight; the four partial blocks are summed
+// in LDS in wave order, so results do not depend on scheduling.  Each lane loads 32 bytes of a row of A
+// (a full 128-byte line per row across the four lane groups) and of a column of X, and feeds them to
+// consecutive MFMA k-steps: lane group g = l/16 holds k-indices k0 + VA*g + q (q = 0..VA-1), and since
+// A and X use the same assignment the products still pair A[i][k] with X[k][j].
+// Grid: x = tile * SUB + 16-column sub-block, y = row block of 16*TM rows.
+template <typename T, typename TY, int TM>
+__global__ __launch_bounds__(256) void k_gemm_sk(const T* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
+                                                 int sub_per_tile, const int* __restrict__ in_idx,
+                                                 const int* __restrict__ out_idx, const double* __restrict__ scale,
+                                                 const T* __restrict__ X, TY* __restrict__ Y, int mode) {
+  constexpr int BM = 16 * TM, PD = 2;
+  constexpr int VH = 16 / sizeof(T);  // values per 16-byte load
+  constexpr int VA = 2 * VH;          // values per lane and row per chunk (two loads)
+  constexpr int KC = 4 * VA;          // k-values per chunk (4 lane groups)
+  typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type vec_t;
+  typedef typename std::conditional<sizeof(T) == 8, double4_t, float4_t>::type acc_t;
+  struct Chunk {
+    vec_t a[TM][2], b[2];
+  };
+  __shared__ T red[4][BM][17];
+  const int4 tile = tiles[blockIdx.x / sub_per_tile];
+  const int c0 = (blockIdx.x % sub_per_tile) * 16;
+  if (c0 >= tile.z) return;  // whole workgroup: uniform exit before any barrier
+  const int ncols = min(16, tile.z - c0);
+  const int r0 = blockIdx.y * BM;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const T* Aop = A + (size_t)tile.x * dm.M * dm.K;
+  const bool col_ok = i < ncols;
+  const T* xcol = X + (size_t)(col_ok ? in_idx[tile.y + c0 + i] : 0) * dm.ldx;
+  // this wave's chunks
+  const int nch = dm.K / KC;
+  const int ch0 = wave * nch / 4, ch1 = (wave + 1) * nch / 4;
+  acc_t acc[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  Chunk buf[PD];
+  auto load = [&](Chunk& c, int ch) {
+    const int k = ch * KC + VA * g;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const vec_t* p = (const vec_t*)(Aop + (size_t)(r0 + 16 * t + i) * dm.K + k);
+      c.a[t][0] = p[0];
+      c.a[t][1] = p[1];
+    }
+    if (col_ok) {
+      c.b[0] = ((const vec_t*)(xcol + k))[0];
+      c.b[1] = ((const vec_t*)(xcol + k))[1];
+    } else {
+      c.b[0] = vec_t{};
+      c.b[1] = vec_t{};
+    }
+  };
+  auto compute = [&](const Chunk& c) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < VH; ++q) {
+        const T bq = ((const T*)&c.b[h])[q];
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          const T aq = ((const T*)&c.a[t][h])[q];
+          if constexpr (sizeof(T) == 8)
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq, bq, acc[t], 0, 0, 0);
+          else
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq, bq, acc[t], 0, 0, 0);
+        }
+      }
+  };
+  // ring of PD chunks in flight; chunk ch lives in buf[(ch - ch0) % PD]
+#pragma unroll
+  for (int d = 0; d < PD; ++d)
+    if (ch0 + d < ch1) load(buf[d], ch0 + d);
+  for (int ch = ch0; ch < ch1; ch += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      if (ch + d < ch1) {
+        compute(buf[d]);
+        if (ch + d + PD < ch1) load(buf[d], ch + d + PD);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = sizeof(T) == 8 ? t * 16 + g + 4 * v : t * 16 + 4 * g + v;
+      red[wave][row][i] = acc[t][v];
+    }
+  __syncthreads();
+  for (int e = tid; e < BM * 16; e += 256) {
+    const int row = e % BM, c = e / BM;
+    if (c >= ncols) continue;
+    const T sum = ((red[0][row][c] + red[1][row][c]) + red[2][row][c]) + red[3][row][c];
+    const int col = tile.y + c0 + c;
+    const TY sc = scale ? (TY)scale[col] : TY(1);
+    store_out(Y + (size_t)out_idx[col] * dm.ldy + r0 + row, sc * (TY)sum, mode);
+  }
+}
+
 // BF16 inputs, FP32 accumulation: BK = 32 per LDS stage, one MFMA k-step.
 template <typename TY>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
@@ -209,36 +313,57 @@ static void check_dims(const GemmDims& d) {
   if (d.M % kGemmBM != 0 || d.K % 32 != 0) throw Error(-1, "gemm: M must be a multiple of 96 and K of 32");
 }
 
-void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, double* Y, int mode, hipStream_t s) {
+// A tiled workgroup runs its whole K loop alone (one per compute unit in small launches), so a launch of
+// fewer than ~160 of them is bound by that latency; the split-K kernel cuts it into more, shorter
+// workgroups.  Crossover measured on translation-pass shapes (NC = 960, 1 or 8 operators, FP64/FP32).
+static bool use_split_k(const GemmJob& job, const GemmDims& d, int kernel) {
+  if (kernel != kGemmAuto) return kernel == kGemmSplitK;
+  return (int64_t)job.n_tiles * (d.M / kGemmBM) < 160;
+}
+
+template <typename T, typename TY>
+static void launch_split_k(const GemmJob& job, const T* A, GemmDims d, const T* X, TY* Y, int mode, hipStream_t s) {
+  constexpr int TM = 3;  // 48-row blocks: M (a multiple of 96) splits evenly
+  const int sub = job.cols_per_tile / 16;
+  hipLaunchKernelGGL((k_gemm_sk<T, TY, TM>), dim3(job.n_tiles * sub, d.M / (16 * TM)), dim3(256), 0, s, A, d,
+                     job.tiles, sub, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+}
+
+// LDS-tiled launch: 64- or 128-column tiles (TN = 1, 2), BK k-values per LDS stage.
+template <typename T, typename TY, int BK>
+static void launch_tiled(const GemmJob& job, const T* A, GemmDims d, const T* X, TY* Y, int mode, hipStream_t s) {
+  if (job.cols_per_tile > kGemmBN)
+    hipLaunchKernelGGL((k_gemm_f<T, TY, 2, BK>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d, job.tiles,
+                       job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  else
+    hipLaunchKernelGGL((k_gemm_f<T, TY, 1, BK>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d, job.tiles,
+                       job.in_idx, job.out_idx, job.scale, X, Y, mode);
+}
+
+template <typename T, typename TY>
+static void gemm_t(const GemmJob& job, const T* A, GemmDims d, const T* X, TY* Y, int mode, hipStream_t s,
+                   int kernel) {
   if (job.n_tiles == 0) return;
   check_dims(d);
-  if (job.cols_per_tile > kGemmBN)
-    hipLaunchKernelGGL((k_gemm_f<double, double, 2, 16>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  constexpr int BK = sizeof(T) == 8 ? 16 : 32;
+  if (use_split_k(job, d, kernel))
+    launch_split_k(job, A, d, X, Y, mode, s);
   else
-    hipLaunchKernelGGL((k_gemm_f<double, double, 1, 16>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+    launch_tiled<T, TY, BK>(job, A, d, X, Y, mode, s);
   KFMM_HIP(hipGetLastError());
 }
 
-template <typename TY>
-static void gemm_f32_t(const GemmJob& job, const float* A, GemmDims d, const float* X, TY* Y, int mode,
-                       hipStream_t s) {
-  if (job.n_tiles == 0) return;
-  check_dims(d);
-  if (job.cols_per_tile > kGemmBN)
-    hipLaunchKernelGGL((k_gemm_f<float, TY, 2, 32>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
-  else
-    hipLaunchKernelGGL((k_gemm_f<float, TY, 1, 32>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, A, d,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, X, Y, mode);
-  KFMM_HIP(hipGetLastError());
+void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, double* Y, int mode, hipStream_t s,
+              int kernel) {
+  gemm_t(job, A, d, X, Y, mode, s, kernel);
 }
-void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, float* Y, int mode, hipStream_t s) {
-  gemm_f32_t(job, A, d, X, Y, mode, s);
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, float* Y, int mode, hipStream_t s,
+              int kernel) {
+  gemm_t(job, A, d, X, Y, mode, s, kernel);
 }
-void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, double* Y, int mode, hipStream_t s) {
-  gemm_f32_t(job, A, d, X, Y, mode, s);
+void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, double* Y, int mode, hipStream_t s,
+              int kernel) {
+  gemm_t(job, A, d, X, Y, mode, s, kernel);
 }
 
 template <typename TY>
@@ -264,7 +389,7 @@ void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __
 // ------------------------------------------------------------------ test hook (see kfmm_selftest_gemm)
 namespace kfmm {
 void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,
-                   const int* out, const double* scale, int ncols, int mode, hipStream_t s) {
+                   const int* out, const double* scale, int ncols, int mode, int kernel, hipStream_t s) {
   Arena a;
   std::vector<int4> tiles;
   // FP32 runs the wide tiles used by the M2L; FP64 runs wide tiles when op == 0 only (as in large launches)
@@ -290,9 +415,9 @@ void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y,
   if (scale) KFMM_HIP(hipMemcpyAsync(job.scale, scale, ncols * sizeof(double), hipMemcpyHostToDevice, s));
   const GemmDims d = GemmDims::Sq(NC);
   if (precision == 0)
-    gemm_f64(job, (const double*)A, d, (const double*)X, (double*)Y, mode, s);
+    gemm_f64(job, (const double*)A, d, (const double*)X, (double*)Y, mode, s, kernel);
   else if (precision == 1)
-    gemm_f32(job, (const float*)A, d, (const float*)X, (float*)Y, mode, s);
+    gemm_f32(job, (const float*)A, d, (const float*)X, (float*)Y, mode, s, kernel);
   else
     gemm_bf16(job, (const __hip_bfloat16*)A, d, (const __hip_bfloat16*)X, (float*)Y, mode, s);
   KFMM_HIP(hipStreamSynchronize(s));

@@ -58,6 +58,14 @@ struct Plan {
   // per-box coefficient buffers (n_box x NC)
   double *q_up = nullptr, *phi_up = nullptr, *phi_dn = nullptr, *tmp = nullptr;
   void *phi_up_lo = nullptr, *phi_dn_lo = nullptr, *phi_up_bf = nullptr;
+  // W pairs (CSR order of the W lists): one output slot of nt(B) x 6 doubles each
+  int n_wp = 0;
+  int *wp_b = nullptr, *wp_a = nullptr;
+  int64_t* wslot_off = nullptr;
+  double* wslot = nullptr;
+  // near field on a second stream, joined before the far-field leaf evaluation
+  hipStream_t near_stream = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // optional phase timing with HIP events (see fmm_profile)
   bool prof = false;
   hipEvent_t ev[KFMM_N_PHASES + 1] = {};

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libkfmm.so")
 
 DISP, STRESS = 0, 1
 FP64, FP32, FP32_M2L_BF16 = 0, 1, 2
-PHASES = ("permute", "s2m", "uc2ue", "m2m", "m2l_prep", "m2l", "m2l_red", "s2l", "down", "leaf")
+PHASES = ("permute", "s2m", "uc2ue", "m2m", "m2l_prep", "m2l", "m2l_red", "s2l", "down", "near", "leaf")
 _STATUS = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_HIP", -4: "E_NOCONV", -5: "E_STATE"}
 
 
@@ -204,15 +204,15 @@ class FmmPlan:
             pass
 
 
-def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0):
-    """Test hook around kfmm_selftest_gemm (see include/kfmm.h)."""
+def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0, kernel=0):
+    """Test hook around kfmm_selftest_gemm (see include/kfmm.h); kernel 1 = tiled, 2 = split-K."""
     import numpy as np
     L = load_library()
     n = len(op)
     ia = lambda v: (ctypes.c_int * max(n, 1))(*[int(x) for x in v])
     sc = None if scale is None else (ctypes.c_double * max(n, 1))(*[float(x) for x in scale])
     NC = int(A.shape[-1])
-    check(L.kfmm_selftest_gemm(precision, ctypes.c_void_p(A.data_ptr()), NC, ctypes.c_void_p(X.data_ptr()),
+    check(L.kfmm_selftest_gemm(precision + 16 * kernel, ctypes.c_void_p(A.data_ptr()), NC, ctypes.c_void_p(X.data_ptr()),
                                ctypes.c_void_p(Y.data_ptr()), ia(op), ia(cols_in), ia(cols_out), sc, n, mode,
                                _stream()))
 

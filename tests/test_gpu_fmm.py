@@ -8,6 +8,7 @@
 """
 import numpy as np
 import pytest
+import torch
 
 from oracle import direct as od
 from tests.fmm_cases import rel_l2, run_fmm, run_oracle
@@ -105,3 +106,4 @@ def test_compressed_m2l(cuda, tol, slack):
     print(f"m2l_tol {tol:.0e}: rank {rank} of 888, compressed err {e_c:.2e}, dense err {e_d:.2e}")
     assert 0 < rank < 888
     assert e_c <= slack * e_d + 1e-7 and e_c < 5e-5
+

@@ -11,7 +11,7 @@ import torch
 pytestmark = pytest.mark.gpu
 
 
-def _case(precision, mode, seed=0, n_ops=3):
+def _case(precision, mode, seed=0, n_ops=3, kernel=0):
     from paper_1612_04082_amd import kfmm
     rng = np.random.default_rng(seed)
     NC, n_box, ncols = 192, 90, 150
@@ -33,7 +33,7 @@ def _case(precision, mode, seed=0, n_ops=3):
     At = torch.tensor(A).to(tdt).cuda()
     Xt = torch.tensor(X).to(tdt).cuda()
     Yt = torch.tensor(Y0).to(ydt).cuda()
-    kfmm.selftest_gemm(precision, At, Xt, Yt, op, cin, cout, scale, mode)
+    kfmm.selftest_gemm(precision, At, Xt, Yt, op, cin, cout, scale, mode, kernel)
     # reference from the rounded inputs
     Ar = At.double().cpu().numpy()
     Xr = Xt.double().cpu().numpy()
@@ -56,8 +56,19 @@ def test_gemm_matches_reference(cuda, precision, tol, mode):
     assert err < tol
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_gemm_kernels(cuda, precision, tol, mode, kernel):
+    """Both FP64/FP32 kernels (LDS-tiled and split-K) forced on the same launches."""
+    err = _case(precision, mode, seed=7, kernel=kernel)
+    print(f"precision={precision} mode={mode} kernel={kernel} rel err {err:.3e}")
+    assert err < tol
+
+
 @pytest.mark.parametrize("mode", [0, 2])
-def test_gemm_single_operator_wide_tiles(cuda, mode):
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_gemm_single_operator_wide_tiles(cuda, mode, kernel):
     """One operator for every column: the FP64 launch then uses the 128-column tiles."""
-    err = _case(0, mode, seed=3, n_ops=1)
+    err = _case(0, mode, seed=3, n_ops=1, kernel=kernel)
     assert err < 1e-13
