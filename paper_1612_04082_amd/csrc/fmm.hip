@@ -212,6 +212,18 @@ __global__ void k_convert<double, __hip_bfloat16>(int64_t n, const double* in, _
   if (i < n) out[i] = __float2bfloat16((float)in[i]);
 }
 
+__global__ void k_fill_zero(int64_t n, double* p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// dst(boxes[i]) += src(i): the X-list check potentials (compact rows) added to qhat
+__global__ __launch_bounds__(256) void k_add_rows(const int* __restrict__ boxes, const double* __restrict__ src,
+                                                  double* __restrict__ dst, int NC) {
+  const int i = blockIdx.x, B = boxes[i];
+  for (int c = threadIdx.x; c < NC; c += blockDim.x) dst[(size_t)B * NC + c] += src[(size_t)i * NC + c];
+}
+
 // Sums of NC-vectors in a fixed order (FP64 accumulation), 16 bytes per lane and per load, four loads in
 // flight.  NC is a multiple of 32.
 template <typename TS>
@@ -364,8 +376,9 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
 constexpr int kStage = 256;  // points staged in LDS per round
 
 // Evaluate the sources of a list of leaves at the check surface of box B (displacement, U and/or P).
-//   S2M: B's own sources at its upward check surface (radius r_up_check), written to q (FP64).
-//   S2L: sources of X(B) at B's downward check surface (radius r_dn_check), r_B * value added to qhat.
+//   S2M: B's own sources at its upward check surface (radius r_up_check), written to row B of q.
+//   S2L: sources of X(B) at B's downward check surface (radius r_dn_check), r_B * value written to row
+//        blockIdx.x of a compact buffer (added to qhat afterwards).
 template <typename T, typename TQ, bool SL, bool DL, bool S2M>
 __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ boxes, TreeView tv,
                                                     const int* __restrict__ list_off,
@@ -426,7 +439,7 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
       if (S2M)
         out[(size_t)B * NC + 3 * tid + d] = (TQ)v;
       else
-        out[(size_t)B * NC + 3 * tid + d] += (TQ)(rB * v);
+        out[(size_t)blockIdx.x * NC + 3 * tid + d] = (TQ)(rB * v);
     }
   }
 }
@@ -942,15 +955,28 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->phi_dn_lo = zalloc(nbc * 4);
     if (o.precision == KFMM_FP32_M2L_BF16) P->phi_up_bf = zalloc(nbc * 2);
   }
+  P->qx = (double*)zalloc(std::max<size_t>(1, (size_t)P->n_x_boxes * NC) * 8);  // padding rows stay zero
   KFMM_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
-  KFMM_HIP(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
-  KFMM_HIP(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
+  for (hipEvent_t* e : {&P->fork_ev, &P->phi_ev, &P->x_ev, &P->join_ev})
+    KFMM_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   KFMM_HIP(hipStreamSynchronize(s));
   P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return P.release();
 }
 
 // ------------------------------------------------------------------------------------------ eval
+
+// Sums the phase times of a profiled evaluation (events recorded on the evaluation stream).
+static void finish_profile(Plan& P) {
+  if (!P.prof) return;
+  KFMM_HIP(hipEventSynchronize(P.ev[KFMM_N_PHASES]));
+  for (int ph = 0; ph < KFMM_N_PHASES; ++ph) {
+    float ms = 0;
+    KFMM_HIP(hipEventElapsedTime(&ms, P.ev[ph], P.ev[ph + 1]));
+    P.phase_ms[ph] += ms;
+  }
+  P.prof_calls++;
+}
 
 template <typename T>
 static void eval_t(Plan& P, int kind, const double* a, const double* b, double* out, hipStream_t s) {
@@ -963,44 +989,69 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   auto mark = [&](int i) {
     if (P.prof) KFMM_HIP(hipEventRecord(P.ev[i], s));
   };
+  // Launches with the single/double-layer variant chosen by which densities are given.
+  auto dispatch = [&](auto&& launch) {
+    if (SLa && DLa)
+      launch(std::true_type(), std::true_type());
+    else if (SLa)
+      launch(std::true_type(), std::false_type());
+    else
+      launch(std::false_type(), std::true_type());
+    KFMM_HIP(hipGetLastError());
+  };
   mark(KFMM_PH_PERMUTE);
-  // densities
   hipLaunchKernelGGL(k_permute_in<T>, dim3((unsigned)((P.n_src + 255) / 256)), dim3(256), 0, s, P.n_src,
                      t.perm_src, P.sw, a, b, (T*)P.dens);
+  KFMM_HIP(hipGetLastError());
   const T* spos = (const T*)P.spos;
   const T* snrm = (const T*)P.snrm;
   const T* dens = (const T*)P.dens;
   const bool far = nb > 1;
   const T* phi_dn = P.prec == KFMM_FP64 ? (const T*)P.phi_dn : (const T*)P.phi_dn_lo;
   const T* phi_up = P.prec == KFMM_FP64 ? (const T*)P.phi_up : (const T*)P.phi_up_lo;
-  // leaf evaluation: parts = 1 far field, 2 near field, 3 both
-  auto leaf_eval = [&](int parts, int accumulate, hipStream_t st) {
+  // leaf evaluation: parts = 1 far field (L2T + W slots, added to out), 2 near field (U lists, stored)
+  auto leaf_eval = [&](int parts, hipStream_t st) {
     auto launch = [&](auto kd, auto sl, auto dl) {
       constexpr int KIND = decltype(kd)::value;
       constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
       hipLaunchKernelGGL((k_leaf_eval<T, KIND, SL, DL>), dim3(P.n_leaves_trg), dim3(256), 0, st, P.leaves_trg, P.tv,
                          t.u_off, t.u_idx, t.w_off, P.wslot_off, P.wslot, spos, snrm, dens, (const T*)P.tpos,
                          t.perm_trg, phi_dn, phi_up, D.surf, n_eq, 1.05, 2.95, NC, parts & 1, (parts >> 1) & 1,
-                         accumulate, kc, out);
+                         parts & 1, kc, out);
     };
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    if (kind == KFMM_DISP) {
-      if (SLa && DLa)
-        launch(I0(), std::true_type(), std::true_type());
-      else if (SLa)
-        launch(I0(), std::true_type(), std::false_type());
-      else
-        launch(I0(), std::false_type(), std::true_type());
-    } else {
-      if (SLa && DLa)
-        launch(I1(), std::true_type(), std::true_type());
-      else if (SLa)
-        launch(I1(), std::true_type(), std::false_type());
-      else
-        launch(I1(), std::false_type(), std::true_type());
-    }
-    KFMM_HIP(hipGetLastError());
+    if (kind == KFMM_DISP)
+      dispatch([&](auto sl, auto dl) { launch(std::integral_constant<int, 0>(), sl, dl); });
+    else
+      dispatch([&](auto sl, auto dl) { launch(std::integral_constant<int, 1>(), sl, dl); });
+  };
+  mark(KFMM_PH_S2M);
+  if (!far) {  // one box: near field only
+    for (int ph = KFMM_PH_UC2UE; ph <= KFMM_PH_NEAR; ++ph) mark(ph);
+    leaf_eval(2, s);
+    mark(KFMM_PH_LEAF);
+    mark(KFMM_N_PHASES);
+    finish_profile(P);
+    return;
+  }
+  // Work that needs no translation result (near field, X lists) and the W lists run, unprofiled, on the
+  // plan's second stream: the near field and the X lists from the end of UC2UE, overlapping the
+  // latency-bound M2M levels; the W lists once phi_up is ready.  Profiled calls run everything here in
+  // phase order.
+  const bool overlap = !P.prof;
+  hipStream_t side = overlap ? P.near_stream : s;
+  auto fork = [&](hipEvent_t e) {
+    if (!overlap) return;
+    KFMM_HIP(hipEventRecord(e, s));
+    KFMM_HIP(hipStreamWaitEvent(side, e, 0));
+  };
+  const int check_block = std::max(64, round_up(n_eq, 64));  // one thread per check point
+  auto s2l = [&](hipStream_t st) {  // X lists -> compact rows of qx
+    if (!P.n_x_boxes) return;
+    dispatch([&](auto sl, auto dl) {
+      constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
+      hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, st,
+                         P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, P.qx);
+    });
   };
   auto w_eval = [&](hipStream_t st) {
     if (!P.n_wp) return;
@@ -1012,150 +1063,115 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
                          (const T*)P.tpos, phi_up, D.surf, n_eq, 1.05, NC, kc, P.wslot);
     KFMM_HIP(hipGetLastError());
   };
-  // The near field only needs the densities: without profiling it runs on the plan's second stream
-  // while the far-field passes (many small, latency-bound launches) run here, and is joined before the
-  // far-field leaf evaluation adds to its output.
-  const bool overlap = far && !P.prof;
+  // S2M, UC2UE
+  dispatch([&](auto sl, auto dl) {
+    constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
+    hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
+                       P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
+                       2.95, NC, kc, P.q_up);
+  });
+  mark(KFMM_PH_UC2UE);
+  gemm_f64(P.job_uc2ue, D.uc2ue, GemmDims::Sq(NC), P.q_up, P.phi_up, kStore, s);
+  fork(P.fork_ev);
   if (overlap) {
-    KFMM_HIP(hipEventRecord(P.fork_ev, s));
-    KFMM_HIP(hipStreamWaitEvent(P.near_stream, P.fork_ev, 0));
-    leaf_eval(2, 0, P.near_stream);
-    KFMM_HIP(hipEventRecord(P.join_ev, P.near_stream));
+    leaf_eval(2, side);
+    s2l(side);
+    KFMM_HIP(hipEventRecord(P.x_ev, side));
   }
-  // one thread per check point (n_eq <= 1024 for p <= 12)
-  const int check_block = std::max(64, round_up(n_eq, 64));
-  mark(KFMM_PH_S2M);
-  if (far) {
-    // S2M
-    auto s2m = [&](auto sl, auto dl) {
-      constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
-      hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
-                         P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
-                         2.95, NC, kc, P.q_up);
-    };
-    if (SLa && DLa)
-      s2m(std::true_type(), std::true_type());
-    else if (SLa)
-      s2m(std::true_type(), std::false_type());
-    else
-      s2m(std::false_type(), std::true_type());
-    KFMM_HIP(hipGetLastError());
-    mark(KFMM_PH_UC2UE);
-    gemm_f64(P.job_uc2ue, D.uc2ue, GemmDims::Sq(NC), P.q_up, P.phi_up, kStore, s);
-    mark(KFMM_PH_M2M);
-    for (const UpLevel& U : P.up_levels) {
-      gemm_f64(U.job, D.m2m, GemmDims::Sq(NC), P.phi_up, P.tmp, kStore, s);
-      if (U.n_par)
-        hipLaunchKernelGGL(k_m2m_reduce<double>, dim3(U.n_par), dim3(reduce_block<double>(NC)), 0, s, U.parents,
-                           U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
-    }
-    KFMM_HIP(hipGetLastError());
-    // M2L into qhat
-    mark(KFMM_PH_M2L_PREP);
-    // qhat is FP64 here in every precision; each box's M2L slots are summed in a fixed order, so repeated
-    // products of one operator are bitwise identical (GMRES sees a fixed operator).
-    double* qhat = P.q_up;  // reuse: S2M potentials are consumed
-    KFMM_HIP(hipMemsetAsync(qhat, 0, nbc * 8, s));
-    if (P.prec == KFMM_FP64) {
-      mark(KFMM_PH_M2L);
-      gemm_f64(P.job_m2l, D.m2l64, GemmDims::Sq(NC), P.phi_up, (double*)P.m2l_slots, kStore, s);
-      mark(KFMM_PH_M2L_RED);
-      if (P.m2l_red_n)
-        hipLaunchKernelGGL((k_slot_reduce<double, double>), dim3(P.m2l_red_n), dim3(reduce_block<double>(NC)), 0, s,
-                           P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const double*)P.m2l_slots, qhat, NC);
-    } else {
-      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
-                         (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
-      if (P.prec == KFMM_FP32 && P.comp) {
-        const CompressedM2L& C = *P.comp;
-        const int NCr = C.NCr;
-        gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
-        mark(KFMM_PH_M2L);
-        gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
-        mark(KFMM_PH_M2L_RED);
-        if (P.m2l_red_n)
-          hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
-                             P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
-        gemm_f64(P.job_uexp, C.U64, GemmDims{NC, NCr, NCr, NC}, P.q_t, qhat, kStore, s);
-      } else if (P.prec == KFMM_FP32) {
-        mark(KFMM_PH_M2L);
-        gemm_f32(P.job_m2l, D.m2l32, GemmDims::Sq(NC), (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);
-      } else {
-        hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
-                           (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
-        mark(KFMM_PH_M2L);
-        gemm_bf16(P.job_m2l, D.m2l16, GemmDims::Sq(NC), (const __hip_bfloat16*)P.phi_up_bf, (float*)P.m2l_slots, kStore, s);
-      }
-      if (!P.comp) {
-        mark(KFMM_PH_M2L_RED);
-        if (P.m2l_red_n)
-          hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NC)), 0, s,
-                             P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
-      }
-    }
-    KFMM_HIP(hipGetLastError());
-    mark(KFMM_PH_S2L);
-    // X list
-    if (P.n_x_boxes) {
-      auto s2l = [&](auto sl, auto dl) {
-        constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
-        hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, s,
-                           P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, qhat);
-      };
-      if (SLa && DLa)
-        s2l(std::true_type(), std::true_type());
-      else if (SLa)
-        s2l(std::true_type(), std::false_type());
-      else
-        s2l(std::false_type(), std::true_type());
-      KFMM_HIP(hipGetLastError());
-    }
-    // downward pass in FP64
-    mark(KFMM_PH_DOWN);
-    gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
-    for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, GemmDims::Sq(NC), P.phi_dn, P.phi_dn, kAdd, s);
-    if (P.prec != KFMM_FP64)
-      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
-                         (int64_t)nbc, P.phi_dn, (float*)P.phi_dn_lo);
-    KFMM_HIP(hipGetLastError());
+  // M2M
+  mark(KFMM_PH_M2M);
+  for (const UpLevel& U : P.up_levels) {
+    gemm_f64(U.job, D.m2m, GemmDims::Sq(NC), P.phi_up, P.tmp, kStore, s);
+    if (U.n_par)
+      hipLaunchKernelGGL(k_m2m_reduce<double>, dim3(U.n_par), dim3(reduce_block<double>(NC)), 0, s, U.parents,
+                         U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
   }
-  if (!far) {  // no far field: empty intermediate phases
-    for (int ph = KFMM_PH_UC2UE; ph <= KFMM_PH_DOWN; ++ph) mark(ph);
-  }
+  KFMM_HIP(hipGetLastError());
+  // M2L into qhat.  qhat is FP64 in every precision; each box's M2L slots are summed in a fixed order,
+  // so repeated products of one operator are bitwise identical (GMRES sees a fixed operator).
+  mark(KFMM_PH_M2L_PREP);
+  double* qhat = P.q_up;  // reuse: the S2M potentials are consumed
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc, qhat);
+  if (P.prec != KFMM_FP64)
+    hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                       (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
+  KFMM_HIP(hipGetLastError());
+  fork(P.phi_ev);  // phi_up ready in the evaluation precision
   if (overlap) {
-    mark(KFMM_PH_NEAR);
-    mark(KFMM_PH_LEAF);
-    w_eval(s);
-    KFMM_HIP(hipStreamWaitEvent(s, P.join_ev, 0));
-    leaf_eval(1, 1, s);
-  } else if (far) {
-    mark(KFMM_PH_NEAR);
-    leaf_eval(2, 0, s);
-    mark(KFMM_PH_LEAF);
-    w_eval(s);
-    leaf_eval(1, 1, s);
+    w_eval(side);
+    KFMM_HIP(hipEventRecord(P.join_ev, side));
+  }
+  if (P.prec == KFMM_FP64) {
+    mark(KFMM_PH_M2L);
+    gemm_f64(P.job_m2l, D.m2l64, GemmDims::Sq(NC), P.phi_up, (double*)P.m2l_slots, kStore, s);
+    mark(KFMM_PH_M2L_RED);
+    if (P.m2l_red_n)
+      hipLaunchKernelGGL((k_slot_reduce<double, double>), dim3(P.m2l_red_n), dim3(reduce_block<double>(NC)), 0, s,
+                         P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const double*)P.m2l_slots, qhat, NC);
+  } else if (P.prec == KFMM_FP32 && P.comp) {
+    const CompressedM2L& C = *P.comp;
+    const int NCr = C.NCr;
+    gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
+    mark(KFMM_PH_M2L);
+    gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
+    mark(KFMM_PH_M2L_RED);
+    if (P.m2l_red_n)
+      hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
+                         P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
+    gemm_f64(P.job_uexp, C.U64, GemmDims{NC, NCr, NCr, NC}, P.q_t, qhat, kStore, s);
   } else {
-    mark(KFMM_PH_NEAR);
-    leaf_eval(2, 0, s);
-    mark(KFMM_PH_LEAF);
-  }
-  mark(KFMM_N_PHASES);
-  if (P.prof) {
-    KFMM_HIP(hipEventSynchronize(P.ev[KFMM_N_PHASES]));
-    for (int ph = 0; ph < KFMM_N_PHASES; ++ph) {
-      float ms = 0;
-      KFMM_HIP(hipEventElapsedTime(&ms, P.ev[ph], P.ev[ph + 1]));
-      P.phase_ms[ph] += ms;
+    if (P.prec == KFMM_FP32) {
+      mark(KFMM_PH_M2L);
+      gemm_f32(P.job_m2l, D.m2l32, GemmDims::Sq(NC), (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);
+    } else {
+      hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                         (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
+      mark(KFMM_PH_M2L);
+      gemm_bf16(P.job_m2l, D.m2l16, GemmDims::Sq(NC), (const __hip_bfloat16*)P.phi_up_bf, (float*)P.m2l_slots, kStore,
+                s);
     }
-    P.prof_calls++;
+    mark(KFMM_PH_M2L_RED);
+    if (P.m2l_red_n)
+      hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NC)), 0, s,
+                         P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
   }
+  KFMM_HIP(hipGetLastError());
+  // X lists, added to qhat
+  mark(KFMM_PH_S2L);
+  if (overlap)
+    KFMM_HIP(hipStreamWaitEvent(s, P.x_ev, 0));
+  else
+    s2l(s);
+  if (P.n_x_boxes)
+    hipLaunchKernelGGL(k_add_rows, dim3(P.n_x_boxes), dim3(reduce_block<double>(NC)), 0, s, P.x_boxes,
+                       (const double*)P.qx, qhat, NC);
+  KFMM_HIP(hipGetLastError());
+  // downward pass in FP64
+  mark(KFMM_PH_DOWN);
+  gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
+  for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, GemmDims::Sq(NC), P.phi_dn, P.phi_dn, kAdd, s);
+  if (P.prec != KFMM_FP64)
+    hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                       (int64_t)nbc, P.phi_dn, (float*)P.phi_dn_lo);
+  KFMM_HIP(hipGetLastError());
+  // leaves: near field (already on the side stream when overlapping), W lists, L2T
+  mark(KFMM_PH_NEAR);
+  if (!overlap) leaf_eval(2, s);
+  mark(KFMM_PH_LEAF);
+  if (overlap)
+    KFMM_HIP(hipStreamWaitEvent(s, P.join_ev, 0));
+  else
+    w_eval(s);
+  leaf_eval(1, s);
+  mark(KFMM_N_PHASES);
+  finish_profile(P);
 }
 
 Plan::~Plan() {
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
-  if (fork_ev) (void)hipEventDestroy(fork_ev);
-  if (join_ev) (void)hipEventDestroy(join_ev);
+  for (hipEvent_t e : {fork_ev, phi_ev, x_ev, join_ev})
+    if (e) (void)hipEventDestroy(e);
   if (near_stream) (void)hipStreamDestroy(near_stream);
 }
 
@@ -1175,7 +1191,9 @@ void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out,
   const int no = kind == KFMM_DISP ? 3 : 6;
   if (P.n_trg == 0) return;
   if (P.empty || (!a && !b)) {
-    KFMM_HIP(hipMemsetAsync(out, 0, sizeof(double) * no * P.n_trg, s));
+    const int64_t n = (int64_t)no * P.n_trg;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, out);
+    KFMM_HIP(hipGetLastError());
     return;
   }
   if (P.prec == KFMM_FP64)

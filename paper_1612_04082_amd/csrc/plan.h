@@ -63,9 +63,11 @@ struct Plan {
   int *wp_b = nullptr, *wp_a = nullptr;
   int64_t* wslot_off = nullptr;
   double* wslot = nullptr;
-  // near field on a second stream, joined before the far-field leaf evaluation
+  // X-list check potentials, one compact row per box of x_boxes
+  double* qx = nullptr;
+  // second stream (near field, X and W lists) and its fork / join events
   hipStream_t near_stream = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, phi_ev = nullptr, x_ev = nullptr, join_ev = nullptr;
   // optional phase timing with HIP events (see fmm_profile)
   bool prof = false;
   hipEvent_t ev[KFMM_N_PHASES + 1] = {};
