@@ -43,10 +43,23 @@ def main():
     ap.add_argument("--p-bem", type=int, default=6, help="expansion order of the BEM solves in the warmstart workload")
     ap.add_argument("--workload", choices=["beam", "sphere", "cells", "cantilever", "warmstart"], default="beam",
                     help="beam: the headline line; the others measure the remaining configurations")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only copy one device buffer of this many MiB into another (a plain copy kernel of known "
+                         "traffic, to scale the HBM byte counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy_mib > 0:
+        import torch
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": n * 4, "calib_copy_bytes_written": n * 4}))
+        return
     if args.workload != "beam":
         import bench_configs
         bench_configs.run(args)

@@ -2,6 +2,9 @@
 
 Every HIP source is compiled with packed FP32 instructions disabled
 (-Xclang -target-feature -Xclang -packed-fp32-ops); the compiler still vectorises ordinary code.
+HIP sources also select the VGPR form of the MFMA instructions (-amdgpu-mfma-vgpr-form): with the
+accumulators in AGPRs the compiler copied every accumulator out of and back into AGPRs around each
+LDS stage of the GEMM loops (two copies per accumulator register per stage, plus a pipeline drain).
 """
 import concurrent.futures
 import os
@@ -25,9 +28,13 @@ def _hipcc():
             return c
 
 
+HIP_ONLY = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+
+
 def _compile(src):
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [_hipcc()] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    extra = HIP_ONLY if src.endswith(".hip") else []
+    cmd = [_hipcc()] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")

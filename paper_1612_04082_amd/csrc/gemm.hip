@@ -15,6 +15,17 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
+// The dispatcher hands workgroups to the 8 XCDs round-robin by linear id (x fastest).  Remapped so that
+// each XCD receives a contiguous range of logical ids: with the row block fastest in the logical order,
+// the workgroups of one column tile (same operator, same X columns) share one XCD's L2, and so do the
+// consecutive tiles of one operator.
+__device__ __forceinline__ int xcd_logical_id() {
+  const int n = gridDim.x * gridDim.y;
+  const int id = blockIdx.x + blockIdx.y * gridDim.x;
+  const int q = n >> 3, r = n & 7, x = id & 7;
+  return x * q + min(x, r) + (id >> 3);
+}
+
 template <typename T>
 __device__ __forceinline__ void store_out(T* p, T v, int mode) {
   if (mode == kStore)
@@ -26,8 +37,9 @@ __device__ __forceinline__ void store_out(T* p, T v, int mode) {
 }
 
 // FP64 / FP32 variant.  Workgroup tile (16*TM) x (64*TN): wave w owns columns [16*TN*w, 16*TN*(w+1))
-// and all rows; the K dimension advances BK per LDS stage (register-prefetched, one stage in flight).
-// Outputs of type TY (FP32 products may be accumulated into FP64).
+// and all rows; the K dimension advances BK per stage.  Two LDS buffers: stage k+1 is written from
+// registers while stage k is multiplied, and stage k+2 is loaded from global memory meanwhile, so one
+// barrier per stage suffices.  Outputs of type TY (FP32 products may be accumulated into FP64).
 template <typename T, typename TY, int TN, int BK>
 __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
                                                 const int* __restrict__ in_idx, const int* __restrict__ out_idx,
@@ -40,10 +52,11 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
   constexpr int B_ELEMS = BK / B_THR_PER_COL;
   static_assert(BM * BK % (VA * 256) == 0, "A tile must split into 16-byte loads");
   static_assert(B_ELEMS % VA == 0, "B tile must split into 16-byte loads");
-  __shared__ T As[BM][BK + 1];
-  __shared__ T Bs[BK][BN + 1];
-  const int4 tile = tiles[blockIdx.x];
-  const int r0 = blockIdx.y * BM;
+  __shared__ T As[2][BM][BK + 1];
+  __shared__ T Bs[2][BK][BN + 1];
+  const int lid = xcd_logical_id();
+  const int4 tile = tiles[lid / gridDim.y];
+  const int r0 = (lid % gridDim.y) * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T* Aop = A + (size_t)tile.x * dm.M * dm.K;
   typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type vec_t;
@@ -66,20 +79,20 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
         rb[e] = vec_t{};
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < A_VEC; ++e) {
       int lin = tid + 256 * e;
       int row = lin / (BK / VA), kv = lin % (BK / VA);
       const T* v = (const T*)&ra[e];
 #pragma unroll
-      for (int q = 0; q < VA; ++q) As[row][kv * VA + q] = v[q];
+      for (int q = 0; q < VA; ++q) As[buf][row][kv * VA + q] = v[q];
     }
 #pragma unroll
     for (int e = 0; e < B_ELEMS / VA; ++e) {
       const T* v = (const T*)&rb[e];
 #pragma unroll
-      for (int q = 0; q < VA; ++q) Bs[bq * B_ELEMS + e * VA + q][bc] = v[q];
+      for (int q = 0; q < VA; ++q) Bs[buf][bq * B_ELEMS + e * VA + q][bc] = v[q];
     }
   };
   typedef typename std::conditional<sizeof(T) == 8, double4_t, float4_t>::type acc_t;
@@ -90,18 +103,22 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
     for (int u = 0; u < TN; ++u) acc[t][u] = acc_t{0, 0, 0, 0};
   const int nk = dm.K / BK;
   load(0);
-  stash();
+  stash(0);
+  if (nk > 1) load(BK);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) load((kt + 1) * BK);
+    const int cur = kt & 1;
+    // buffer cur ^ 1 was last read in iteration kt - 1, which every wave has left (barrier below)
+    if (kt + 1 < nk) stash(cur ^ 1);
+    if (kt + 2 < nk) load((kt + 2) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       T b[TN];
 #pragma unroll
-      for (int u = 0; u < TN; ++u) b[u] = Bs[ks * 4 + (lane >> 4)][(wave * TN + u) * 16 + (lane & 15)];
+      for (int u = 0; u < TN; ++u) b[u] = Bs[cur][ks * 4 + (lane >> 4)][(wave * TN + u) * 16 + (lane & 15)];
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        T a = As[t * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+        T a = As[cur][t * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
 #pragma unroll
         for (int u = 0; u < TN; ++u) {
           if constexpr (sizeof(T) == 8)
@@ -112,10 +129,6 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
       }
     }
     __syncthreads();
-    if (kt + 1 < nk) {
-      stash();
-      __syncthreads();
-    }
   }
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
@@ -142,7 +155,7 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
 // (a full 128-byte line per row across the four lane groups) and of a column of X, and feeds them to
 // consecutive MFMA k-steps: lane group g = l/16 holds k-indices k0 + VA*g + q (q = 0..VA-1), and since
 // A and X use the same assignment the products still pair A[i][k] with X[k][j].
-// Grid: x = tile * SUB + 16-column sub-block, y = row block of 16*TM rows.
+// Grid: x = tile * SUB + 16-column sub-block, y = row block of 16*TM rows (remapped per XCD as above).
 template <typename T, typename TY, int TM>
 __global__ __launch_bounds__(256) void k_gemm_sk(const T* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
                                                  int sub_per_tile, const int* __restrict__ in_idx,
@@ -158,11 +171,13 @@ __global__ __launch_bounds__(256) void k_gemm_sk(const T* __restrict__ A, GemmDi
     vec_t a[TM][2], b[2];
   };
   __shared__ T red[4][BM][17];
-  const int4 tile = tiles[blockIdx.x / sub_per_tile];
-  const int c0 = (blockIdx.x % sub_per_tile) * 16;
+  const int lid = xcd_logical_id();
+  const int bx = lid / gridDim.y;
+  const int4 tile = tiles[bx / sub_per_tile];
+  const int c0 = (bx % sub_per_tile) * 16;
   if (c0 >= tile.z) return;  // whole workgroup: uniform exit before any barrier
   const int ncols = min(16, tile.z - c0);
-  const int r0 = blockIdx.y * BM;
+  const int r0 = (lid % gridDim.y) * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = lane & 15, g = lane >> 4;
   const T* Aop = A + (size_t)tile.x * dm.M * dm.K;
@@ -247,8 +262,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
   constexpr int BK = 32, BM = kGemmBM, BN = kGemmBN, TM = kGemmTM, PAD = 8;
   __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][BK + PAD];
-  const int4 tile = tiles[blockIdx.x];
-  const int r0 = blockIdx.y * BM;
+  const int lid = xcd_logical_id();
+  const int4 tile = tiles[lid / gridDim.y];
+  const int r0 = (lid % gridDim.y) * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const __bf16* Aop = A + (size_t)tile.x * dm.M * dm.K;
   // A tile: BM rows x 32 bf16 = BM*4 chunks of 8 (16 bytes); B tile: 64 columns x 4 chunks
@@ -313,12 +329,13 @@ static void check_dims(const GemmDims& d) {
   if (d.M % kGemmBM != 0 || d.K % 32 != 0) throw Error(-1, "gemm: M must be a multiple of 96 and K of 32");
 }
 
-// A tiled workgroup runs its whole K loop alone (one per compute unit in small launches), so a launch of
-// fewer than ~160 of them is bound by that latency; the split-K kernel cuts it into more, shorter
-// workgroups.  Crossover measured on translation-pass shapes (NC = 960, 1 or 8 operators, FP64/FP32).
+// A tiled workgroup runs its whole K loop alone (one per compute unit in small launches), so small
+// launches are bound by that latency; the split-K kernel cuts them into more, shorter workgroups.  The
+// crossover, measured on translation-pass shapes (NC = 960, 1 or 8 operators, FP64 with 64-column and
+// FP32 with 128-column tiles), sits near 20k tile columns x row blocks.
 static bool use_split_k(const GemmJob& job, const GemmDims& d, int kernel) {
   if (kernel != kGemmAuto) return kernel == kGemmSplitK;
-  return (int64_t)job.n_tiles * (d.M / kGemmBM) < 160;
+  return (int64_t)job.n_tiles * job.cols_per_tile * (d.M / kGemmBM) < 20480;
 }
 
 template <typename T, typename TY>
