@@ -118,7 +118,10 @@ int fmm_plan_info(kfmm_plan_t plan, fmm_info* info /* host */);
  * phases on the caller's stream and wait for them at the end of the call (so profiled calls are
  * synchronous); fmm_profile(plan, 0) stops it.  Unprofiled calls run the near field on a second
  * stream of the plan, concurrently with the far-field passes; profiled calls run every phase in turn
- * on the caller's stream.  fmm_phase_times writes, for each phase, the summed
+ * on the caller's stream.  fmm_profile(plan, 2) times only the M2L contraction launch, with a pair of
+ * events around it and no other change to the call (no synchronisation, same streams); its summed
+ * milliseconds are reported in the KFMM_PH_M2L entry of fmm_phase_times (which then waits for the
+ * recorded events), every other entry 0.  fmm_phase_times writes, for each phase, the summed
  * milliseconds over the profiled calls (host array of KFMM_N_PHASES doubles) and their number.
  * Enabling resets the sums.
  */
@@ -273,7 +276,8 @@ int ws_load(ws_net_t net, const char* path);
  * X and Y hold NC-vectors (stride NC).  op, in, out, scale (scale may be NULL) are HOST arrays of ncols
  * entries with op non-decreasing; NC must be a multiple of 96.  Synchronises the stream.
  * precision + 16 * k selects the FP64 / FP32 kernel: k = 0 as the library chooses, 1 the LDS-tiled
- * kernel, 2 the split-K kernel used for launches with few columns.
+ * kernel, 2 the split-K kernel used for launches with few columns, 3 / 4 the LDS-tiled kernel with one /
+ * two LDS buffers.
  */
 int kfmm_selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,
                        const int* out, const double* scale, int ncols, int mode, void* stream);

@@ -2,9 +2,10 @@
 
 Every HIP source is compiled with packed FP32 instructions disabled
 (-Xclang -target-feature -Xclang -packed-fp32-ops); the compiler still vectorises ordinary code.
-HIP sources also select the VGPR form of the MFMA instructions (-amdgpu-mfma-vgpr-form): with the
-accumulators in AGPRs the compiler copied every accumulator out of and back into AGPRs around each
-LDS stage of the GEMM loops (two copies per accumulator register per stage, plus a pipeline drain).
+gemm.hip (the FP64 translation GEMMs) selects the VGPR form of the MFMA instructions
+(-amdgpu-mfma-vgpr-form): with the accumulators in AGPRs the compiler copied every accumulator out of and
+back into AGPRs around each LDS stage of those loops.  The FP32 M2L kernel (gemm_f32.hip) keeps the
+default form, which measured faster for it.
 """
 import concurrent.futures
 import os
@@ -17,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkfmm.so")
 ARCH = os.environ.get("KFMM_ARCH", "gfx950")
 
-SOURCES = ["tree.hip", "gemm.hip", "fmm.hip", "bem.hip", "learn.hip", "operators.cpp", "capi.cpp"]
+SOURCES = ["tree.hip", "gemm.hip", "gemm_f32.hip", "fmm.hip", "bem.hip", "learn.hip", "operators.cpp", "capi.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 
@@ -28,12 +29,12 @@ def _hipcc():
             return c
 
 
-HIP_ONLY = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
+EXTRA = {"gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, src + ".o")
-    extra = HIP_ONLY if src.endswith(".hip") else []
+    extra = EXTRA.get(src, [])
     cmd = [_hipcc()] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

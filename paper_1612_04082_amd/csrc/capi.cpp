@@ -118,13 +118,15 @@ extern "C" int fmm_plan_info(kfmm_plan_t plan, fmm_info* info) {
 extern "C" int fmm_profile(kfmm_plan_t plan, int enable) {
   return guarded([&] {
     KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr, "plan is NULL");
-    plan_profile(*plan->impl, enable != 0);
+    KFMM_REQUIRE(enable >= 0 && enable <= 2, "enable must be 0, 1 or 2");
+    plan_profile(*plan->impl, enable);
   });
 }
 
 extern "C" int fmm_phase_times(kfmm_plan_t plan, double* ms, int64_t* calls) {
   return guarded([&] {
     KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr && ms != nullptr, "NULL argument");
+    if (plan->impl->light) plan_light_harvest(*plan->impl, true);
     for (int i = 0; i < KFMM_N_PHASES; ++i) ms[i] = plan->impl->phase_ms[i];
     if (calls) *calls = plan->impl->prof_calls;
   });
@@ -349,7 +351,7 @@ extern "C" int kfmm_selftest_gemm(int precision, const void* A, int NC, const vo
     const int kernel = precision >> 4;
     precision &= 15;
     KFMM_REQUIRE(precision >= 0 && precision <= 2 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
-    KFMM_REQUIRE(kernel >= 0 && kernel <= 2 && (kernel == 0 || precision <= 1), "bad kernel selector");
+    KFMM_REQUIRE(kernel >= 0 && kernel <= 4 && (kernel == 0 || precision <= 1), "bad kernel selector");
     KFMM_REQUIRE(NC > 0 && NC % kGemmBM == 0, "NC must be a positive multiple of 96");
     for (int i = 1; i < ncols; ++i) KFMM_REQUIRE(op[i] >= op[i - 1], "columns must be sorted by op");
     selftest_gemm(precision, A, NC, X, Y, op, in, out, scale, ncols, mode, kernel, (hipStream_t)stream);

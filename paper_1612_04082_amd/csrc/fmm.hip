@@ -989,6 +989,18 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   auto mark = [&](int i) {
     if (P.prof) KFMM_HIP(hipEventRecord(P.ev[i], s));
   };
+  int light_slot = -1;
+  auto m2l_begin = [&]() {
+    if (!P.light) return;
+    if (P.lev_count == Plan::kLightRing) plan_light_harvest(P, false);
+    light_slot = (P.lev_head + P.lev_count) % Plan::kLightRing;
+    KFMM_HIP(hipEventRecord(P.lev[2 * light_slot], s));
+  };
+  auto m2l_end = [&]() {
+    if (light_slot < 0) return;
+    KFMM_HIP(hipEventRecord(P.lev[2 * light_slot + 1], s));
+    P.lev_count++;
+  };
   // Launches with the single/double-layer variant chosen by which densities are given.
   auto dispatch = [&](auto&& launch) {
     if (SLa && DLa)
@@ -1103,7 +1115,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   }
   if (P.prec == KFMM_FP64) {
     mark(KFMM_PH_M2L);
+    m2l_begin();
     gemm_f64(P.job_m2l, D.m2l64, GemmDims::Sq(NC), P.phi_up, (double*)P.m2l_slots, kStore, s);
+    m2l_end();
     mark(KFMM_PH_M2L_RED);
     if (P.m2l_red_n)
       hipLaunchKernelGGL((k_slot_reduce<double, double>), dim3(P.m2l_red_n), dim3(reduce_block<double>(NC)), 0, s,
@@ -1113,7 +1127,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     const int NCr = C.NCr;
     gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
     mark(KFMM_PH_M2L);
+    m2l_begin();
     gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
+    m2l_end();
     mark(KFMM_PH_M2L_RED);
     if (P.m2l_red_n)
       hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
@@ -1122,13 +1138,17 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   } else {
     if (P.prec == KFMM_FP32) {
       mark(KFMM_PH_M2L);
+      m2l_begin();
       gemm_f32(P.job_m2l, D.m2l32, GemmDims::Sq(NC), (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);
+      m2l_end();
     } else {
       hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                          (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
       mark(KFMM_PH_M2L);
+      m2l_begin();
       gemm_bf16(P.job_m2l, D.m2l16, GemmDims::Sq(NC), (const __hip_bfloat16*)P.phi_up_bf, (float*)P.m2l_slots, kStore,
                 s);
+      m2l_end();
     }
     mark(KFMM_PH_M2L_RED);
     if (P.m2l_red_n)
@@ -1170,6 +1190,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
 Plan::~Plan() {
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : lev)
+    if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : {fork_ev, phi_ev, x_ev, join_ev})
     if (e) (void)hipEventDestroy(e);
   if (near_stream) (void)hipStreamDestroy(near_stream);
@@ -1177,13 +1199,32 @@ Plan::~Plan() {
 
 int plan_m2l_rank(const Plan& P) { return P.comp ? P.comp->r : 0; }
 
-void plan_profile(Plan& P, bool enable) {
-  if (enable && !P.ev[0])
+void plan_profile(Plan& P, int mode) {
+  if (P.light) plan_light_harvest(P, true);
+  if (mode == 1 && !P.ev[0])
     for (auto& e : P.ev) KFMM_HIP(hipEventCreate(&e));
-  P.prof = enable;
-  if (enable) {
+  if (mode == 2 && !P.lev[0])
+    for (auto& e : P.lev) KFMM_HIP(hipEventCreate(&e));
+  P.prof = mode == 1;
+  P.light = mode == 2;
+  if (mode != 0) {
     for (double& v : P.phase_ms) v = 0;
     P.prof_calls = 0;
+  }
+}
+
+// Adds the elapsed times of recorded M2L event pairs (the oldest one, or all) to the M2L phase.
+void plan_light_harvest(Plan& P, bool all) {
+  while (P.lev_count > 0) {
+    const int i = P.lev_head;
+    KFMM_HIP(hipEventSynchronize(P.lev[2 * i + 1]));
+    float ms = 0;
+    KFMM_HIP(hipEventElapsedTime(&ms, P.lev[2 * i], P.lev[2 * i + 1]));
+    P.phase_ms[KFMM_PH_M2L] += ms;
+    P.prof_calls++;
+    P.lev_head = (i + 1) % Plan::kLightRing;
+    P.lev_count--;
+    if (!all) break;
   }
 }
 

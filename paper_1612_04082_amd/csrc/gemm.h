@@ -51,8 +51,9 @@ struct GemmDims {
 };
 
 // kernel: kGemmAuto picks the tiled kernel, or the split-K kernel for launches too small to fill the
-// chip; the other values force one of them (test hook).
-enum GemmKernel { kGemmAuto = 0, kGemmTiled = 1, kGemmSplitK = 2 };
+// chip, and the tiled kernel's LDS buffering by launch size; the other values force a choice (test hook):
+// tiled with automatic buffering, split-K, tiled single-buffered, tiled double-buffered.
+enum GemmKernel { kGemmAuto = 0, kGemmTiled = 1, kGemmSplitK = 2, kGemmTiled1 = 3, kGemmTiled2 = 4 };
 void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, double* Y, int mode, hipStream_t s,
               int kernel = kGemmAuto);
 void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, float* Y, int mode, hipStream_t s,

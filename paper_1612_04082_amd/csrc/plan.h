@@ -68,8 +68,12 @@ struct Plan {
   // second stream (near field, X and W lists) and its fork / join events
   hipStream_t near_stream = nullptr;
   hipEvent_t fork_ev = nullptr, phi_ev = nullptr, x_ev = nullptr, join_ev = nullptr;
-  // optional phase timing with HIP events (see fmm_profile)
+  // optional phase timing with HIP events (see fmm_profile); light: M2L launch only, events in a ring
   bool prof = false;
+  bool light = false;
+  static constexpr int kLightRing = 64;
+  hipEvent_t lev[2 * kLightRing] = {};
+  int lev_head = 0, lev_count = 0;
   hipEvent_t ev[KFMM_N_PHASES + 1] = {};
   double phase_ms[KFMM_N_PHASES] = {};
   int64_t prof_calls = 0;
@@ -83,7 +87,8 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
                   int64_t n_trg, const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, const fmm_opts& o,
                   hipStream_t s);
 void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out, hipStream_t s);
-void plan_profile(Plan& P, bool enable);
+void plan_profile(Plan& P, int mode);
+void plan_light_harvest(Plan& P, bool all);
 int plan_m2l_rank(const Plan& P);
 
 }  // namespace kfmm

@@ -183,7 +183,9 @@ class FmmPlan:
         return {k: getattr(inf, k) for k, _ in FmmInfo._fields_}
 
     def profile(self, enable=True):
-        check(load_library().fmm_profile(self._h, 1 if enable else 0))
+        """True: time every phase (calls run in turn on one stream); "m2l": time only the M2L launch."""
+        mode = 2 if enable == "m2l" else (1 if enable else 0)
+        check(load_library().fmm_profile(self._h, mode))
 
     def phase_times(self):
         """Summed milliseconds per phase over the profiled evals, and the number of evals."""
@@ -205,7 +207,8 @@ class FmmPlan:
 
 
 def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0, kernel=0):
-    """Test hook around kfmm_selftest_gemm (see include/kfmm.h); kernel 1 = tiled, 2 = split-K."""
+    """Test hook around kfmm_selftest_gemm (see include/kfmm.h); kernel 1 = tiled, 2 = split-K,
+    3 / 4 = tiled with one / two LDS buffers."""
     import numpy as np
     L = load_library()
     n = len(op)

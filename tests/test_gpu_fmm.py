@@ -107,3 +107,26 @@ def test_compressed_m2l(cuda, tol, slack):
     assert 0 < rank < 888
     assert e_c <= slack * e_d + 1e-7 and e_c < 5e-5
 
+
+
+def test_profile_modes(cuda):
+    """Phase timing (every phase in turn) and M2L-only timing leave the results bitwise unchanged."""
+    from tests.fmm_cases import to_dev, K, G
+    from paper_1612_04082_amd import kfmm
+    c = geo.sphere_cloud(6000, seed=4)
+    plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G, p=6, leaf_max=64,
+                        precision=kfmm.FP32, m2l_tol=1e-6)
+    a, b = to_dev(c["a"]), to_dev(c["a"][::-1].copy())
+    ref = plan.eval(kfmm.DISP, a, b)
+    plan.profile(True)
+    got1 = plan.eval(kfmm.DISP, a, b)
+    ph, n1 = plan.phase_times()
+    plan.profile("m2l")
+    for _ in range(3):
+        got2 = plan.eval(kfmm.DISP, a, b)
+    m2l, n2 = plan.phase_times()
+    plan.profile(False)
+    plan.close()
+    assert torch.equal(ref, got1) and torch.equal(ref, got2)
+    assert n1 == 1 and all(v >= 0 for v in ph.values()) and ph["m2l"] > 0
+    assert n2 == 3 and m2l["m2l"] > 0 and all(v == 0 for k, v in m2l.items() if k != "m2l")

@@ -58,16 +58,16 @@ def test_gemm_matches_reference(cuda, precision, tol, mode):
 
 @pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6)])
 @pytest.mark.parametrize("mode", [0, 1, 2])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [2, 3, 4])
 def test_gemm_kernels(cuda, precision, tol, mode, kernel):
-    """Both FP64/FP32 kernels (LDS-tiled and split-K) forced on the same launches."""
+    """Every FP64/FP32 kernel (split-K, LDS-tiled with one or two buffers) forced on the same launches."""
     err = _case(precision, mode, seed=7, kernel=kernel)
     print(f"precision={precision} mode={mode} kernel={kernel} rel err {err:.3e}")
     assert err < tol
 
 
 @pytest.mark.parametrize("mode", [0, 2])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [2, 3, 4])
 def test_gemm_single_operator_wide_tiles(cuda, mode, kernel):
     """One operator for every column: the FP64 launch then uses the 128-column tiles."""
     err = _case(0, mode, seed=3, n_ops=1, kernel=kernel)
