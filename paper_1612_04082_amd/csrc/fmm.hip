@@ -46,7 +46,7 @@ struct CompressedM2L {
   double tol = 0;
   int r = 0, NCr = 0;
   double* Ut64 = nullptr;  // NCr x NC row-major (row k = k-th basis vector, rows >= r zero)
-  double* U64 = nullptr;   // NC x NCr row-major
+  double* DU64 = nullptr;  // DC2DE * U, NC x NCr row-major: downward equivalent densities from q~ directly
   float* Ut32 = nullptr;   // NCr x NC
   float* C32 = nullptr;    // 316 x NCr x NCr row-major
 };
@@ -330,16 +330,11 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
   c->r = r;
   c->NCr = round_up(r, kGemmBM);
   const int NCr = c->NCr;
-  std::vector<double> Ut((size_t)NCr * NC, 0.0), U((size_t)NC * NCr, 0.0);
+  std::vector<double> Ut((size_t)NCr * NC, 0.0);
   for (int k = 0; k < r; ++k)
-    for (int i = 0; i < n; ++i) {
-      Ut[(size_t)k * NC + i] = vecs[(size_t)k * n + i];
-      U[(size_t)i * NCr + k] = vecs[(size_t)k * n + i];
-    }
+    for (int i = 0; i < n; ++i) Ut[(size_t)k * NC + i] = vecs[(size_t)k * n + i];
   c->Ut64 = d.arena.get<double>(Ut.size());
-  c->U64 = d.arena.get<double>(U.size());
   KFMM_HIP(hipMemcpy(c->Ut64, Ut.data(), sizeof(double) * Ut.size(), hipMemcpyHostToDevice));
-  KFMM_HIP(hipMemcpy(c->U64, U.data(), sizeof(double) * U.size(), hipMemcpyHostToDevice));
   std::vector<float> Ut32(Ut.begin(), Ut.end());
   c->Ut32 = d.arena.get<float>(Ut32.size());
   KFMM_HIP(hipMemcpy(c->Ut32, Ut32.data(), sizeof(float) * Ut32.size(), hipMemcpyHostToDevice));
@@ -360,6 +355,22 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
     GemmJob j1 = upload_job(tmp, c1, s, kGemmBN), j2 = upload_job(tmp, c2, s, kGemmBN);
     gemm_f64(j1, d.m2l64, GemmDims::Sq(NC), c->Ut64, T, kStore, s);
     gemm_f64(j2, c->Ut64, GemmDims{NCr, NC, NC, NCr}, T, C64, kStore, s);
+  }
+  // DC2DE * U (columns k < r): rows k of Y = DC2DE u_k, transposed on the host
+  {
+    GemmCols cd;
+    for (int k = 0; k < r; ++k) cd.add(0, k, k);
+    GemmJob jd = upload_job(tmp, cd, s, kGemmBN);
+    double* Y = tmp.get<double>((size_t)NCr * NC);
+    KFMM_HIP(hipMemsetAsync(Y, 0, sizeof(double) * NCr * NC, s));
+    gemm_f64(jd, d.dc2de, GemmDims::Sq(NC), c->Ut64, Y, kStore, s);
+    std::vector<double> hy((size_t)NCr * NC), du((size_t)NC * NCr, 0.0);
+    KFMM_HIP(hipMemcpyAsync(hy.data(), Y, sizeof(double) * hy.size(), hipMemcpyDeviceToHost, s));
+    KFMM_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < r; ++k)
+      for (int i = 0; i < NC; ++i) du[(size_t)i * NCr + k] = hy[(size_t)k * NC + i];
+    c->DU64 = d.arena.get<double>(du.size());
+    KFMM_HIP(hipMemcpy(c->DU64, du.data(), sizeof(double) * du.size(), hipMemcpyHostToDevice));
   }
   c->C32 = d.arena.get<float>((size_t)nops * NCr * NCr);
   const int64_t nc = (int64_t)nops * NCr * NCr;
@@ -858,17 +869,18 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->m2l_red_idx = upload_vec(P->arena, idx, s);
     int slot_len = D.NC;
     if (o.precision == KFMM_FP32 && o.m2l_tol > 0) {
-      // compressed M2L: phi~ = U^T phi for every source box, r x r contractions per pair, q = U q~ per target
+      // compressed M2L: phi~ = U^T phi for every source box, r x r contractions per pair, and the downward
+      // pass starts from q~ with DC2DE * U
       P->comp = get_compressed(*P->ops, o.m2l_tol, s);
       slot_len = P->comp->NCr;
-      GemmCols cu, ce;
+      GemmCols cu;
       for (int b2 = 0; b2 < nb; ++b2)
         if (t.h_src_e[b2] > t.h_src_b[b2]) cu.add(0, b2, b2);
-      for (int b2 : boxes) ce.add(0, b2, b2);
       P->job_ut = upload_job(P->arena, cu, s, 2 * kGemmBN);
-      P->job_uexp = upload_job(P->arena, ce, s, kGemmBN);
       P->phi_t = P->arena.get<float>((size_t)nb * slot_len);
+      // rows of boxes without V lists stay zero: the downward pass applies DC2DE * U to every box
       P->q_t = P->arena.get<double>((size_t)nb * slot_len);
+      KFMM_HIP(hipMemsetAsync(P->q_t, 0, sizeof(double) * nb * slot_len, s));
     }
     P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
     P->job_m2l = upload_job(P->arena, sc, s, o.precision == KFMM_FP32 ? 2 * kGemmBN : kGemmBN);
@@ -900,6 +912,13 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     for (int b = 0; b < nb; ++b)
       if (t.h_level[b] >= 2 && ht(b)) c.add(0, b, b);
     P->job_dc2de = upload_job(P->arena, c, s, wide(c));
+    // compressed M2L: the X-list check potentials get DC2DE on their own (added after DC2DE * U q~)
+    if (P->comp) {
+      GemmCols cx;
+      for (int i = 0; i < (int)x_boxes.size(); ++i)
+        if (t.h_level[x_boxes[i]] >= 2 && ht(x_boxes[i])) cx.add(0, i, x_boxes[i]);
+      P->job_dcx = upload_job(P->arena, cx, s, wide(cx));
+    }
     P->dn_levels.clear();
     for (int l = 3; l <= t.depth; ++l) {
       GemmCols cl;
@@ -1103,7 +1122,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   // so repeated products of one operator are bitwise identical (GMRES sees a fixed operator).
   mark(KFMM_PH_M2L_PREP);
   double* qhat = P.q_up;  // reuse: the S2M potentials are consumed
-  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc, qhat);
+  const bool fused_down = P.prec == KFMM_FP32 && P.comp;  // DC2DE * U applied to q~ (no qhat)
+  if (!fused_down)
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc, qhat);
   if (P.prec != KFMM_FP64)
     hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                        (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
@@ -1134,7 +1155,6 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     if (P.m2l_red_n)
       hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
                          P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
-    gemm_f64(P.job_uexp, C.U64, GemmDims{NC, NCr, NCr, NC}, P.q_t, qhat, kStore, s);
   } else {
     if (P.prec == KFMM_FP32) {
       mark(KFMM_PH_M2L);
@@ -1162,13 +1182,19 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     KFMM_HIP(hipStreamWaitEvent(s, P.x_ev, 0));
   else
     s2l(s);
-  if (P.n_x_boxes)
+  if (P.n_x_boxes && !fused_down)
     hipLaunchKernelGGL(k_add_rows, dim3(P.n_x_boxes), dim3(reduce_block<double>(NC)), 0, s, P.x_boxes,
                        (const double*)P.qx, qhat, NC);
   KFMM_HIP(hipGetLastError());
   // downward pass in FP64
   mark(KFMM_PH_DOWN);
-  gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
+  if (fused_down) {
+    const int NCr = P.comp->NCr;
+    gemm_f64(P.job_dc2de, P.comp->DU64, GemmDims{NC, NCr, NCr, NC}, P.q_t, P.phi_dn, kStore, s);
+    gemm_f64(P.job_dcx, D.dc2de, GemmDims::Sq(NC), P.qx, P.phi_dn, kAdd, s);
+  } else {
+    gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
+  }
   for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, GemmDims::Sq(NC), P.phi_dn, P.phi_dn, kAdd, s);
   if (P.prec != KFMM_FP64)
     hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,

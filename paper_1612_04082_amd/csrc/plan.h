@@ -46,7 +46,7 @@ struct Plan {
   GemmJob job_uc2ue, job_m2l, job_dc2de;
   // compressed M2L (FP32 with opts.m2l_tol > 0)
   std::shared_ptr<CompressedM2L> comp;
-  GemmJob job_ut, job_uexp;
+  GemmJob job_ut, job_dcx;  // U^T projection of source boxes; DC2DE of the X-list rows
   float* phi_t = nullptr;   // U^T phi_up per box (n_box x NCr)
   double* q_t = nullptr;    // reduced compressed check potentials (n_box x NCr)
   // M2L: per-pair output slots (FP64 or FP32) and their fixed-order reduction per target box
