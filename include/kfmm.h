@@ -274,7 +274,7 @@ int ws_load(ws_net_t net, const char* path);
  *   Y[:, out[j]] (=, +=, atomic +=) scale[j] * A[op[j]] * X[:, in[j]]
  * precision 0: A, X, Y FP64; 1: FP32; 2: A, X bfloat16 and Y FP32.  A holds NC x NC row-major operators,
  * X and Y hold NC-vectors (stride NC).  op, in, out, scale (scale may be NULL) are HOST arrays of ncols
- * entries with op non-decreasing; NC must be a multiple of 96.  Synchronises the stream.
+ * entries with op non-decreasing; NC must be a multiple of 96 or 128.  Synchronises the stream.
  * precision + 16 * k selects the FP64 / FP32 kernel: k = 0 as the library chooses, 1 the LDS-tiled
  * kernel, 2 the split-K kernel used for launches with few columns, 3 / 4 the LDS-tiled kernel with one /
  * two LDS buffers.

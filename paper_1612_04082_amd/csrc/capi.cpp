@@ -352,7 +352,7 @@ extern "C" int kfmm_selftest_gemm(int precision, const void* A, int NC, const vo
     precision &= 15;
     KFMM_REQUIRE(precision >= 0 && precision <= 2 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
     KFMM_REQUIRE(kernel >= 0 && kernel <= 4 && (kernel == 0 || precision <= 1), "bad kernel selector");
-    KFMM_REQUIRE(NC > 0 && NC % kGemmBM == 0, "NC must be a positive multiple of 96");
+    KFMM_REQUIRE(NC > 0 && gemm_tm(NC) != 0, "NC must be a positive multiple of 96 or 128");
     for (int i = 1; i < ncols; ++i) KFMM_REQUIRE(op[i] >= op[i - 1], "columns must be sorted by op");
     selftest_gemm(precision, A, NC, X, Y, op, in, out, scale, ncols, mode, kernel, (hipStream_t)stream);
   });

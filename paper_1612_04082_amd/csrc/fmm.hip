@@ -88,7 +88,7 @@ static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, 
     d->p = p;
     d->n = op.n;
     d->n_eq = op.n_eq;
-    d->NC = round_up(op.n, kGemmBM);
+    d->NC = gemm_pad(op.n);
     d->m2l_index = op.m2l_index;
     const int NC = d->NC;
     auto up = [&](const std::vector<double>& v) {
@@ -328,7 +328,7 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
   while (r < n && lam[r] > 0 && std::sqrt(lam[r] / lam[0]) > tol) ++r;
   r = std::max(r, 1);
   c->r = r;
-  c->NCr = round_up(r, kGemmBM);
+  c->NCr = gemm_pad(r);
   const int NCr = c->NCr;
   std::vector<double> Ut((size_t)NCr * NC, 0.0);
   for (int k = 0; k < r; ++k)

@@ -17,9 +17,17 @@ namespace kfmm {
 
 enum GemmMode { kStore = 0, kAdd = 1, kAtomicAdd = 2 };
 
-constexpr int kGemmBN = 64;     // columns per tile
-constexpr int kGemmTM = 6;      // 16-row MFMA tiles per wave
-constexpr int kGemmBM = 16 * kGemmTM;  // 96 rows per workgroup; NC is a multiple of this
+constexpr int kGemmBN = 64;  // columns per tile
+
+// Rows per workgroup are 16 * TM with TM = 6 (M a multiple of 96) or TM = 8 (M a multiple of 128).
+inline int gemm_tm(int M) { return M % 96 == 0 ? 6 : (M % 128 == 0 ? 8 : 0); }
+
+// Padded length of an n-vector of coefficients: the smallest multiple of 32 that is also a multiple of
+// 96 or 128 (p = 8: 888 -> 896), else the next multiple of 96.
+inline int gemm_pad(int n) {
+  const int c = (n + 31) / 32 * 32;
+  return gemm_tm(c) ? c : (n + 95) / 96 * 96;
+}
 
 struct GemmJob {  // device arrays describing one launch
   int n_tiles = 0;
@@ -44,7 +52,7 @@ struct GemmCols {
 
 // Shape of one launch: operators are M x K row-major (leading dimension K, stride M*K between
 // operators), X vectors have K entries at stride ldx, Y vectors M entries at stride ldy.  M must be a
-// multiple of 96 and K of 32.  Sq(NC) is the square case used by the translations.
+// multiple of 96 or 128 and K of 32.  Sq(NC) is the square case used by the translations.
 struct GemmDims {
   int M, K, ldx, ldy;
   static GemmDims Sq(int NC) { return GemmDims{NC, NC, NC, NC}; }

@@ -13,8 +13,12 @@ static void gemm_bf16_t(const GemmJob& job, const __hip_bfloat16* A, GemmDims d,
                         int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
   check_dims(d);
-  hipLaunchKernelGGL((k_gemm_bf16<TY>), dim3(job.n_tiles, d.M / kGemmBM), dim3(256), 0, s, (const __bf16*)A, d,
-                     job.tiles, job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
+  if (gemm_tm(d.M) == 6)
+    hipLaunchKernelGGL((k_gemm_bf16<TY, 6>), dim3(job.n_tiles, d.M / 96), dim3(256), 0, s, (const __bf16*)A, d,
+                       job.tiles, job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16<TY, 8>), dim3(job.n_tiles, d.M / 128), dim3(256), 0, s, (const __bf16*)A, d,
+                       job.tiles, job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
   KFMM_HIP(hipGetLastError());
 }
 void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, float* Y, int mode,

@@ -44,12 +44,12 @@ __device__ __forceinline__ void store_out(T* p, T v, int mode) {
 // multiplied (one barrier per stage; for launches with about one workgroup per compute unit).  NBUF = 1:
 // half the LDS, so more workgroups fit on a compute unit (for large launches).  Outputs of type TY (FP32
 // products may be accumulated into FP64).
-template <typename T, typename TY, int TN, int BK, int NBUF>
+template <typename T, typename TY, int TN, int BK, int NBUF, int TM>
 __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
                                                 const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                 const double* __restrict__ scale, const T* __restrict__ X,
                                                 TY* __restrict__ Y, int mode) {
-  constexpr int TM = kGemmTM, BM = 16 * TM, BN = 64 * TN;
+  constexpr int BM = 16 * TM, BN = 64 * TN;
   constexpr int VA = 16 / sizeof(T);  // elements per 16-byte global load
   constexpr int A_VEC = BM * BK / VA / 256;  // vector loads per thread for the A tile
   constexpr int B_THR_PER_COL = 256 / BN;    // threads sharing one column of the X tile
@@ -274,12 +274,13 @@ __global__ __launch_bounds__(256) void k_gemm_sk(const T* __restrict__ A, GemmDi
 }
 
 // BF16 inputs, FP32 accumulation: BK = 32 per LDS stage, one MFMA k-step.
-template <typename TY>
+template <typename TY, int TM>
 __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
                                                    const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                    const double* __restrict__ scale, const __bf16* __restrict__ X,
                                                    TY* __restrict__ Y, int mode) {
-  constexpr int BK = 32, BM = kGemmBM, BN = kGemmBN, TM = kGemmTM, PAD = 8;
+  constexpr int BK = 32, BM = 16 * TM, BN = kGemmBN, PAD = 8;
+  static_assert(BM * 4 <= 512, "A tile: at most two 16-byte chunks per thread");
   __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][BK + PAD];
   const int lid = xcd_logical_id();
@@ -287,8 +288,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
   const int r0 = (lid % gridDim.y) * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const __bf16* Aop = A + (size_t)tile.x * dm.M * dm.K;
-  // A tile: BM rows x 32 bf16 = BM*4 chunks of 8 (16 bytes); B tile: 64 columns x 4 chunks
-  constexpr int A_CH = BM * BK / 8 / 256;  // 1.5 -> use 2 with guard
+  // A tile: BM rows x 32 bf16 = BM*4 chunks of 8 (16 bytes), at most 2 per thread; B tile: 64 columns x 4
+  // chunks
   const int bc = tid >> 2, bq = tid & 3;
   const int col_ok = bc < tile.z;
   const __bf16* xcol = X + (size_t)(col_ok ? in_idx[tile.y + bc] : 0) * dm.ldx;
@@ -312,7 +313,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
     }
     *(uint4*)&Bs[bc][8 * bq] = rb;
   };
-  (void)A_CH;
   float4_t acc[TM];
 #pragma unroll
   for (int t = 0; t < TM; ++t) acc[t] = float4_t{0, 0, 0, 0};
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A,
 }
 
 inline void check_dims(const GemmDims& d) {
-  if (d.M % kGemmBM != 0 || d.K % 32 != 0) throw Error(-1, "gemm: M must be a multiple of 96 and K of 32");
+  if (!gemm_tm(d.M) || d.K % 32 != 0) throw Error(-1, "gemm: M must be a multiple of 96 or 128 and K of 32");
 }
 
 // A tiled workgroup runs its whole K loop alone (one per compute unit in small launches), so small
@@ -355,39 +355,52 @@ inline void check_dims(const GemmDims& d) {
 // FP32 with 128-column tiles), sits near 20k tile columns x row blocks.
 inline bool use_split_k(const GemmJob& job, const GemmDims& d, int kernel) {
   if (kernel != kGemmAuto) return kernel == kGemmSplitK;
-  return (int64_t)job.n_tiles * job.cols_per_tile * (d.M / kGemmBM) < 20480;
+  return (int64_t)job.n_tiles * job.cols_per_tile * d.M / 96 < 20480;
 }
 
 template <typename T, typename TY>
 void launch_split_k(const GemmJob& job, const T* A, GemmDims d, const T* X, TY* Y, int mode, hipStream_t s) {
-  constexpr int TM = 3;  // 48-row blocks: M (a multiple of 96) splits evenly
   const int sub = job.cols_per_tile / 16;
-  hipLaunchKernelGGL((k_gemm_sk<T, TY, TM>), dim3(job.n_tiles * sub, d.M / (16 * TM)), dim3(256), 0, s, A, d,
-                     job.tiles, sub, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  if (d.M % 48 == 0)  // 48-row blocks
+    hipLaunchKernelGGL((k_gemm_sk<T, TY, 3>), dim3(job.n_tiles * sub, d.M / 48), dim3(256), 0, s, A, d, job.tiles,
+                       sub, job.in_idx, job.out_idx, job.scale, X, Y, mode);
+  else  // M a multiple of 128: 64-row blocks
+    hipLaunchKernelGGL((k_gemm_sk<T, TY, 4>), dim3(job.n_tiles * sub, d.M / 64), dim3(256), 0, s, A, d, job.tiles,
+                       sub, job.in_idx, job.out_idx, job.scale, X, Y, mode);
 }
 
-// LDS-tiled launch: 64- or 128-column tiles (TN = 1, 2), BK k-values per LDS stage; double-buffered
-// LDS below ~4 workgroups per compute unit, single-buffered (more resident workgroups) above.
-template <typename T, typename TY, int BK>
-void launch_tiled(const GemmJob& job, const T* A, GemmDims d, const T* X, TY* Y, int mode, hipStream_t s,
-                         int kernel) {
-  const dim3 grid(job.n_tiles, d.M / kGemmBM);
+// LDS-tiled launch: 64- or 128-column tiles (TN = 1, 2), 96- or 64-row blocks (TM = 6, 4), BK k-values
+// per LDS stage; double-buffered LDS below ~4 workgroups per compute unit, single-buffered (more resident
+// workgroups) above.
+template <typename T, typename TY, int BK, int TM>
+void launch_tiled_tm(const GemmJob& job, const T* A, GemmDims d, const T* X, TY* Y, int mode, hipStream_t s,
+                     int kernel) {
+  const dim3 grid(job.n_tiles, d.M / (16 * TM));
   const bool big = kernel == kGemmTiled1 || (kernel != kGemmTiled2 && (int64_t)grid.x * grid.y >= 1024);
   if (job.cols_per_tile > kGemmBN) {
     if (big)
-      hipLaunchKernelGGL((k_gemm_f<T, TY, 2, BK, 1>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx, job.out_idx,
-                         job.scale, X, Y, mode);
+      hipLaunchKernelGGL((k_gemm_f<T, TY, 2, BK, 1, TM>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx,
+                         job.out_idx, job.scale, X, Y, mode);
     else
-      hipLaunchKernelGGL((k_gemm_f<T, TY, 2, BK, 2>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx, job.out_idx,
-                         job.scale, X, Y, mode);
+      hipLaunchKernelGGL((k_gemm_f<T, TY, 2, BK, 2, TM>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx,
+                         job.out_idx, job.scale, X, Y, mode);
   } else {
     if (big)
-      hipLaunchKernelGGL((k_gemm_f<T, TY, 1, BK, 1>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx, job.out_idx,
-                         job.scale, X, Y, mode);
+      hipLaunchKernelGGL((k_gemm_f<T, TY, 1, BK, 1, TM>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx,
+                         job.out_idx, job.scale, X, Y, mode);
     else
-      hipLaunchKernelGGL((k_gemm_f<T, TY, 1, BK, 2>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx, job.out_idx,
-                         job.scale, X, Y, mode);
+      hipLaunchKernelGGL((k_gemm_f<T, TY, 1, BK, 2, TM>), grid, dim3(256), 0, s, A, d, job.tiles, job.in_idx,
+                         job.out_idx, job.scale, X, Y, mode);
   }
+}
+
+template <typename T, typename TY, int BK>
+void launch_tiled(const GemmJob& job, const T* A, GemmDims d, const T* X, TY* Y, int mode, hipStream_t s,
+                  int kernel) {
+  if (gemm_tm(d.M) == 6)
+    launch_tiled_tm<T, TY, BK, 6>(job, A, d, X, Y, mode, s, kernel);
+  else  // M a multiple of 128: 64-row blocks (twice the workgroups of 128-row blocks)
+    launch_tiled_tm<T, TY, BK, 4>(job, A, d, X, Y, mode, s, kernel);
 }
 
 template <typename T, typename TY>

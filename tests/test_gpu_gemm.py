@@ -11,10 +11,10 @@ import torch
 pytestmark = pytest.mark.gpu
 
 
-def _case(precision, mode, seed=0, n_ops=3, kernel=0):
+def _case(precision, mode, seed=0, n_ops=3, kernel=0, NC=192):
     from paper_1612_04082_amd import kfmm
     rng = np.random.default_rng(seed)
-    NC, n_box, ncols = 192, 90, 150
+    n_box, ncols = 90, 150
     A = rng.normal(size=(n_ops, NC, NC))
     X = rng.normal(size=(n_box, NC))
     op = np.sort(rng.integers(0, n_ops, size=ncols))
@@ -72,3 +72,15 @@ def test_gemm_single_operator_wide_tiles(cuda, mode, kernel):
     """One operator for every column: the FP64 launch then uses the 128-column tiles."""
     err = _case(0, mode, seed=3, n_ops=1, kernel=kernel)
     assert err < 1e-13
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6), (2, 2e-6)])
+@pytest.mark.parametrize("kernel", [0, 2, 3, 4])
+def test_gemm_128_row_blocks(cuda, precision, tol, kernel):
+    """NC a multiple of 128 but not of 96 (the padding of p = 8 vectors, 888 -> 896): 128-row blocks
+    in the tiled kernels, 64-row blocks in the split-K kernel."""
+    if precision == 2 and kernel:
+        pytest.skip("the BF16 kernel has no variants")
+    for mode in (0, 2):
+        err = _case(precision, mode, seed=11, kernel=kernel, NC=256)
+        assert err < tol, (mode, err)
