@@ -62,7 +62,8 @@ typedef struct {
   int max_depth;      /* deepest octree level; 0 -> 16 */
   size_t mem_limit;   /* bytes of device memory the plan may use; 0 = no limit */
   double m2l_tol;     /* KFMM_FP32 only: > 0 compresses the M2L operators onto one shared basis, keeping the
-                         singular directions above m2l_tol (relative) of sum_o K_o K_o^T's square root; 0 = dense */
+                         singular directions above m2l_tol (relative) of sum_o K_o K_o^T's square root, their
+                         count rounded up to the GEMM padding (fmm_info.m2l_rank); 0 = dense */
 } fmm_opts;
 
 typedef struct kfmm_plan* kfmm_plan_t;

@@ -327,8 +327,10 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
   int r = 0;
   while (r < n && lam[r] > 0 && std::sqrt(lam[r] / lam[0]) > tol) ++r;
   r = std::max(r, 1);
-  c->r = r;
+  // the contractions run on r padded to the GEMM granularity anyway: keep that many basis vectors
   c->NCr = gemm_pad(r);
+  r = std::min(n, c->NCr);
+  c->r = r;
   const int NCr = c->NCr;
   std::vector<double> Ut((size_t)NCr * NC, 0.0);
   for (int k = 0; k < r; ++k)
