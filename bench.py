@@ -62,7 +62,7 @@ def main():
     ap.add_argument("--rows", type=int, default=2000, help="oracle sample for the cantilever workload")
     ap.add_argument("--iters", type=int, default=20, help="Algorithm 1 iterations for the warmstart workload")
     ap.add_argument("--measure-from", type=int, default=11)
-    ap.add_argument("--p-bem", type=int, default=6, help="expansion order of the BEM solves in the warmstart workload")
+    ap.add_argument("--p-bem", type=int, default=8, help="expansion order of the BEM solves in the warmstart workload")
     ap.add_argument("--workload", choices=["beam", "sphere", "cells", "cantilever", "warmstart"], default="beam",
                     help="beam: the headline line; the others measure the remaining configurations")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
