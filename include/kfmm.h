@@ -77,7 +77,8 @@ typedef struct kfmm_plan* kfmm_plan_t;
  *   src_nrm  N x 3  unit normals at the sources, or NULL (then only single-layer densities may be used)
  *   src_w    N      source weights (area x quadrature weight), or NULL for all ones
  *   n_src    N >= 0
- *   trg_xyz  M x 3  target points, or NULL: targets are the sources themselves (M must equal N)
+ *   trg_xyz  M x 3  target points, or NULL: targets are the sources themselves (M must equal N), or no
+ *                   targets (M = 0)
  *   n_trg    M >= 0
  *   batch_src, batch_trg  (host) offsets of n_batch independent geometries, n_batch + 1 entries each,
  *            starting at 0 and ending at N (resp. M); or NULL with n_batch <= 1 for one geometry.

@@ -56,7 +56,8 @@ extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* s
     KFMM_REQUIRE(n_src >= 0 && n_trg >= 0, "negative size");
     KFMM_REQUIRE(n_src < (int64_t)1 << 31 && n_trg < (int64_t)1 << 31, "too many points (max 2^31 - 1)");
     KFMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "src_xyz is NULL");
-    if (trg_xyz == nullptr) KFMM_REQUIRE(n_trg == n_src, "aliased targets need n_trg == n_src");
+    // trg_xyz NULL: the targets are the sources (n_trg == n_src), or there are none (n_trg == 0)
+    if (trg_xyz == nullptr) KFMM_REQUIRE(n_trg == n_src || n_trg == 0, "aliased targets need n_trg == n_src");
     KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_M2L_BF16, "unknown precision");
     KFMM_REQUIRE(opts->p == 0 || (opts->p >= 3 && opts->p <= 12), "p must be in [3, 12]");
     KFMM_REQUIRE(opts->leaf_max >= 0 && opts->max_depth >= 0, "negative leaf_max or max_depth");
@@ -66,18 +67,19 @@ extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* s
     if (n_batch <= 1 || batch_src == nullptr) {
       KFMM_REQUIRE(n_batch <= 1, "batch offsets are NULL");
       bs = {0, n_src};
-      bt = {0, trg_xyz ? n_trg : n_src};
+      bt = {0, n_trg};
     } else {
       KFMM_REQUIRE(batch_trg != nullptr || trg_xyz == nullptr, "batch_trg is NULL");
       bs.assign(batch_src, batch_src + n_batch + 1);
-      bt = trg_xyz ? std::vector<int64_t>(batch_trg, batch_trg + n_batch + 1) : bs;
-      KFMM_REQUIRE(bs.front() == 0 && bs.back() == n_src && bt.front() == 0 && bt.back() == (trg_xyz ? n_trg : n_src),
+      bt = trg_xyz ? std::vector<int64_t>(batch_trg, batch_trg + n_batch + 1)
+                   : (n_trg == n_src ? bs : std::vector<int64_t>(n_batch + 1, 0));
+      KFMM_REQUIRE(bs.front() == 0 && bs.back() == n_src && bt.front() == 0 && bt.back() == n_trg,
                    "batch offsets must start at 0 and end at the point counts");
       for (int g = 0; g < n_batch; ++g)
         KFMM_REQUIRE(bs[g + 1] >= bs[g] && bt[g + 1] >= bt[g], "batch offsets must be non-decreasing");
     }
     hipStream_t s = (hipStream_t)stream;
-    Plan* p = plan_create(src_xyz, src_nrm, src_w, n_src, trg_xyz, trg_xyz ? n_trg : n_src, bs, bt, *opts, s);
+    Plan* p = plan_create(src_xyz, src_nrm, src_w, n_src, trg_xyz, n_trg, bs, bt, *opts, s);
     *out = new kfmm_plan{p};
   });
 }

@@ -748,7 +748,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   P->el = Elastic::make(o.K, o.G);
   P->prec = o.precision;
   P->n_src = n_src;
-  P->alias = trg == nullptr;
+  P->alias = trg == nullptr && n_trg == n_src;  // NULL with n_trg == 0 (and n_src > 0): no targets
   P->n_trg = P->alias ? n_src : n_trg;
   P->has_nrm = nrm != nullptr;
   P->arena.limit = o.mem_limit;

@@ -130,13 +130,17 @@ def moduli(G=1.0, nu=0.3):
     return 2.0 * G * (1.0 + nu) / (3.0 * (1.0 - 2.0 * nu))
 
 
-def _dptr(t, name, shape_last=None):
+def _dptr(t, name, shape_last=None, rows=None):
+    """Device pointer of a contiguous FP64 CUDA tensor; rows: required leading dimension (the library
+    reads exactly that many records, so a shorter array must not reach it)."""
     if t is None:
         return None
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
-    if shape_last is not None and t.shape[-1] != shape_last:
+    if shape_last is not None and (t.dim() < 2 or t.shape[-1] != shape_last):
         raise ValueError(f"{name} must have last dimension {shape_last}")
+    if rows is not None and int(t.shape[0]) != int(rows):
+        raise ValueError(f"{name} must have {rows} rows, got {int(t.shape[0])}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -164,7 +168,9 @@ class FmmPlan:
             bs = (ctypes.c_int64 * len(batch_src))(*[int(v) for v in batch_src])
             bt_list = batch_trg if batch_trg is not None else batch_src
             bt = (ctypes.c_int64 * len(bt_list))(*[int(v) for v in bt_list])
-        check(L.fmm_plan(ctypes.byref(self._h), _dptr(src, "src", 3), _dptr(nrm, "nrm", 3), _dptr(w, "w"),
+        if w is not None and (w.dim() != 1 or int(w.shape[0]) != self.n_src):
+            raise ValueError(f"w must have shape ({self.n_src},)")
+        check(L.fmm_plan(ctypes.byref(self._h), _dptr(src, "src", 3), _dptr(nrm, "nrm", 3, self.n_src), _dptr(w, "w"),
                          self.n_src, _dptr(trg, "trg", 3), self.n_trg, bs, bt, nb, ctypes.byref(self.opts),
                          _stream()))
 
@@ -173,8 +179,8 @@ class FmmPlan:
         if out is None:
             dev = self._keep[0].device
             out = torch.empty((self.n_trg, no), dtype=torch.float64, device=dev)
-        check(load_library().fmm_eval(self._h, kind, _dptr(a, "a", 3), _dptr(b, "b", 3), _dptr(out, "out", no),
-                                      _stream()))
+        check(load_library().fmm_eval(self._h, kind, _dptr(a, "a", 3, self.n_src), _dptr(b, "b", 3, self.n_src),
+                                      _dptr(out, "out", no, self.n_trg), _stream()))
         return out
 
     def info(self):
@@ -224,8 +230,10 @@ def _problem(tri, bc_type, bc_val, K, G):
     if not (bc_type.is_cuda and bc_type.dtype == torch.int8 and bc_type.is_contiguous()):
         raise TypeError("bc_type must be a contiguous int8 CUDA tensor")
     T = int(tri.shape[0])
+    if tuple(tri.shape[1:]) != (3, 3) or tuple(bc_type.shape) != (T, 3):
+        raise ValueError("tri must be (T,3,3) and bc_type (T,3)")
     return BemProblem(T, _dptr(tri, "tri").value, ctypes.c_void_p(bc_type.data_ptr()).value,
-                      _dptr(bc_val, "bc_val", 3).value, K, G)
+                      _dptr(bc_val, "bc_val", 3, T).value, K, G)
 
 
 def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_iter=2000, x0=None, p=8,
@@ -237,7 +245,7 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
     if K is None:
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G)
-    alt = _dptr(x0_alt, "x0_alt", 3)
+    alt = _dptr(x0_alt, "x0_alt", 3, int(tri.shape[0]))
     opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0),
                    alt.value if alt is not None else None)
     T = int(tri.shape[0])
@@ -245,7 +253,7 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
     u = torch.empty_like(x) if want_full else None
     t = torch.empty_like(x) if want_full else None
     st = BemStats()
-    rc = L.bem_solve(ctypes.byref(prob), ctypes.byref(opts), _dptr(x0, "x0", 3), _dptr(x, "x", 3),
+    rc = L.bem_solve(ctypes.byref(prob), ctypes.byref(opts), _dptr(x0, "x0", 3, T), _dptr(x, "x", 3),
                      _dptr(u, "u", 3), _dptr(t, "t", 3), ctypes.byref(st), _stream())
     stats = {k: getattr(st, k) for k, _ in BemStats._fields_}
     stats["start_coef"] = list(st.start_coef)
@@ -264,7 +272,8 @@ def bem_stress(tri, bc_type, bc_val, u, t, trg, K=None, G=1.0, p=8, leaf_max=128
     fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
     M = int(trg.shape[0])
     out = torch.empty((M, 6), dtype=torch.float64, device=trg.device)
-    check(L.bem_stress(ctypes.byref(prob), _dptr(u, "u", 3), _dptr(t, "t", 3), _dptr(trg, "trg", 3), M,
+    T = int(tri.shape[0])
+    check(L.bem_stress(ctypes.byref(prob), _dptr(u, "u", 3, T), _dptr(t, "t", 3, T), _dptr(trg, "trg", 3), M,
                        _dptr(out, "out", 6), ctypes.byref(fo), _stream()))
     return out
 
@@ -292,7 +301,8 @@ def bem_matvec(tri, bc_type, bc_val, x=None, which=0, K=None, G=1.0, p=8, leaf_m
     prob = _problem(tri, bc_type, bc_val, K, G)
     fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
     y = torch.empty((int(tri.shape[0]), 3), dtype=torch.float64, device=tri.device)
-    check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3), _dptr(y, "y", 3), _stream()))
+    check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3, int(tri.shape[0])),
+                       _dptr(y, "y", 3), _stream()))
     return y
 
 
@@ -335,6 +345,8 @@ class WarmStartNet:
         import numpy as np
         g = np.empty(self.num_params(), dtype=np.float32)
         loss = ctypes.c_float()
+        if int(R.shape[0]) != int(X.shape[0]):
+            raise ValueError("X and R must have the same number of rows")
         check(load_library().ws_loss_grad(self._h, _fptr(X, "X", WS_DIN), _fptr(R, "R", 3), int(X.shape[0]),
                                           ctypes.byref(loss), g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                                           _stream()))
@@ -343,13 +355,15 @@ class WarmStartNet:
     def predict(self, feat, x_mapped, scale):
         x0 = torch.empty_like(x_mapped)
         check(load_library().ws_predict(self._h, _fptr(feat, "feat", WS_DIN), int(feat.shape[0]),
-                                        _dptr(x_mapped, "x_mapped", 3), float(scale), _dptr(x0, "x0", 3), _stream()))
+                                        _dptr(x_mapped, "x_mapped", 3, int(feat.shape[0])), float(scale),
+                                        _dptr(x0, "x0", 3), _stream()))
         return x0
 
     def train(self, feat, x_mapped, x_target, scale, epochs=50, lr=1e-3):
         loss = ctypes.c_float()
-        check(load_library().ws_train(self._h, _fptr(feat, "feat", WS_DIN), _dptr(x_mapped, "x_mapped", 3),
-                                      _dptr(x_target, "x_target", 3), int(feat.shape[0]), float(scale), int(epochs),
+        n = int(feat.shape[0])
+        check(load_library().ws_train(self._h, _fptr(feat, "feat", WS_DIN), _dptr(x_mapped, "x_mapped", 3, n),
+                                      _dptr(x_target, "x_target", 3, n), n, float(scale), int(epochs),
                                       float(lr), ctypes.byref(loss), _stream()))
         return loss.value
 
@@ -382,7 +396,8 @@ def ws_features(prev, u_prev, t_prev, nxt):
     feat = torch.empty((T, WS_DIN), dtype=torch.float32, device=dev)
     xm = torch.empty((T, 3), dtype=torch.float64, device=dev)
     scale = ctypes.c_double()
-    check(L.ws_features(ctypes.byref(pp), _dptr(u_prev, "u_prev", 3), _dptr(t_prev, "t_prev", 3), ctypes.byref(pn),
+    Tp = int(prev["tri"].shape[0])
+    check(L.ws_features(ctypes.byref(pp), _dptr(u_prev, "u_prev", 3, Tp), _dptr(t_prev, "t_prev", 3, Tp), ctypes.byref(pn),
                         _fptr(feat, "feat", WS_DIN), _dptr(xm, "x_mapped", 3), ctypes.byref(scale), _stream()))
     return feat, xm, scale.value
 

@@ -14,10 +14,11 @@ def to_dev(x):
 
 
 def run_fmm(src, nrm, w, a, b, kind, trg=None, precision=1, p=6, leaf_max=64, svd_eps=0.0, batch=None,
-            batch_trg=None, return_plan=False):
+            batch_trg=None, return_plan=False, max_depth=0):
     from paper_1612_04082_amd import kfmm
     plan = kfmm.FmmPlan(to_dev(src), to_dev(nrm), to_dev(w), to_dev(trg), K=K, G=G, p=p, leaf_max=leaf_max,
-                        precision=precision, svd_eps=svd_eps, batch_src=batch, batch_trg=batch_trg)
+                        precision=precision, svd_eps=svd_eps, batch_src=batch, batch_trg=batch_trg,
+                        max_depth=max_depth)
     out = plan.eval(kind, to_dev(a), to_dev(b))
     torch.cuda.synchronize()
     res = out.cpu().numpy()
