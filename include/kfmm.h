@@ -44,7 +44,11 @@ enum {
   KFMM_FP64 = 0,          /* everything in FP64 (near field, far field, translations) */
   KFMM_FP32 = 1,          /* near field, check/equivalent evaluations and M2L in FP32; pseudo-inverse
                              and M2M/L2L translations in FP64 */
-  KFMM_FP32_M2L_BF16 = 2  /* as KFMM_FP32 but M2L in BF16 on the matrix cores, FP32 accumulation */
+  KFMM_FP32_M2L_BF16 = 2, /* as KFMM_FP32 but M2L in BF16 on the matrix cores, FP32 accumulation */
+  KFMM_FP32_M2L_SPLIT16 = 3 /* as KFMM_FP32 but the M2L contractions on the FP16 matrix cores: every operator
+                               and every source vector, scaled by a power of two, is split into a high and a
+                               low FP16 part and the product is accumulated in FP32 from the three terms
+                               hi*hi + hi*lo + lo*hi (about 22-bit operands, close to FP32 accuracy) */
 };
 
 /* Target kind of fmm_eval. */
@@ -57,13 +61,14 @@ typedef struct {
   double K, G;        /* bulk and shear modulus */
   int p;              /* equivalent-surface order: p points per cube edge, 6(p-1)^2+2 points; 0 -> 6 */
   int leaf_max;       /* a box is split while it holds more than leaf_max sources + targets; 0 -> 64 */
-  int precision;      /* KFMM_FP64, KFMM_FP32 or KFMM_FP32_M2L_BF16 */
+  int precision;      /* KFMM_FP64, KFMM_FP32, KFMM_FP32_M2L_BF16 or KFMM_FP32_M2L_SPLIT16 */
   double svd_eps;     /* relative singular-value cutoff of the check-to-equivalent pseudo-inverse; 0 -> 1e-8 */
   int max_depth;      /* deepest octree level; 0 -> 16 */
   size_t mem_limit;   /* bytes of device memory the plan may use; 0 = no limit */
-  double m2l_tol;     /* KFMM_FP32 only: > 0 compresses the M2L operators onto one shared basis, keeping the
-                         singular directions above m2l_tol (relative) of sum_o K_o K_o^T's square root, their
-                         count rounded up to the GEMM padding (fmm_info.m2l_rank); 0 = dense */
+  double m2l_tol;     /* KFMM_FP32 and KFMM_FP32_M2L_SPLIT16: > 0 compresses the M2L operators onto one
+                         shared basis, keeping the singular directions above m2l_tol (relative) of
+                         sum_o K_o K_o^T's square root, their count rounded up to the GEMM padding
+                         (fmm_info.m2l_rank); 0 = dense */
 } fmm_opts;
 
 typedef struct kfmm_plan* kfmm_plan_t;
@@ -274,7 +279,9 @@ int ws_load(ws_net_t net, const char* path);
 /*
  * Test hook: one launch of the batched gather/scatter GEMM used by every translation,
  *   Y[:, out[j]] (=, +=, atomic +=) scale[j] * A[op[j]] * X[:, in[j]]
- * precision 0: A, X, Y FP64; 1: FP32; 2: A, X bfloat16 and Y FP32.  A holds NC x NC row-major operators,
+ * precision 0: A, X, Y FP64; 1: FP32; 2: A, X bfloat16 and Y FP32; 3: A, X, Y FP32 with the products on
+ * the FP16 matrix cores (A and X split into high and low FP16 parts, see KFMM_FP32_M2L_SPLIT16; NC a
+ * multiple of 96 or 64).  A holds NC x NC row-major operators,
  * X and Y hold NC-vectors (stride NC).  op, in, out, scale (scale may be NULL) are HOST arrays of ncols
  * entries with op non-decreasing; NC must be a multiple of 96 or 128.  Synchronises the stream.
  * precision + 16 * k selects the FP64 / FP32 kernel: k = 0 as the library chooses, 1 the LDS-tiled

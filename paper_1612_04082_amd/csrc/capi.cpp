@@ -58,7 +58,7 @@ extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* s
     KFMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "src_xyz is NULL");
     // trg_xyz NULL: the targets are the sources (n_trg == n_src), or there are none (n_trg == 0)
     if (trg_xyz == nullptr) KFMM_REQUIRE(n_trg == n_src || n_trg == 0, "aliased targets need n_trg == n_src");
-    KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_M2L_BF16, "unknown precision");
+    KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_M2L_SPLIT16, "unknown precision");
     KFMM_REQUIRE(opts->p == 0 || (opts->p >= 3 && opts->p <= 12), "p must be in [3, 12]");
     KFMM_REQUIRE(opts->leaf_max >= 0 && opts->max_depth >= 0, "negative leaf_max or max_depth");
     KFMM_REQUIRE(opts->m2l_tol >= 0 && opts->m2l_tol < 1, "m2l_tol must be in [0, 1)");
@@ -352,9 +352,10 @@ extern "C" int kfmm_selftest_gemm(int precision, const void* A, int NC, const vo
   return guarded([&] {
     const int kernel = precision >> 4;
     precision &= 15;
-    KFMM_REQUIRE(precision >= 0 && precision <= 2 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
+    KFMM_REQUIRE(precision >= 0 && precision <= 3 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
     KFMM_REQUIRE(kernel >= 0 && kernel <= 4 && (kernel == 0 || precision <= 1), "bad kernel selector");
     KFMM_REQUIRE(NC > 0 && gemm_tm(NC) != 0, "NC must be a positive multiple of 96 or 128");
+    for (int i = 0; i < ncols; ++i) KFMM_REQUIRE(op[i] >= 0 && in[i] >= 0 && out[i] >= 0, "negative index");
     for (int i = 1; i < ncols; ++i) KFMM_REQUIRE(op[i] >= op[i - 1], "columns must be sorted by op");
     selftest_gemm(precision, A, NC, X, Y, op, in, out, scale, ncols, mode, kernel, (hipStream_t)stream);
   });

@@ -49,6 +49,8 @@ struct CompressedM2L {
   double* DU64 = nullptr;  // DC2DE * U, NC x NCr row-major: downward equivalent densities from q~ directly
   float* Ut32 = nullptr;   // NCr x NC
   float* C32 = nullptr;    // 316 x NCr x NCr row-major
+  uint16_t* Ch3 = nullptr;      // C32 split into FP16 high / low parts (see split_h3), made on first use
+  float* Ch3_scale = nullptr;   // power-of-two scale per operator
 };
 
 struct DeviceOps {
@@ -57,6 +59,9 @@ struct DeviceOps {
   double *uc2ue = nullptr, *dc2de = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l64 = nullptr;
   float* m2l32 = nullptr;
   __hip_bfloat16* m2l16 = nullptr;
+  uint16_t* m2l_h3 = nullptr;     // m2l64 split into FP16 high / low parts, made on first use
+  float* m2l_h3_scale = nullptr;  // power-of-two scale per operator
+  std::mutex h3_mutex;
   double* surf = nullptr;  // n_eq x 3
   std::vector<int> m2l_index;
   std::map<double, std::shared_ptr<CompressedM2L>> comp;  // by relative cutoff
@@ -382,6 +387,26 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
   KFMM_HIP(hipStreamSynchronize(s));
   d.comp[tol] = c;
   return c;
+}
+
+// Split-FP16 copies of the M2L operators (dense, or the compressed C_o of c), made once per device.
+static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(d.h3_mutex);
+  const int nops = 316;
+  if (c) {
+    if (c->Ch3) return;
+    const int64_t len = (int64_t)c->NCr * c->NCr;
+    c->Ch3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
+    c->Ch3_scale = d.arena.get<float>(nops);
+    split_h3(c->C32, nops, len, len, c->Ch3, c->Ch3_scale, s);
+  } else {
+    if (d.m2l_h3) return;
+    const int64_t len = (int64_t)d.NC * d.NC;
+    d.m2l_h3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
+    d.m2l_h3_scale = d.arena.get<float>(nops);
+    split_h3(d.m2l64, nops, len, len, d.m2l_h3, d.m2l_h3_scale, s);
+  }
+  KFMM_HIP(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------------------ check-surface evaluations (S2M, X)
@@ -870,7 +895,8 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->m2l_red_off = upload_vec(P->arena, off, s);
     P->m2l_red_idx = upload_vec(P->arena, idx, s);
     int slot_len = D.NC;
-    if (o.precision == KFMM_FP32 && o.m2l_tol > 0) {
+    const bool split16 = o.precision == KFMM_FP32_M2L_SPLIT16;
+    if ((o.precision == KFMM_FP32 || split16) && o.m2l_tol > 0) {
       // compressed M2L: phi~ = U^T phi for every source box, r x r contractions per pair, and the downward
       // pass starts from q~ with DC2DE * U
       P->comp = get_compressed(*P->ops, o.m2l_tol, s);
@@ -880,12 +906,18 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
         if (t.h_src_e[b2] > t.h_src_b[b2]) cu.add(0, b2, b2);
       P->job_ut = upload_job(P->arena, cu, s, 2 * kGemmBN);
       P->phi_t = P->arena.get<float>((size_t)nb * slot_len);
+      KFMM_HIP(hipMemsetAsync(P->phi_t, 0, sizeof(float) * nb * slot_len, s));  // boxes without sources
       // rows of boxes without V lists stay zero: the downward pass applies DC2DE * U to every box
       P->q_t = P->arena.get<double>((size_t)nb * slot_len);
       KFMM_HIP(hipMemsetAsync(P->q_t, 0, sizeof(double) * nb * slot_len, s));
     }
     P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
-    P->job_m2l = upload_job(P->arena, sc, s, o.precision == KFMM_FP32 ? 2 * kGemmBN : kGemmBN);
+    P->job_m2l = upload_job(P->arena, sc, s, o.precision == KFMM_FP32 || split16 ? 2 * kGemmBN : kGemmBN);
+    if (split16) {
+      ensure_split_ops(*P->ops, P->comp.get(), s);
+      P->phi_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * slot_len);
+      P->phi_h3_scale = P->arena.get<float>(std::max(nb, 1));
+    }
     P->n_v_pairs = (int64_t)c.op.size();
     if (std::getenv("KFMM_DEBUG_STATS")) {  // occupancy of target-box blocks x offsets (design statistics)
       for (int bs : {16, 32, 64}) {
@@ -1124,7 +1156,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   // so repeated products of one operator are bitwise identical (GMRES sees a fixed operator).
   mark(KFMM_PH_M2L_PREP);
   double* qhat = P.q_up;  // reuse: the S2M potentials are consumed
-  const bool fused_down = P.prec == KFMM_FP32 && P.comp;  // DC2DE * U applied to q~ (no qhat)
+  const bool split16 = P.prec == KFMM_FP32_M2L_SPLIT16;
+  const bool fused_down = (P.prec == KFMM_FP32 || split16) && P.comp;  // DC2DE * U applied to q~ (no qhat)
   if (!fused_down)
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc, qhat);
   if (P.prec != KFMM_FP64)
@@ -1145,13 +1178,18 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     if (P.m2l_red_n)
       hipLaunchKernelGGL((k_slot_reduce<double, double>), dim3(P.m2l_red_n), dim3(reduce_block<double>(NC)), 0, s,
                          P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const double*)P.m2l_slots, qhat, NC);
-  } else if (P.prec == KFMM_FP32 && P.comp) {
+  } else if (fused_down) {
     const CompressedM2L& C = *P.comp;
     const int NCr = C.NCr;
     gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
+    if (split16) split_h3(P.phi_t, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
     mark(KFMM_PH_M2L);
     m2l_begin();
-    gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
+    if (split16)
+      gemm_h3(P.job_m2l, C.Ch3, C.Ch3_scale, GemmDims{NCr, NCr, 2 * NCr, NCr}, P.phi_h3, P.phi_h3_scale,
+              (float*)P.m2l_slots, kStore, s);
+    else
+      gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
     m2l_end();
     mark(KFMM_PH_M2L_RED);
     if (P.m2l_red_n)
@@ -1162,6 +1200,13 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       mark(KFMM_PH_M2L);
       m2l_begin();
       gemm_f32(P.job_m2l, D.m2l32, GemmDims::Sq(NC), (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);
+      m2l_end();
+    } else if (split16) {
+      split_h3((const float*)P.phi_up_lo, nb, NC, NC, P.phi_h3, P.phi_h3_scale, s);
+      mark(KFMM_PH_M2L);
+      m2l_begin();
+      gemm_h3(P.job_m2l, D.m2l_h3, D.m2l_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, P.phi_h3, P.phi_h3_scale,
+              (float*)P.m2l_slots, kStore, s);
       m2l_end();
     } else {
       hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,

@@ -11,6 +11,7 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <vector>
 
 namespace kfmm {
@@ -72,6 +73,19 @@ void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __
                hipStream_t s);
 void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, double* Y, int mode,
                hipStream_t s);
+
+// Split-FP16 products (gemm_h3.hip).  split_h3 writes n_rows rows of len values (a multiple of 8, read at
+// stride ld) as split rows of 2 * len FP16 numbers, chunks of [hi of 8 values][lo of the same 8] after
+// division by the row's power-of-two scale (written to scale[row]); an operator set is split with one row
+// per operator (len = M * K).  gemm_h3 runs the gather/scatter product on such operands: A_op split
+// operators with scales a_scale[op], X split vectors (d.ldx = FP16 numbers per split vector, at least
+// 2 * d.K) with scales x_scale[box], FP32 outputs.  M must be a multiple of 96 or 64, K of 32, at most
+// 128 columns per tile.
+void split_h3(const float* src, int64_t n_rows, int64_t len, int64_t ld, uint16_t* dst, float* scale, hipStream_t s);
+void split_h3(const double* src, int64_t n_rows, int64_t len, int64_t ld, uint16_t* dst, float* scale,
+              hipStream_t s);
+void gemm_h3(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDims d, const uint16_t* X,
+             const float* x_scale, float* Y, int mode, hipStream_t s);
 
 // Runs one gather/scatter GEMM launch from host column descriptors (test hook).
 void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,

@@ -49,6 +49,9 @@ struct Plan {
   GemmJob job_ut, job_dcx;  // U^T projection of source boxes; DC2DE of the X-list rows
   float* phi_t = nullptr;   // U^T phi_up per box (n_box x NCr)
   double* q_t = nullptr;    // reduced compressed check potentials (n_box x NCr)
+  // KFMM_FP32_M2L_SPLIT16: M2L source vectors split into FP16 high / low parts, power-of-two scale per box
+  uint16_t* phi_h3 = nullptr;
+  float* phi_h3_scale = nullptr;
   // M2L: per-pair output slots (FP64 or FP32) and their fixed-order reduction per target box
   void* m2l_slots = nullptr;
   int m2l_red_n = 0;

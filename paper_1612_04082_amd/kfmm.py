@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkfmm.so")
 
 DISP, STRESS = 0, 1
-FP64, FP32, FP32_M2L_BF16 = 0, 1, 2
+FP64, FP32, FP32_M2L_BF16, FP32_M2L_SPLIT16 = 0, 1, 2, 3
 PHASES = ("permute", "s2m", "uc2ue", "m2m", "m2l_prep", "m2l", "m2l_red", "s2l", "down", "near", "leaf")
 _STATUS = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_HIP", -4: "E_NOCONV", -5: "E_STATE"}
 
@@ -214,13 +214,21 @@ class FmmPlan:
 
 def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0, kernel=0):
     """Test hook around kfmm_selftest_gemm (see include/kfmm.h); kernel 1 = tiled, 2 = split-K,
-    3 / 4 = tiled with one / two LDS buffers."""
-    import numpy as np
+    3 / 4 = tiled with one / two LDS buffers.  precision 3 = FP32 tensors, products on the FP16 matrix
+    cores with split operands."""
     L = load_library()
     n = len(op)
+    dt = {0: (torch.float64,) * 3, 1: (torch.float32,) * 3, 2: (torch.bfloat16, torch.bfloat16, torch.float32),
+          3: (torch.float32,) * 3}[precision]
+    NC = int(A.shape[-1])
+    for t, d, name in ((A, dt[0], "A"), (X, dt[1], "X"), (Y, dt[2], "Y")):
+        if not (t.is_cuda and t.dtype == d and t.is_contiguous() and t.shape[-1] == NC):
+            raise TypeError(f"{name}: expected a contiguous CUDA {d} tensor with {NC} columns")
+    if n and not (max(op) < A.reshape(-1, NC, NC).shape[0] and max(cols_in) < X.shape[0]
+                  and max(cols_out) < Y.shape[0] and min(min(op), min(cols_in), min(cols_out)) >= 0):
+        raise ValueError("column index out of range")
     ia = lambda v: (ctypes.c_int * max(n, 1))(*[int(x) for x in v])
     sc = None if scale is None else (ctypes.c_double * max(n, 1))(*[float(x) for x in scale])
-    NC = int(A.shape[-1])
     check(L.kfmm_selftest_gemm(precision + 16 * kernel, ctypes.c_void_p(A.data_ptr()), NC, ctypes.c_void_p(X.data_ptr()),
                                ctypes.c_void_p(Y.data_ptr()), ia(op), ia(cols_in), ia(cols_out), sc, n, mode,
                                _stream()))

@@ -2,7 +2,7 @@
 
   * one-leaf trees: the method reduces to the direct sum (near field only) -> FP64 rounding level;
   * the unit-sphere cloud of 4096 points (plain KIFMM check): FP64 error small and falling with p;
-  * FP32 and BF16-M2L precisions at their stated tolerances;
+  * FP32, BF16-M2L and split-FP16-M2L precisions at their stated tolerances;
   * stress targets distinct from the sources;
   * the double-layer jump identity evaluated through the FMM (int P = -I at interior targets).
 """
@@ -107,6 +107,31 @@ def test_compressed_m2l(cuda, tol, slack):
     assert 0 < rank < 888
     assert e_c <= slack * e_d + 1e-7 and e_c < 5e-5
 
+
+
+@pytest.mark.parametrize("m2l_tol", [0.0, 3e-7])
+def test_split16_m2l_matches_fp32(cuda, m2l_tol):
+    """M2L on the FP16 matrix cores with split operands (dense and compressed operators): the result
+    agrees with the FP32 matrix-core M2L to well below the method's error, and the error against the
+    oracle stays at the FP32 level."""
+    from tests.fmm_cases import to_dev, K, G
+    from paper_1612_04082_amd import kfmm
+    c = geo.sphere_cloud(4096, seed=1)
+    rng = np.random.default_rng(9)
+    b = rng.normal(size=c["src"].shape)
+    ref = run_oracle(c["src"], c["nrm"], c["w"], c["a"], b, od.DISP)
+    out = {}
+    for prec in (kfmm.FP32, kfmm.FP32_M2L_SPLIT16):
+        plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G, p=8, leaf_max=64,
+                            precision=prec, m2l_tol=m2l_tol)
+        out[prec] = plan.eval(od.DISP, to_dev(c["a"]), to_dev(b)).cpu().numpy()
+        assert plan.info()["n_v_pairs"] > 0
+        plan.close()
+    d = rel_l2(out[kfmm.FP32_M2L_SPLIT16], out[kfmm.FP32])
+    e32, e16 = rel_l2(out[kfmm.FP32], ref), rel_l2(out[kfmm.FP32_M2L_SPLIT16], ref)
+    print(f"m2l_tol {m2l_tol:.0e}: split16 vs fp32 {d:.2e}, errors {e16:.2e} / {e32:.2e}")
+    assert d < 1e-6
+    assert e16 <= 1.02 * e32 + 1e-7
 
 
 def test_profile_modes(cuda):

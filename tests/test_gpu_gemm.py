@@ -28,7 +28,7 @@ def _case(precision, mode, seed=0, n_ops=3, kernel=0, NC=192):
         cout = rng.permutation(n_box)[:ncols2]
     scale = rng.uniform(0.5, 2.0, size=len(op))
     Y0 = rng.normal(size=(n_box, NC))
-    tdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16}[precision]
+    tdt = {0: torch.float64, 1: torch.float32, 2: torch.bfloat16, 3: torch.float32}[precision]
     ydt = torch.float64 if precision == 0 else torch.float32
     At = torch.tensor(A).to(tdt).cuda()
     Xt = torch.tensor(X).to(tdt).cuda()
@@ -48,7 +48,7 @@ def _case(precision, mode, seed=0, n_ops=3, kernel=0, NC=192):
     return err
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6), (2, 2e-6)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6), (2, 2e-6), (3, 2e-6)])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_gemm_matches_reference(cuda, precision, tol, mode):
     err = _case(precision, mode)
@@ -74,13 +74,49 @@ def test_gemm_single_operator_wide_tiles(cuda, mode, kernel):
     assert err < 1e-13
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6), (2, 2e-6)])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 2e-6), (2, 2e-6), (3, 2e-6)])
 @pytest.mark.parametrize("kernel", [0, 2, 3, 4])
 def test_gemm_128_row_blocks(cuda, precision, tol, kernel):
     """NC a multiple of 128 but not of 96 (the padding of p = 8 vectors, 888 -> 896): 128-row blocks
-    in the tiled kernels, 64-row blocks in the split-K kernel."""
-    if precision == 2 and kernel:
-        pytest.skip("the BF16 kernel has no variants")
+    in the tiled kernels, 64-row blocks in the split-K and split-FP16 kernels."""
+    if precision >= 2 and kernel:
+        pytest.skip("the BF16 and split-FP16 kernels have no variants")
     for mode in (0, 2):
         err = _case(precision, mode, seed=11, kernel=kernel, NC=256)
         assert err < tol, (mode, err)
+
+
+@pytest.mark.parametrize("NC", [96, 192, 256])
+def test_split16_wide_range(cuda, NC):
+    """Split-FP16 products with operators and vectors spanning many decades: operators 27 decades apart,
+    vectors 20 decades apart, and inside each operator and vector entries spread over 4 decades (rows
+    and components graded by 10^(-4 i / NC), inside the 2^-17 range of full split precision).  Every
+    output element must carry an FP32-level error relative to its own |A| |x|, not to the largest entry
+    of its operator or vector."""
+    from paper_1612_04082_amd import kfmm
+    rng = np.random.default_rng(21)
+    n_ops, n_box, ncols = 4, 70, 300
+    grade = 10.0 ** (-4.0 * np.arange(NC) / NC)
+    A = rng.normal(size=(n_ops, NC, NC)) * (10.0 ** np.array([-15, -3, 4, 12]))[:, None, None]
+    A *= grade[None, :, None]
+    X = rng.normal(size=(n_box, NC)) * (10.0 ** rng.uniform(-10, 10, size=n_box))[:, None] * grade[None, :]
+    X[3] = 0.0  # an all-zero vector
+    op = np.sort(rng.integers(0, n_ops, size=ncols))
+    cin = rng.integers(0, n_box, size=ncols)
+    cout = np.arange(ncols)
+    At = torch.tensor(A, dtype=torch.float32).cuda()
+    Xt = torch.tensor(X, dtype=torch.float32).cuda()
+    Yt = torch.zeros(ncols, NC, dtype=torch.float32).cuda()
+    kfmm.selftest_gemm(3, At, Xt, Yt, op, cin, cout, None, 0)
+    Ar, Xr = At.double().cpu().numpy(), Xt.double().cpu().numpy()
+    got = Yt.double().cpu().numpy()
+    worst = 0.0
+    for j in range(ncols):
+        ref = Ar[op[j]] @ Xr[cin[j]]
+        bound = np.abs(Ar[op[j]]) @ np.abs(Xr[cin[j]])  # error scale of any summation order, per element
+        if not bound.max() > 0:
+            assert not got[j].any()
+            continue
+        worst = max(worst, (np.abs(got[j] - ref) / bound).max())
+    print(f"NC={NC} worst error / (|A||x|) per element {worst:.2e}")
+    assert worst < 2e-6
