@@ -42,9 +42,12 @@ enum {
 /* Internal arithmetic of fmm_eval. */
 enum {
   KFMM_FP64 = 0,          /* everything in FP64 (near field, far field, translations) */
-  KFMM_FP32 = 1,          /* near field, check/equivalent evaluations and M2L in FP32; pseudo-inverse
-                             and M2M/L2L translations in FP64 */
-  KFMM_FP32_M2L_BF16 = 2, /* as KFMM_FP32 but M2L in BF16 on the matrix cores, FP32 accumulation */
+  KFMM_FP32 = 1,          /* near field, check/equivalent evaluations, M2L and translations in FP32; the
+                             M2M/L2L chains run on scaled check potentials (smooth fields, no cancellation)
+                             and the check-to-equivalent pseudo-inverses are applied in their SVD-factored
+                             form (an orthogonal rotation, then a column-scaled one), once per box */
+  KFMM_FP32_M2L_BF16 = 2, /* near field, check/equivalent evaluations in FP32, M2L in BF16 on the matrix
+                             cores (FP32 accumulation), pseudo-inverse and M2M/L2L translations in FP64 */
   KFMM_FP32_M2L_SPLIT16 = 3 /* as KFMM_FP32 but the M2L contractions on the FP16 matrix cores: every operator
                                and every source vector, scaled by a power of two, is split into a high and a
                                low FP16 part and the product is accumulated in FP32 from the three terms
@@ -135,13 +138,15 @@ int fmm_plan_info(kfmm_plan_t plan, fmm_info* info /* host */);
 enum {
   KFMM_PH_PERMUTE = 0, /* densities into tree order */
   KFMM_PH_S2M,         /* sources -> upward check potentials of leaves */
-  KFMM_PH_UC2UE,       /* upward check -> equivalent densities of leaves */
-  KFMM_PH_M2M,         /* upward translations, all levels */
+  KFMM_PH_UC2UE,       /* upward check -> equivalent densities of leaves (FP64 translations only) */
+  KFMM_PH_M2M,         /* upward translations, all levels (FP32 translations: and then check ->
+                          equivalent densities of every box) */
   KFMM_PH_M2L_PREP,    /* clearing and converting for the M2L */
   KFMM_PH_M2L,         /* M2L contraction (matrix cores), all levels */
   KFMM_PH_M2L_RED,     /* sum of the per-pair M2L outputs of every target box (fixed order) */
   KFMM_PH_S2L,         /* X list: sources -> downward check potentials */
-  KFMM_PH_DOWN,        /* downward check -> equivalent, L2L, all levels */
+  KFMM_PH_DOWN,        /* downward check -> equivalent, L2L, all levels (FP32 translations: L2L on check
+                          potentials, then check -> equivalent at the target leaves) */
   KFMM_PH_NEAR,        /* near field (U list) at the target leaves */
   KFMM_PH_LEAF,        /* far field at the target leaves: L2T + W list */
   KFMM_N_PHASES

@@ -47,16 +47,22 @@ struct CompressedM2L {
   int r = 0, NCr = 0;
   double* Ut64 = nullptr;  // NCr x NC row-major (row k = k-th basis vector, rows >= r zero)
   double* DU64 = nullptr;  // DC2DE * U, NC x NCr row-major: downward equivalent densities from q~ directly
+  float* U32 = nullptr;    // U, NC x NCr row-major (FP32 translations: qhat = U q~)
   float* Ut32 = nullptr;   // NCr x NC
   float* C32 = nullptr;    // 316 x NCr x NCr row-major
   uint16_t* Ch3 = nullptr;      // C32 split into FP16 high / low parts (see split_h3), made on first use
   float* Ch3_scale = nullptr;   // power-of-two scale per operator
+  uint16_t* Ut_h3 = nullptr;    // Ut32 split likewise (one operator)
+  float* Ut_h3_scale = nullptr;
 };
 
 struct DeviceOps {
   int device = -1;
   int p = 0, n = 0, NC = 0, n_eq = 0;
   double *uc2ue = nullptr, *dc2de = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l64 = nullptr;
+  // FP32 translations: factored pseudo-inverses (UC2UE = fu2 fu1, DC2DE = fd2 fd1) and the M2M / L2L
+  // translations on check potentials (8 each)
+  float *fu1 = nullptr, *fu2 = nullptr, *fd1 = nullptr, *fd2 = nullptr, *m2mq32 = nullptr, *l2lq32 = nullptr;
   float* m2l32 = nullptr;
   __hip_bfloat16* m2l16 = nullptr;
   uint16_t* m2l_h3 = nullptr;     // m2l64 split into FP16 high / low parts, made on first use
@@ -118,6 +124,26 @@ static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, 
     }
     d->l2l = up(cat);
     d->surf = up(op.surf);
+    auto up32 = [&](const std::vector<double>& v) {
+      std::vector<float> f(v.begin(), v.end());
+      float* ptr = d->arena.get<float>(f.size());
+      KFMM_HIP(hipMemcpy(ptr, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+      return ptr;
+    };
+    auto cat8 = [&](const std::vector<std::vector<double>>& m) {
+      std::vector<double> all;
+      for (int c = 0; c < 8; ++c) {
+        auto v = pad_square(m[c], op.n, NC);
+        all.insert(all.end(), v.begin(), v.end());
+      }
+      return all;
+    };
+    d->m2mq32 = up32(cat8(op.m2m_q));
+    d->l2lq32 = up32(cat8(op.l2l_q));
+    d->fu1 = up32(pad_square(op.fu1, op.n, NC));
+    d->fu2 = up32(pad_square(op.fu2, op.n, NC));
+    d->fd1 = up32(pad_square(op.fd1, op.n, NC));
+    d->fd2 = up32(pad_square(op.fd2, op.n, NC));
     // M2L operators in the requested precisions are uploaded lazily below
     std::vector<double> m2l_all;
     m2l_all.reserve(op.m2l.size() * (size_t)NC * NC);
@@ -217,14 +243,16 @@ __global__ void k_convert<double, __hip_bfloat16>(int64_t n, const double* in, _
   if (i < n) out[i] = __float2bfloat16((float)in[i]);
 }
 
-__global__ void k_fill_zero(int64_t n, double* p) {
+template <typename T>
+__global__ void k_fill_zero(int64_t n, T* p) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
+  if (i < n) p[i] = T(0);
 }
 
 // dst(boxes[i]) += src(i): the X-list check potentials (compact rows) added to qhat
-__global__ __launch_bounds__(256) void k_add_rows(const int* __restrict__ boxes, const double* __restrict__ src,
-                                                  double* __restrict__ dst, int NC) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_add_rows(const int* __restrict__ boxes, const T* __restrict__ src,
+                                                  T* __restrict__ dst, int NC) {
   const int i = blockIdx.x, B = boxes[i];
   for (int c = threadIdx.x; c < NC; c += blockDim.x) dst[(size_t)B * NC + c] += src[(size_t)i * NC + c];
 }
@@ -379,6 +407,13 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
     c->DU64 = d.arena.get<double>(du.size());
     KFMM_HIP(hipMemcpy(c->DU64, du.data(), sizeof(double) * du.size(), hipMemcpyHostToDevice));
   }
+  {  // U itself (NC x NCr, column k = k-th basis vector) for the FP32 translations
+    std::vector<float> u32((size_t)NC * NCr, 0.0f);
+    for (int k = 0; k < r; ++k)
+      for (int i = 0; i < NC; ++i) u32[(size_t)i * NCr + k] = (float)Ut[(size_t)k * NC + i];
+    c->U32 = d.arena.get<float>(u32.size());
+    KFMM_HIP(hipMemcpy(c->U32, u32.data(), sizeof(float) * u32.size(), hipMemcpyHostToDevice));
+  }
   c->C32 = d.arena.get<float>((size_t)nops * NCr * NCr);
   const int64_t nc = (int64_t)nops * NCr * NCr;
   hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, nc,
@@ -399,6 +434,10 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     c->Ch3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
     c->Ch3_scale = d.arena.get<float>(nops);
     split_h3(c->C32, nops, len, len, c->Ch3, c->Ch3_scale, s);
+    const int64_t ulen = (int64_t)c->NCr * d.NC;
+    c->Ut_h3 = d.arena.get<uint16_t>((size_t)2 * ulen);
+    c->Ut_h3_scale = d.arena.get<float>(1);
+    split_h3(c->Ut32, 1, ulen, ulen, c->Ut_h3, c->Ut_h3_scale, s);
   } else {
     if (d.m2l_h3) return;
     const int64_t len = (int64_t)d.NC * d.NC;
@@ -414,7 +453,8 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
 constexpr int kStage = 256;  // points staged in LDS per round
 
 // Evaluate the sources of a list of leaves at the check surface of box B (displacement, U and/or P).
-//   S2M: B's own sources at its upward check surface (radius r_up_check), written to row B of q.
+//   S2M: B's own sources at its upward check surface (radius r_up_check), written to row B of q (times
+//        r_B with s2m_r: the scaled check potential qhat of the check-potential translations).
 //   S2L: sources of X(B) at B's downward check surface (radius r_dn_check), r_B * value written to row
 //        blockIdx.x of a compact buffer (added to qhat afterwards).
 template <typename T, typename TQ, bool SL, bool DL, bool S2M>
@@ -423,7 +463,7 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
                                                     const int* __restrict__ list_idx, const T* __restrict__ spos4,
                                                     const T* __restrict__ snrm4, const T* __restrict__ dens8,
                                                     const double* __restrict__ surf, int n_eq, double radius, int NC,
-                                                    KConst<T> kc, TQ* __restrict__ out) {
+                                                    KConst<T> kc, TQ* __restrict__ out, int s2m_r = 0) {
   __shared__ T sp[kStage][4];
   __shared__ T sn[kStage][4];
   __shared__ T sd[kStage][8];
@@ -475,7 +515,7 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
     for (int d = 0; d < 3; ++d) {
       double v = (double)(kc.cU * vU[d] - kc.cP * vP[d]);
       if (S2M)
-        out[(size_t)B * NC + 3 * tid + d] = (TQ)v;
+        out[(size_t)B * NC + 3 * tid + d] = (TQ)(s2m_r ? rB * v : v);
       else
         out[(size_t)blockIdx.x * NC + 3 * tid + d] = (TQ)(rB * v);
     }
@@ -772,6 +812,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   P->opts = o;
   P->el = Elastic::make(o.K, o.G);
   P->prec = o.precision;
+  P->f32t = o.precision == KFMM_FP32 || o.precision == KFMM_FP32_M2L_SPLIT16;
   P->n_src = n_src;
   P->alias = trg == nullptr && n_trg == n_src;  // NULL with n_trg == 0 (and n_src > 0): no targets
   P->n_trg = P->alias ? n_src : n_trg;
@@ -846,6 +887,12 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     GemmCols c;
     for (int b : leaves_src) c.add(0, b, b, half(b));
     P->job_uc2ue = upload_job(P->arena, c, s, wide(c));
+    if (P->f32t) {  // UC2UE on the check potentials of every box with sources at level >= 2
+      GemmCols ca;
+      for (int b = 0; b < nb; ++b)
+        if (t.h_level[b] >= 2 && hs(b)) ca.add(0, b, b);
+      P->job_up_all = upload_job(P->arena, ca, s, wide(ca));
+    }
   }
   // M2M per level (deepest first): children with sources, grouped by octant; parents reduce.  Parents
   // at levels 0 and 1 are skipped: V and W lists only hold boxes of level >= 2.
@@ -908,8 +955,13 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       P->phi_t = P->arena.get<float>((size_t)nb * slot_len);
       KFMM_HIP(hipMemsetAsync(P->phi_t, 0, sizeof(float) * nb * slot_len, s));  // boxes without sources
       // rows of boxes without V lists stay zero: the downward pass applies DC2DE * U to every box
-      P->q_t = P->arena.get<double>((size_t)nb * slot_len);
-      KFMM_HIP(hipMemsetAsync(P->q_t, 0, sizeof(double) * nb * slot_len, s));
+      if (P->f32t) {
+        P->q_t_f = P->arena.get<float>((size_t)nb * slot_len);
+        KFMM_HIP(hipMemsetAsync(P->q_t_f, 0, sizeof(float) * nb * slot_len, s));
+      } else {
+        P->q_t = P->arena.get<double>((size_t)nb * slot_len);
+        KFMM_HIP(hipMemsetAsync(P->q_t, 0, sizeof(double) * nb * slot_len, s));
+      }
     }
     P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
     P->job_m2l = upload_job(P->arena, sc, s, o.precision == KFMM_FP32 || split16 ? 2 * kGemmBN : kGemmBN);
@@ -917,6 +969,10 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       ensure_split_ops(*P->ops, P->comp.get(), s);
       P->phi_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * slot_len);
       P->phi_h3_scale = P->arena.get<float>(std::max(nb, 1));
+      if (P->comp) {  // the U^T projection runs split too: phi_up split per box
+        P->phi_up_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * D.NC);
+        P->phi_up_h3_scale = P->arena.get<float>(std::max(nb, 1));
+      }
     }
     P->n_v_pairs = (int64_t)c.op.size();
     if (std::getenv("KFMM_DEBUG_STATS")) {  // occupancy of target-box blocks x offsets (design statistics)
@@ -946,6 +1002,12 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     for (int b = 0; b < nb; ++b)
       if (t.h_level[b] >= 2 && ht(b)) c.add(0, b, b);
     P->job_dc2de = upload_job(P->arena, c, s, wide(c));
+    if (P->f32t) {  // DC2DE at the leaves only: the downward pass carries check potentials
+      GemmCols cl;
+      for (int b : leaves_trg)
+        if (t.h_level[b] >= 2) cl.add(0, b, b);
+      P->job_dn_leaf = upload_job(P->arena, cl, s, wide(cl));
+    }
     // compressed M2L: the X-list check potentials get DC2DE on their own (added after DC2DE * U q~)
     if (P->comp) {
       GemmCols cx;
@@ -999,16 +1061,23 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     return p;
   };
   const size_t nbc = (size_t)nb * NC;
-  P->q_up = (double*)zalloc(nbc * 8);
-  P->phi_up = (double*)zalloc(nbc * 8);
-  P->phi_dn = (double*)zalloc(nbc * 8);
-  P->tmp = (double*)zalloc(nbc * 8);
+  const size_t nxc = std::max<size_t>(1, (size_t)P->n_x_boxes * NC);
+  if (P->f32t) {
+    P->q_f = (float*)zalloc(nbc * 4);
+    P->tmp_f = (float*)zalloc(nbc * 4);
+    P->qx_f = (float*)zalloc(nxc * 4);  // padding rows stay zero
+  } else {
+    P->q_up = (double*)zalloc(nbc * 8);
+    P->phi_up = (double*)zalloc(nbc * 8);
+    P->phi_dn = (double*)zalloc(nbc * 8);
+    P->tmp = (double*)zalloc(nbc * 8);
+    P->qx = (double*)zalloc(nxc * 8);  // padding rows stay zero
+  }
   if (!f64) {
     P->phi_up_lo = zalloc(nbc * 4);
     P->phi_dn_lo = zalloc(nbc * 4);
     if (o.precision == KFMM_FP32_M2L_BF16) P->phi_up_bf = zalloc(nbc * 2);
   }
-  P->qx = (double*)zalloc(std::max<size_t>(1, (size_t)P->n_x_boxes * NC) * 8);  // padding rows stay zero
   KFMM_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
   for (hipEvent_t* e : {&P->fork_ev, &P->phi_ev, &P->x_ev, &P->join_ev})
     KFMM_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
@@ -1114,8 +1183,12 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     if (!P.n_x_boxes) return;
     dispatch([&](auto sl, auto dl) {
       constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
-      hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, st,
-                         P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, P.qx);
+      if (P.f32t)
+        hipLaunchKernelGGL((k_check_eval<T, float, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, st,
+                           P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, P.qx_f);
+      else
+        hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, st,
+                           P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, P.qx);
     });
   };
   auto w_eval = [&](hipStream_t st) {
@@ -1131,12 +1204,20 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   // S2M, UC2UE
   dispatch([&](auto sl, auto dl) {
     constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
-    hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
-                       P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
-                       2.95, NC, kc, P.q_up);
+    if (P.f32t)  // scaled check potentials qhat = r q
+      hipLaunchKernelGGL((k_check_eval<T, float, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
+                         P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
+                         2.95, NC, kc, P.q_f, 1);
+    else
+      hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
+                         P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
+                         2.95, NC, kc, P.q_up);
   });
   mark(KFMM_PH_UC2UE);
-  gemm_f64(P.job_uc2ue, D.uc2ue, GemmDims::Sq(NC), P.q_up, P.phi_up, kStore, s);
+  float* const phi_up_f = (float*)P.phi_up_lo;
+  float* const phi_dn_f = (float*)P.phi_dn_lo;
+  // FP32 translations: UC2UE runs after the M2M chain, for every box at once (in the M2M phase)
+  if (!P.f32t) gemm_f64(P.job_uc2ue, D.uc2ue, GemmDims::Sq(NC), P.q_up, P.phi_up, kStore, s);
   fork(P.fork_ev);
   if (overlap) {
     leaf_eval(2, side);
@@ -1146,21 +1227,39 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   // M2M
   mark(KFMM_PH_M2M);
   for (const UpLevel& U : P.up_levels) {
-    gemm_f64(U.job, D.m2m, GemmDims::Sq(NC), P.phi_up, P.tmp, kStore, s);
-    if (U.n_par)
-      hipLaunchKernelGGL(k_m2m_reduce<double>, dim3(U.n_par), dim3(reduce_block<double>(NC)), 0, s, U.parents,
-                         U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
+    if (P.f32t) {  // qhat_up(parent) = sum_c M2M_q_c qhat_up(child)
+      gemm_f32(U.job, D.m2mq32, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
+      if (U.n_par)
+        hipLaunchKernelGGL(k_m2m_reduce<float>, dim3(U.n_par), dim3(reduce_block<float>(NC)), 0, s, U.parents,
+                           U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp_f, P.q_f, NC);
+    } else {
+      gemm_f64(U.job, D.m2m, GemmDims::Sq(NC), P.phi_up, P.tmp, kStore, s);
+      if (U.n_par)
+        hipLaunchKernelGGL(k_m2m_reduce<double>, dim3(U.n_par), dim3(reduce_block<double>(NC)), 0, s, U.parents,
+                           U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
+    }
+  }
+  if (P.f32t) {  // phi_up = UC2UE qhat_up = fu2 (fu1 qhat_up)
+    gemm_f32(P.job_up_all, D.fu1, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
+    gemm_f32(P.job_up_all, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
   }
   KFMM_HIP(hipGetLastError());
   // M2L into qhat.  qhat is FP64 in every precision; each box's M2L slots are summed in a fixed order,
   // so repeated products of one operator are bitwise identical (GMRES sees a fixed operator).
   mark(KFMM_PH_M2L_PREP);
-  double* qhat = P.q_up;  // reuse: the S2M potentials are consumed
+  double* qhat = P.q_up;  // reuse: the S2M potentials are consumed (FP64 translations)
+  float* qhat_f = P.q_f;  // the same with FP32 translations
   const bool split16 = P.prec == KFMM_FP32_M2L_SPLIT16;
   const bool fused_down = (P.prec == KFMM_FP32 || split16) && P.comp;  // DC2DE * U applied to q~ (no qhat)
-  if (!fused_down)
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc, qhat);
-  if (P.prec != KFMM_FP64)
+  if (!fused_down) {
+    if (P.f32t)
+      hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc,
+                         qhat_f);
+    else
+      hipLaunchKernelGGL(k_fill_zero<double>, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc,
+                         qhat);
+  }
+  if (P.prec != KFMM_FP64 && !P.f32t)
     hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                        (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
   KFMM_HIP(hipGetLastError());
@@ -1181,8 +1280,14 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   } else if (fused_down) {
     const CompressedM2L& C = *P.comp;
     const int NCr = C.NCr;
-    gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
-    if (split16) split_h3(P.phi_t, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
+    if (split16) {
+      split_h3((const float*)phi_up_f, nb, NC, NC, P.phi_up_h3, P.phi_up_h3_scale, s);
+      gemm_h3(P.job_ut, C.Ut_h3, C.Ut_h3_scale, GemmDims{NCr, NC, 2 * NC, NCr}, P.phi_up_h3, P.phi_up_h3_scale,
+              P.phi_t, kStore, s);
+      split_h3(P.phi_t, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
+    } else {
+      gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
+    }
     mark(KFMM_PH_M2L);
     m2l_begin();
     if (split16)
@@ -1193,8 +1298,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     m2l_end();
     mark(KFMM_PH_M2L_RED);
     if (P.m2l_red_n)
-      hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
-                         P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
+      hipLaunchKernelGGL((k_slot_reduce<float, float>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
+                         P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t_f, NCr);
   } else {
     if (P.prec == KFMM_FP32) {
       mark(KFMM_PH_M2L);
@@ -1218,9 +1323,14 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       m2l_end();
     }
     mark(KFMM_PH_M2L_RED);
-    if (P.m2l_red_n)
-      hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NC)), 0, s,
-                         P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
+    if (P.m2l_red_n) {
+      if (P.f32t)
+        hipLaunchKernelGGL((k_slot_reduce<float, float>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NC)), 0, s,
+                           P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, qhat_f, NC);
+      else
+        hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NC)), 0, s,
+                           P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, qhat, NC);
+    }
   }
   KFMM_HIP(hipGetLastError());
   // X lists, added to qhat
@@ -1229,23 +1339,43 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     KFMM_HIP(hipStreamWaitEvent(s, P.x_ev, 0));
   else
     s2l(s);
-  if (P.n_x_boxes && !fused_down)
-    hipLaunchKernelGGL(k_add_rows, dim3(P.n_x_boxes), dim3(reduce_block<double>(NC)), 0, s, P.x_boxes,
-                       (const double*)P.qx, qhat, NC);
-  KFMM_HIP(hipGetLastError());
-  // downward pass in FP64
-  mark(KFMM_PH_DOWN);
-  if (fused_down) {
-    const int NCr = P.comp->NCr;
-    gemm_f64(P.job_dc2de, P.comp->DU64, GemmDims{NC, NCr, NCr, NC}, P.q_t, P.phi_dn, kStore, s);
-    gemm_f64(P.job_dcx, D.dc2de, GemmDims::Sq(NC), P.qx, P.phi_dn, kAdd, s);
-  } else {
-    gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
+  if (P.n_x_boxes && !fused_down) {
+    if (P.f32t)
+      hipLaunchKernelGGL(k_add_rows<float>, dim3(P.n_x_boxes), dim3(reduce_block<float>(NC)), 0, s, P.x_boxes,
+                         (const float*)P.qx_f, qhat_f, NC);
+    else
+      hipLaunchKernelGGL(k_add_rows<double>, dim3(P.n_x_boxes), dim3(reduce_block<double>(NC)), 0, s, P.x_boxes,
+                         (const double*)P.qx, qhat, NC);
   }
-  for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, GemmDims::Sq(NC), P.phi_dn, P.phi_dn, kAdd, s);
-  if (P.prec != KFMM_FP64)
-    hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
-                       (int64_t)nbc, P.phi_dn, (float*)P.phi_dn_lo);
+  KFMM_HIP(hipGetLastError());
+  mark(KFMM_PH_DOWN);
+  if (P.f32t) {
+    // downward pass in FP32 on check potentials: qhat = U q~ + X rows (compressed), qhat(child) +=
+    // L2L_q qhat(parent) level by level, then phi_dn = DC2DE qhat = fd2 (fd1 qhat) at the target leaves
+    if (fused_down) {
+      const int NCr = P.comp->NCr;
+      gemm_f32(P.job_dc2de, P.comp->U32, GemmDims{NC, NCr, NCr, NC}, P.q_t_f, qhat_f, kStore, s);
+      if (P.n_x_boxes)
+        hipLaunchKernelGGL(k_add_rows<float>, dim3(P.n_x_boxes), dim3(reduce_block<float>(NC)), 0, s, P.x_boxes,
+                           (const float*)P.qx_f, qhat_f, NC);
+    }
+    for (const GemmJob& J : P.dn_levels) gemm_f32(J, D.l2lq32, GemmDims::Sq(NC), qhat_f, qhat_f, kAdd, s);
+    gemm_f32(P.job_dn_leaf, D.fd1, GemmDims::Sq(NC), qhat_f, P.tmp_f, kStore, s);
+    gemm_f32(P.job_dn_leaf, D.fd2, GemmDims::Sq(NC), P.tmp_f, phi_dn_f, kStore, s);
+  } else {
+    // downward pass in FP64
+    if (fused_down) {
+      const int NCr = P.comp->NCr;
+      gemm_f64(P.job_dc2de, P.comp->DU64, GemmDims{NC, NCr, NCr, NC}, P.q_t, P.phi_dn, kStore, s);
+      gemm_f64(P.job_dcx, D.dc2de, GemmDims::Sq(NC), P.qx, P.phi_dn, kAdd, s);
+    } else {
+      gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
+    }
+    for (const GemmJob& J : P.dn_levels) gemm_f64(J, D.l2l, GemmDims::Sq(NC), P.phi_dn, P.phi_dn, kAdd, s);
+    if (P.prec != KFMM_FP64)
+      hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
+                         (int64_t)nbc, P.phi_dn, (float*)P.phi_dn_lo);
+  }
   KFMM_HIP(hipGetLastError());
   // leaves: near field (already on the side stream when overlapping), W lists, L2T
   mark(KFMM_PH_NEAR);
@@ -1306,7 +1436,7 @@ void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out,
   if (P.n_trg == 0) return;
   if (P.empty || (!a && !b)) {
     const int64_t n = (int64_t)no * P.n_trg;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, out);
+    hipLaunchKernelGGL(k_fill_zero<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, out);
     KFMM_HIP(hipGetLastError());
     return;
   }

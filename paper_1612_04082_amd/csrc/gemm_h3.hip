@@ -131,17 +131,31 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
 #pragma unroll
     for (int u = 0; u < TN; ++u) acc[t][u] = float4_t{0, 0, 0, 0};
   auto compute = [&](int cur) {
+    // every operator fragment of the stage is read before the first product, so the products of one
+    // stage issue back to back
+    half8_t ah[TM], al[TM];
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
       const int w = (t * 16 + i16) * RW + 8 * g;
-      const half8_t ah = *(const half8_t*)&As[cur][w];
-      const half8_t al = *(const half8_t*)&As[cur][w + 4];
+      ah[t] = *(const half8_t*)&As[cur][w];
+      al[t] = *(const half8_t*)&As[cur][w + 4];
+    }
 #pragma unroll
-      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[u], acc[t][u], 0, 0, 0);
+    for (int t = 0; t < TM; ++t) {
 #pragma unroll
-      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[u], acc[t][u], 0, 0, 0);
+      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t], bh[u], acc[t][u], 0, 0, 0);
 #pragma unroll
-      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[u], acc[t][u], 0, 0, 0);
+      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t], bl[u], acc[t][u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[t], bh[u], acc[t][u], 0, 0, 0);
+    }
+    // issue order: the fragments of rows 0 and 1, then the products of row t each followed by the reads
+    // of row t + 2, so that LDS latency hides behind products already issued
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * TN, 0);
+      if (t + 2 < TM) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
     }
   };
   const int ns = dm.K / 32;

@@ -13,6 +13,21 @@
 //   L2L_c  = DC2DE * U[child c dc <- parent de]     phi_down(child) += L2L_c * phi_down(parent)
 // where qhat = r_l * (downward check potential).  U is symmetric and reciprocal, so U[dc<-de] is the
 // transpose of U[uc<-ue] and one SVD serves both pseudo-inverses.
+//
+// The pseudo-inverses are also kept in factored form, U[uc<-ue] = Us S Vs^T:
+//   UC2UE = (Vs S^-1) Us^T,   DC2DE = (Us S^-1) Vs^T.
+// Applied as the two factors in turn, each product rounds relative to its own terms (an orthogonal
+// rotation, then a column-scaled one), so they can run in FP32: the explicit UC2UE has entries up to
+// 1/s_min with heavy cancellation against a smooth check potential, and FP32 rounding of those entries
+// or of their running sum leaves errors far above the field itself.
+//
+// The same translations written on check potentials (qhat = r_l * check potential, phi = UC2UE qhat up,
+// phi = DC2DE qhat down):
+//   M2M_q_c = U[parent uc <- child c ue] * UC2UE     qhat_up(parent) = sum_c M2M_q_c * qhat_up(child c)
+//   L2L_q_c = U[child c dc <- parent de] * DC2DE     qhat_dn(child) += L2L_q_c * qhat_dn(parent)
+// A check potential is a smooth field sample, and these operators map smooth fields to smooth fields
+// without cancellation, so chains of them run in FP32; an equivalent density carries the pinv's
+// amplified high-order modes, and every product with it (M2M_c, L2L_c) cancels them in its sum.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -157,16 +172,15 @@ static void jacobi_svd(const std::vector<double>& A, int n, std::vector<double>&
   }
 }
 
-// Pseudo-inverse of a square n x n row-major matrix, singular values below eps * s_max discarded.
-static std::vector<double> pinv_jacobi(const std::vector<double>& A, int n, double eps, int* rank_out) {
-  std::vector<double> W, V, sig;
-  jacobi_svd(A, n, W, V, sig);
+// Pseudo-inverse of a square n x n row-major matrix from its one-sided Jacobi SVD (W = A V, column j of
+// W = s_j u_j, V[j n + i] = (v_j)_i), singular values below eps * s_max discarded.
+static std::vector<double> pinv_from_svd(const std::vector<double>& W, const std::vector<double>& V,
+                                         const std::vector<double>& sig, int n, double eps, int* rank_out) {
   double smax = 0;
   for (double v : sig) smax = std::max(smax, v);
   // pinv = V diag(1/s) U^T with U_j = W_j / s_j  ->  pinv[i][k] = sum_j V[i][j] W[k][j] / s_j^2
   std::vector<double> P((size_t)n * n, 0.0);
   int rank = 0;
-  std::vector<double> scaled((size_t)n * n, 0.0);  // column j: W_j / s_j^2 (kept columns only)
   std::vector<int> keep;
   for (int j = 0; j < n; ++j)
     if (sig[j] > eps * smax) {
@@ -181,6 +195,27 @@ static std::vector<double> pinv_jacobi(const std::vector<double>& A, int n, doub
     }
   if (rank_out) *rank_out = rank;
   return P;
+}
+
+// The two factors of UC2UE and of DC2DE (row-major n x n, discarded directions as zero rows / columns):
+//   fu1 = Us^T, fu2 = Vs S^-1 (UC2UE = fu2 fu1);  fd1 = Vs^T, fd2 = Us S^-1 (DC2DE = fd2 fd1).
+static void pinv_factors(const std::vector<double>& W, const std::vector<double>& V, const std::vector<double>& sig,
+                         int n, double eps, Operators& op) {
+  double smax = 0;
+  for (double v : sig) smax = std::max(smax, v);
+  for (auto* m : {&op.fu1, &op.fu2, &op.fd1, &op.fd2}) m->assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    if (!(sig[j] > eps * smax)) continue;
+    const double s = sig[j];
+    for (int k = 0; k < n; ++k) {
+      const double u = W[(size_t)j * n + k] / s;  // (u_j)_k
+      const double v = V[(size_t)j * n + k];      // (v_j)_k
+      op.fu1[(size_t)j * n + k] = u;
+      op.fu2[(size_t)k * n + j] = v / s;
+      op.fd1[(size_t)j * n + k] = v;
+      op.fd2[(size_t)k * n + j] = u / s;
+    }
+  }
 }
 
 // C = A B for n x n row-major FP64 matrices.
@@ -207,17 +242,19 @@ static std::string cache_path(int p, const Elastic& e, double eps) {
     d = std::string(home ? home : "/tmp") + "/.cache/kfmm";
   }
   char name[256];
-  std::snprintf(name, sizeof(name), "/uc2ue_p%d_nu%.17g_G%.17g_eps%.3g_r1.05_2.95.bin", p, e.nu, e.G, eps);
+  std::snprintf(name, sizeof(name), "/svd_uc_ue_p%d_nu%.17g_G%.17g_r1.05_2.95.bin", p, e.nu, e.G);
+  (void)eps;  // the SVD does not depend on the cutoff
   return d + name;
 }
 
+// Cache file: n, then the SVD (W, V, sig) as one array of 2 n^2 + n doubles, then a checksum.
 static bool load_cache(const std::string& path, int n, std::vector<double>& P) {
   std::ifstream f(path, std::ios::binary);
   if (!f) return false;
   int nn = 0;
   f.read((char*)&nn, sizeof(int));
   if (nn != n) return false;
-  P.resize((size_t)n * n);
+  P.resize((size_t)2 * n * n + n);
   f.read((char*)P.data(), sizeof(double) * P.size());
   uint64_t chk = 0, ref = 0;
   f.read((char*)&ref, sizeof(ref));
@@ -276,16 +313,29 @@ Operators build_operators(int p, const Elastic& e, double svd_eps) {
   std::vector<double> K((size_t)n * n);
   kernel_matrix_U(e, uc.data(), op.n_eq, ue.data(), op.n_eq, K.data());
   std::string path = cache_path(p, e, svd_eps);
-  if (!load_cache(path, n, op.uc2ue)) {
-    op.uc2ue = pinv_jacobi(K, n, svd_eps, &op.rank);
-    save_cache(path, n, op.uc2ue);
+  std::vector<double> W, V, sig, packed;
+  if (load_cache(path, n, packed)) {
+    const size_t nn = (size_t)n * n;
+    W.assign(packed.begin(), packed.begin() + nn);
+    V.assign(packed.begin() + nn, packed.begin() + 2 * nn);
+    sig.assign(packed.begin() + 2 * nn, packed.end());
+  } else {
+    jacobi_svd(K, n, W, V, sig);
+    packed = W;
+    packed.insert(packed.end(), V.begin(), V.end());
+    packed.insert(packed.end(), sig.begin(), sig.end());
+    save_cache(path, n, packed);
   }
+  op.uc2ue = pinv_from_svd(W, V, sig, n, svd_eps, &op.rank);
+  pinv_factors(W, V, sig, n, svd_eps, op);
   op.dc2de.resize((size_t)n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) op.dc2de[(size_t)i * n + j] = op.uc2ue[(size_t)j * n + i];
   // M2M and L2L per child octant c (bit0 x, bit1 y, bit2 z; child centre = parent centre + 0.5 o r_parent)
   op.m2m.resize(8);
   op.l2l.resize(8);
+  op.m2m_q.resize(8);
+  op.l2l_q.resize(8);
   for (int c = 0; c < 8; ++c) {
     double o[3] = {(c & 1) ? 1.0 : -1.0, (c & 2) ? 1.0 : -1.0, (c & 4) ? 1.0 : -1.0};
     // parent frame (unit parent half-width): child upward equivalent surface
@@ -293,12 +343,14 @@ Operators build_operators(int p, const Elastic& e, double svd_eps) {
     std::vector<double> Kc((size_t)n * n);
     kernel_matrix_U(e, uc.data(), op.n_eq, che.data(), op.n_eq, Kc.data());
     op.m2m[c] = matmul(op.uc2ue, Kc, n);
+    op.m2m_q[c] = matmul(Kc, op.uc2ue, n);
     // child frame (unit child half-width): parent downward equivalent surface at -o with half-width 2*RE_DN
     std::vector<double> cdc = scaled(RC_DN, 0, 0, 0);
     std::vector<double> pde = scaled(2.0 * RE_DN, -o[0], -o[1], -o[2]);
     std::vector<double> Kl((size_t)n * n);
     kernel_matrix_U(e, cdc.data(), op.n_eq, pde.data(), op.n_eq, Kl.data());
     op.l2l[c] = matmul(op.dc2de, Kl, n);
+    op.l2l_q[c] = matmul(Kl, op.dc2de, n);
   }
   // M2L for every index offset d in [-3,3]^3 with max |d_i| >= 2 (316 offsets)
   std::vector<double> dc = scaled(RC_DN, 0, 0, 0);

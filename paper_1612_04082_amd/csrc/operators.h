@@ -11,8 +11,11 @@ struct Operators {
   double r_up_equiv = 0, r_up_check = 0, r_dn_check = 0, r_dn_equiv = 0;
   std::vector<double> surf;                 // n_eq x 3 unit cube-surface points
   std::vector<double> uc2ue, dc2de;         // n x n
+  std::vector<double> fu1, fu2, fd1, fd2;   // n x n factors: UC2UE = fu2 fu1, DC2DE = fd2 fd1
   std::vector<std::vector<double>> m2m;     // 8 x (n x n)
   std::vector<std::vector<double>> l2l;     // 8 x (n x n)
+  std::vector<std::vector<double>> m2m_q;   // 8 x (n x n): the same translations on check potentials
+  std::vector<std::vector<double>> l2l_q;   // 8 x (n x n)
   std::vector<std::vector<double>> m2l;     // 316 x (n x n)
   std::vector<int> m2l_index;               // 343 -> compact index (or -1), key (dx+3)+7(dy+3)+49(dz+3)
 };

@@ -31,6 +31,9 @@ struct Plan {
   Elastic el{};
   int prec = 0;
   bool alias = false, has_nrm = false, empty = false;
+  // FP32 translations (KFMM_FP32, KFMM_FP32_M2L_SPLIT16): M2M and L2L on check potentials and factored
+  // pseudo-inverses, in FP32 on FP32 buffers; otherwise the translations run in FP64
+  bool f32t = false;
   int64_t n_src = 0, n_trg = 0;
   int NC = 0, n_eq = 0;
   std::shared_ptr<DeviceOps> ops;
@@ -44,6 +47,8 @@ struct Plan {
   int n_leaves_src = 0, n_leaves_trg = 0, n_x_boxes = 0;
   int *leaves_src = nullptr, *leaves_trg = nullptr, *x_boxes = nullptr;
   GemmJob job_uc2ue, job_m2l, job_dc2de;
+  // FP32 translations: UC2UE over every box with sources at level >= 2, DC2DE over the target leaves
+  GemmJob job_up_all, job_dn_leaf;
   // compressed M2L (FP32 with opts.m2l_tol > 0)
   std::shared_ptr<CompressedM2L> comp;
   GemmJob job_ut, job_dcx;  // U^T projection of source boxes; DC2DE of the X-list rows
@@ -52,14 +57,19 @@ struct Plan {
   // KFMM_FP32_M2L_SPLIT16: M2L source vectors split into FP16 high / low parts, power-of-two scale per box
   uint16_t* phi_h3 = nullptr;
   float* phi_h3_scale = nullptr;
+  uint16_t* phi_up_h3 = nullptr;  // compressed case: phi_up split the same way (input of the U^T projection)
+  float* phi_up_h3_scale = nullptr;
   // M2L: per-pair output slots (FP64 or FP32) and their fixed-order reduction per target box
   void* m2l_slots = nullptr;
   int m2l_red_n = 0;
   int *m2l_red_box = nullptr, *m2l_red_off = nullptr, *m2l_red_idx = nullptr;
   std::vector<UpLevel> up_levels;
   std::vector<GemmJob> dn_levels;
-  // per-box coefficient buffers (n_box x NC)
+  // per-box coefficient buffers (n_box x NC): FP64 translations
   double *q_up = nullptr, *phi_up = nullptr, *phi_dn = nullptr, *tmp = nullptr;
+  // FP32 translations: check potentials (upward, then downward qhat), work rows, reduced compressed check
+  // potentials (n_box x NCr) and X-list rows; the equivalent densities are phi_up_lo / phi_dn_lo
+  float *q_f = nullptr, *tmp_f = nullptr, *q_t_f = nullptr, *qx_f = nullptr;
   void *phi_up_lo = nullptr, *phi_dn_lo = nullptr, *phi_up_bf = nullptr;
   // W pairs (CSR order of the W lists): one output slot of nt(B) x 6 doubles each
   int n_wp = 0;
