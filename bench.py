@@ -3,12 +3,13 @@
 Workload (the configuration the headline metric is quoted on): the 120 x 20 x 20 box-beam surface,
 201,344 quadrature points with outward normals and area weights, targets = sources, random single-
 and double-layer densities N(0,1); one step = one fmm_eval of the displacement of the combined
-single + double layer (S2M, M2M, M2L, L2L, X, W, L2T, near field), FP32 arithmetic with FP64
-translations, p = 8, leaf <= 128 (the smallest order that reaches 1e-5 relative error on this
-surface; p = 6 and p = 7 stop near 1.5e-4 and 2.4e-5), M2L compressed onto a shared basis with relative
-cutoff 3e-7 (463 directions, kept as 480 = the padded width of the contraction; 3.3e-6 error against
-2.4e-6 dense).  The plan (tree, lists, operators) is built once outside the timed
-region, as the paper excludes tree construction from its per-pass rate.
+single + double layer (S2M, M2M, M2L, L2L, X, W, L2T, near field), p = 8, leaf <= 128 (the smallest
+order that reaches 1e-5 relative error on this surface; p = 6 and p = 7 stop near 1.5e-4 and 2.4e-5).
+Default arithmetic (--precision split16): point evaluations and translations in FP32 (M2M / L2L on
+check potentials, factored pseudo-inverses), the M2L contraction on the FP16 matrix cores with operands
+split into high and low FP16 parts; M2L compressed onto a shared basis with relative cutoff 3e-7 (463
+directions, kept as 480 = the padded width of the contraction).  The plan (tree, lists, operators) is
+built once outside the timed region, as the paper excludes tree construction from its per-pass rate.
 
 Printed JSON line: metric/value/unit, timing, the relative error on a 40,000-target sample against the
 FP64 oracle, the roofline of the dominant kernel (M2L contraction on the matrix cores) from HIP events
@@ -31,16 +32,16 @@ KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "bf16": "k_gem
 
 # HBM bytes of one M2L launch of the default configuration, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
-# profiles/m2l_fp32_boxbeam_p8_leaf128.md.  Valid only for the kernel sources it was measured on.
-M2L_TRAFFIC = {"sources_sha256": "896706bb9ba871abeba2a6cf2ddc167ccfa75f22616af13a732fca157b48ff4a",
-               "fetch_kib": 443939.0, "write_kib": 212896.0}
-M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_f32.hip",
-               "paper_1612_04082_amd/csrc/fmm.hip")
+# profiles/m2l_split16_boxbeam_p8_leaf128.md.  Valid only for the kernel sources it was measured on.
+M2L_TRAFFIC = {"sources_sha256": "135e1a1034ea8812b492280d1158365a1d27b331e5b4986d7a1d6f4c27021106",
+               "fetch_kib": 442864.0, "write_kib": 212899.0}
+M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
+               "paper_1612_04082_amd/csrc/gemm.h")
 
 
 def m2l_traffic_bytes(args):
     import hashlib
-    if (args.precision, args.p, args.leaf, args.m2l_tol) != ("fp32", 8, 128, 3e-7):
+    if (args.precision, args.p, args.leaf, args.m2l_tol) != ("split16", 8, 128, 3e-7):
         return None
     h = hashlib.sha256()
     for f in M2L_SOURCES:
@@ -56,7 +57,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "split16"], default="fp32")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "split16"], default="split16")
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=128)
     ap.add_argument("--sample", type=int, default=40000)

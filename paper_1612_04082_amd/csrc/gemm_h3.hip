@@ -29,6 +29,60 @@ __device__ __forceinline__ float pow2_scale(T m) {
   return ldexpf(1.0f, e);
 }
 
+// Split of one 8-value chunk with the multiplier inv (a power of two): [hi of the 8][lo of the 8].
+template <typename TIN>
+__device__ __forceinline__ void split8(const TIN* v, double inv, uint4* d) {
+  union {
+    _Float16 h[16];
+    uint4 q[2];
+  } u;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double x = (double)v[j] * inv;
+    const _Float16 hi = (_Float16)(float)x;
+    u.h[j] = hi;
+    u.h[8 + j] = (_Float16)(float)(x - (double)hi);
+  }
+  d[0] = u.q[0];
+  d[1] = u.q[1];
+}
+
+// Short rows (len <= 64 * 8 * CH, rows 16-byte aligned): one wave per row, every chunk read once into
+// registers (up to CH per lane), the scale from a wave reduction, then split and stored.
+template <int CH>
+__global__ __launch_bounds__(64) void k_split_h3_short(int64_t len, const float* __restrict__ src, int64_t ld,
+                                                       uint4* __restrict__ dst, float* __restrict__ scale) {
+  const int64_t row = blockIdx.x;
+  const float* x = src + row * ld;
+  const int lane = threadIdx.x, nch = (int)(len / 8);
+  float4_t v[CH][2];
+  float m = 0.0f;
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int c = lane + 64 * k;
+    if (c < nch) {
+      v[k][0] = *(const float4_t*)(x + 8 * c);
+      v[k][1] = *(const float4_t*)(x + 8 * c + 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m = fmaxf(m, fmaxf(fabsf(v[k][0][q]), fabsf(v[k][1][q])));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  const float s = pow2_scale(m);
+  if (lane == 0) scale[row] = s;
+  const double inv = 1.0 / (double)s;
+  uint4* d = dst + row * (len / 4);
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int c = lane + 64 * k;
+    if (c < nch) {
+      const float f[8] = {v[k][0][0], v[k][0][1], v[k][0][2], v[k][0][3], v[k][1][0], v[k][1][1], v[k][1][2], v[k][1][3]};
+      split8(f, inv, d + 2 * c);
+    }
+  }
+}
+
 // One wave per row: the row's power-of-two scale (written to scale[row]) and its split copy.
 // Rows are `len` values (a multiple of 8) at stride ld; split rows are 2 * len FP16 at stride 2 * len.
 template <typename TIN>
@@ -45,21 +99,7 @@ __global__ __launch_bounds__(64) void k_split_h3(int64_t len, const TIN* __restr
   if (lane == 0) scale[row] = s;
   const double inv = 1.0 / (double)s;  // exact: s is a power of two
   uint4* d = dst + row * (len / 4);
-  for (int64_t c = lane; c < len / 8; c += 64) {
-    union {
-      _Float16 h[16];
-      uint4 q[2];
-    } u;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const double v = (double)x[8 * c + j] * inv;
-      const _Float16 hi = (_Float16)(float)v;
-      u.h[j] = hi;
-      u.h[8 + j] = (_Float16)(float)(v - (double)hi);
-    }
-    d[2 * c] = u.q[0];
-    d[2 * c + 1] = u.q[1];
-  }
+  for (int64_t c = lane; c < len / 8; c += 64) split8(x + 8 * c, inv, d + 2 * c);
 }
 
 // Workgroup tile (16*TM) rows x 128 columns, 4 waves side by side: wave w owns columns [32w, 32w+32)
@@ -193,7 +233,16 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
 void split_h3(const float* src, int64_t n_rows, int64_t len, int64_t ld, uint16_t* dst, float* scale, hipStream_t s) {
   if (n_rows == 0) return;
   KFMM_REQUIRE(len % 8 == 0, "split_h3: row length must be a multiple of 8");
-  hipLaunchKernelGGL((k_split_h3<float>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst, scale);
+  const bool aligned = ld % 4 == 0 && ((uintptr_t)src & 15) == 0;
+  if (aligned && len <= 64 * 8)
+    hipLaunchKernelGGL((k_split_h3_short<1>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst,
+                       scale);
+  else if (aligned && len <= 64 * 8 * 2)
+    hipLaunchKernelGGL((k_split_h3_short<2>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst,
+                       scale);
+  else
+    hipLaunchKernelGGL((k_split_h3<float>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst,
+                       scale);
   KFMM_HIP(hipGetLastError());
 }
 void split_h3(const double* src, int64_t n_rows, int64_t len, int64_t ld, uint16_t* dst, float* scale,
