@@ -48,10 +48,12 @@ enum {
                              form (an orthogonal rotation, then a column-scaled one), once per box */
   KFMM_FP32_M2L_BF16 = 2, /* near field, check/equivalent evaluations in FP32, M2L in BF16 on the matrix
                              cores (FP32 accumulation), pseudo-inverse and M2M/L2L translations in FP64 */
-  KFMM_FP32_M2L_SPLIT16 = 3 /* as KFMM_FP32 but the M2L contractions on the FP16 matrix cores: every operator
-                               and every source vector, scaled by a power of two, is split into a high and a
-                               low FP16 part and the product is accumulated in FP32 from the three terms
-                               hi*hi + hi*lo + lo*hi (about 22-bit operands, close to FP32 accuracy) */
+  KFMM_FP32_M2L_SPLIT16 = 3 /* as KFMM_FP32 but the M2L contractions, the M2M/L2L translations on check
+                               potentials and the orthogonal factors of the pseudo-inverses on the FP16
+                               matrix cores: every operator and every input vector, scaled by a power of
+                               two, is split into a high and a low FP16 part and the product is accumulated
+                               in FP32 from hi*hi + hi*lo + lo*hi (about 22-bit operands, close to FP32
+                               accuracy); the column-scaled pseudo-inverse factors stay FP32 */
 };
 
 /* Target kind of fmm_eval. */

@@ -54,6 +54,8 @@ struct CompressedM2L {
   float* Ch3_scale = nullptr;   // power-of-two scale per operator
   uint16_t* Ut_h3 = nullptr;    // Ut32 split likewise (one operator)
   float* Ut_h3_scale = nullptr;
+  uint16_t* U_h3 = nullptr;     // U32 split likewise (one operator)
+  float* U_h3_scale = nullptr;
 };
 
 struct DeviceOps {
@@ -67,6 +69,10 @@ struct DeviceOps {
   __hip_bfloat16* m2l16 = nullptr;
   uint16_t* m2l_h3 = nullptr;     // m2l64 split into FP16 high / low parts, made on first use
   float* m2l_h3_scale = nullptr;  // power-of-two scale per operator
+  // split-FP16 copies (one scale per operator) of M2M_q, L2L_q (8 each) and of the orthogonal pseudo-inverse
+  // factors fu1, fd1, made on first use
+  uint16_t *m2mq_h3 = nullptr, *l2lq_h3 = nullptr, *fu1_h3 = nullptr, *fd1_h3 = nullptr;
+  float *m2mq_h3_scale = nullptr, *l2lq_h3_scale = nullptr, *fu1_h3_scale = nullptr, *fd1_h3_scale = nullptr;
   std::mutex h3_mutex;
   double* surf = nullptr;  // n_eq x 3
   std::vector<int> m2l_index;
@@ -300,16 +306,21 @@ __global__ __launch_bounds__(256) void k_slot_reduce(const int* __restrict__ box
   }
 }
 
-// phi_up(parent) = sum over children with sources of T(child), children in order
+// phi_up(parent) = sum over children with sources of T(child), children in order.  With split != nullptr
+// (FP32 only) the parent's row is also written in split-FP16 form (see split_h3: power-of-two scale from
+// the row's largest magnitude, [hi 8 | lo 8] chunks), for the split-FP16 products of the next level.
 template <typename T>
 __global__ __launch_bounds__(256) void k_m2m_reduce(const int* parents, int n_par, const int* child_first,
                                                     const int* child_count, const int* src_b, const int* src_e,
-                                                    const T* __restrict__ tmp, T* __restrict__ phi, int NC) {
+                                                    const T* __restrict__ tmp, T* __restrict__ phi, int NC,
+                                                    uint16_t* __restrict__ split = nullptr,
+                                                    float* __restrict__ split_scale = nullptr) {
   constexpr int V = Vec16<T>::V;
   int pi = blockIdx.x;
   if (pi >= n_par) return;
   int P = parents[pi];
   int f = child_first[P], nc = child_count[P];
+  float m = 0.0f;
   for (int c = threadIdx.x * V; c < NC; c += blockDim.x * V) {
     double acc[V] = {};
     for (int k = 0; k < nc; ++k) {
@@ -321,7 +332,41 @@ __global__ __launch_bounds__(256) void k_m2m_reduce(const int* parents, int n_pa
       }
     }
 #pragma unroll
-    for (int e = 0; e < V; ++e) phi[(size_t)P * NC + c + e] = (T)acc[e];
+    for (int e = 0; e < V; ++e) {
+      phi[(size_t)P * NC + c + e] = (T)acc[e];
+      m = fmaxf(m, fabsf((float)(T)acc[e]));
+    }
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (!split) return;
+    // block maximum: waves by shuffles, then across the (at most 4) waves through LDS
+    __shared__ float wmax[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = wmax[0];
+    for (int w = 1; w < (int)(blockDim.x + 63) / 64; ++w) m = fmaxf(m, wmax[w]);
+    int e2 = 0;
+    float sc = 1.0f;
+    if (m > 0.0f && m < INFINITY) {
+      frexpf(m, &e2);  // m = f 2^e2, f in [0.5, 1): scale to put m in [2^14, 2^15)
+      sc = ldexpf(1.0f, max(-126, min(127, e2 - 15)));
+    }
+    if (threadIdx.x == 0) split_scale[P] = sc;
+    const float inv = 1.0f / sc;
+    _Float16* d = (_Float16*)split + (size_t)P * 2 * NC;
+    for (int c = threadIdx.x * V; c < NC; c += blockDim.x * V) {  // 4 values: half of one 8-value chunk
+      const float* x = (const float*)phi + (size_t)P * NC + c;     // this thread's own writes
+      _Float16* hi = d + 16 * (c / 8) + (c % 8);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const float v = x[e] * inv;
+        const _Float16 h = (_Float16)v;
+        hi[e] = h;
+        hi[8 + e] = (_Float16)(v - (float)h);
+      }
+    }
   }
 }
 
@@ -428,8 +473,24 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
 static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
   std::lock_guard<std::mutex> lock(d.h3_mutex);
   const int nops = 316;
+  const int64_t sq = (int64_t)d.NC * d.NC;
+  auto split_set = [&](const float* src, int n, int64_t len, uint16_t*& dst, float*& sc) {
+    dst = d.arena.get<uint16_t>((size_t)n * 2 * len);
+    sc = d.arena.get<float>(n);
+    split_h3(src, n, len, len, dst, sc, s);
+  };
+  if (!d.m2mq_h3) {
+    split_set(d.m2mq32, 8, sq, d.m2mq_h3, d.m2mq_h3_scale);
+    split_set(d.l2lq32, 8, sq, d.l2lq_h3, d.l2lq_h3_scale);
+    split_set(d.fu1, 1, sq, d.fu1_h3, d.fu1_h3_scale);
+    split_set(d.fd1, 1, sq, d.fd1_h3, d.fd1_h3_scale);
+  }
   if (c) {
-    if (c->Ch3) return;
+    if (c->Ch3) {
+      KFMM_HIP(hipStreamSynchronize(s));
+      return;
+    }
+    split_set(c->U32, 1, (int64_t)d.NC * c->NCr, c->U_h3, c->U_h3_scale);
     const int64_t len = (int64_t)c->NCr * c->NCr;
     c->Ch3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
     c->Ch3_scale = d.arena.get<float>(nops);
@@ -438,8 +499,7 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     c->Ut_h3 = d.arena.get<uint16_t>((size_t)2 * ulen);
     c->Ut_h3_scale = d.arena.get<float>(1);
     split_h3(c->Ut32, 1, ulen, ulen, c->Ut_h3, c->Ut_h3_scale, s);
-  } else {
-    if (d.m2l_h3) return;
+  } else if (!d.m2l_h3) {
     const int64_t len = (int64_t)d.NC * d.NC;
     d.m2l_h3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
     d.m2l_h3_scale = d.arena.get<float>(nops);
@@ -969,10 +1029,9 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       ensure_split_ops(*P->ops, P->comp.get(), s);
       P->phi_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * slot_len);
       P->phi_h3_scale = P->arena.get<float>(std::max(nb, 1));
-      if (P->comp) {  // the U^T projection runs split too: phi_up split per box
-        P->phi_up_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * D.NC);
-        P->phi_up_h3_scale = P->arena.get<float>(std::max(nb, 1));
-      }
+      // NC-wide split rows per box: check potentials for the translations, phi_up for the U^T projection
+      P->phi_up_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * D.NC);
+      P->phi_up_h3_scale = P->arena.get<float>(std::max(nb, 1));
     }
     P->n_v_pairs = (int64_t)c.op.size();
     if (std::getenv("KFMM_DEBUG_STATS")) {  // occupancy of target-box blocks x offsets (design statistics)
@@ -1016,12 +1075,14 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       P->job_dcx = upload_job(P->arena, cx, s, wide(cx));
     }
     P->dn_levels.clear();
+    P->dn_lv.clear();
     for (int l = 3; l <= t.depth; ++l) {
       GemmCols cl;
       for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
         if (ht(b)) cl.add(octant(b), t.h_parent[b], b);
       if (cl.op.empty()) continue;
       P->dn_levels.push_back(upload_job(P->arena, sorted_by_op(cl), s, wide(cl)));
+      P->dn_lv.push_back(l);
     }
   }
   // W pairs and their output slots
@@ -1214,6 +1275,13 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
                          2.95, NC, kc, P.q_up);
   });
   mark(KFMM_PH_UC2UE);
+  const bool split16 = P.prec == KFMM_FP32_M2L_SPLIT16;
+  uint16_t* const xq = P.phi_up_h3;  // split16: NC-wide split rows (check potentials, later phi_up)
+  float* const xq_scale = P.phi_up_h3_scale;
+  if (split16) split_h3(P.q_f, nb, NC, NC, xq, xq_scale, s);  // the leaves' check potentials
+  // split-FP16 products pay off on launches of a dozen column tiles or more; smaller ones (the upper levels)
+  // run the FP32 split-K kernel, which cuts K across more workgroups
+  auto big = [](const GemmJob& J) { return J.n_tiles >= 12; };
   float* const phi_up_f = (float*)P.phi_up_lo;
   float* const phi_dn_f = (float*)P.phi_dn_lo;
   // FP32 translations: UC2UE runs after the M2M chain, for every box at once (in the M2M phase)
@@ -1227,11 +1295,15 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   // M2M
   mark(KFMM_PH_M2M);
   for (const UpLevel& U : P.up_levels) {
-    if (P.f32t) {  // qhat_up(parent) = sum_c M2M_q_c qhat_up(child)
-      gemm_f32(U.job, D.m2mq32, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
+    if (P.f32t) {  // qhat_up(parent) = sum_c M2M_q_c qhat_up(child); split16: parents' split rows too
+      if (split16 && big(U.job))
+        gemm_h3(U.job, D.m2mq_h3, D.m2mq_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, P.tmp_f, kStore, s);
+      else
+        gemm_f32(U.job, D.m2mq32, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
       if (U.n_par)
         hipLaunchKernelGGL(k_m2m_reduce<float>, dim3(U.n_par), dim3(reduce_block<float>(NC)), 0, s, U.parents,
-                           U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp_f, P.q_f, NC);
+                           U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp_f, P.q_f, NC,
+                           split16 ? xq : nullptr, split16 ? xq_scale : nullptr);
     } else {
       gemm_f64(U.job, D.m2m, GemmDims::Sq(NC), P.phi_up, P.tmp, kStore, s);
       if (U.n_par)
@@ -1239,8 +1311,12 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
                            U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
     }
   }
-  if (P.f32t) {  // phi_up = UC2UE qhat_up = fu2 (fu1 qhat_up)
-    gemm_f32(P.job_up_all, D.fu1, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
+  if (P.f32t) {  // phi_up = UC2UE qhat_up = fu2 (fu1 qhat_up); fu1 is orthogonal (split16 products)
+    if (split16)
+      gemm_h3(P.job_up_all, D.fu1_h3, D.fu1_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, P.tmp_f, kStore,
+              s);
+    else
+      gemm_f32(P.job_up_all, D.fu1, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
     gemm_f32(P.job_up_all, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
   }
   KFMM_HIP(hipGetLastError());
@@ -1249,7 +1325,6 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   mark(KFMM_PH_M2L_PREP);
   double* qhat = P.q_up;  // reuse: the S2M potentials are consumed (FP64 translations)
   float* qhat_f = P.q_f;  // the same with FP32 translations
-  const bool split16 = P.prec == KFMM_FP32_M2L_SPLIT16;
   const bool fused_down = (P.prec == KFMM_FP32 || split16) && P.comp;  // DC2DE * U applied to q~ (no qhat)
   if (!fused_down) {
     if (P.f32t)
@@ -1352,15 +1427,37 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   if (P.f32t) {
     // downward pass in FP32 on check potentials: qhat = U q~ + X rows (compressed), qhat(child) +=
     // L2L_q qhat(parent) level by level, then phi_dn = DC2DE qhat = fd2 (fd1 qhat) at the target leaves
+    // (split16: U, L2L_q and fd1 as split-FP16 products, their inputs split level by level)
     if (fused_down) {
       const int NCr = P.comp->NCr;
-      gemm_f32(P.job_dc2de, P.comp->U32, GemmDims{NC, NCr, NCr, NC}, P.q_t_f, qhat_f, kStore, s);
+      if (split16) {
+        split_h3(P.q_t_f, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
+        gemm_h3(P.job_dc2de, P.comp->U_h3, P.comp->U_h3_scale, GemmDims{NC, NCr, 2 * NCr, NC}, P.phi_h3,
+                P.phi_h3_scale, qhat_f, kStore, s);
+      } else {
+        gemm_f32(P.job_dc2de, P.comp->U32, GemmDims{NC, NCr, NCr, NC}, P.q_t_f, qhat_f, kStore, s);
+      }
       if (P.n_x_boxes)
         hipLaunchKernelGGL(k_add_rows<float>, dim3(P.n_x_boxes), dim3(reduce_block<float>(NC)), 0, s, P.x_boxes,
                            (const float*)P.qx_f, qhat_f, NC);
     }
-    for (const GemmJob& J : P.dn_levels) gemm_f32(J, D.l2lq32, GemmDims::Sq(NC), qhat_f, qhat_f, kAdd, s);
-    gemm_f32(P.job_dn_leaf, D.fd1, GemmDims::Sq(NC), qhat_f, P.tmp_f, kStore, s);
+    for (size_t i = 0; i < P.dn_levels.size(); ++i) {
+      if (split16 && big(P.dn_levels[i])) {  // split the parents' level, then qhat(child) += L2L_q qhat(parent)
+        const int l = P.dn_lv[i], b0 = t.level_start[l - 1], b1 = t.level_start[l];
+        split_h3(qhat_f + (size_t)b0 * NC, b1 - b0, NC, NC, xq + (size_t)b0 * 2 * NC, xq_scale + b0, s);
+        gemm_h3(P.dn_levels[i], D.l2lq_h3, D.l2lq_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, qhat_f,
+                kAdd, s);
+      } else {
+        gemm_f32(P.dn_levels[i], D.l2lq32, GemmDims::Sq(NC), qhat_f, qhat_f, kAdd, s);
+      }
+    }
+    if (split16) {
+      split_h3(qhat_f, nb, NC, NC, xq, xq_scale, s);
+      gemm_h3(P.job_dn_leaf, D.fd1_h3, D.fd1_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, P.tmp_f, kStore,
+              s);
+    } else {
+      gemm_f32(P.job_dn_leaf, D.fd1, GemmDims::Sq(NC), qhat_f, P.tmp_f, kStore, s);
+    }
     gemm_f32(P.job_dn_leaf, D.fd2, GemmDims::Sq(NC), P.tmp_f, phi_dn_f, kStore, s);
   } else {
     // downward pass in FP64

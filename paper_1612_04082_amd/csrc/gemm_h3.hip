@@ -47,14 +47,17 @@ __device__ __forceinline__ void split8(const TIN* v, double inv, uint4* d) {
   d[1] = u.q[1];
 }
 
-// Short rows (len <= 64 * 8 * CH, rows 16-byte aligned): one wave per row, every chunk read once into
-// registers (up to CH per lane), the scale from a wave reduction, then split and stored.
+// Short rows (len <= 64 * 8 * CH, rows 16-byte aligned): one wave per row (four rows per workgroup), every
+// chunk read once into registers (up to CH per lane), the scale from a wave reduction, then split (in FP32:
+// v - fp16(v) is exact) and stored.
 template <int CH>
-__global__ __launch_bounds__(64) void k_split_h3_short(int64_t len, const float* __restrict__ src, int64_t ld,
-                                                       uint4* __restrict__ dst, float* __restrict__ scale) {
-  const int64_t row = blockIdx.x;
+__global__ __launch_bounds__(256) void k_split_h3_short(int64_t n_rows, int64_t len, const float* __restrict__ src,
+                                                        int64_t ld, uint4* __restrict__ dst,
+                                                        float* __restrict__ scale) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n_rows) return;  // whole waves leave; no barrier follows
   const float* x = src + row * ld;
-  const int lane = threadIdx.x, nch = (int)(len / 8);
+  const int lane = threadIdx.x & 63, nch = (int)(len / 8);
   float4_t v[CH][2];
   float m = 0.0f;
 #pragma unroll
@@ -71,14 +74,21 @@ __global__ __launch_bounds__(64) void k_split_h3_short(int64_t len, const float*
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   const float s = pow2_scale(m);
   if (lane == 0) scale[row] = s;
-  const double inv = 1.0 / (double)s;
+  const float inv = 1.0f / s;  // exact: s is a power of two
   uint4* d = dst + row * (len / 4);
 #pragma unroll
   for (int k = 0; k < CH; ++k) {
     const int c = lane + 64 * k;
     if (c < nch) {
-      const float f[8] = {v[k][0][0], v[k][0][1], v[k][0][2], v[k][0][3], v[k][1][0], v[k][1][1], v[k][1][2], v[k][1][3]};
-      split8(f, inv, d + 2 * c);
+      half8_t h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float y = (j < 4 ? v[k][0][j] : v[k][1][j - 4]) * inv;
+        h[j] = (_Float16)y;
+        l[j] = (_Float16)(y - (float)h[j]);
+      }
+      d[2 * c] = __builtin_bit_cast(uint4, h);
+      d[2 * c + 1] = __builtin_bit_cast(uint4, l);
     }
   }
 }
@@ -234,12 +244,11 @@ void split_h3(const float* src, int64_t n_rows, int64_t len, int64_t ld, uint16_
   if (n_rows == 0) return;
   KFMM_REQUIRE(len % 8 == 0, "split_h3: row length must be a multiple of 8");
   const bool aligned = ld % 4 == 0 && ((uintptr_t)src & 15) == 0;
+  const unsigned nblk = (unsigned)((n_rows + 3) / 4);
   if (aligned && len <= 64 * 8)
-    hipLaunchKernelGGL((k_split_h3_short<1>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst,
-                       scale);
+    hipLaunchKernelGGL((k_split_h3_short<1>), dim3(nblk), dim3(256), 0, s, n_rows, len, src, ld, (uint4*)dst, scale);
   else if (aligned && len <= 64 * 8 * 2)
-    hipLaunchKernelGGL((k_split_h3_short<2>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst,
-                       scale);
+    hipLaunchKernelGGL((k_split_h3_short<2>), dim3(nblk), dim3(256), 0, s, n_rows, len, src, ld, (uint4*)dst, scale);
   else
     hipLaunchKernelGGL((k_split_h3<float>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst,
                        scale);
