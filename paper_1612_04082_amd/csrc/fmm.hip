@@ -1024,7 +1024,11 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       }
     }
     P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
-    P->job_m2l = upload_job(P->arena, sc, s, o.precision == KFMM_FP32 || split16 ? 2 * kGemmBN : kGemmBN);
+    // column tiles: 128 (FP32 and split FP16), 192 for the split-FP16 compressed contraction when its rank is a
+    // multiple of 160 (160 x 192 workgroup tiles, fewer operand bytes per product), 64 otherwise
+    int m2l_cols = o.precision == KFMM_FP32 || split16 ? 2 * kGemmBN : kGemmBN;
+    if (split16 && P->comp && P->comp->NCr % 160 == 0) m2l_cols = 3 * kGemmBN;
+    P->job_m2l = upload_job(P->arena, sc, s, m2l_cols);
     if (split16) {
       ensure_split_ops(*P->ops, P->comp.get(), s);
       P->phi_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * slot_len);

@@ -112,18 +112,20 @@ __global__ __launch_bounds__(64) void k_split_h3(int64_t len, const TIN* __restr
   for (int64_t c = lane; c < len / 8; c += 64) split8(x + 8 * c, inv, d + 2 * c);
 }
 
-// Workgroup tile (16*TM) rows x 128 columns, 4 waves side by side: wave w owns columns [32w, 32w+32)
-// (two 16-column MFMA blocks) and all rows.  The operator tile (hi and lo) is staged in LDS per 32-value
+// Workgroup tile (16*TM) rows x (64*TN) columns, 4 waves side by side: wave w owns columns
+// [16 TN w, 16 TN (w+1)) (TN 16-column MFMA blocks) and all rows.  Larger tiles read fewer operand bytes per
+// product, which is what limits this kernel (at the M2L shape 160 x 192 tiles took 174 us where 96 x 128
+// took 226 us, with the same occupancy-limited register budget).  The operator tile (hi and lo) is staged in LDS per 32-value
 // k-stage, double-buffered (one barrier per stage); LDS rows are 36 words apart so that the 16-byte
 // operand reads of any 16 consecutive lanes fall in distinct banks.  X operands are private to a wave
 // and are loaded straight from global memory into registers, one stage ahead.
-template <int TM>
+template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, GemmDims dm,
                                                  const float* __restrict__ a_scale, const int4* __restrict__ tiles,
                                                  const int* __restrict__ in_idx, const int* __restrict__ out_idx,
                                                  const double* __restrict__ scale, const u32x4_t* __restrict__ X,
                                                  const float* __restrict__ x_scale, float* __restrict__ Y, int mode) {
-  constexpr int BM = 16 * TM, TN = 2, RW = 36;
+  constexpr int BM = 16 * TM, RW = 36;
   constexpr int A_PER_THR = BM * 8 / 256;  // 16-byte pieces of the operator tile per thread and stage
   static_assert(BM * 8 % 256 == 0, "operator tile must split into 16-byte pieces");
   __shared__ __attribute__((aligned(16))) uint32_t As[2][BM * RW];
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
   int src[TN];
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
-    const int j = wave * 32 + u * 16 + i16;
+    const int j = wave * 16 * TN + u * 16 + i16;
     ok[u] = j < tile.z;
     src[u] = ok[u] ? in_idx[tile.y + j] : 0;
     xc[u] = X + (size_t)src[u] * (dm.ldx / 8);
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
 #pragma unroll
   for (int u = 0; u < TN; ++u) {
     if (!ok[u]) continue;
-    const int col = tile.y + wave * 32 + u * 16 + i16;
+    const int col = tile.y + wave * 16 * TN + u * 16 + i16;
     const float sc = x_scale[src[u]] * (scale ? (float)scale[col] : 1.0f);
     float* ycol = Y + (size_t)out_idx[col] * dm.ldy + r0 + 4 * g;
 #pragma unroll
@@ -262,18 +264,36 @@ void split_h3(const double* src, int64_t n_rows, int64_t len, int64_t ld, uint16
   KFMM_HIP(hipGetLastError());
 }
 
+template <int TM>
+static void launch_h3(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDims d, const uint16_t* X,
+                      const float* x_scale, float* Y, int mode, hipStream_t s) {
+  const dim3 grid(job.n_tiles, d.M / (16 * TM));
+  const auto* a = (const u32x4_t*)A;
+  const auto* x = (const u32x4_t*)X;
+  if (job.cols_per_tile <= 64)
+    hipLaunchKernelGGL((k_gemm_h3<TM, 1>), grid, dim3(256), 0, s, a, d, a_scale, job.tiles, job.in_idx, job.out_idx,
+                       job.scale, x, x_scale, Y, mode);
+  else if (job.cols_per_tile <= 128)
+    hipLaunchKernelGGL((k_gemm_h3<TM, 2>), grid, dim3(256), 0, s, a, d, a_scale, job.tiles, job.in_idx, job.out_idx,
+                       job.scale, x, x_scale, Y, mode);
+  else
+    hipLaunchKernelGGL((k_gemm_h3<TM, 3>), grid, dim3(256), 0, s, a, d, a_scale, job.tiles, job.in_idx, job.out_idx,
+                       job.scale, x, x_scale, Y, mode);
+}
+
 void gemm_h3(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDims d, const uint16_t* X,
              const float* x_scale, float* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
-  KFMM_REQUIRE(job.cols_per_tile <= 2 * kGemmBN, "gemm_h3: at most 128 columns per tile");
+  KFMM_REQUIRE(job.cols_per_tile <= 3 * kGemmBN, "gemm_h3: at most 192 columns per tile");
   KFMM_REQUIRE(d.K % 32 == 0 && d.ldx % 8 == 0 && d.ldx >= 2 * d.K, "gemm_h3: bad K or ldx");
   if (mode == kStore) KFMM_REQUIRE(d.ldy % 4 == 0, "gemm_h3: ldy must be a multiple of 4 for vector stores");
-  if (d.M % 96 == 0)
-    hipLaunchKernelGGL((k_gemm_h3<6>), dim3(job.n_tiles, d.M / 96), dim3(256), 0, s, (const u32x4_t*)A, d, a_scale,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, (const u32x4_t*)X, x_scale, Y, mode);
+  // 160-row blocks for wide tiles (the M2L contraction at r = 480), else 96- or 64-row blocks
+  if (d.M % 160 == 0 && job.cols_per_tile > 2 * kGemmBN)
+    launch_h3<10>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+  else if (d.M % 96 == 0)
+    launch_h3<6>(job, A, a_scale, d, X, x_scale, Y, mode, s);
   else if (d.M % 64 == 0)
-    hipLaunchKernelGGL((k_gemm_h3<4>), dim3(job.n_tiles, d.M / 64), dim3(256), 0, s, (const u32x4_t*)A, d, a_scale,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, (const u32x4_t*)X, x_scale, Y, mode);
+    launch_h3<4>(job, A, a_scale, d, X, x_scale, Y, mode, s);
   else
     throw Error(-1, "gemm_h3: M must be a multiple of 96 or 64");
   KFMM_HIP(hipGetLastError());

@@ -86,7 +86,15 @@ def test_gemm_128_row_blocks(cuda, precision, tol, kernel):
         assert err < tol, (mode, err)
 
 
-@pytest.mark.parametrize("NC", [96, 192, 256])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_split16_wide_tiles(cuda, mode):
+    """Split FP16 at NC = 480 (the compressed M2L width): 160-row x 192-column workgroup tiles."""
+    err = _case(3, mode, seed=5, NC=480)
+    print(f"mode={mode} rel err {err:.3e}")
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("NC", [96, 192, 256, 480])
 def test_split16_wide_range(cuda, NC):
     """Split-FP16 products with operators and vectors spanning many decades: operators 27 decades apart,
     vectors 20 decades apart, and inside each operator and vector entries spread over 4 decades (rows
