@@ -48,12 +48,11 @@ struct CompressedM2L {
   double* Ut64 = nullptr;  // NCr x NC row-major (row k = k-th basis vector, rows >= r zero)
   double* DU64 = nullptr;  // DC2DE * U, NC x NCr row-major: downward equivalent densities from q~ directly
   float* U32 = nullptr;    // U, NC x NCr row-major (FP32 translations: qhat = U q~)
+  float* G32 = nullptr;    // U^T fu2, NCr x NC row-major (FP32 translations: phi~ = U^T UC2UE qhat = G (fu1 qhat))
   float* Ut32 = nullptr;   // NCr x NC
   float* C32 = nullptr;    // 316 x NCr x NCr row-major
   uint16_t* Ch3 = nullptr;      // C32 split into FP16 high / low parts (see split_h3), made on first use
   float* Ch3_scale = nullptr;   // power-of-two scale per operator
-  uint16_t* Ut_h3 = nullptr;    // Ut32 split likewise (one operator)
-  float* Ut_h3_scale = nullptr;
   uint16_t* U_h3 = nullptr;     // U32 split likewise (one operator)
   float* U_h3_scale = nullptr;
 };
@@ -65,6 +64,7 @@ struct DeviceOps {
   // FP32 translations: factored pseudo-inverses (UC2UE = fu2 fu1, DC2DE = fd2 fd1) and the M2M / L2L
   // translations on check potentials (8 each)
   float *fu1 = nullptr, *fu2 = nullptr, *fd1 = nullptr, *fd2 = nullptr, *m2mq32 = nullptr, *l2lq32 = nullptr;
+  double* fu2t_64 = nullptr;  // fu2 transposed, FP64 (rows = columns of fu2), for U^T fu2
   float* m2l32 = nullptr;
   __hip_bfloat16* m2l16 = nullptr;
   uint16_t* m2l_h3 = nullptr;     // m2l64 split into FP16 high / low parts, made on first use
@@ -150,6 +150,12 @@ static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, 
     d->fu2 = up32(pad_square(op.fu2, op.n, NC));
     d->fd1 = up32(pad_square(op.fd1, op.n, NC));
     d->fd2 = up32(pad_square(op.fd2, op.n, NC));
+    {
+      std::vector<double> f = pad_square(op.fu2, op.n, NC), ft((size_t)NC * NC);
+      for (int i = 0; i < NC; ++i)
+        for (int j = 0; j < NC; ++j) ft[(size_t)j * NC + i] = f[(size_t)i * NC + j];
+      d->fu2t_64 = up(ft);
+    }
     // M2L operators in the requested precisions are uploaded lazily below
     std::vector<double> m2l_all;
     m2l_all.reserve(op.m2l.size() * (size_t)NC * NC);
@@ -452,6 +458,21 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
     c->DU64 = d.arena.get<double>(du.size());
     KFMM_HIP(hipMemcpy(c->DU64, du.data(), sizeof(double) * du.size(), hipMemcpyHostToDevice));
   }
+  {  // G = U^T fu2 (NCr x NC): column c = U^T (fu2 e_c) from the rows of fu2^T, transposed on the host
+    GemmCols cg;
+    for (int c2 = 0; c2 < NC; ++c2) cg.add(0, c2, c2);
+    GemmJob jg = upload_job(tmp, cg, s, kGemmBN);
+    double* Yg = tmp.get<double>((size_t)NC * NCr);
+    gemm_f64(jg, c->Ut64, GemmDims{NCr, NC, NC, NCr}, d.fu2t_64, Yg, kStore, s);
+    std::vector<double> hg((size_t)NC * NCr);
+    KFMM_HIP(hipMemcpyAsync(hg.data(), Yg, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s));
+    KFMM_HIP(hipStreamSynchronize(s));
+    std::vector<float> g32((size_t)NCr * NC, 0.0f);
+    for (int c2 = 0; c2 < NC; ++c2)
+      for (int k = 0; k < NCr; ++k) g32[(size_t)k * NC + c2] = (float)hg[(size_t)c2 * NCr + k];
+    c->G32 = d.arena.get<float>(g32.size());
+    KFMM_HIP(hipMemcpy(c->G32, g32.data(), sizeof(float) * g32.size(), hipMemcpyHostToDevice));
+  }
   {  // U itself (NC x NCr, column k = k-th basis vector) for the FP32 translations
     std::vector<float> u32((size_t)NC * NCr, 0.0f);
     for (int k = 0; k < r; ++k)
@@ -495,10 +516,6 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     c->Ch3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
     c->Ch3_scale = d.arena.get<float>(nops);
     split_h3(c->C32, nops, len, len, c->Ch3, c->Ch3_scale, s);
-    const int64_t ulen = (int64_t)c->NCr * d.NC;
-    c->Ut_h3 = d.arena.get<uint16_t>((size_t)2 * ulen);
-    c->Ut_h3_scale = d.arena.get<float>(1);
-    split_h3(c->Ut32, 1, ulen, ulen, c->Ut_h3, c->Ut_h3_scale, s);
   } else if (!d.m2l_h3) {
     const int64_t len = (int64_t)d.NC * d.NC;
     d.m2l_h3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
@@ -952,6 +969,14 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       for (int b = 0; b < nb; ++b)
         if (t.h_level[b] >= 2 && hs(b)) ca.add(0, b, b);
       P->job_up_all = upload_job(P->arena, ca, s, wide(ca));
+      // with the compressed M2L, full equivalent densities are only read by the W lists: the second
+      // factor runs on the W-list source boxes, the M2L takes U^T UC2UE qhat = G (fu1 qhat) directly
+      std::vector<char> isw(nb, 0);
+      for (int k : t.h_w_idx) isw[k] = 1;
+      GemmCols cw;
+      for (int b = 0; b < nb; ++b)
+        if (isw[b] && t.h_level[b] >= 2 && hs(b)) cw.add(0, b, b);
+      P->job_up_w = upload_job(P->arena, cw, s, wide(cw));
     }
   }
   // M2M per level (deepest first): children with sources, grouped by octant; parents reduce.  Parents
@@ -1321,7 +1346,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
               s);
     else
       gemm_f32(P.job_up_all, D.fu1, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
-    gemm_f32(P.job_up_all, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
+    // fu2: every box for the dense M2L, the W-list boxes only with the compressed one (tmp_f keeps fu1 qhat)
+    gemm_f32(P.comp ? P.job_up_w : P.job_up_all, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
   }
   KFMM_HIP(hipGetLastError());
   // M2L into qhat.  qhat is FP64 in every precision; each box's M2L slots are summed in a fixed order,
@@ -1359,14 +1385,11 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   } else if (fused_down) {
     const CompressedM2L& C = *P.comp;
     const int NCr = C.NCr;
-    if (split16) {
-      split_h3((const float*)phi_up_f, nb, NC, NC, P.phi_up_h3, P.phi_up_h3_scale, s);
-      gemm_h3(P.job_ut, C.Ut_h3, C.Ut_h3_scale, GemmDims{NCr, NC, 2 * NC, NCr}, P.phi_up_h3, P.phi_up_h3_scale,
-              P.phi_t, kStore, s);
-      split_h3(P.phi_t, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
-    } else {
+    if (P.f32t)  // phi~ = U^T UC2UE qhat = G (fu1 qhat)
+      gemm_f32(P.job_ut, C.G32, GemmDims{NCr, NC, NC, NCr}, P.tmp_f, P.phi_t, kStore, s);
+    else
       gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
-    }
+    if (split16) split_h3(P.phi_t, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
     mark(KFMM_PH_M2L);
     m2l_begin();
     if (split16)

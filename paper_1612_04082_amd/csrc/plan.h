@@ -49,6 +49,7 @@ struct Plan {
   GemmJob job_uc2ue, job_m2l, job_dc2de;
   // FP32 translations: UC2UE over every box with sources at level >= 2, DC2DE over the target leaves
   GemmJob job_up_all, job_dn_leaf;
+  GemmJob job_up_w;  // compressed M2L: the W-list source boxes (the only full equivalent densities read)
   // compressed M2L (FP32 with opts.m2l_tol > 0)
   std::shared_ptr<CompressedM2L> comp;
   GemmJob job_ut, job_dcx;  // U^T projection of source boxes; DC2DE of the X-list rows
