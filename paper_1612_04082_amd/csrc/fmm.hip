@@ -49,6 +49,9 @@ struct CompressedM2L {
   double* DU64 = nullptr;  // DC2DE * U, NC x NCr row-major: downward equivalent densities from q~ directly
   float* U32 = nullptr;    // U, NC x NCr row-major (FP32 translations: qhat = U q~)
   float* G32 = nullptr;    // U^T fu2, NCr x NC row-major (FP32 translations: phi~ = U^T UC2UE qhat = G (fu1 qhat))
+  float* Gv32 = nullptr;   // U^T vs = G diag(sigma) (split FP16: phi~ = Gv (diag(inv_sig) fu1 qhat))
+  uint16_t* Gv_h3 = nullptr;
+  float* Gv_h3_scale = nullptr;
   float* Ut32 = nullptr;   // NCr x NC
   float* C32 = nullptr;    // 316 x NCr x NCr row-major
   uint16_t* Ch3 = nullptr;      // C32 split into FP16 high / low parts (see split_h3), made on first use
@@ -65,6 +68,11 @@ struct DeviceOps {
   // translations on check potentials (8 each)
   float *fu1 = nullptr, *fu2 = nullptr, *fd1 = nullptr, *fd2 = nullptr, *m2mq32 = nullptr, *l2lq32 = nullptr;
   double* fu2t_64 = nullptr;  // fu2 transposed, FP64 (rows = columns of fu2), for U^T fu2
+  // fu2 = vs diag(inv_sig), fd2 = us diag(inv_sig): the orthogonal parts (FP32) and 1/sigma (host, device)
+  float *vs32 = nullptr, *us32 = nullptr, *inv_sig32 = nullptr;
+  std::vector<double> inv_sig;
+  uint16_t *vs_h3 = nullptr, *us_h3 = nullptr;  // split-FP16 copies (one scale each), made on first use
+  float *vs_h3_scale = nullptr, *us_h3_scale = nullptr;
   float* m2l32 = nullptr;
   __hip_bfloat16* m2l16 = nullptr;
   uint16_t* m2l_h3 = nullptr;     // m2l64 split into FP16 high / low parts, made on first use
@@ -150,6 +158,11 @@ static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, 
     d->fu2 = up32(pad_square(op.fu2, op.n, NC));
     d->fd1 = up32(pad_square(op.fd1, op.n, NC));
     d->fd2 = up32(pad_square(op.fd2, op.n, NC));
+    d->vs32 = up32(pad_square(op.vs, op.n, NC));
+    d->us32 = up32(pad_square(op.us, op.n, NC));
+    d->inv_sig.assign(NC, 0.0);
+    for (int j = 0; j < op.n; ++j) d->inv_sig[j] = op.inv_sig[j];
+    d->inv_sig32 = up32(d->inv_sig);
     {
       std::vector<double> f = pad_square(op.fu2, op.n, NC), ft((size_t)NC * NC);
       for (int i = 0; i < NC; ++i)
@@ -467,11 +480,17 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
     std::vector<double> hg((size_t)NC * NCr);
     KFMM_HIP(hipMemcpyAsync(hg.data(), Yg, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, s));
     KFMM_HIP(hipStreamSynchronize(s));
-    std::vector<float> g32((size_t)NCr * NC, 0.0f);
+    std::vector<float> g32((size_t)NCr * NC, 0.0f), gv32((size_t)NCr * NC, 0.0f);
     for (int c2 = 0; c2 < NC; ++c2)
-      for (int k = 0; k < NCr; ++k) g32[(size_t)k * NC + c2] = (float)hg[(size_t)c2 * NCr + k];
+      for (int k = 0; k < NCr; ++k) {
+        const double gkc = hg[(size_t)c2 * NCr + k];
+        g32[(size_t)k * NC + c2] = (float)gkc;
+        if (d.inv_sig[c2] > 0) gv32[(size_t)k * NC + c2] = (float)(gkc / d.inv_sig[c2]);
+      }
     c->G32 = d.arena.get<float>(g32.size());
     KFMM_HIP(hipMemcpy(c->G32, g32.data(), sizeof(float) * g32.size(), hipMemcpyHostToDevice));
+    c->Gv32 = d.arena.get<float>(gv32.size());
+    KFMM_HIP(hipMemcpy(c->Gv32, gv32.data(), sizeof(float) * gv32.size(), hipMemcpyHostToDevice));
   }
   {  // U itself (NC x NCr, column k = k-th basis vector) for the FP32 translations
     std::vector<float> u32((size_t)NC * NCr, 0.0f);
@@ -501,6 +520,8 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     split_h3(src, n, len, len, dst, sc, s);
   };
   if (!d.m2mq_h3) {
+    split_set(d.vs32, 1, sq, d.vs_h3, d.vs_h3_scale);
+    split_set(d.us32, 1, sq, d.us_h3, d.us_h3_scale);
     split_set(d.m2mq32, 8, sq, d.m2mq_h3, d.m2mq_h3_scale);
     split_set(d.l2lq32, 8, sq, d.l2lq_h3, d.l2lq_h3_scale);
     split_set(d.fu1, 1, sq, d.fu1_h3, d.fu1_h3_scale);
@@ -512,6 +533,7 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
       return;
     }
     split_set(c->U32, 1, (int64_t)d.NC * c->NCr, c->U_h3, c->U_h3_scale);
+    split_set(c->Gv32, 1, (int64_t)c->NCr * d.NC, c->Gv_h3, c->Gv_h3_scale);
     const int64_t len = (int64_t)c->NCr * c->NCr;
     c->Ch3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
     c->Ch3_scale = d.arena.get<float>(nops);
@@ -1311,6 +1333,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   // split-FP16 products pay off on launches of a dozen column tiles or more; smaller ones (the upper levels)
   // run the FP32 split-K kernel, which cuts K across more workgroups
   auto big = [](const GemmJob& J) { return J.n_tiles >= 12; };
+  // the 1/sigma-scaled split pass handles rows of up to 1024 values (p <= 8); beyond, fu2 / fd2 / G in FP32
+  const bool sig_split = split16 && NC <= 1024;
   float* const phi_up_f = (float*)P.phi_up_lo;
   float* const phi_dn_f = (float*)P.phi_dn_lo;
   // FP32 translations: UC2UE runs after the M2M chain, for every box at once (in the M2M phase)
@@ -1346,8 +1370,15 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
               s);
     else
       gemm_f32(P.job_up_all, D.fu1, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);
-    // fu2: every box for the dense M2L, the W-list boxes only with the compressed one (tmp_f keeps fu1 qhat)
-    gemm_f32(P.comp ? P.job_up_w : P.job_up_all, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
+    // fu2: every box for the dense M2L, the W-list boxes only with the compressed one (tmp_f keeps fu1 qhat).
+    // split16: fu2 = vs diag(inv_sig), with 1/sigma applied in the split pass and vs as split products
+    const GemmJob& J2 = P.comp ? P.job_up_w : P.job_up_all;
+    if (sig_split) {
+      split_h3(P.tmp_f, nb, NC, NC, xq, xq_scale, s, D.inv_sig32);
+      gemm_h3(J2, D.vs_h3, D.vs_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, phi_up_f, kStore, s);
+    } else {
+      gemm_f32(J2, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
+    }
   }
   KFMM_HIP(hipGetLastError());
   // M2L into qhat.  qhat is FP64 in every precision; each box's M2L slots are summed in a fixed order,
@@ -1385,7 +1416,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   } else if (fused_down) {
     const CompressedM2L& C = *P.comp;
     const int NCr = C.NCr;
-    if (P.f32t)  // phi~ = U^T UC2UE qhat = G (fu1 qhat)
+    if (sig_split)  // phi~ = Gv (diag(inv_sig) fu1 qhat), the scaled rows split in the UC2UE step above
+      gemm_h3(P.job_ut, C.Gv_h3, C.Gv_h3_scale, GemmDims{NCr, NC, 2 * NC, NCr}, xq, xq_scale, P.phi_t, kStore, s);
+    else if (P.f32t)  // phi~ = U^T UC2UE qhat = G (fu1 qhat)
       gemm_f32(P.job_ut, C.G32, GemmDims{NCr, NC, NC, NCr}, P.tmp_f, P.phi_t, kStore, s);
     else
       gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
@@ -1485,7 +1518,13 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     } else {
       gemm_f32(P.job_dn_leaf, D.fd1, GemmDims::Sq(NC), qhat_f, P.tmp_f, kStore, s);
     }
-    gemm_f32(P.job_dn_leaf, D.fd2, GemmDims::Sq(NC), P.tmp_f, phi_dn_f, kStore, s);
+    if (sig_split) {  // fd2 = us diag(inv_sig): 1/sigma in the split pass, us as split products
+      split_h3(P.tmp_f, nb, NC, NC, xq, xq_scale, s, D.inv_sig32);
+      gemm_h3(P.job_dn_leaf, D.us_h3, D.us_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, phi_dn_f, kStore,
+              s);
+    } else {
+      gemm_f32(P.job_dn_leaf, D.fd2, GemmDims::Sq(NC), P.tmp_f, phi_dn_f, kStore, s);
+    }
   } else {
     // downward pass in FP64
     if (fused_down) {

@@ -50,10 +50,12 @@ __device__ __forceinline__ void split8(const TIN* v, double inv, uint4* d) {
 // Short rows (len <= 64 * 8 * CH, rows 16-byte aligned): one wave per row (four rows per workgroup), every
 // chunk read once into registers (up to CH per lane), the scale from a wave reduction, then split (in FP32:
 // v - fp16(v) is exact) and stored.
+// kscale (optional): value k of every row is multiplied by kscale[k] before the split.
 template <int CH>
 __global__ __launch_bounds__(256) void k_split_h3_short(int64_t n_rows, int64_t len, const float* __restrict__ src,
                                                         int64_t ld, uint4* __restrict__ dst,
-                                                        float* __restrict__ scale) {
+                                                        float* __restrict__ scale,
+                                                        const float* __restrict__ kscale) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n_rows) return;  // whole waves leave; no barrier follows
   const float* x = src + row * ld;
@@ -66,6 +68,10 @@ __global__ __launch_bounds__(256) void k_split_h3_short(int64_t n_rows, int64_t 
     if (c < nch) {
       v[k][0] = *(const float4_t*)(x + 8 * c);
       v[k][1] = *(const float4_t*)(x + 8 * c + 4);
+      if (kscale) {
+        v[k][0] *= *(const float4_t*)(kscale + 8 * c);
+        v[k][1] *= *(const float4_t*)(kscale + 8 * c + 4);
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) m = fmaxf(m, fmaxf(fabsf(v[k][0][q]), fabsf(v[k][1][q])));
     }
@@ -242,15 +248,20 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
   }
 }
 
-void split_h3(const float* src, int64_t n_rows, int64_t len, int64_t ld, uint16_t* dst, float* scale, hipStream_t s) {
+void split_h3(const float* src, int64_t n_rows, int64_t len, int64_t ld, uint16_t* dst, float* scale, hipStream_t s,
+              const float* kscale) {
   if (n_rows == 0) return;
   KFMM_REQUIRE(len % 8 == 0, "split_h3: row length must be a multiple of 8");
   const bool aligned = ld % 4 == 0 && ((uintptr_t)src & 15) == 0;
+  KFMM_REQUIRE(!kscale || (aligned && len <= 64 * 8 * 2 && ((uintptr_t)kscale & 15) == 0),
+               "split_h3: per-value scales need aligned rows of at most 1024 values");
   const unsigned nblk = (unsigned)((n_rows + 3) / 4);
   if (aligned && len <= 64 * 8)
-    hipLaunchKernelGGL((k_split_h3_short<1>), dim3(nblk), dim3(256), 0, s, n_rows, len, src, ld, (uint4*)dst, scale);
+    hipLaunchKernelGGL((k_split_h3_short<1>), dim3(nblk), dim3(256), 0, s, n_rows, len, src, ld, (uint4*)dst, scale,
+                       kscale);
   else if (aligned && len <= 64 * 8 * 2)
-    hipLaunchKernelGGL((k_split_h3_short<2>), dim3(nblk), dim3(256), 0, s, n_rows, len, src, ld, (uint4*)dst, scale);
+    hipLaunchKernelGGL((k_split_h3_short<2>), dim3(nblk), dim3(256), 0, s, n_rows, len, src, ld, (uint4*)dst, scale,
+                       kscale);
   else
     hipLaunchKernelGGL((k_split_h3<float>), dim3((unsigned)n_rows), dim3(64), 0, s, len, src, ld, (uint4*)dst,
                        scale);

@@ -203,7 +203,8 @@ static void pinv_factors(const std::vector<double>& W, const std::vector<double>
                          int n, double eps, Operators& op) {
   double smax = 0;
   for (double v : sig) smax = std::max(smax, v);
-  for (auto* m : {&op.fu1, &op.fu2, &op.fd1, &op.fd2}) m->assign((size_t)n * n, 0.0);
+  for (auto* m : {&op.fu1, &op.fu2, &op.fd1, &op.fd2, &op.vs, &op.us}) m->assign((size_t)n * n, 0.0);
+  op.inv_sig.assign(n, 0.0);
   for (int j = 0; j < n; ++j) {
     if (!(sig[j] > eps * smax)) continue;
     const double s = sig[j];
@@ -214,7 +215,10 @@ static void pinv_factors(const std::vector<double>& W, const std::vector<double>
       op.fu2[(size_t)k * n + j] = v / s;
       op.fd1[(size_t)j * n + k] = v;
       op.fd2[(size_t)k * n + j] = u / s;
+      op.vs[(size_t)k * n + j] = v;
+      op.us[(size_t)k * n + j] = u;
     }
+    op.inv_sig[j] = 1.0 / s;
   }
 }
 

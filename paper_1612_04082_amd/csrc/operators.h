@@ -12,6 +12,7 @@ struct Operators {
   std::vector<double> surf;                 // n_eq x 3 unit cube-surface points
   std::vector<double> uc2ue, dc2de;         // n x n
   std::vector<double> fu1, fu2, fd1, fd2;   // n x n factors: UC2UE = fu2 fu1, DC2DE = fd2 fd1
+  std::vector<double> vs, us, inv_sig;      // fu2 = vs diag(inv_sig), fd2 = us diag(inv_sig) (orthogonal vs, us)
   std::vector<std::vector<double>> m2m;     // 8 x (n x n)
   std::vector<std::vector<double>> l2l;     // 8 x (n x n)
   std::vector<std::vector<double>> m2m_q;   // 8 x (n x n): the same translations on check potentials

@@ -109,10 +109,11 @@ def test_compressed_m2l(cuda, tol, slack):
 
 
 
-@pytest.mark.parametrize("m2l_tol", [0.0, 3e-7])
-def test_split16_m2l_matches_fp32(cuda, m2l_tol):
-    """M2L on the FP16 matrix cores with split operands (dense and compressed operators): the result
-    agrees with the FP32 matrix-core M2L to well below the method's error, and the error against the
+@pytest.mark.parametrize("m2l_tol,p", [(0.0, 8), (3e-7, 8), (3e-7, 9)])
+def test_split16_m2l_matches_fp32(cuda, m2l_tol, p):
+    """Split-FP16 products (M2L, translations, pseudo-inverse factors; dense and compressed operators, and
+    p = 9 where the coefficient vectors exceed 1024 values and the scaled split falls back to FP32): the
+    result agrees with the FP32 evaluation to well below the method's error, and the error against the
     oracle stays at the FP32 level."""
     from tests.fmm_cases import to_dev, K, G
     from paper_1612_04082_amd import kfmm
@@ -122,14 +123,14 @@ def test_split16_m2l_matches_fp32(cuda, m2l_tol):
     ref = run_oracle(c["src"], c["nrm"], c["w"], c["a"], b, od.DISP)
     out = {}
     for prec in (kfmm.FP32, kfmm.FP32_M2L_SPLIT16):
-        plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G, p=8, leaf_max=64,
+        plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G, p=p, leaf_max=64,
                             precision=prec, m2l_tol=m2l_tol)
         out[prec] = plan.eval(od.DISP, to_dev(c["a"]), to_dev(b)).cpu().numpy()
         assert plan.info()["n_v_pairs"] > 0
         plan.close()
     d = rel_l2(out[kfmm.FP32_M2L_SPLIT16], out[kfmm.FP32])
     e32, e16 = rel_l2(out[kfmm.FP32], ref), rel_l2(out[kfmm.FP32_M2L_SPLIT16], ref)
-    print(f"m2l_tol {m2l_tol:.0e}: split16 vs fp32 {d:.2e}, errors {e16:.2e} / {e32:.2e}")
+    print(f"p {p} m2l_tol {m2l_tol:.0e}: split16 vs fp32 {d:.2e}, errors {e16:.2e} / {e32:.2e}")
     assert d < 1e-6
     assert e16 <= 1.02 * e32 + 1e-7
 
