@@ -555,14 +555,17 @@ constexpr int kStage = 256;  // points staged in LDS per round
 //   S2M: B's own sources at its upward check surface (radius r_up_check), written to row B of q (times
 //        r_B with s2m_r: the scaled check potential qhat of the check-potential translations).
 //   S2L: sources of X(B) at B's downward check surface (radius r_dn_check), r_B * value written to row
-//        blockIdx.x of a compact buffer (added to qhat afterwards).
+//        blockIdx.x of a compact buffer (added to qhat afterwards).  With pair_src, one workgroup per X pair
+//        (boxes[i], pair_src[i]), row i of a per-pair buffer (summed per box in list order afterwards): the
+//        X lists differ in length by an order of magnitude, so per-box workgroups left a long tail.
 template <typename T, typename TQ, bool SL, bool DL, bool S2M>
 __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ boxes, TreeView tv,
                                                     const int* __restrict__ list_off,
                                                     const int* __restrict__ list_idx, const T* __restrict__ spos4,
                                                     const T* __restrict__ snrm4, const T* __restrict__ dens8,
                                                     const double* __restrict__ surf, int n_eq, double radius, int NC,
-                                                    KConst<T> kc, TQ* __restrict__ out, int s2m_r = 0) {
+                                                    KConst<T> kc, TQ* __restrict__ out, int s2m_r = 0,
+                                                    const int* __restrict__ pair_src = nullptr) {
   __shared__ T sp[kStage][4];
   __shared__ T sn[kStage][4];
   __shared__ T sd[kStage][8];
@@ -586,9 +589,9 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
     }
     __syncthreads();
   };
-  const int nl = S2M ? 1 : list_off[B + 1] - list_off[B];
+  const int nl = S2M || pair_src ? 1 : list_off[B + 1] - list_off[B];
   for (int li = 0; li < nl; ++li) {
-    const int A = S2M ? B : list_idx[list_off[B] + li];
+    const int A = S2M ? B : (pair_src ? pair_src[blockIdx.x] : list_idx[list_off[B] + li]);
     double o[3] = {0, 0, 0};
     if (!S2M) box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
     const int s0 = tv.src_b[A], ns = tv.src_e[A] - s0;
@@ -1164,6 +1167,25 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   P->n_u_pairs = up;
   P->n_w_pairs = (int64_t)t.h_w_idx.size();
   P->n_x_pairs = (int64_t)t.h_x_idx.size();
+  {  // X pairs in list order (grouped by box in x_boxes order) and their per-box reduction
+    std::vector<int> xb, xa, roff = {0}, ridx, rbox;
+    for (int i = 0; i < (int)x_boxes.size(); ++i) {
+      const int b = x_boxes[i];
+      for (int k = t.h_x_off[b]; k < t.h_x_off[b + 1]; ++k) {
+        ridx.push_back((int)xb.size());
+        xb.push_back(b);
+        xa.push_back(t.h_x_idx[k]);
+      }
+      rbox.push_back(i);
+      roff.push_back((int)xb.size());
+    }
+    P->n_xp = (int)xb.size();
+    P->xp_b = upload_vec(P->arena, xb, s);
+    P->xp_a = upload_vec(P->arena, xa, s);
+    P->xr_box = upload_vec(P->arena, rbox, s);
+    P->xr_off = upload_vec(P->arena, roff, s);
+    P->xr_idx = upload_vec(P->arena, ridx, s);
+  }
   P->n_leaf = 0;
   for (int b = 0; b < nb; ++b) P->n_leaf += t.h_is_leaf[b];
   // ---- work buffers (zeroed once; padding rows stay zero)
@@ -1174,6 +1196,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   };
   const size_t nbc = (size_t)nb * NC;
   const size_t nxc = std::max<size_t>(1, (size_t)P->n_x_boxes * NC);
+  P->xslot = zalloc(std::max<size_t>(1, (size_t)P->n_xp * NC) * (P->f32t ? 4 : 8));
   if (P->f32t) {
     P->q_f = (float*)zalloc(nbc * 4);
     P->tmp_f = (float*)zalloc(nbc * 4);
@@ -1291,17 +1314,26 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     KFMM_HIP(hipStreamWaitEvent(side, e, 0));
   };
   const int check_block = std::max(64, round_up(n_eq, 64));  // one thread per check point
-  auto s2l = [&](hipStream_t st) {  // X lists -> compact rows of qx
+  auto s2l = [&](hipStream_t st) {  // X pairs -> per-pair rows, summed per box (list order) into qx
     if (!P.n_x_boxes) return;
     dispatch([&](auto sl, auto dl) {
       constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
       if (P.f32t)
-        hipLaunchKernelGGL((k_check_eval<T, float, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, st,
-                           P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, P.qx_f);
+        hipLaunchKernelGGL((k_check_eval<T, float, SL, DL, false>), dim3(P.n_xp), dim3(check_block), 0, st, P.xp_b,
+                           P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, (float*)P.xslot, 0,
+                           P.xp_a);
       else
-        hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_x_boxes), dim3(check_block), 0, st,
-                           P.x_boxes, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, P.qx);
+        hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_xp), dim3(check_block), 0, st,
+                           P.xp_b, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc,
+                           (double*)P.xslot, 0, P.xp_a);
     });
+    if (P.f32t)
+      hipLaunchKernelGGL((k_slot_reduce<float, float>), dim3(P.n_x_boxes), dim3(reduce_block<float>(NC)), 0, st,
+                         P.xr_box, P.xr_off, P.xr_idx, (const float*)P.xslot, P.qx_f, NC);
+    else
+      hipLaunchKernelGGL((k_slot_reduce<double, double>), dim3(P.n_x_boxes), dim3(reduce_block<double>(NC)), 0, st,
+                         P.xr_box, P.xr_off, P.xr_idx, (const double*)P.xslot, P.qx, NC);
+    KFMM_HIP(hipGetLastError());
   };
   auto w_eval = [&](hipStream_t st) {
     if (!P.n_wp) return;

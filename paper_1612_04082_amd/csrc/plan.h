@@ -78,8 +78,13 @@ struct Plan {
   int *wp_b = nullptr, *wp_a = nullptr;
   int64_t* wslot_off = nullptr;
   double* wslot = nullptr;
-  // X-list check potentials, one compact row per box of x_boxes
+  // X-list check potentials, one compact row per box of x_boxes; computed per X pair (one row each, in
+  // list order) and summed per box
   double* qx = nullptr;
+  int n_xp = 0;
+  int *xp_b = nullptr, *xp_a = nullptr;                       // pair -> target box, source box
+  int *xr_box = nullptr, *xr_off = nullptr, *xr_idx = nullptr;  // per-box reduction of the pair rows
+  void* xslot = nullptr;
   // second stream (near field, X and W lists) and its fork / join events
   hipStream_t near_stream = nullptr;
   hipEvent_t fork_ev = nullptr, phi_ev = nullptr, x_ev = nullptr, join_ev = nullptr;
