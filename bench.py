@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 
 # Matrix-core peaks for the M2L contraction's algorithmic FLOP: FP64, FP32, BF16 dense; split16 runs three
 # FP16 products per algorithmic product, so its ceiling is the FP16 dense peak / 3.
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "split16": 2500.0 / 3}
-KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "bf16": "k_gemm_bf16",
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "split16": 2500.0 / 3, "fp32t64": 157.3}
+KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_gemm_f<float>", "bf16": "k_gemm_bf16",
            "split16": "k_gemm_h3 (FP16 high/low split, 3 MFMA products)"}
 
 # HBM bytes of one M2L launch of the default configuration, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
@@ -57,7 +57,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "split16"], default="split16")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "split16", "fp32t64"], default="split16",
+                    help="fp32t64: FP32 M2L with FP64 pseudo-inverses and translations")
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=128)
     ap.add_argument("--sample", type=int, default=40000)
@@ -100,7 +101,7 @@ def main():
 
     dev = torch.device("cuda:0")
     prec = {"fp64": kfmm.FP64, "fp32": kfmm.FP32, "bf16": kfmm.FP32_M2L_BF16,
-            "split16": kfmm.FP32_M2L_SPLIT16}[args.precision]
+            "split16": kfmm.FP32_M2L_SPLIT16, "fp32t64": kfmm.FP32_TRANS64}[args.precision]
     c = geo.box_beam_cloud(seed=2)
     n = c["src"].shape[0]
     t = lambda x: torch.tensor(x, dtype=torch.float64, device=dev)
@@ -142,7 +143,7 @@ def main():
     phases = {k: v / calls for k, v in phases.items()}
     nco = 3 * info["n_eq"]
     m2l_flops = info["n_v_pairs"] * 2.0 * nco * nco
-    if args.m2l_tol > 0 and args.precision in ("fp32", "split16"):  # compressed: r x r per pair (r reported by the plan)
+    if args.m2l_tol > 0 and args.precision in ("fp32", "split16", "fp32t64"):  # compressed: r x r per pair (r reported by the plan)
         nco = info.get("m2l_rank") or nco
         m2l_flops = info["n_v_pairs"] * 2.0 * nco * nco
     achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
@@ -176,7 +177,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32+bf16", "split16": "f32+f16x2"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32+bf16", "split16": "f32+f16x2",
+                  "fp32t64": "f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "box-beam 120x20x20 surface, 201344 quadrature points, single+double layer "
                                f"displacement, targets=sources, p={args.p}, leaf<={args.leaf}",

@@ -48,12 +48,14 @@ enum {
                              form (an orthogonal rotation, then a column-scaled one), once per box */
   KFMM_FP32_M2L_BF16 = 2, /* near field, check/equivalent evaluations in FP32, M2L in BF16 on the matrix
                              cores (FP32 accumulation), pseudo-inverse and M2M/L2L translations in FP64 */
-  KFMM_FP32_M2L_SPLIT16 = 3 /* as KFMM_FP32 but the M2L contractions, the M2M/L2L translations on check
+  KFMM_FP32_M2L_SPLIT16 = 3, /* as KFMM_FP32 but the M2L contractions, the M2M/L2L translations on check
                                potentials and the orthogonal factors of the pseudo-inverses on the FP16
                                matrix cores: every operator and every input vector, scaled by a power of
                                two, is split into a high and a low FP16 part and the product is accumulated
                                in FP32 from hi*hi + hi*lo + lo*hi (about 22-bit operands, close to FP32
                                accuracy); the column-scaled pseudo-inverse factors stay FP32 */
+  KFMM_FP32_TRANS64 = 4     /* near field, check/equivalent evaluations and M2L in FP32 (as KFMM_FP32), the
+                               pseudo-inverses and M2M/L2L translations in FP64 on equivalent densities */
 };
 
 /* Target kind of fmm_eval. */
@@ -66,11 +68,11 @@ typedef struct {
   double K, G;        /* bulk and shear modulus */
   int p;              /* equivalent-surface order: p points per cube edge, 6(p-1)^2+2 points; 0 -> 6 */
   int leaf_max;       /* a box is split while it holds more than leaf_max sources + targets; 0 -> 64 */
-  int precision;      /* KFMM_FP64, KFMM_FP32, KFMM_FP32_M2L_BF16 or KFMM_FP32_M2L_SPLIT16 */
+  int precision;      /* KFMM_FP64, KFMM_FP32, KFMM_FP32_M2L_BF16, KFMM_FP32_M2L_SPLIT16 or KFMM_FP32_TRANS64 */
   double svd_eps;     /* relative singular-value cutoff of the check-to-equivalent pseudo-inverse; 0 -> 1e-8 */
   int max_depth;      /* deepest octree level; 0 -> 16 */
   size_t mem_limit;   /* bytes of device memory the plan may use; 0 = no limit */
-  double m2l_tol;     /* KFMM_FP32 and KFMM_FP32_M2L_SPLIT16: > 0 compresses the M2L operators onto one
+  double m2l_tol;     /* KFMM_FP32, KFMM_FP32_M2L_SPLIT16, KFMM_FP32_TRANS64: > 0 compresses the M2L onto one
                          shared basis, keeping the singular directions above m2l_tol (relative) of
                          sum_o K_o K_o^T's square root, their count rounded up to the GEMM padding
                          (fmm_info.m2l_rank); 0 = dense */

@@ -58,7 +58,7 @@ extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* s
     KFMM_REQUIRE(n_src == 0 || src_xyz != nullptr, "src_xyz is NULL");
     // trg_xyz NULL: the targets are the sources (n_trg == n_src), or there are none (n_trg == 0)
     if (trg_xyz == nullptr) KFMM_REQUIRE(n_trg == n_src || n_trg == 0, "aliased targets need n_trg == n_src");
-    KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_M2L_SPLIT16, "unknown precision");
+    KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_TRANS64, "unknown precision");
     KFMM_REQUIRE(opts->p == 0 || (opts->p >= 3 && opts->p <= 12), "p must be in [3, 12]");
     KFMM_REQUIRE(opts->leaf_max >= 0 && opts->max_depth >= 0, "negative leaf_max or max_depth");
     KFMM_REQUIRE(opts->m2l_tol >= 0 && opts->m2l_tol < 1, "m2l_tol must be in [0, 1)");

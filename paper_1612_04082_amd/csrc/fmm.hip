@@ -1053,7 +1053,8 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->m2l_red_idx = upload_vec(P->arena, idx, s);
     int slot_len = D.NC;
     const bool split16 = o.precision == KFMM_FP32_M2L_SPLIT16;
-    if ((o.precision == KFMM_FP32 || split16) && o.m2l_tol > 0) {
+    const bool fp32m2l = o.precision == KFMM_FP32 || o.precision == KFMM_FP32_TRANS64;
+    if ((fp32m2l || split16) && o.m2l_tol > 0) {
       // compressed M2L: phi~ = U^T phi for every source box, r x r contractions per pair, and the downward
       // pass starts from q~ with DC2DE * U
       P->comp = get_compressed(*P->ops, o.m2l_tol, s);
@@ -1076,7 +1077,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
     // column tiles: 128 (FP32 and split FP16), 192 for the split-FP16 compressed contraction when its rank is a
     // multiple of 160 (160 x 192 workgroup tiles, fewer operand bytes per product), 64 otherwise
-    int m2l_cols = o.precision == KFMM_FP32 || split16 ? 2 * kGemmBN : kGemmBN;
+    int m2l_cols = fp32m2l || split16 ? 2 * kGemmBN : kGemmBN;
     if (split16 && P->comp && P->comp->NCr % 160 == 0) m2l_cols = 3 * kGemmBN;
     P->job_m2l = upload_job(P->arena, sc, s, m2l_cols);
     if (split16) {
@@ -1303,9 +1304,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     return;
   }
   // Work that needs no translation result (near field, X lists) and the W lists run, unprofiled, on the
-  // plan's second stream: the near field and the X lists from the end of UC2UE, overlapping the
-  // latency-bound M2M levels; the W lists once phi_up is ready.  Profiled calls run everything here in
-  // phase order.
+  // plan's second stream: the near field and the X lists from the start (after the permutation),
+  // overlapping S2M and the latency-bound M2M levels; the W lists once phi_up is ready.  Profiled calls run
+  // everything here in phase order.
   const bool overlap = !P.prof;
   hipStream_t side = overlap ? P.near_stream : s;
   auto fork = [&](hipEvent_t e) {
@@ -1345,6 +1346,13 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
                          (const T*)P.tpos, phi_up, D.surf, n_eq, 1.05, NC, kc, P.wslot);
     KFMM_HIP(hipGetLastError());
   };
+  // the near field and the X lists need only the points: on the second stream from here
+  fork(P.fork_ev);
+  if (overlap) {
+    leaf_eval(2, side);
+    s2l(side);
+    KFMM_HIP(hipEventRecord(P.x_ev, side));
+  }
   // S2M, UC2UE
   dispatch([&](auto sl, auto dl) {
     constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
@@ -1371,12 +1379,6 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   float* const phi_dn_f = (float*)P.phi_dn_lo;
   // FP32 translations: UC2UE runs after the M2M chain, for every box at once (in the M2M phase)
   if (!P.f32t) gemm_f64(P.job_uc2ue, D.uc2ue, GemmDims::Sq(NC), P.q_up, P.phi_up, kStore, s);
-  fork(P.fork_ev);
-  if (overlap) {
-    leaf_eval(2, side);
-    s2l(side);
-    KFMM_HIP(hipEventRecord(P.x_ev, side));
-  }
   // M2M
   mark(KFMM_PH_M2M);
   for (const UpLevel& U : P.up_levels) {
@@ -1418,7 +1420,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   mark(KFMM_PH_M2L_PREP);
   double* qhat = P.q_up;  // reuse: the S2M potentials are consumed (FP64 translations)
   float* qhat_f = P.q_f;  // the same with FP32 translations
-  const bool fused_down = (P.prec == KFMM_FP32 || split16) && P.comp;  // DC2DE * U applied to q~ (no qhat)
+  const bool fp32m2l = P.prec == KFMM_FP32 || P.prec == KFMM_FP32_TRANS64;
+  const bool fused_down = (fp32m2l || split16) && P.comp;  // DC2DE * U applied to q~ (no qhat)
   if (!fused_down) {
     if (P.f32t)
       hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc,
@@ -1464,11 +1467,16 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
     m2l_end();
     mark(KFMM_PH_M2L_RED);
-    if (P.m2l_red_n)
-      hipLaunchKernelGGL((k_slot_reduce<float, float>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
-                         P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t_f, NCr);
+    if (P.m2l_red_n) {
+      if (P.f32t)
+        hipLaunchKernelGGL((k_slot_reduce<float, float>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
+                           P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t_f, NCr);
+      else
+        hipLaunchKernelGGL((k_slot_reduce<float, double>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
+                           P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t, NCr);
+    }
   } else {
-    if (P.prec == KFMM_FP32) {
+    if (fp32m2l) {
       mark(KFMM_PH_M2L);
       m2l_begin();
       gemm_f32(P.job_m2l, D.m2l32, GemmDims::Sq(NC), (const float*)P.phi_up_lo, (float*)P.m2l_slots, kStore, s);

@@ -156,3 +156,24 @@ def test_profile_modes(cuda):
     assert torch.equal(ref, got1) and torch.equal(ref, got2)
     assert n1 == 1 and all(v >= 0 for v in ph.values()) and ph["m2l"] > 0
     assert n2 == 3 and m2l["m2l"] > 0 and all(v == 0 for k, v in m2l.items() if k != "m2l")
+
+
+def test_fp32_trans64_matches_fp32(cuda):
+    """FP32 M2L with FP64 pseudo-inverses and translations (KFMM_FP32_TRANS64, compressed M2L) against the
+    FP32 translations on check potentials: both at the method's error, close to each other."""
+    from tests.fmm_cases import to_dev, K, G
+    from paper_1612_04082_amd import kfmm
+    c = geo.sphere_cloud(4096, seed=1)
+    rng = np.random.default_rng(10)
+    b = rng.normal(size=c["src"].shape)
+    ref = run_oracle(c["src"], c["nrm"], c["w"], c["a"], b, od.DISP)
+    out = {}
+    for prec in (kfmm.FP32, kfmm.FP32_TRANS64):
+        plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G, p=8, leaf_max=64,
+                            precision=prec, m2l_tol=3e-7)
+        out[prec] = plan.eval(od.DISP, to_dev(c["a"]), to_dev(b)).cpu().numpy()
+        plan.close()
+    d = rel_l2(out[kfmm.FP32_TRANS64], out[kfmm.FP32])
+    e32, e64 = rel_l2(out[kfmm.FP32], ref), rel_l2(out[kfmm.FP32_TRANS64], ref)
+    print(f"trans64 vs fp32 translations {d:.2e}, errors {e64:.2e} / {e32:.2e}")
+    assert d < 1e-6 and e64 < 5e-5 and e32 < 5e-5
