@@ -33,8 +33,8 @@ KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_
 # HBM bytes of one M2L launch of the default configuration, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
 # profiles/m2l_split16_boxbeam_p8_leaf128.md.  Valid only for the kernel sources it was measured on.
-M2L_TRAFFIC = {"sources_sha256": "135e1a1034ea8812b492280d1158365a1d27b331e5b4986d7a1d6f4c27021106",
-               "fetch_kib": 442864.0, "write_kib": 212899.0}
+M2L_TRAFFIC = {"sources_sha256": "9c14d043d58d4574a5ce2c0b4e06d6be0a1df5d6738b8ef93cee38822554d231",
+               "fetch_kib": 425422.0, "write_kib": 212892.0}
 M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
                "paper_1612_04082_amd/csrc/gemm.h")
 
