@@ -3,8 +3,10 @@
 Workload (the configuration the headline metric is quoted on): the 120 x 20 x 20 box-beam surface,
 201,344 quadrature points with outward normals and area weights, targets = sources, random single-
 and double-layer densities N(0,1); one step = one fmm_eval of the displacement of the combined
-single + double layer (S2M, M2M, M2L, L2L, X, W, L2T, near field), p = 8, leaf <= 128 (the smallest
-order that reaches 1e-5 relative error on this surface; p = 6 and p = 7 stop near 1.5e-4 and 2.4e-5).
+single + double layer (S2M, M2M, M2L, L2L, X, W, L2T, near field), p = 8 (the smallest order that reaches
+1e-5 relative error on this surface; p = 6 and p = 7 stop near 1.5e-4 and 2.4e-5), leaf <= 256 (on this
+surface leaf limits 96 and 128 give one tree, 160 to 256 another with 13% fewer boxes, depth 6 and 6%
+fewer seconds per eval; 320 merges into 1,064 boxes and quadruples the near field).
 Default arithmetic (--precision split16): point evaluations and translations in FP32 (M2M / L2L on
 check potentials, factored pseudo-inverses), the M2L contraction on the FP16 matrix cores with operands
 split into high and low FP16 parts; M2L compressed onto a shared basis with relative cutoff 3e-7 (463
@@ -32,16 +34,16 @@ KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_
 
 # HBM bytes of one M2L launch of the default configuration, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
-# profiles/m2l_split16_boxbeam_p8_leaf128.md.  Valid only for the kernel sources it was measured on.
+# profiles/m2l_split16_boxbeam_p8_leaf256.md.  Valid only for the kernel sources it was measured on.
 M2L_TRAFFIC = {"sources_sha256": "9c14d043d58d4574a5ce2c0b4e06d6be0a1df5d6738b8ef93cee38822554d231",
-               "fetch_kib": 425422.0, "write_kib": 212892.0}
+               "fetch_kib": 412226.0, "write_kib": 202316.0}
 M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
                "paper_1612_04082_amd/csrc/gemm.h")
 
 
 def m2l_traffic_bytes(args):
     import hashlib
-    if (args.precision, args.p, args.leaf, args.m2l_tol) != ("split16", 8, 128, 3e-7):
+    if (args.precision, args.p, args.leaf, args.m2l_tol) != ("split16", 8, 256, 3e-7):
         return None
     h = hashlib.sha256()
     for f in M2L_SOURCES:
@@ -60,7 +62,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "split16", "fp32t64"], default="split16",
                     help="fp32t64: FP32 M2L with FP64 pseudo-inverses and translations")
     ap.add_argument("--p", type=int, default=8)
-    ap.add_argument("--leaf", type=int, default=128)
+    ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--sample", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--m2l-tol", type=float, default=3e-7, help="shared-basis M2L compression cutoff (FP32); 0 = dense")
