@@ -2,7 +2,8 @@
 
 sphere      4,096 points on the unit sphere, single layer, FP64, p = 6, leaf <= 64; full O(N^2) oracle.
 cells       64 periodic-cell bodies (unit cube minus ellipsoids, 20k-200k points each) in ONE batched plan,
-            single + double layer, FP32 (or BF16 M2L with --precision bf16); also 64 separate plans; oracle on
+            single + double layer, FP32 (BF16 M2L with --precision bf16; split FP16 with the compressed M2L with
+            --precision split16); also 64 separate plans; oracle on
             1,000 targets per cell.
 cantilever  8:1:1 cantilever with 64 spherical holes (~965k quadrature points): bem_solve (FP64, tol 1e-6),
             then the stress at the 128^3 interior lattice; oracle rows of the matrix-vector product and stress
@@ -68,7 +69,8 @@ def sphere(args):
 
 def cells(args):
     from oracle import direct as od
-    prec = kfmm.FP32_M2L_BF16 if args.precision == "bf16" else kfmm.FP32
+    prec = {"bf16": kfmm.FP32_M2L_BF16, "split16": kfmm.FP32_M2L_SPLIT16}.get(args.precision, kfmm.FP32)
+    tol = args.m2l_tol if args.precision == "split16" else 0.0  # compressed M2L with the split-FP16 arithmetic
     cl = geo.cell_batch(64)
     src = np.concatenate([c["src"] for c in cl])
     nrm = np.concatenate([c["nrm"] for c in cl])
@@ -79,7 +81,7 @@ def cells(args):
     n = src.shape[0]
     t0 = time.time()
     plan = kfmm.FmmPlan(_t(src), _t(nrm), _t(w), K=K, G=G, p=args.p, leaf_max=args.leaf, precision=prec,
-                        batch_src=list(off))
+                        batch_src=list(off), m2l_tol=tol)
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     da, db = _t(a), _t(b)
@@ -92,7 +94,7 @@ def cells(args):
     t0 = time.time()
     for c in cl:
         plans.append(kfmm.FmmPlan(_t(c["src"]), _t(c["nrm"]), _t(c["w"]), K=K, G=G, p=args.p, leaf_max=args.leaf,
-                                  precision=prec))
+                                  precision=prec, m2l_tol=tol))
         bufs.append((_t(c["a"]), _t(c["b"]), torch.empty((c["src"].shape[0], 3), dtype=torch.float64, device="cuda")))
     torch.cuda.synchronize()
     plan_seq_s = time.time() - t0
@@ -120,8 +122,10 @@ def cells(args):
         errs.append(float(np.linalg.norm(got[off[g]:off[g + 1]][idx] - ref) / np.linalg.norm(ref)))
     tcpu = time.time() - tc
     return dict(metric="FMM target points/s (64 cells, one batched plan)", value=n / (ms * 1e-3),
-                unit="target points/s", ms_per_step=ms, dtype="f32+bf16" if prec == kfmm.FP32_M2L_BF16 else "f32",
-                config=dict(workload=f"64 periodic-cell bodies, {n} points, SL+DL, p={args.p}, leaf<={args.leaf}"),
+                unit="target points/s", ms_per_step=ms,
+                dtype={kfmm.FP32_M2L_BF16: "f32+bf16", kfmm.FP32_M2L_SPLIT16: "f32+f16x2"}.get(prec, "f32"),
+                config=dict(workload=f"64 periodic-cell bodies, {n} points, SL+DL, p={args.p}, leaf<={args.leaf}",
+                            m2l_tol=tol),
                 sequential=dict(ms_per_step=ms_seq, value=n / (ms_seq * 1e-3), plan_seconds=plan_seq_s),
                 plan_seconds=plan_s, rel_err_max_cell=max(errs), rel_err_median_cell=float(np.median(errs)),
                 cpu_baseline=dict(value=64000 / tcpu, unit="target points/s", cores=_cores(), kind="oracle",
