@@ -73,7 +73,10 @@ __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(
 // Displacement at a target from one source (d = source - target, r2 = |d|^2 > 0):
 //   v += U(d) wa + P(d, n) wb           (eq. disp_1, eq. disp_2 read with the leading minus)
 // The prefactors cU, cP are applied by the caller after the sum (they are common to all pairs).
-// vU accumulates the bracket of U, vP the bracket of P.
+// vU accumulates the bracket of U, vP the bracket of P.  Used for S2M: the upward check potentials carry
+// the far field of every source, and at targets many box sizes away that field is a small remainder of
+// cancelling contributions, so their rounding matters there (with the one-accumulator form below, on
+// prefactor-scaled densities, targets 40 radii from a sphere of sources went from 5.0e-6 to 1.3e-5).
 template <typename T, bool SL, bool DL>
 __device__ __forceinline__ void disp_pair(T dx, T dy, T dz, T r2, const T* wa, const T* wb, T nx, T ny, T nz,
                                           const KConst<T>& k, T* vU, T* vP) {
@@ -99,6 +102,44 @@ __device__ __forceinline__ void disp_pair(T dx, T dy, T dz, T r2, const T* wa, c
     vP[0] += f * k.a12 * wb[0] + g * dx - h * (dx * nwb - nx * dwb);
     vP[1] += f * k.a12 * wb[1] + g * dy - h * (dy * nwb - ny * dwb);
     vP[2] += f * k.a12 * wb[2] + g * dz - h * (dz * nwb - nz * dwb);
+  }
+}
+
+// Displacement at a target from one source (d = source - target, r2 = |d|^2 > 0), the kernel prefactors
+// folded into the densities (wa' = cU wa, wb' = cP wb, nwb = n . wb'), one accumulator:
+//   v += cU U(d) wa + P(d, n) wb   (eq. disp_1, eq. disp_2 read with the leading minus)
+//   16 pi (1-nu) G U(d) wa = (3-4nu) wa / r + d (d.wa) / r^3
+//   -8 pi (1-nu) P(d, n) wb = (d.n)/r^3 [(1-2nu) wb + 3 d (d.wb)/r^2] - (1-2nu) [d (n.wb) - n (d.wb)] / r^3
+// expanded as v_i += t wa'_i + sc d_i - fp wb'_i - c2 n_i with t = (3-4nu)/r, fp = (1-2nu)(d.n)/r^3,
+// sc = (d.wa')/r^3 - 3 (d.n)(d.wb')/r^5 + (1-2nu)(n.wb')/r^3, c2 = (1-2nu)(d.wb')/r^3 (about 44 operations per
+// pair; separate U and P accumulators with the prefactors applied at the end take about 51).
+template <typename T, bool SL, bool DL>
+__device__ __forceinline__ void disp_pair_f(T dx, T dy, T dz, T r2, const T* wa, const T* wb, T nwb, T nx, T ny,
+                                            T nz, const KConst<T>& k, T* v) {
+  const T ir = rsqrt_t<T>(r2);
+  const T ir2 = ir * ir, ir3 = ir2 * ir;
+  T sc = T(0), t = T(0), fp = T(0), c2 = T(0);
+  if (SL) {
+    const T dwa = dx * wa[0] + dy * wa[1] + dz * wa[2];
+    sc = dwa * ir3;
+    t = k.a34 * ir;
+  }
+  if (DL) {
+    const T dwb = dx * wb[0] + dy * wb[1] + dz * wb[2];
+    const T dn = dx * nx + dy * ny + dz * nz;
+    const T f = dn * ir3;
+    const T h = k.a12 * ir3;
+    fp = k.a12 * f;
+    sc += h * nwb - T(3) * f * dwb * ir2;
+    c2 = h * dwb;
+  }
+  const T d[3] = {dx, dy, dz}, n[3] = {nx, ny, nz};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T acc = v[i] + sc * d[i];
+    if (SL) acc += t * wa[i];
+    if (DL) acc -= fp * wb[i] + c2 * n[i];
+    v[i] = acc;
   }
 }
 

@@ -551,6 +551,26 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
 
 constexpr int kStage = 256;  // points staged in LDS per round
 
+// One source point into LDS for the displacement kernels: position (plus the box offset o), normal, and the
+// densities with the kernel prefactors folded in: (cU w a, n . cP w b, cP w b, 0) (see disp_pair_f).
+template <typename T>
+__device__ __forceinline__ void stage_source(T* p, T* n, T* dd, const double* o, const T* __restrict__ spos4,
+                                             const T* __restrict__ snrm4, const T* __restrict__ dens8, int64_t g,
+                                             const KConst<T>& kc) {
+  for (int d = 0; d < 3; ++d) {
+    p[d] = (T)o[d] + spos4[4 * g + d];
+    n[d] = snrm4[4 * g + d];
+  }
+  T nb = T(0);
+  for (int d = 0; d < 3; ++d) {
+    dd[d] = kc.cU * dens8[8 * g + d];
+    dd[4 + d] = kc.cP * dens8[8 * g + 4 + d];
+    nb += n[d] * dd[4 + d];
+  }
+  dd[3] = nb;
+  dd[7] = T(0);
+}
+
 // Evaluate the sources of a list of leaves at the check surface of box B (displacement, U and/or P).
 //   S2M: B's own sources at its upward check surface (radius r_up_check), written to row B of q (times
 //        r_B with s2m_r: the scaled check potential qhat of the check-potential translations).
@@ -575,6 +595,8 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
   T x[3] = {0, 0, 0};
   if (tid < n_eq)
     for (int d = 0; d < 3; ++d) x[d] = (T)(radius * rB * surf[3 * tid + d]);
+  // S2M: U and P brackets apart, prefactors at the end (see disp_pair); S2L: one accumulator on
+  // prefactor-scaled densities (disp_pair_f)
   T vU[3] = {0, 0, 0}, vP[3] = {0, 0, 0};
   int fill = 0;
   auto flush = [&](int n) {
@@ -584,7 +606,11 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
         T dx = sp[j][0] - x[0], dy = sp[j][1] - x[1], dz = sp[j][2] - x[2];
         T r2 = dx * dx + dy * dy + dz * dz;
         if (r2 == T(0)) continue;
-        disp_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, vU, vP);
+        if (S2M)
+          disp_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, vU, vP);
+        else
+          disp_pair_f<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sd[j][3], sn[j][0], sn[j][1], sn[j][2], kc,
+                                 vU);
       }
     }
     __syncthreads();
@@ -602,12 +628,16 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
         fill = 0;
       }
       for (int i = tid; i < cnt; i += blockDim.x) {
-        int64_t g = s0 + base + i;
-        for (int d = 0; d < 3; ++d) {
-          sp[fill + i][d] = (T)o[d] + spos4[4 * g + d];
-          sn[fill + i][d] = snrm4[4 * g + d];
+        const int64_t g = s0 + base + i;
+        if (S2M) {
+          for (int d = 0; d < 3; ++d) {
+            sp[fill + i][d] = (T)o[d] + spos4[4 * g + d];
+            sn[fill + i][d] = snrm4[4 * g + d];
+          }
+          for (int d = 0; d < 8; ++d) sd[fill + i][d] = dens8[8 * g + d];
+        } else {
+          stage_source(sp[fill + i], sn[fill + i], sd[fill + i], o, spos4, snrm4, dens8, g, kc);
         }
-        for (int d = 0; d < 8; ++d) sd[fill + i][d] = dens8[8 * g + d];
       }
       fill += cnt;
     }
@@ -615,11 +645,11 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
   flush(fill);
   if (tid < n_eq) {
     for (int d = 0; d < 3; ++d) {
-      double v = (double)(kc.cU * vU[d] - kc.cP * vP[d]);
+      const double vd = S2M ? (double)(kc.cU * vU[d] - kc.cP * vP[d]) : (double)vU[d];
       if (S2M)
-        out[(size_t)B * NC + 3 * tid + d] = (TQ)(s2m_r ? rB * v : v);
+        out[(size_t)B * NC + 3 * tid + d] = (TQ)(s2m_r ? rB * vd : vd);
       else
-        out[(size_t)blockIdx.x * NC + 3 * tid + d] = (TQ)(rB * v);
+        out[(size_t)blockIdx.x * NC + 3 * tid + d] = (TQ)(rB * vd);
     }
   }
 }
@@ -683,13 +713,15 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
             if (r2 == T(0)) continue;
             if (near) {
               if (KIND == 0)
-                disp_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU[q], aP[q]);
+                disp_pair_f<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sd[j][3], sn[j][0], sn[j][1], sn[j][2], kc,
+                                       aU[q]);
               else
                 stress_pair<T, SL, DL>(dx, dy, dz, r2, sd[j], sd[j] + 4, sn[j][0], sn[j][1], sn[j][2], kc, aU[q],
                                        aP[q]);
             } else {
+              // far field: unscaled equivalent density, U bracket in aP (times cU at the end)
               if (KIND == 0)
-                disp_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
+                disp_pair_f<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), T(0), kc, aP[q]);
               else
                 stress_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
             }
@@ -734,11 +766,15 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
         }
         for (int i = tid; i < cnt; i += blockDim.x) {
           int64_t g = s0 + base + i;
-          for (int d = 0; d < 3; ++d) {
-            sp[fill + i][d] = (T)o[d] + spos4[4 * g + d];
-            sn[fill + i][d] = snrm4[4 * g + d];
+          if (KIND == 0) {
+            stage_source(sp[fill + i], sn[fill + i], sd[fill + i], o, spos4, snrm4, dens8, g, kc);
+          } else {
+            for (int d = 0; d < 3; ++d) {
+              sp[fill + i][d] = (T)o[d] + spos4[4 * g + d];
+              sn[fill + i][d] = snrm4[4 * g + d];
+            }
+            for (int d = 0; d < 8; ++d) sd[fill + i][d] = dens8[8 * g + d];
           }
-          for (int d = 0; d < 8; ++d) sd[fill + i][d] = dens8[8 * g + d];
         }
         fill += cnt;
       }
@@ -748,8 +784,8 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
     for (int q = 0; q < TPL; ++q)
       for (int c = 0; c < NO; ++c) {
         double v;
-        if (KIND == 0)
-          v = (double)kc.cU * (double)aU[q][c] - (double)kc.cP * (double)aP[q][c];
+        if (KIND == 0)  // near field: prefactors folded into the staged densities; far field: times cU here
+          v = (double)aU[q][c] + (double)kc.cU * (double)aP[q][c];
         else
           v = (double)kc.cD * (double)aU[q][c] + (double)kc.cS * (double)aP[q][c];
         red[tid][q * NO + c] = act ? v : 0.0;
@@ -833,7 +869,7 @@ __global__ __launch_bounds__(256) void k_w_eval(const int* __restrict__ pair_b, 
             T r2 = dx * dx + dy * dy + dz * dz;
             if (r2 == T(0)) continue;
             if (KIND == 0)
-              disp_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
+              disp_pair_f<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), T(0), kc, aU[q]);
             else
               stress_pair<T, true, false>(dx, dy, dz, r2, sd[j], sd[j], T(0), T(0), T(0), kc, aU[q], aP[q]);
           }
