@@ -1098,7 +1098,8 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       GemmCols cu;
       for (int b2 = 0; b2 < nb; ++b2)
         if (t.h_src_e[b2] > t.h_src_b[b2]) cu.add(0, b2, b2);
-      P->job_ut = upload_job(P->arena, cu, s, 2 * kGemmBN);
+      // split FP16: 64-column tiles (a few thousand boxes in 128-column tiles leave most compute units idle)
+      P->job_ut = upload_job(P->arena, cu, s, split16 ? kGemmBN : 2 * kGemmBN);
       P->phi_t = P->arena.get<float>((size_t)nb * slot_len);
       KFMM_HIP(hipMemsetAsync(P->phi_t, 0, sizeof(float) * nb * slot_len, s));  // boxes without sources
       // rows of boxes without V lists stay zero: the downward pass applies DC2DE * U to every box
@@ -1443,12 +1444,11 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     // fu2: every box for the dense M2L, the W-list boxes only with the compressed one (tmp_f keeps fu1 qhat).
     // split16: fu2 = vs diag(inv_sig), with 1/sigma applied in the split pass and vs as split products
     const GemmJob& J2 = P.comp ? P.job_up_w : P.job_up_all;
-    if (sig_split) {
-      split_h3(P.tmp_f, nb, NC, NC, xq, xq_scale, s, D.inv_sig32);
+    if (sig_split) split_h3(P.tmp_f, nb, NC, NC, xq, xq_scale, s, D.inv_sig32);  // also the input of Gv
+    if (sig_split && big(J2))
       gemm_h3(J2, D.vs_h3, D.vs_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, phi_up_f, kStore, s);
-    } else {
+    else  // a few W boxes: the FP32 split-K kernel is faster
       gemm_f32(J2, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
-    }
   }
   KFMM_HIP(hipGetLastError());
   // M2L into qhat.  qhat is FP64 in every precision; each box's M2L slots are summed in a fixed order,
