@@ -34,11 +34,12 @@ KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_
 
 # HBM bytes of one M2L launch of the default configuration, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
-# profiles/m2l_split16_boxbeam_p8_leaf256.md.  Valid only for the kernel sources it was measured on.
-M2L_TRAFFIC = {"sources_sha256": "9c14d043d58d4574a5ce2c0b4e06d6be0a1df5d6738b8ef93cee38822554d231",
-               "fetch_kib": 412226.0, "write_kib": 202316.0}
+# profiles/m2l_split16_boxbeam_p8_leaf256.md.  Valid only for the kernel sources and the launch set-up (tile
+# widths, in fmm.hip) it was measured on.
+M2L_TRAFFIC = {"sources_sha256": "5f6b28e8f1d7ffbe284fa69c81e2d1c9f197f41177696306bedcf001eb987e6f",
+               "fetch_kib": 420982.0, "write_kib": 202334.0}
 M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
-               "paper_1612_04082_amd/csrc/gemm.h")
+               "paper_1612_04082_amd/csrc/gemm.h", "paper_1612_04082_amd/csrc/fmm.hip")
 
 
 def m2l_traffic_bytes(args):

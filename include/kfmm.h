@@ -295,7 +295,8 @@ int ws_load(ws_net_t net, const char* path);
  * entries with op non-decreasing; NC must be a multiple of 96 or 128.  Synchronises the stream.
  * precision + 16 * k selects the FP64 / FP32 kernel: k = 0 as the library chooses, 1 the LDS-tiled
  * kernel, 2 the split-K kernel used for launches with few columns, 3 / 4 the LDS-tiled kernel with one /
- * two LDS buffers.
+ * two LDS buffers.  With precision 3, k = 1 runs 64-column tiles (the width of the translation passes)
+ * instead of the M2L's 128.
  */
 int kfmm_selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y, const int* op, const int* in,
                        const int* out, const double* scale, int ncols, int mode, void* stream);

@@ -353,7 +353,8 @@ extern "C" int kfmm_selftest_gemm(int precision, const void* A, int NC, const vo
     const int kernel = precision >> 4;
     precision &= 15;
     KFMM_REQUIRE(precision >= 0 && precision <= 3 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
-    KFMM_REQUIRE(kernel >= 0 && kernel <= 4 && (kernel == 0 || precision <= 1), "bad kernel selector");
+    KFMM_REQUIRE(kernel >= 0 && kernel <= 4 && (kernel == 0 || precision <= 1 || (precision == 3 && kernel == 1)),
+                 "bad kernel selector");
     KFMM_REQUIRE(NC > 0 && gemm_tm(NC) != 0, "NC must be a positive multiple of 96 or 128");
     for (int i = 0; i < ncols; ++i) KFMM_REQUIRE(op[i] >= 0 && in[i] >= 0 && out[i] >= 0, "negative index");
     for (int i = 1; i < ncols; ++i) KFMM_REQUIRE(op[i] >= op[i - 1], "columns must be sorted by op");

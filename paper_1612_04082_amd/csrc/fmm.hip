@@ -1112,10 +1112,9 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       }
     }
     P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
-    // column tiles: 128 (FP32 and split FP16), 192 for the split-FP16 compressed contraction when its rank is a
-    // multiple of 160 (160 x 192 workgroup tiles, fewer operand bytes per product), 64 otherwise
-    int m2l_cols = fp32m2l || split16 ? 2 * kGemmBN : kGemmBN;
-    if (split16 && P->comp && P->comp->NCr % 160 == 0) m2l_cols = 3 * kGemmBN;
+    // column tiles: 128 (FP32 and split FP16; 160 x 128 workgroup tiles for the split-FP16 compressed
+    // contraction when its rank is a multiple of 160), 64 otherwise
+    const int m2l_cols = fp32m2l || split16 ? 2 * kGemmBN : kGemmBN;
     P->job_m2l = upload_job(P->arena, sc, s, m2l_cols);
     if (split16) {
       ensure_split_ops(*P->ops, P->comp.get(), s);

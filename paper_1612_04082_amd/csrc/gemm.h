@@ -79,8 +79,8 @@ void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __
 // division by the row's power-of-two scale (written to scale[row]); an operator set is split with one row
 // per operator (len = M * K).  gemm_h3 runs the gather/scatter product on such operands: A_op split
 // operators with scales a_scale[op], X split vectors (d.ldx = FP16 numbers per split vector, at least
-// 2 * d.K) with scales x_scale[box], FP32 outputs.  M must be a multiple of 96 or 64, K of 32, at most
-// 192 columns per tile (tiles of more than 128 columns with M a multiple of 160 use 160-row blocks).
+// 2 * d.K) with scales x_scale[box], FP32 outputs.  M must be a multiple of 96 or 64, K of 32 (at least
+// 64), at most 128 columns per tile (128-column tiles with M a multiple of 160 use 160-row blocks).
 // kscale (optional, FP32 rows of at most 1024 values): value k of every row multiplied by kscale[k] first.
 void split_h3(const float* src, int64_t n_rows, int64_t len, int64_t ld, uint16_t* dst, float* scale, hipStream_t s,
               const float* kscale = nullptr);

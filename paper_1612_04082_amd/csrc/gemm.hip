@@ -40,12 +40,12 @@ void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y,
                    const int* out, const double* scale, int ncols, int mode, int kernel, hipStream_t s) {
   Arena a;
   std::vector<int4> tiles;
-  // FP32 runs the wide tiles used by the M2L; split FP16 too (192 columns when NC is a multiple of 160, as at
-  // the M2L's r = 480); FP64 runs wide tiles when op == 0 only (as in large launches)
+  // FP32 and split FP16 run the wide tiles used by the M2L; FP64 runs wide tiles when op == 0 only (as in
+  // large launches)
   int tile_cols = (precision == 1 || precision == 3 || (precision == 0 && ncols > 0 && op[ncols - 1] == 0))
                       ? 2 * kGemmBN
                       : kGemmBN;
-  if (precision == 3 && NC % 160 == 0) tile_cols = 3 * kGemmBN;
+  if (precision == 3 && kernel == 1) tile_cols = kGemmBN;  // the translation passes' 64-column tiles
   int i = 0;
   while (i < ncols) {
     int j = i;

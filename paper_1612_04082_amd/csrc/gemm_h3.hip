@@ -21,8 +21,9 @@ typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
 // Workgroup tile (16*TM) rows x (64*TN) columns, 4 waves side by side: wave w owns columns
 // [16 TN w, 16 TN (w+1)) (TN 16-column MFMA blocks) and all rows.  Larger tiles read fewer operand bytes
-// per product, which is what limits this kernel (at the M2L shape 160 x 192 tiles took 174 us where
-// 96 x 128 took 226 us).  The operator tile (hi and lo) is staged in LDS per 32-value k-stage,
+// per product (at the M2L shape, r = 480, 160 x 192 tiles took 174 us where 96 x 128 took 226 us), and
+// 160 x 128 tiles beat both in the full evaluation (about 4% below 160 x 192: the same occupancy, half as
+// many workgroups again).  The operator tile (hi and lo) is staged in LDS per 32-value k-stage,
 // double-buffered (one barrier per stage); LDS rows are 36 words apart so that the 16-byte operand reads
 // of any 16 consecutive lanes fall in distinct banks.  X operands are private to a wave and are loaded
 // straight from global memory into registers, one stage ahead.
@@ -149,38 +150,220 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
   }
 }
 
-template <int TM>
+// Variant for launches with few workgroups (fewer than about two per compute unit), where the kernel above
+// waits on memory latency: the same tiles and LDS staging, with PD stages of loads in flight (a ring of PD register sets): the loads of stage i + PD are issued
+// before stage i is multiplied, and stage i + 1 moves to LDS after it.  Every load is unconditional (the
+// columns past a ragged tile's end read column 0, whose products are never stored; stage indices clamp
+// to the last stage), so the compiler counts the loads in flight exactly instead of draining them at each
+// stage.
+//
+// KW > 1 (launches with few workgroups): KW groups of 4 waves take contiguous parts of the k range, each
+// with its own LDS buffers, and their partial tiles are summed in LDS in group order, so results do not
+// depend on scheduling.
+template <int TM, int TN, int KW, int PD>
+__global__ __launch_bounds__(256 * KW) void k_gemm_h3k(const u32x4_t* __restrict__ A, GemmDims dm,
+                                                      const float* __restrict__ a_scale,
+                                                      const int4* __restrict__ tiles, const int* __restrict__ in_idx,
+                                                      const int* __restrict__ out_idx,
+                                                      const double* __restrict__ scale, const u32x4_t* __restrict__ X,
+                                                      const float* __restrict__ x_scale, float* __restrict__ Y,
+                                                      int mode) {
+  constexpr int BM = 16 * TM, RW = 36;
+  constexpr int NP = BM * 8;                // 16-byte pieces of the operator tile per stage
+  constexpr int APT = (NP + 255) / 256;     // pieces per thread (the last round partial when NP % 256 != 0)
+  constexpr int LDS_TILE = KW * 2 * BM * RW, LDS_RED = KW > 1 ? BM * 64 * TN : 0;
+  __shared__ __attribute__((aligned(16))) uint32_t lds[LDS_TILE > LDS_RED ? LDS_TILE : LDS_RED];
+  const int lid = xcd_logical_id();
+  const int4 tile = tiles[lid / gridDim.y];
+  const int r0 = (lid % gridDim.y) * BM;
+  const int tid = threadIdx.x & 255, kg = threadIdx.x >> 8;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, g = lane >> 4;
+  uint32_t* const As = lds + kg * 2 * BM * RW;  // this group's two stage buffers
+  const int rowq = dm.K / 4;                    // 16-byte pieces per split row
+  const u32x4_t* Aop = A + ((size_t)tile.x * dm.M + r0) * rowq;
+  const u32x4_t* xc[TN];
+  bool ok[TN];
+  int src[TN];
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int j = wave * 16 * TN + u * 16 + i16;
+    ok[u] = j < tile.z;
+    src[u] = ok[u] ? in_idx[tile.y + j] : 0;
+    xc[u] = X + (size_t)src[u] * (dm.ldx / 8);
+  }
+  const int ns = dm.K / 32;
+  const int s0 = kg * ns / KW, my = (kg + 1) * ns / KW - s0;  // this group's stages (>= 1, see gemm_h3)
+  const int nmax = (ns + KW - 1) / KW;                        // stages of the longest group
+  struct Stage {
+    u32x4_t a[APT], xh[TN], xl[TN];
+  };
+  Stage ring[PD];
+  half8_t bh[TN], bl[TN];
+  auto load = [&](Stage& L, int st) {
+#pragma unroll
+    for (int e = 0; e < APT; ++e) {
+      const int lin = NP % 256 == 0 ? tid + 256 * e : min(tid + 256 * e, NP - 1);
+      L.a[e] = Aop[(size_t)(lin >> 3) * rowq + 8 * st + (lin & 7)];
+    }
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      L.xh[u] = xc[u][8 * st + 2 * g];
+      L.xl[u] = xc[u][8 * st + 2 * g + 1];
+    }
+  };
+  auto stash = [&](const Stage& L, int buf) {
+#pragma unroll
+    for (int e = 0; e < APT; ++e) {
+      const int lin = tid + 256 * e;
+      if (NP % 256 == 0 || lin < NP) *(u32x4_t*)&As[buf * BM * RW + (lin >> 3) * RW + 4 * (lin & 7)] = L.a[e];
+    }
+#pragma unroll
+    for (int u = 0; u < TN; ++u) {
+      bh[u] = __builtin_bit_cast(half8_t, L.xh[u]);
+      bl[u] = __builtin_bit_cast(half8_t, L.xl[u]);
+    }
+  };
+  float4_t acc[TM][TN];
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[t][u] = float4_t{0, 0, 0, 0};
+  auto compute = [&](int cur) {
+    // every operator fragment of the stage is read before the first product, so the products of one
+    // stage issue back to back
+    half8_t ah[TM], al[TM];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int w = cur * BM * RW + (t * 16 + i16) * RW + 8 * g;
+      ah[t] = *(const half8_t*)&As[w];
+      al[t] = *(const half8_t*)&As[w + 4];
+    }
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+#pragma unroll
+      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t], bh[u], acc[t][u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[t], bl[u], acc[t][u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[t], bh[u], acc[t][u], 0, 0, 0);
+    }
+    // issue order: the fragments of rows 0 and 1, then the products of row t each followed by the reads
+    // of row t + 2, so that LDS latency hides behind products already issued
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * TN, 0);
+      if (t + 2 < TM) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+    }
+  };
+  // stages 0 .. PD-1 in flight, stage 0 staged; ring slot d holds the stages congruent to d mod PD
+#pragma unroll
+  for (int d = 0; d < PD; ++d) load(ring[d], s0 + min(d, my - 1));
+  stash(ring[0], 0);
+  __syncthreads();
+  for (int i0 = 0; i0 < nmax; i0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const int i = i0 + d;
+      // slot d (stage i) was staged at the end of the previous stage; it now takes stage i + PD
+      load(ring[d], s0 + min(i + PD, my - 1));
+      __builtin_amdgcn_sched_barrier(0);  // the loads stay ahead of the products (else they sink below them)
+      if (i < my) compute(i & 1);
+      // buffer (i + 1) & 1 was last read in stage i - 1, which every wave has left (barrier below);
+      // past the group's last stage this writes a copy nobody reads
+      stash(ring[(d + 1) % PD], (i + 1) & 1);
+      __syncthreads();
+    }
+  }
+  if constexpr (KW > 1) {  // group partial tiles summed into group 0 in group order
+    float4_t* red = (float4_t*)lds;
+#pragma unroll 1
+    for (int q = 1; q < KW; ++q) {
+      if (kg == q) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+          for (int u = 0; u < TN; ++u) red[(t * TN + u) * 256 + tid] = acc[t][u];
+      }
+      __syncthreads();
+      if (kg == 0) {
+#pragma unroll
+        for (int t = 0; t < TM; ++t)
+#pragma unroll
+          for (int u = 0; u < TN; ++u) acc[t][u] += red[(t * TN + u) * 256 + tid];
+      }
+      __syncthreads();
+    }
+    if (kg != 0) return;
+  }
+  const float sa = a_scale[tile.x];
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    if (!ok[u]) continue;
+    const int col = tile.y + wave * 16 * TN + u * 16 + i16;
+    const float sc = x_scale[src[u]] * (scale ? (float)scale[col] : 1.0f);
+    float* ycol = Y + (size_t)out_idx[col] * dm.ldy + r0 + 4 * g;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const float4_t v = (acc[t][u] * sa) * sc;  // scales applied one at a time (no product underflow)
+      if (mode == kStore) {
+        *(float4_t*)(ycol + t * 16) = v;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) store_out(ycol + t * 16 + q, v[q], mode);
+      }
+    }
+  }
+}
+
+template <int TM, int TN>
 static void launch_h3(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDims d, const uint16_t* X,
                       const float* x_scale, float* Y, int mode, hipStream_t s) {
   const dim3 grid(job.n_tiles, d.M / (16 * TM));
-  const auto* a = (const u32x4_t*)A;
-  const auto* x = (const u32x4_t*)X;
-  if (job.cols_per_tile <= 64)
-    hipLaunchKernelGGL((k_gemm_h3<TM, 1>), grid, dim3(256), 0, s, a, d, a_scale, job.tiles, job.in_idx, job.out_idx,
-                       job.scale, x, x_scale, Y, mode);
-  else if (job.cols_per_tile <= 128)
-    hipLaunchKernelGGL((k_gemm_h3<TM, 2>), grid, dim3(256), 0, s, a, d, a_scale, job.tiles, job.in_idx, job.out_idx,
-                       job.scale, x, x_scale, Y, mode);
-  else
-    hipLaunchKernelGGL((k_gemm_h3<TM, 3>), grid, dim3(256), 0, s, a, d, a_scale, job.tiles, job.in_idx, job.out_idx,
-                       job.scale, x, x_scale, Y, mode);
+  hipLaunchKernelGGL((k_gemm_h3<TM, TN>), grid, dim3(256), 0, s, (const u32x4_t*)A, d, a_scale, job.tiles,
+                     job.in_idx, job.out_idx, job.scale, (const u32x4_t*)X, x_scale, Y, mode);
 }
 
+template <int TM, int TN, int KW, int PD>
+static void launch_h3k(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDims d, const uint16_t* X,
+                       const float* x_scale, float* Y, int mode, hipStream_t s) {
+  KFMM_REQUIRE(d.K / 32 >= KW, "gemm_h3: fewer k-stages than k groups");
+  const dim3 grid(job.n_tiles, d.M / (16 * TM));
+  hipLaunchKernelGGL((k_gemm_h3k<TM, TN, KW, PD>), grid, dim3(256 * KW), 0, s, (const u32x4_t*)A, d, a_scale,
+                     job.tiles, job.in_idx, job.out_idx, job.scale, (const u32x4_t*)X, x_scale, Y, mode);
+}
+
+// Launches with fewer than 512 workgroups (two per compute unit) in 64-column tiles run the latency-hiding
+// variant: measured on translation shapes, the upper levels of the M2M / L2L passes (8 operators,
+// 896 x 896, 700 columns) take 12.7 instead of 19.3 us and the 480 x 896 U^T product (3000 columns)
+// 14.9 instead of 17.5 us; with more workgroups the plain kernel is as fast or faster.
 void gemm_h3(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDims d, const uint16_t* X,
              const float* x_scale, float* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
-  KFMM_REQUIRE(job.cols_per_tile <= 3 * kGemmBN, "gemm_h3: at most 192 columns per tile");
-  KFMM_REQUIRE(d.K % 32 == 0 && d.ldx % 8 == 0 && d.ldx >= 2 * d.K, "gemm_h3: bad K or ldx");
+  KFMM_REQUIRE(job.cols_per_tile <= 2 * kGemmBN, "gemm_h3: at most 128 columns per tile");
+  KFMM_REQUIRE(d.K % 32 == 0 && d.K >= 64 && d.ldx % 8 == 0 && d.ldx >= 2 * d.K, "gemm_h3: bad K or ldx");
   if (mode == kStore) KFMM_REQUIRE(d.ldy % 4 == 0, "gemm_h3: ldy must be a multiple of 4 for vector stores");
-  // 160-row blocks for wide tiles (the M2L contraction at r = 480), else 96- or 64-row blocks
-  if (d.M % 160 == 0 && job.cols_per_tile > 2 * kGemmBN)
-    launch_h3<10>(job, A, a_scale, d, X, x_scale, Y, mode, s);
-  else if (d.M % 96 == 0)
-    launch_h3<6>(job, A, a_scale, d, X, x_scale, Y, mode, s);
-  else if (d.M % 64 == 0)
-    launch_h3<4>(job, A, a_scale, d, X, x_scale, Y, mode, s);
-  else
-    throw Error(-1, "gemm_h3: M must be a multiple of 96 or 64");
+  KFMM_REQUIRE(d.M % 96 == 0 || d.M % 64 == 0, "gemm_h3: M must be a multiple of 96 or 64");
+  const int64_t nt = job.n_tiles;
+  if (job.cols_per_tile > kGemmBN) {  // 128-column tiles: 160-row blocks (the M2L at r = 480), else 96 / 64
+    if (d.M % 160 == 0)
+      launch_h3<10, 2>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+    else if (d.M % 96 == 0)
+      launch_h3<6, 2>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+    else
+      launch_h3<4, 2>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+  } else if (d.M % 96 == 0) {  // 64-column tiles
+    if (nt * (d.M / 96) < 512)
+      launch_h3k<6, 1, 2, 2>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+    else
+      launch_h3<6, 1>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+  } else {
+    if (nt * (d.M / 64) < 512)
+      launch_h3k<4, 1, 2, 2>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+    else
+      launch_h3<4, 1>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+  }
   KFMM_HIP(hipGetLastError());
 }
 

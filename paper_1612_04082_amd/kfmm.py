@@ -215,7 +215,7 @@ class FmmPlan:
 def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0, kernel=0):
     """Test hook around kfmm_selftest_gemm (see include/kfmm.h); kernel 1 = tiled, 2 = split-K,
     3 / 4 = tiled with one / two LDS buffers.  precision 3 = FP32 tensors, products on the FP16 matrix
-    cores with split operands."""
+    cores with split operands (kernel 1: 64-column tiles, as in the translation passes)."""
     L = load_library()
     n = len(op)
     dt = {0: (torch.float64,) * 3, 1: (torch.float32,) * 3, 2: (torch.bfloat16, torch.bfloat16, torch.float32),

@@ -88,7 +88,7 @@ def test_gemm_128_row_blocks(cuda, precision, tol, kernel):
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_split16_wide_tiles(cuda, mode):
-    """Split FP16 at NC = 480 (the compressed M2L width): 160-row x 192-column workgroup tiles."""
+    """Split FP16 at NC = 480 (the compressed M2L width): 160-row x 128-column workgroup tiles."""
     err = _case(3, mode, seed=5, NC=480)
     print(f"mode={mode} rel err {err:.3e}")
     assert err < 2e-6
@@ -127,4 +127,41 @@ def test_split16_wide_range(cuda, NC):
             continue
         worst = max(worst, (np.abs(got[j] - ref) / bound).max())
     print(f"NC={NC} worst error / (|A||x|) per element {worst:.2e}")
+    assert worst < 2e-6
+
+
+@pytest.mark.parametrize("NC,ncols,n_ops", [(896, 2000, 1), (896, 300, 8), (480, 300, 1), (192, 16500, 1),
+                                            (256, 9000, 1)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_split16_translation_tiles(cuda, NC, ncols, n_ops, mode):
+    """Split FP16 in the 64-column tiles of the translation passes, at launch sizes that take each
+    workgroup shape: 112-row blocks (NC = 896, many columns), two k groups per workgroup (few columns:
+    NC = 896 with 8 operators, NC = 480), one group of 96- and 64-row blocks (many columns at NC = 192,
+    256); ragged last tiles, store and add.  Per element the error must stay at FP32 level relative to
+    |A| |x| (plus |Y0| when adding)."""
+    from paper_1612_04082_amd import kfmm
+    rng = np.random.default_rng(31 + NC + ncols)
+    n_box = 200
+    A = rng.normal(size=(n_ops, NC, NC)).astype(np.float32)
+    X = rng.normal(size=(n_box, NC)).astype(np.float32)
+    op = np.sort(rng.integers(0, n_ops, size=ncols))
+    cin = np.sort(rng.integers(0, n_box, size=ncols))
+    cout = rng.permutation(ncols)
+    Y0 = rng.normal(size=(ncols, NC)).astype(np.float32)
+    Yt = torch.tensor(Y0).cuda()
+    kfmm.selftest_gemm(3, torch.tensor(A).cuda(), torch.tensor(X).cuda(), Yt, op, cin, cout, None, mode, kernel=1)
+    got = Yt.double().cpu().numpy()
+    A64, X64 = A.astype(np.float64), X.astype(np.float64)
+    worst = 0.0
+    for o in range(n_ops):
+        j = np.nonzero(op == o)[0]
+        if not len(j):
+            continue
+        prod = X64[cin[j]] @ A64[o].T
+        bound = np.abs(X64[cin[j]]) @ np.abs(A64[o]).T
+        ref = prod + (Y0[cout[j]] if mode == 1 else 0.0)
+        if mode == 1:
+            bound = bound + np.abs(Y0[cout[j]])
+        worst = max(worst, (np.abs(got[cout[j]] - ref) / bound).max())
+    print(f"NC={NC} ncols={ncols} ops={n_ops} mode={mode} worst error / (|A||x|) {worst:.2e}")
     assert worst < 2e-6
