@@ -94,7 +94,7 @@ def test_split16_wide_tiles(cuda, mode):
     assert err < 2e-6
 
 
-@pytest.mark.parametrize("NC", [96, 192, 256, 480])
+@pytest.mark.parametrize("NC", [96, 192, 256, 384, 480, 896])
 def test_split16_wide_range(cuda, NC):
     """Split-FP16 products with operators and vectors spanning many decades: operators 27 decades apart,
     vectors 20 decades apart, and inside each operator and vector entries spread over 4 decades (rows
