@@ -36,8 +36,8 @@ KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
 # profiles/m2l_split16_boxbeam_p8_leaf256.md.  Valid only for the kernel sources and the launch set-up (tile
 # widths, in fmm.hip) it was measured on.
-M2L_TRAFFIC = {"sources_sha256": "5f6b28e8f1d7ffbe284fa69c81e2d1c9f197f41177696306bedcf001eb987e6f",
-               "fetch_kib": 420982.0, "write_kib": 202334.0}
+M2L_TRAFFIC = {"sources_sha256": "673f48f5f3d23d08f88459b2e994cd762c9131830e8815187b19b20e1b37ee02",
+               "fetch_kib": 421149.0, "write_kib": 202333.0}
 M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
                "paper_1612_04082_amd/csrc/gemm.h", "paper_1612_04082_amd/csrc/fmm.hip")
 
