@@ -1,0 +1,92 @@
+"""C-ABI surface of libkfmm.so on the host (no GPU is touched).
+
+Every function that include/kfmm.h declares must be exported by the in-tree library, and the argument
+checks that precede any device call must report their errors through the return code (KFMM_E_ARG) and
+kfmm_last_error.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kfmm.h")
+KFMM_E_ARG = -1
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)  # comments (argument notes sit inside them)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = "\n".join(l for l in text.splitlines() if not l.lstrip().startswith("#"))
+    # a declaration: return type (optionally const / pointer), name, "(" ... ");" at file scope
+    decl = re.compile(r"^\s*(?:const\s+)?(?:unsigned\s+)?[A-Za-z_]\w*\s*\**\s+\**\s*([A-Za-z_]\w*)\s*\(", re.M)
+    return sorted({m.group(1) for m in decl.finditer(text)} - {"struct", "typedef", "enum"})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1612_04082_amd import build, kfmm
+    if not os.path.exists(kfmm.LIB_PATH):
+        build.build()
+    L = kfmm.load_library()
+    L.kfmm_last_error.restype = ctypes.c_char_p
+    return L
+
+
+def last_error(L):
+    return L.kfmm_last_error().decode()
+
+
+def test_header_declarations_found():
+    names = declared_functions()
+    for must in ("fmm_plan", "fmm_eval", "fmm_plan_destroy", "bem_solve", "bem_stress", "ws_train",
+                 "kfmm_topological_derivative", "kfmm_selftest_gemm", "kfmm_last_error"):
+        assert must in names, (must, names)
+    assert len(names) >= 20, names
+
+
+def test_every_declared_function_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"declared in include/kfmm.h but not exported: {missing}"
+
+
+def test_plan_argument_errors(lib):
+    from paper_1612_04082_amd import kfmm
+    plan = ctypes.c_void_p()
+    xyz = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+
+    def call(out, opts, n=1):
+        return lib.fmm_plan(out, xyz, xyz, xyz, n, None, n, None, None, 0, opts, None)
+
+    good = dict(K=1.0, G=1.0, p=6, leaf_max=64, precision=kfmm.FP64, svd_eps=0.0, max_depth=0, mem_limit=0,
+                m2l_tol=0.0)
+    assert call(None, ctypes.byref(kfmm.FmmOpts(**good))) == KFMM_E_ARG
+    assert last_error(lib) == "out is NULL"
+    assert call(ctypes.byref(plan), None) == KFMM_E_ARG
+    assert last_error(lib) == "opts is NULL"
+    for change, msg in ((dict(K=-1.0), "moduli"), (dict(G=float("nan")), "moduli"),
+                        (dict(precision=9), "unknown precision"), (dict(p=2), "p must be in"),
+                        (dict(m2l_tol=1.5), "m2l_tol"), (dict(leaf_max=-4), "negative leaf_max")):
+        opts = kfmm.FmmOpts(**{**good, **change})
+        assert call(ctypes.byref(plan), ctypes.byref(opts)) == KFMM_E_ARG, change
+        assert msg in last_error(lib), (change, last_error(lib))
+        assert not plan.value  # *out cleared before the checks
+    assert call(ctypes.byref(plan), ctypes.byref(kfmm.FmmOpts(**good)), n=-1) == KFMM_E_ARG
+    assert "negative size" in last_error(lib)
+
+
+def test_selftest_gemm_selector_errors(lib):
+    idx = (ctypes.c_int * 1)(0)
+
+    def call(precision, mode=0, NC=96):
+        return lib.kfmm_selftest_gemm(precision, None, NC, None, None, idx, idx, idx, None, 0, mode, None)
+
+    assert call(7) == KFMM_E_ARG and last_error(lib) == "bad arguments"
+    assert call(1, mode=3) == KFMM_E_ARG and last_error(lib) == "bad arguments"
+    # kernel selectors: FP64 / FP32 take 0..4, split FP16 only 0 and 1 (64-column tiles), BF16 only 0
+    assert call(3 + 16 * 2) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
+    assert call(2 + 16 * 1) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
+    assert call(1 + 16 * 5) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
+    assert call(3, NC=100) == KFMM_E_ARG and "multiple of 96 or 128" in last_error(lib)
