@@ -151,15 +151,13 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
 }
 
 // Variant for launches with few workgroups (fewer than about two per compute unit), where the kernel above
-// waits on memory latency: the same tiles and LDS staging, with PD stages of loads in flight (a ring of PD register sets): the loads of stage i + PD are issued
-// before stage i is multiplied, and stage i + 1 moves to LDS after it.  Every load is unconditional (the
+// waits on memory latency: the same tiles and LDS staging, with PD stages of loads in flight in a ring of
+// PD register sets.  The loads of stage i + PD are issued before stage i is multiplied (a scheduling
+// barrier keeps them there), and stage i + 1 moves to LDS after it.  Every load is unconditional (the
 // columns past a ragged tile's end read column 0, whose products are never stored; stage indices clamp
 // to the last stage), so the compiler counts the loads in flight exactly instead of draining them at each
-// stage.
-//
-// KW > 1 (launches with few workgroups): KW groups of 4 waves take contiguous parts of the k range, each
-// with its own LDS buffers, and their partial tiles are summed in LDS in group order, so results do not
-// depend on scheduling.
+// stage.  KW groups of 4 waves take contiguous parts of the k range, each with its own LDS buffers, and
+// their partial tiles are summed in LDS in group order, so results do not depend on scheduling.
 template <int TM, int TN, int KW, int PD>
 __global__ __launch_bounds__(256 * KW) void k_gemm_h3k(const u32x4_t* __restrict__ A, GemmDims dm,
                                                       const float* __restrict__ a_scale,
