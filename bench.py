@@ -146,7 +146,8 @@ def main():
     phases = {k: v / calls for k, v in phases.items()}
     nco = 3 * info["n_eq"]
     m2l_flops = info["n_v_pairs"] * 2.0 * nco * nco
-    if args.m2l_tol > 0 and args.precision in ("fp32", "split16", "fp32t64"):  # compressed: r x r per pair (r reported by the plan)
+    # compressed: r x r per pair (r reported by the plan)
+    if args.m2l_tol > 0 and args.precision in ("fp32", "split16", "fp32t64"):
         nco = info.get("m2l_rank") or nco
         m2l_flops = info["n_v_pairs"] * 2.0 * nco * nco
     achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12

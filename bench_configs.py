@@ -215,7 +215,8 @@ def warmstart(args):
                           seconds_std=float(np.std(sec)))
     return dict(metric="BEM solve time learned vs plain (s per solve, mean over measured iterations)",
                 value=summ["net"]["seconds_mean"], unit="s", higher_is_better=False, dtype="f64",
-                config=dict(workload=f"Algorithm 1 on 120x15x15 voxels, C=0.001, tol 1e-6, GMRES(200), FMM p={args.p_bem} FP64"),
+                config=dict(workload=f"Algorithm 1 on 120x15x15 voxels, C=0.001, tol 1e-6, GMRES(200), "
+                                     f"FMM p={args.p_bem} FP64"),
                 summary=summ, speedup_vs_zero=summ["zero"]["seconds_mean"] / summ["net"]["seconds_mean"],
                 speedup_vs_prev=summ["prev"]["seconds_mean"] / summ["net"]["seconds_mean"],
                 iterations=[dict(iter=r["iter"], alpha=r.get("alpha"), T=r["T"]) for r in rec])
