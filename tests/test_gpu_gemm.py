@@ -137,8 +137,8 @@ def test_split16_translation_tiles(cuda, NC, ncols, n_ops, mode):
     """Split FP16 in the 64-column tiles of the translation passes, at launch sizes that take each
     workgroup shape: 112-row blocks (NC = 896, many columns), two k groups per workgroup (few columns:
     NC = 896 with 8 operators, NC = 480), one group of 96- and 64-row blocks (many columns at NC = 192,
-    256); ragged last tiles, store and add.  Per element the error must stay at FP32 level relative to
-    |A| |x| (plus |Y0| when adding)."""
+    256); ragged last tiles, store, and add with per-column factors.  Per element the error must stay at
+    FP32 level relative to |A| |x| (plus |Y0| when adding)."""
     from paper_1612_04082_amd import kfmm
     rng = np.random.default_rng(31 + NC + ncols)
     n_box = 200
@@ -148,8 +148,9 @@ def test_split16_translation_tiles(cuda, NC, ncols, n_ops, mode):
     cin = np.sort(rng.integers(0, n_box, size=ncols))
     cout = rng.permutation(ncols)
     Y0 = rng.normal(size=(ncols, NC)).astype(np.float32)
+    scale = rng.uniform(0.5, 2.0, size=ncols) if mode == 1 else None  # per-column factors with add
     Yt = torch.tensor(Y0).cuda()
-    kfmm.selftest_gemm(3, torch.tensor(A).cuda(), torch.tensor(X).cuda(), Yt, op, cin, cout, None, mode, kernel=1)
+    kfmm.selftest_gemm(3, torch.tensor(A).cuda(), torch.tensor(X).cuda(), Yt, op, cin, cout, scale, mode, kernel=1)
     got = Yt.double().cpu().numpy()
     A64, X64 = A.astype(np.float64), X.astype(np.float64)
     worst = 0.0
@@ -157,8 +158,9 @@ def test_split16_translation_tiles(cuda, NC, ncols, n_ops, mode):
         j = np.nonzero(op == o)[0]
         if not len(j):
             continue
-        prod = X64[cin[j]] @ A64[o].T
-        bound = np.abs(X64[cin[j]]) @ np.abs(A64[o]).T
+        sj = scale[j][:, None] if scale is not None else 1.0
+        prod = sj * (X64[cin[j]] @ A64[o].T)
+        bound = sj * (np.abs(X64[cin[j]]) @ np.abs(A64[o]).T)
         ref = prod + (Y0[cout[j]] if mode == 1 else 0.0)
         if mode == 1:
             bound = bound + np.abs(Y0[cout[j]])
