@@ -79,7 +79,7 @@ def main():
                          "traffic, to scale the HBM byte counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        print("bench.py: the library runs on one GPU (there is no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.calib_copy_mib > 0:
         import torch
