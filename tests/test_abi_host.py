@@ -90,3 +90,37 @@ def test_selftest_gemm_selector_errors(lib):
     assert call(2 + 16 * 1) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
     assert call(1 + 16 * 5) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
     assert call(3, NC=100) == KFMM_E_ARG and "multiple of 96 or 128" in last_error(lib)
+
+
+def test_moduli_round_trip():
+    """K from (G, nu) inverts the relation nu = (3K - 2G) / (2 (3K + G)) stated with the ABI."""
+    from paper_1612_04082_amd import kfmm
+    for G, nu in ((1.0, 0.3), (2.5, 0.0), (0.7, 0.45), (3.0, -0.2)):
+        K = kfmm.moduli(G, nu)
+        assert abs((3 * K - 2 * G) / (2 * (3 * K + G)) - nu) < 1e-14
+
+
+def test_binding_rejects_host_and_misshaped_tensors(lib):
+    """The binding hands the library device pointers only: host tensors and misshaped inputs are refused
+    before any library call."""
+    import torch
+    from paper_1612_04082_amd import kfmm
+    x = torch.zeros((8, 3), dtype=torch.float64)
+    with pytest.raises(TypeError):
+        kfmm._dptr(x, "src", 3)                      # host memory
+    with pytest.raises(TypeError):
+        kfmm.FmmPlan(x)                              # host memory, before the plan call
+    with pytest.raises(ValueError):
+        kfmm.FmmPlan(x, w=torch.ones(5, dtype=torch.float64))  # weights of the wrong length
+    with pytest.raises(TypeError):
+        kfmm.selftest_gemm(1, torch.zeros((1, 96, 96)), torch.zeros((2, 96)), torch.zeros((2, 96)), [0], [0], [0])
+    assert kfmm._dptr(None, "b") is None
+
+
+def test_error_code_and_message_reach_python(lib):
+    """A failing ABI call surfaces as KfmmError carrying the status and the library's message."""
+    from paper_1612_04082_amd import kfmm
+    opts = kfmm.FmmOpts(1.0, 1.0, 6, 64, kfmm.FP64, 0.0, 0, 0, 0.0)
+    with pytest.raises(kfmm.KfmmError) as e:
+        kfmm.check(lib.fmm_plan(None, None, None, None, 0, None, 0, None, None, 0, ctypes.byref(opts), None))
+    assert "out is NULL" in str(e.value) and e.value.code == KFMM_E_ARG
