@@ -134,11 +134,12 @@ def test_split16_wide_range(cuda, NC):
                                             (256, 9000, 1)])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_split16_translation_tiles(cuda, NC, ncols, n_ops, mode):
-    """Split FP16 in the 64-column tiles of the translation passes, at launch sizes that take each
-    workgroup shape: 112-row blocks (NC = 896, many columns), two k groups per workgroup (few columns:
-    NC = 896 with 8 operators, NC = 480), one group of 96- and 64-row blocks (many columns at NC = 192,
-    256); ragged last tiles, store, and add with per-column factors.  Per element the error must stay at
-    FP32 level relative to |A| |x| (plus |Y0| when adding)."""
+    """Split FP16 in the 64-column tiles of the translation passes, at launch sizes that take each kernel:
+    the k-group, two-stage-prefetch variant below 512 workgroups (NC = 896 with 2,000 columns: 448
+    workgroups of 64 rows; NC = 896 with 8 operators; NC = 480: 96-row blocks) and the plain kernel above
+    (NC = 192 with 16,500 columns: 516 workgroups of 96 rows; NC = 256 with 9,000 columns: 564 of 64 rows);
+    ragged last tiles, store, and add with per-column factors.  Per element the error must stay at FP32
+    level relative to |A| |x| (plus |Y0| when adding)."""
     from paper_1612_04082_amd import kfmm
     rng = np.random.default_rng(31 + NC + ncols)
     n_box = 200
