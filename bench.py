@@ -36,7 +36,7 @@ KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
 # profiles/m2l_split16_boxbeam_p8_leaf256.md.  Valid only for the kernel sources and the launch set-up (tile
 # widths, in fmm.hip) it was measured on.
-M2L_TRAFFIC = {"sources_sha256": "d39daeaa8e0475cae84ccbd3e65945b5102c1f961e0b23285a184ca74ceffb51",
+M2L_TRAFFIC = {"sources_sha256": "679ef9f5580076c5a0ea2e566091d51330aa3dd03d8d8e705a58af3e96c3f48a",
                "fetch_kib": 421149.0, "write_kib": 202333.0}
 M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
                "paper_1612_04082_amd/csrc/gemm.h", "paper_1612_04082_amd/csrc/fmm.hip")

@@ -585,7 +585,9 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
                                                     const T* __restrict__ snrm4, const T* __restrict__ dens8,
                                                     const double* __restrict__ surf, int n_eq, double radius, int NC,
                                                     KConst<T> kc, TQ* __restrict__ out, int s2m_r = 0,
-                                                    const int* __restrict__ pair_src = nullptr) {
+                                                    const int* __restrict__ pair_src = nullptr,
+                                                    uint16_t* __restrict__ split = nullptr,
+                                                    float* __restrict__ split_scale = nullptr) {
   __shared__ T sp[kStage][4];
   __shared__ T sn[kStage][4];
   __shared__ T sd[kStage][8];
@@ -643,13 +645,48 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
     }
   }
   flush(fill);
+  TQ qv[3] = {0, 0, 0};
   if (tid < n_eq) {
     for (int d = 0; d < 3; ++d) {
       const double vd = S2M ? (double)(kc.cU * vU[d] - kc.cP * vP[d]) : (double)vU[d];
-      if (S2M)
-        out[(size_t)B * NC + 3 * tid + d] = (TQ)(s2m_r ? rB * vd : vd);
-      else
+      if (S2M) {
+        qv[d] = (TQ)(s2m_r ? rB * vd : vd);
+        out[(size_t)B * NC + 3 * tid + d] = qv[d];
+      } else {
         out[(size_t)blockIdx.x * NC + 3 * tid + d] = (TQ)(rB * vd);
+      }
+    }
+  }
+  if constexpr (S2M && sizeof(TQ) == 4) {
+    // S2M with split != nullptr: the row's split-FP16 copy as split_h3 writes it (power-of-two scale from
+    // the row's largest magnitude, [hi 8 | lo 8] chunks); the padding entries past 3 n_eq are zero
+    if (split) {
+      __shared__ float wmax[16];
+      float m = fmaxf(fabsf((float)qv[0]), fmaxf(fabsf((float)qv[1]), fabsf((float)qv[2])));
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+      if ((tid & 63) == 0) wmax[tid >> 6] = m;
+      __syncthreads();
+      m = wmax[0];
+      for (int w = 1; w < (int)(blockDim.x + 63) / 64; ++w) m = fmaxf(m, wmax[w]);
+      int e2 = 0;
+      float sc = 1.0f;
+      if (m > 0.0f && m < INFINITY) {
+        frexpf(m, &e2);  // m = f 2^e2, f in [0.5, 1): scale to put m in [2^14, 2^15)
+        sc = ldexpf(1.0f, max(-126, min(127, e2 - 15)));
+      }
+      if (tid == 0) split_scale[B] = sc;
+      const float inv = 1.0f / sc;
+      _Float16* d = (_Float16*)split + (size_t)B * 2 * NC;
+      auto put = [&](int k, float v) {
+        const float y = v * inv;
+        const _Float16 h = (_Float16)y;
+        d[16 * (k / 8) + (k % 8)] = h;
+        d[16 * (k / 8) + 8 + (k % 8)] = (_Float16)(y - (float)h);
+      };
+      if (tid < n_eq)
+        for (int dd = 0; dd < 3; ++dd) put(3 * tid + dd, (float)qv[dd]);
+      for (int k = 3 * n_eq + tid; k < NC; k += blockDim.x) put(k, 0.0f);
     }
   }
 }
@@ -1390,22 +1427,24 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     KFMM_HIP(hipEventRecord(P.x_ev, side));
   }
   // S2M, UC2UE
+  const bool split16 = P.prec == KFMM_FP32_M2L_SPLIT16;
+  uint16_t* const xq = P.phi_up_h3;  // split16: NC-wide split rows (check potentials, later phi_up)
+  float* const xq_scale = P.phi_up_h3_scale;
   dispatch([&](auto sl, auto dl) {
     constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
-    if (P.f32t)  // scaled check potentials qhat = r q
+    if (P.f32t)  // scaled check potentials qhat = r q; split16: the leaves' split rows too
       hipLaunchKernelGGL((k_check_eval<T, float, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
                          P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
-                         2.95, NC, kc, P.q_f, 1);
+                         2.95, NC, kc, P.q_f, 1, (const int*)nullptr, split16 ? xq : nullptr,
+                         split16 ? xq_scale : nullptr);
     else
       hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, true>), dim3(P.n_leaves_src), dim3(check_block), 0, s,
                          P.leaves_src, P.tv, (const int*)nullptr, (const int*)nullptr, spos, snrm, dens, D.surf, n_eq,
                          2.95, NC, kc, P.q_up);
   });
   mark(KFMM_PH_UC2UE);
-  const bool split16 = P.prec == KFMM_FP32_M2L_SPLIT16;
-  uint16_t* const xq = P.phi_up_h3;  // split16: NC-wide split rows (check potentials, later phi_up)
-  float* const xq_scale = P.phi_up_h3_scale;
-  if (split16) split_h3(P.q_f, nb, NC, NC, xq, xq_scale, s);  // the leaves' check potentials
+  // split16: the split rows read next are the leaves' (written by S2M above) and the parents' (written by
+  // the M2M reductions below); the rows of leaves without sources are never read
   // split-FP16 products pay off on launches of a dozen column tiles or more; smaller ones (the upper levels)
   // run the FP32 split-K kernel, which cuts K across more workgroups
   auto big = [](const GemmJob& J) { return J.n_tiles >= 12; };
