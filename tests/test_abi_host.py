@@ -124,3 +124,23 @@ def test_error_code_and_message_reach_python(lib):
     with pytest.raises(kfmm.KfmmError) as e:
         kfmm.check(lib.fmm_plan(None, None, None, None, 0, None, 0, None, None, 0, ctypes.byref(opts), None))
     assert "out is NULL" in str(e.value) and e.value.code == KFMM_E_ARG
+
+
+def test_other_entry_points_check_arguments_first(lib):
+    """NULL handles and out-of-range selectors are reported before any device work; destroying a NULL
+    handle is a no-op; an empty topological-derivative request succeeds without touching the device."""
+    from paper_1612_04082_amd import kfmm
+    raw = ctypes.CDLL(kfmm.LIB_PATH)  # own function objects: the binding's argtypes stay untouched
+    assert raw.fmm_eval(None, 0, None, None, None, None) == KFMM_E_ARG and last_error(lib) == "plan is NULL"
+    assert raw.fmm_plan_info(None, None) == KFMM_E_ARG and last_error(lib) == "NULL argument"
+    assert raw.fmm_profile(None, 1) == KFMM_E_ARG and last_error(lib) == "plan is NULL"
+    assert raw.fmm_plan_destroy(None) == 0
+    assert raw.ws_destroy(None) == 0
+    n = ctypes.c_int64(-1)
+    assert raw.ws_num_params(None, ctypes.byref(n)) != 0 and n.value == -1
+    assert last_error(lib) == "network is NULL"
+    td = raw.kfmm_topological_derivative
+    td.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    assert td(None, 0, 1.0, 1.0, None, None) == 0
+    assert td(None, 0, -1.0, 1.0, None, None) == KFMM_E_ARG and "moduli" in last_error(lib)
+    assert td(None, 5, 1.0, 1.0, None, None) == KFMM_E_ARG and last_error(lib) == "bad arguments"
