@@ -13,9 +13,12 @@ split into high and low FP16 parts; M2L compressed onto a shared basis with rela
 directions, kept as 480 = the padded width of the contraction).  The plan (tree, lists, operators) is
 built once outside the timed region, as the paper excludes tree construction from its per-pass rate.
 
-Printed JSON line: metric/value/unit, timing, the relative error on a 40,000-target sample against the
-FP64 oracle, the roofline of the dominant kernel (M2L contraction on the matrix cores) from HIP events
-recorded inside the library on the evaluation stream, and the oracle timed on the host cores.
+Printed JSON line: metric/value/unit, timing, the relative L2 and max-norm errors of the timed loop's own
+output on a 40,000-target sample against the FP64 oracle, the roofline of the dominant kernel (the M2L
+contraction; bound = the larger of its algorithmic FLOP at the matrix peak and its algorithmic bytes at
+the HBM peak, its launch time from HIP events recorded inside the library on the evaluation stream), the
+whole evaluation's T_ideal / T_measured (every phase's algorithmic work at the peak of its unit, from
+fmm_plan_work), and the oracle timed on the host cores.
 """
 import argparse
 import json
@@ -26,11 +29,42 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Matrix-core peaks for the M2L contraction's algorithmic FLOP: FP64, FP32, BF16 dense; split16 runs three
-# FP16 products per algorithmic product, so its ceiling is the FP16 dense peak / 3.
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "split16": 2500.0 / 3, "fp32t64": 157.3}
+# Published MI355X peaks (TFLOP/s; HBM in TB/s).  Algorithmic FLOP are priced at the dense peak of the unit
+# a phase runs on: the split-FP16 products at the FP16 dense matrix peak (the three FP16 products per
+# algorithmic product are the implementation's cost, reported apart as the matrix-pipe utilisation).
+HBM_TBS = 8.0
+VALU_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 157.3, "split16": 157.3, "fp32t64": 157.3}
+M2L_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "split16": 2500.0, "fp32t64": 157.3}
+TRANS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 78.6, "split16": 2500.0, "fp32t64": 78.6}
+MFMA_PRODUCTS = {"split16": 3}  # matrix-core products per algorithmic product
 KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_gemm_f<float>", "bf16": "k_gemm_bf16",
            "split16": "k_gemm_h3 (FP16 high/low split, 3 MFMA products)"}
+PHASE_UNIT = {"permute": "hbm", "m2l_red": "hbm", "s2m": "valu", "s2l": "valu", "near": "valu", "leaf": "valu",
+              "uc2ue": "trans", "m2m": "trans", "m2l_prep": "trans", "down": "trans", "m2l": "m2l"}
+
+
+def phase_peak_tflops(phase, precision):
+    u = PHASE_UNIT[phase]
+    return {"hbm": None, "valu": VALU_TFLOPS[precision], "trans": TRANS_TFLOPS[precision],
+            "m2l": M2L_TFLOPS[precision]}[u]
+
+
+def ideal_ms(flops, nbytes, peak_tflops):
+    """Roofline time of a phase: the larger of its FLOP at the unit's peak and its bytes at the HBM peak."""
+    t_f = flops / (peak_tflops * 1e12) if peak_tflops else 0.0
+    return max(t_f, nbytes / (HBM_TBS * 1e12)) * 1e3
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
 
 # HBM bytes of one M2L launch of the default configuration, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
@@ -137,6 +171,7 @@ def main():
     m2l_timed, m2l_calls = plan.phase_times()
     m2l_ms = m2l_timed["m2l"] / m2l_calls
     plan.profile(False)
+    timed_out = out.cpu().numpy()  # the accuracy check below reads the timed loop's own result
     # phase timing: events recorded inside the library on the evaluation stream
     plan.profile(True)
     for _ in range(args.steps):
@@ -144,21 +179,43 @@ def main():
     phases, calls = plan.phase_times()
     plan.profile(False)
     phases = {k: v / calls for k, v in phases.items()}
-    nco = 3 * info["n_eq"]
-    m2l_flops = info["n_v_pairs"] * 2.0 * nco * nco
-    # compressed: r x r per pair (r reported by the plan)
-    if args.m2l_tol > 0 and args.precision in ("fp32", "split16", "fp32t64"):
-        nco = info.get("m2l_rank") or nco
-        m2l_flops = info["n_v_pairs"] * 2.0 * nco * nco
-    achieved = m2l_flops / (m2l_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    work = plan.work(kfmm.DISP, True, True)
+    # dominant kernel: the M2L contraction; its roofline is the larger of the algorithmic FLOP at the matrix
+    # peak and the algorithmic bytes (operators, input and output vectors, each once) at the HBM peak
+    m2l_flops, m2l_bytes = work["m2l"]
+    peak_mfma = M2L_TFLOPS[args.precision]
+    t_mfma = m2l_flops / (peak_mfma * 1e12)
+    t_hbm = m2l_bytes / (HBM_TBS * 1e12)
+    m2l_s = m2l_ms * 1e-3
+    mfma_view = {"achieved": m2l_flops / m2l_s / 1e12, "peak": peak_mfma, "unit": "TFLOP/s",
+                 "frac": t_mfma / m2l_s}
+    hbm_view = {"achieved": m2l_bytes / m2l_s / 1e9, "peak": HBM_TBS * 1e3, "unit": "GB/s", "frac": t_hbm / m2l_s}
+    main = hbm_view if t_hbm >= t_mfma else mfma_view
+    roofline = {"bound": "hbm" if t_hbm >= t_mfma else "mfma",
+                "kernel": f"M2L contraction ({KERNELS[args.precision]}, one launch per eval)",
+                **main, "traffic": m2l_traffic_bytes(args),
+                "flops_per_launch": m2l_flops, "bytes_per_launch": m2l_bytes, "avg_ms": m2l_ms,
+                "avg_ms_alone": phases["m2l"], "mfma_view": mfma_view, "hbm_view": hbm_view}
+    if args.precision in MFMA_PRODUCTS:
+        roofline["mfma_pipe_util"] = MFMA_PRODUCTS[args.precision] * mfma_view["frac"]
+    # whole evaluation: T_ideal = sum over phases of each phase's roofline time, against the timed step
+    per_phase = {}
+    t_ideal = 0.0
+    for ph, (fl, by) in work.items():
+        ti = ideal_ms(fl, by, phase_peak_tflops(ph, args.precision))
+        t_ideal += ti
+        if fl or by:
+            per_phase[ph] = {"flops": fl, "bytes": by, "ideal_ms": ti, "measured_ms_alone": phases[ph],
+                             "frac": ti / phases[ph] if phases[ph] > 0 else None}
+    whole = {"t_ideal_ms": t_ideal, "t_measured_ms": ms, "frac": t_ideal / ms, "phases": per_phase,
+             "peaks": {"hbm_TBs": HBM_TBS, "valu_TFLOPs": VALU_TFLOPS[args.precision],
+                       "translations_TFLOPs": TRANS_TFLOPS[args.precision], "m2l_TFLOPs": peak_mfma}}
     # accuracy on a sample of targets vs the FP64 oracle (also the CPU baseline)
     rng = np.random.default_rng(2)
     idx = np.sort(rng.choice(n, size=min(args.sample, n), replace=False))
-    res = {}
-    gpu_out = out.cpu().numpy()[idx]
+    gpu_out = timed_out[idx]
     cpu_baseline = None
-    rel_err = None
+    rel_err = eps_inf = None
     if not args.no_cpu_baseline:
         from oracle import direct as od
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -167,9 +224,11 @@ def main():
                         nthreads=cores)
         tcpu = time.time() - tc
         rel_err = float(np.linalg.norm(gpu_out - ref) / np.linalg.norm(ref))
+        eps_inf = float(np.abs(gpu_out - ref).max() / np.abs(ref).max())
+        pairs = float(len(idx)) * n
         cpu_baseline = {"value": len(idx) / tcpu, "unit": "target points/s", "cores": cores, "kind": "oracle",
-                        "sample": f"{len(idx)} targets x {n} sources, FP64 direct sum (C, OpenMP)",
-                        "seconds": tcpu}
+                        "sample": f"{len(idx)} targets x {n} sources, FP64 direct sum (C, OpenMP), single + double "
+                                  "layer", "seconds": tcpu, "pairs_per_s": pairs / tcpu, "cpu_model": cpu_model()}
     line = {
         "metric": "FMM target points/s at 1e-5 rel err",
         "value": value,
@@ -189,11 +248,10 @@ def main():
                    "n_targets": n, "n_sources": n, "precision": args.precision, "p": args.p, "leaf_max": args.leaf,
                    "m2l_tol": args.m2l_tol, "m2l_rank": info.get("m2l_rank")},
         "rel_err": rel_err,
-        "roofline": {"bound": "mfma", "kernel": f"M2L contraction ({KERNELS[args.precision]}, one launch per eval)",
-                     "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": m2l_traffic_bytes(args),
-                     "flops_per_launch": m2l_flops, "avg_ms": m2l_ms,
-                     "avg_ms_alone": phases["m2l"]},
+        "rel_err_source": "output of the timed (overlapped) evaluations",
+        "eps_inf": eps_inf,
+        "roofline": roofline,
+        "roofline_whole_eval": whole,
         "cpu_baseline": cpu_baseline,
         "phases_ms": phases,
         "plan_seconds": plan_s,

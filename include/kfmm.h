@@ -128,6 +128,16 @@ typedef struct {
 int fmm_plan_info(kfmm_plan_t plan, fmm_info* info /* host */);
 
 /*
+ * fmm_plan_target_lists -- which far-field paths reach each target (a diagnostic for parity tests; the
+ * adaptive lists of Sec. 2.2, "Kernel-independent fast multipole method").  For every target, in the
+ * caller's order, flags[i] gets bit 0 if its leaf has a W list (upward densities of smaller boxes
+ * evaluated at the target), bit 1 if its leaf has an X list (sources of larger boxes evaluated on the
+ * leaf's downward check surface) and bit 2 if an ancestor box of the leaf has an X list.
+ *   flags  M int32 (host), overwritten.  Synchronises the device (copies the target permutation).
+ */
+int fmm_plan_target_lists(kfmm_plan_t plan, int32_t* flags /* host */);
+
+/*
  * Phase timing.  fmm_profile(plan, 1) makes every following fmm_eval record HIP events between its
  * phases on the caller's stream and wait for them at the end of the call (so profiled calls are
  * synchronous); fmm_profile(plan, 0) stops it.  Unprofiled calls run the near field on a second
@@ -157,6 +167,18 @@ enum {
 };
 int fmm_profile(kfmm_plan_t plan, int enable);
 int fmm_phase_times(kfmm_plan_t plan, double* ms /* host, KFMM_N_PHASES */, int64_t* calls /* host */);
+
+/*
+ * fmm_plan_work -- algorithmic work of one fmm_eval of this plan, per phase (the KFMM_PH_* order): the
+ * floating-point operations and the HBM bytes the method itself needs (Sec. 2.2 passes: every operator
+ * and coefficient vector read once, every result written once, operand sizes without padding), for the
+ * roofline of each phase.  Point-pair costs: U 29, P 45, U+P 65, D 50, S 90, D+S 130 operations.
+ *   kind            KFMM_DISP or KFMM_STRESS
+ *   with_a, with_b  non-zero if the single-layer (resp. double-layer) density is given
+ *   flops, bytes    (host) KFMM_N_PHASES doubles each, overwritten
+ */
+int fmm_plan_work(kfmm_plan_t plan, int kind, int with_a, int with_b, double* flops /* host */,
+                  double* bytes /* host */);
 
 /* Release the plan and its device memory.  NULL is a no-op. */
 int fmm_plan_destroy(kfmm_plan_t plan);

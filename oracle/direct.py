@@ -22,10 +22,10 @@ def lib():
     global _lib
     if _lib is None:
         path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
-            os.path.join(_build.HERE, "direct.c")
-        ):
-            _build.build()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} not built: run __graft_entry__.build() or python -m oracle.build")
+        if os.path.getmtime(path) < os.path.getmtime(os.path.join(_build.HERE, "direct.c")):
+            raise ImportError(f"{path} is older than oracle/direct.c: rebuild it (python -m oracle.build)")
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64

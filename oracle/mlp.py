@@ -5,7 +5,8 @@ solution, Sec. 5 "fast update", and leaves the method open):
     h1 = silu(X W1 + b1),  h2 = silu(h1 W2 + b2),  y = h2 W3 + b3
 with silu(z) = z * sigmoid(z).  Loss L = mean over all outputs of (y - Y)^2.
 Backward pass by the chain rule; Adam (Kingma & Ba 2015) with bias correction.
-Parity pinned by tests/test_oracle_mlp.py (central finite differences; Adam closed forms).
+Parity pinned by tests/test_oracle_mlp_td.py (a closed-form forward pass, central finite differences,
+Adam closed forms).
 """
 import numpy as np
 

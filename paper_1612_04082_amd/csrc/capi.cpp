@@ -117,6 +117,37 @@ extern "C" int fmm_plan_info(kfmm_plan_t plan, fmm_info* info) {
   });
 }
 
+extern "C" int fmm_plan_target_lists(kfmm_plan_t plan, int32_t* flags) {
+  return guarded([&] {
+    KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr && flags != nullptr, "NULL argument");
+    Plan& P = *plan->impl;
+    if (P.n_trg == 0) return;
+    std::memset(flags, 0, sizeof(int32_t) * (size_t)P.n_trg);
+    const Tree& t = P.tree;
+    if (P.empty || t.n_box == 0 || t.perm_trg == nullptr) return;
+    std::vector<int> perm((size_t)P.n_trg);
+    KFMM_HIP(hipMemcpy(perm.data(), t.perm_trg, sizeof(int) * perm.size(), hipMemcpyDeviceToHost));
+    auto has = [](const std::vector<int>& off, int b) { return off.size() > (size_t)b + 1 && off[b + 1] > off[b]; };
+    for (int b = 0; b < t.n_box; ++b) {
+      if (!t.h_is_leaf[b]) continue;
+      int32_t f = (has(t.h_w_off, b) ? 1 : 0) | (has(t.h_x_off, b) ? 2 : 0);
+      for (int a = t.h_parent[b]; a >= 0; a = t.h_parent[a])
+        if (has(t.h_x_off, a)) f |= 4;
+      for (int i = t.h_trg_b[b]; i < t.h_trg_e[b]; ++i) flags[perm[i]] = f;
+    }
+  });
+}
+
+extern "C" int fmm_plan_work(kfmm_plan_t plan, int kind, int with_a, int with_b, double* flops, double* bytes) {
+  return guarded([&] {
+    KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr && flops != nullptr && bytes != nullptr, "NULL argument");
+    KFMM_REQUIRE(kind == KFMM_DISP || kind == KFMM_STRESS, "kind must be KFMM_DISP or KFMM_STRESS");
+    KFMM_REQUIRE(with_b == 0 || plan->impl->has_nrm || plan->impl->n_src == 0,
+                 "double-layer density needs normals in the plan");
+    plan_work(*plan->impl, kind, with_a != 0, with_b != 0, flops, bytes);
+  });
+}
+
 extern "C" int fmm_profile(kfmm_plan_t plan, int enable) {
   return guarded([&] {
     KFMM_REQUIRE(plan != nullptr && plan->impl != nullptr, "plan is NULL");

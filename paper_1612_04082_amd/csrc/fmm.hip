@@ -1679,6 +1679,97 @@ Plan::~Plan() {
 
 int plan_m2l_rank(const Plan& P) { return P.comp ? P.comp->r : 0; }
 
+// Algorithmic work of one evaluation per phase: the floating-point operations and HBM bytes the method
+// itself needs (operand dimensions without the GEMM padding, each operator and each coefficient vector
+// read once, each result written once), not what the kernels execute.  Kernel-pair costs per point pair,
+// counted from the closed forms of eqs. disp_1, disp_2, stress_2, stress_3: U 29, P 45, U+P 65, D 50,
+// S 90, D+S 130 (one reciprocal square root each).  The per-pair M2L slots and their reduction are a
+// design choice of this library, so the reduction phase carries no algorithmic work.
+void plan_work(const Plan& P, int kind, bool sl, bool dl, double* flops, double* bytes) {
+  for (int i = 0; i < KFMM_N_PHASES; ++i) flops[i] = bytes[i] = 0.0;
+  if (P.empty || P.n_trg == 0 || (!sl && !dl)) return;
+  const Tree& t = P.tree;
+  const double n = 3.0 * P.n_eq, neq = P.n_eq;
+  const bool f32t = P.f32t, comp = P.comp != nullptr;
+  // bytes per coefficient of the translations and of the M2L (split FP16: hi + lo, 4 bytes)
+  const double vb = f32t ? 4.0 : 8.0;
+  const double mb = P.prec == KFMM_FP64 ? 8.0 : P.prec == KFMM_FP32_M2L_BF16 ? 2.0 : 4.0;
+  const double r = comp ? (double)P.comp->r : n;
+  const double f_src = sl && dl ? (kind == KFMM_DISP ? 65 : 130) : sl ? (kind == KFMM_DISP ? 29 : 50)
+                                                                     : (kind == KFMM_DISP ? 45 : 90);
+  const double f_s2m = sl && dl ? 65 : sl ? 29 : 45;  // sources at check points (displacement kernels)
+  const double f_l2t = kind == KFMM_DISP ? 29 : 50;   // single-layer equivalent densities at targets
+  const double n_src = (double)P.n_src, n_trg = (double)P.n_trg;
+  const double dens_in = 3.0 * ((sl ? 1 : 0) + (dl ? 1 : 0));
+  flops[KFMM_PH_PERMUTE] = 0;
+  bytes[KFMM_PH_PERMUTE] = n_src * (8.0 * dens_in + 8.0 + 4.0 + (P.prec == KFMM_FP64 ? 8.0 : 4.0) * dens_in);
+  // box classes
+  const int nb = t.n_box;
+  double n_up = 0, n_up_child = 0, n_dn = 0, n_dn_child = 0, n_tleaf = 0, src_in_leaves = 0;
+  for (int b = 0; b < nb; ++b) {
+    const bool hs = t.h_src_e[b] > t.h_src_b[b], ht = t.h_trg_e[b] > t.h_trg_b[b];
+    if (hs && t.h_level[b] >= 2) {
+      n_up += 1;
+      if (t.h_level[b] >= 3) n_up_child += 1;
+    }
+    if (ht && t.h_level[b] >= 2) {
+      n_dn += 1;
+      if (t.h_level[b] >= 3) n_dn_child += 1;
+    }
+    if (t.h_is_leaf[b] && ht) n_tleaf += 1;
+    if (t.h_is_leaf[b] && hs) src_in_leaves += t.h_src_e[b] - t.h_src_b[b];
+  }
+  std::vector<char> vsrc(nb, 0), vtrg(nb, 0), wsrc(nb, 0);
+  for (size_t i = 0; i < t.h_v_src.size(); ++i) vsrc[t.h_v_src[i]] = vtrg[t.h_v_trg[i]] = 1;
+  double n_vsrc = 0, n_vtrg = 0, n_wsrc = 0, w_pts = 0, x_pts = 0;
+  for (int b = 0; b < nb; ++b) {
+    n_vsrc += vsrc[b];
+    n_vtrg += vtrg[b];
+    for (int i = t.h_w_off[b]; i < t.h_w_off[b + 1]; ++i) {
+      wsrc[t.h_w_idx[i]] = 1;
+      w_pts += t.h_trg_e[b] - t.h_trg_b[b];
+    }
+    for (int i = t.h_x_off[b]; i < t.h_x_off[b + 1]; ++i) {
+      const int a = t.h_x_idx[i];
+      x_pts += t.h_src_e[a] - t.h_src_b[a];
+    }
+  }
+  for (int b = 0; b < nb; ++b) n_wsrc += wsrc[b];
+  const double pt_bytes = (P.prec == KFMM_FP64 ? 8.0 : 4.0) * (6.0 + dens_in);  // position, normal, densities
+  // a product of an (rows x cols) operator with `cnt` vectors
+  auto gemm = [&](int ph, double rows, double cols, double cnt, double ob) {
+    flops[ph] += 2.0 * rows * cols * cnt;
+    bytes[ph] += rows * cols * ob + cnt * (rows + cols) * vb;
+  };
+  const double ob = vb;  // operators in the evaluation precision (split FP16: 4 bytes per value)
+  flops[KFMM_PH_S2M] = src_in_leaves * neq * f_s2m;
+  bytes[KFMM_PH_S2M] = src_in_leaves * pt_bytes + n_up * n * vb;
+  if (f32t) {
+    gemm(KFMM_PH_M2M, n, n, n_up_child, 8 * ob);  // M2M_q, children into parents
+    gemm(KFMM_PH_M2M, n, n, n_up, ob);            // fu1
+    gemm(KFMM_PH_M2M, n, n, comp ? n_wsrc : n_up, ob);  // fu2 (compressed: W-list source boxes only)
+  } else {
+    gemm(KFMM_PH_UC2UE, n, n, n_up, ob);
+    gemm(KFMM_PH_M2M, n, n, n_up_child, 8 * ob);
+  }
+  if (comp) gemm(KFMM_PH_M2L_PREP, r, n, n_up, ob);  // phi~ = U^T phi_up
+  flops[KFMM_PH_M2L] = 2.0 * r * r * (double)P.n_v_pairs;
+  bytes[KFMM_PH_M2L] = 316.0 * r * r * mb + (n_vsrc + n_vtrg) * r * mb;
+  flops[KFMM_PH_S2L] = x_pts * neq * f_s2m;
+  bytes[KFMM_PH_S2L] = x_pts * pt_bytes;
+  if (comp) gemm(KFMM_PH_DOWN, n, r, n_vtrg, ob);  // qhat = U q~
+  else if (!f32t) gemm(KFMM_PH_DOWN, n, n, n_dn, ob);  // DC2DE per box (FP64 translations)
+  gemm(KFMM_PH_DOWN, n, n, n_dn_child, 8 * ob);       // L2L, parents into children
+  if (f32t) {
+    gemm(KFMM_PH_DOWN, n, n, n_tleaf, ob);  // fd1
+    gemm(KFMM_PH_DOWN, n, n, n_tleaf, ob);  // fd2
+  }
+  flops[KFMM_PH_NEAR] = (double)P.n_u_pairs * f_src;
+  bytes[KFMM_PH_NEAR] = (n_src + n_trg) * pt_bytes + n_trg * 8.0 * (kind == KFMM_DISP ? 3 : 6);
+  flops[KFMM_PH_LEAF] = (n_trg + w_pts) * neq * f_l2t;
+  bytes[KFMM_PH_LEAF] = n_tleaf * n * vb + (n_wsrc) * n * vb + n_trg * 8.0 * (kind == KFMM_DISP ? 3 : 6);
+}
+
 void plan_profile(Plan& P, int mode) {
   if (P.light) plan_light_harvest(P, true);
   if (mode == 1 && !P.ev[0])

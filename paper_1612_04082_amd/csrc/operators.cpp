@@ -28,6 +28,10 @@
 // A check potential is a smooth field sample, and these operators map smooth fields to smooth fields
 // without cancellation, so chains of them run in FP32; an equivalent density carries the pinv's
 // amplified high-order modes, and every product with it (M2M_c, L2L_c) cancels them in its sum.
+#include <sys/stat.h>
+#include <sys/types.h>
+
+#include <cerrno>
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -272,9 +276,14 @@ static bool load_cache(const std::string& path, int n, std::vector<double>& P) {
 }
 
 static void save_cache(const std::string& path, int n, const std::vector<double>& P) {
+  // create the cache directory with mkdir(2), one path component at a time (no shell, no child process)
   std::string dir = path.substr(0, path.rfind('/'));
-  std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-  if (std::system(cmd.c_str()) != 0) return;
+  for (size_t pos = 1; pos <= dir.size(); ++pos) {
+    if (pos == dir.size() || dir[pos] == '/') {
+      std::string part = dir.substr(0, pos);
+      if (::mkdir(part.c_str(), 0755) != 0 && errno != EEXIST) return;
+    }
+  }
   std::string tmp = path + ".tmp" + std::to_string((long)std::rand());
   std::ofstream f(tmp, std::ios::binary);
   if (!f) return;

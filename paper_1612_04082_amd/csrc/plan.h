@@ -110,5 +110,6 @@ void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out,
 void plan_profile(Plan& P, int mode);
 void plan_light_harvest(Plan& P, bool all);
 int plan_m2l_rank(const Plan& P);
+void plan_work(const Plan& P, int kind, bool sl, bool dl, double* flops, double* bytes);
 
 }  // namespace kfmm

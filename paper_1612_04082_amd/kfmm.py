@@ -78,6 +78,11 @@ def load_library():
     L.fmm_plan_info.restype = ctypes.c_int
     L.fmm_plan_destroy.argtypes = [vp]
     L.fmm_plan_destroy.restype = ctypes.c_int
+    L.fmm_plan_work.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)]
+    L.fmm_plan_work.restype = ctypes.c_int
+    L.fmm_plan_target_lists.argtypes = [vp, ctypes.POINTER(i32)]
+    L.fmm_plan_target_lists.restype = ctypes.c_int
     L.fmm_profile.argtypes = [vp, ctypes.c_int]
     L.fmm_profile.restype = ctypes.c_int
     L.fmm_phase_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -187,6 +192,22 @@ class FmmPlan:
         inf = FmmInfo()
         check(load_library().fmm_plan_info(self._h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in FmmInfo._fields_}
+
+    def work(self, kind, with_a=True, with_b=True):
+        """Algorithmic FLOP and HBM bytes of one evaluation, per phase: {phase: (flops, bytes)}."""
+        fl = (ctypes.c_double * len(PHASES))()
+        by = (ctypes.c_double * len(PHASES))()
+        check(load_library().fmm_plan_work(self._h, kind, int(bool(with_a)), int(bool(with_b)), fl, by))
+        return {ph: (fl[i], by[i]) for i, ph in enumerate(PHASES)}
+
+    def target_lists(self):
+        """Host int32 array, one entry per target (caller order): bit 0 = its leaf has a W list, bit 1 = its
+        leaf has an X list, bit 2 = an ancestor of its leaf has an X list."""
+        import numpy as np
+        flags = np.zeros(self.n_trg, dtype=np.int32)
+        if self.n_trg:
+            check(load_library().fmm_plan_target_lists(self._h, flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return flags
 
     def profile(self, enable=True):
         """True: time every phase (calls run in turn on one stream); "m2l": time only the M2L launch."""

@@ -133,6 +133,7 @@ def test_other_entry_points_check_arguments_first(lib):
     raw = ctypes.CDLL(kfmm.LIB_PATH)  # own function objects: the binding's argtypes stay untouched
     assert raw.fmm_eval(None, 0, None, None, None, None) == KFMM_E_ARG and last_error(lib) == "plan is NULL"
     assert raw.fmm_plan_info(None, None) == KFMM_E_ARG and last_error(lib) == "NULL argument"
+    assert raw.fmm_plan_target_lists(None, None) == KFMM_E_ARG and last_error(lib) == "NULL argument"
     assert raw.fmm_profile(None, 1) == KFMM_E_ARG and last_error(lib) == "plan is NULL"
     assert raw.fmm_plan_destroy(None) == 0
     assert raw.ws_destroy(None) == 0

@@ -1,0 +1,104 @@
+"""The benchmark's exact configuration against the FP64 oracle, element by element.
+
+Box beam, 201,344 quadrature points (targets = sources), single + double layer displacement
+(eq. fmm_summation with eqs. disp_1, disp_2), p = 8, leaf <= 256, FP32 passes with the M2L contraction and
+the translations on the FP16 matrix cores (split operands), M2L compressed onto a shared basis at cutoff
+3e-7.  Two evaluations run back to back on the default schedule (near field and W/X lists on the second
+stream, no profiling), exactly as the benchmark's timed loop runs them; both must be bitwise equal and the
+second is compared with the oracle's direct sums on 5,000 random targets plus every target of every leaf
+whose W or X list is non-empty (the adaptive paths a random sample would mostly miss).
+
+Bars (FP32 target of the method): relative L2 error <= 1e-5 over the compared targets, every target's
+error vector |v_t - v_ref,t| <= 1e-4 max_t |v_ref,t|, and the W/X subset on its own <= 1e-5.
+The same bars hold for a batched plan of periodic-cell bodies in the same arithmetic.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as od
+from tests.fmm_cases import G, K, rel_l2, to_dev
+from workloads import geometry as geo
+
+pytestmark = pytest.mark.gpu
+
+HEADLINE = dict(p=8, leaf_max=256, m2l_tol=3e-7)
+
+
+def _errors(got, ref):
+    d = np.linalg.norm(got - ref, axis=1)
+    vmax = np.linalg.norm(ref, axis=1).max()
+    return rel_l2(got, ref), float(d.max() / vmax), d, vmax
+
+
+def test_headline_box_beam_timed_schedule(cuda):
+    from paper_1612_04082_amd import kfmm
+    c = geo.box_beam_cloud(seed=2)
+    n = c["src"].shape[0]
+    print(f"headline: box beam {n} points, split-FP16, p=8, leaf<=256, m2l_tol 3e-7", flush=True)
+    plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G,
+                        precision=kfmm.FP32_M2L_SPLIT16, **HEADLINE)
+    a, b = to_dev(c["a"]), to_dev(c["b"])
+    out1 = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    out2 = torch.empty_like(out1)
+    plan.eval(kfmm.DISP, a, b, out1)
+    plan.eval(kfmm.DISP, a, b, out2)
+    torch.cuda.synchronize()
+    flags = plan.target_lists()
+    info = plan.info()
+    plan.close()
+    assert info["n_src"] == 201344 and info["m2l_rank"] == 480
+    assert torch.equal(out1, out2), "back-to-back evaluations differ"
+    got_all = out2.cpu().numpy()
+    wx = np.nonzero(flags & 3)[0]
+    rng = np.random.default_rng(12)
+    rnd = rng.choice(n, size=5000, replace=False)
+    idx = np.union1d(rnd, wx)
+    print(f"  {info['n_w_pairs']} W pairs, {info['n_x_pairs']} X pairs; {wx.size} targets in leaves with W/X lists; "
+          f"{idx.size} targets compared", flush=True)
+    assert wx.size > 0
+    ref = od.direct(od.DISP, c["src"][idx], c["src"], c["w"], a=c["a"], b=c["b"], nrm=c["nrm"], K=K, G=G)
+    got = got_all[idx]
+    e2, einf, d, vmax = _errors(got, ref)
+    sel = np.isin(idx, wx)
+    e2_wx = rel_l2(got[sel], ref[sel])
+    print(f"  rel L2 {e2:.3e}, eps_inf {einf:.3e}, W/X subset rel L2 {e2_wx:.3e}, worst target {idx[d.argmax()]}")
+    assert e2 <= 1e-5 and e2_wx <= 1e-5
+    assert np.all(d <= 1e-4 * vmax), f"{int((d > 1e-4 * vmax).sum())} targets above 1e-4 max|v_ref|"
+
+
+def test_headline_batched_cells(cuda):
+    """Six periodic-cell bodies in one batched plan, the headline arithmetic (split-FP16, p = 8,
+    leaf <= 256, cutoff 3e-7): per cell 600 random targets plus every W/X-list target, same bars."""
+    from paper_1612_04082_amd import kfmm
+    cells = geo.cell_batch(6)
+    src = np.concatenate([c["src"] for c in cells])
+    nrm = np.concatenate([c["nrm"] for c in cells])
+    w = np.concatenate([c["w"] for c in cells])
+    a = np.concatenate([c["a"] for c in cells])
+    b = np.concatenate([c["b"] for c in cells])
+    off = np.concatenate([[0], np.cumsum([c["src"].shape[0] for c in cells])])
+    print(f"batched cells: {len(cells)} cells, {src.shape[0]} points", flush=True)
+    plan = kfmm.FmmPlan(to_dev(src), to_dev(nrm), to_dev(w), K=K, G=G, precision=kfmm.FP32_M2L_SPLIT16,
+                        batch_src=list(off), **HEADLINE)
+    da, db = to_dev(a), to_dev(b)
+    out1 = plan.eval(kfmm.DISP, da, db)
+    out2 = plan.eval(kfmm.DISP, da, db)
+    torch.cuda.synchronize()
+    flags = plan.target_lists()
+    plan.close()
+    assert torch.equal(out1, out2)
+    got_all = out2.cpu().numpy()
+    rng = np.random.default_rng(13)
+    n_wx = 0
+    for g, c in enumerate(cells):
+        ng = c["src"].shape[0]
+        wx = np.nonzero(flags[off[g]:off[g + 1]] & 3)[0]
+        n_wx += wx.size
+        idx = np.union1d(rng.choice(ng, size=600, replace=False), wx)
+        ref = od.direct(od.DISP, c["src"][idx], c["src"], c["w"], a=c["a"], b=c["b"], nrm=c["nrm"], K=K, G=G)
+        e2, einf, d, vmax = _errors(got_all[off[g]:off[g + 1]][idx], ref)
+        print(f"  cell {g}: {ng} points, {wx.size} W/X targets, rel L2 {e2:.3e}, eps_inf {einf:.3e}")
+        assert e2 <= 1e-5, (g, e2)
+        assert np.all(d <= 1e-4 * vmax), g
+    assert n_wx > 0

@@ -23,6 +23,22 @@ def test_mlp_gradient_finite_differences():
             assert abs(fd - g[k].reshape(-1)[idx]) <= 1e-7 * max(1e-3, abs(fd)) + 1e-10
 
 
+def test_mlp_forward_closed_form():
+    """A hand-built network whose pre-activations land on 0 and +-ln 3, where silu is exact:
+    silu(0) = 0, silu(ln 3) = (3/4) ln 3 (sigmoid(ln 3) = 3/4), silu(-ln 3) = -(1/4) ln 3.  Pins the
+    composition (bias after each product, silu on the hidden layers only, X W row convention)."""
+    l3 = np.log(3.0)
+    p = dict(W1=np.eye(2), b1=np.array([1.0, -2.0]),
+             W2=np.array([[(l3 - 1) / (0.75 * l3), (1 - l3) / (0.75 * l3)], [5.0, 7.0]]), b2=np.array([1.0, -1.0]),
+             W3=np.array([[1.0, 0.0, 2.0], [0.0, 1.0, 2.0]]), b3=np.array([0.5, 0.0, -1.0]))
+    X = np.array([[l3 - 1.0, 2.0]])     # z1 = (ln 3, 0), h1 = ((3/4) ln 3, 0)
+    y, (_, z1, h1, z2, h2) = mlp.forward(p, X)
+    assert np.allclose(z1, [[l3, 0.0]], rtol=1e-15, atol=1e-15)
+    assert np.allclose(z2, [[l3, -l3]], rtol=1e-14, atol=1e-15)
+    assert np.allclose(h2, [[0.75 * l3, -0.25 * l3]], rtol=1e-14)
+    assert np.allclose(y, [[0.75 * l3 + 0.5, -0.25 * l3, l3 - 1.0]], rtol=1e-14)
+
+
 def test_silu_grad():
     z = np.linspace(-6, 6, 101)
     h = 1e-6

@@ -1,8 +1,13 @@
 """Seeded synthetic inputs shaped like the paper's workloads (Sec. 3 and Sec. 4).
 
 This module only generates inputs (points, normals, weights, densities, triangles, boundary
-conditions).  It holds none of the kernel, FMM or solver arithmetic and is shared by tests, the
-benchmark and the oracle-side checks.  Every generator takes an explicit seed and uses
+conditions) and is shared by tests, the benchmark and the oracle-side checks.  It holds no kernel, FMM
+or solver arithmetic.  One piece of the method's discretisation does live here: quadrature_cloud places
+the 16 quadrature points of a triangle (4 midpoint sub-triangles x the symmetric 4-point rule, Sec. 2.2
+"Matrix-vector products") to turn a surface into an FMM source cloud (the box beam and the periodic
+cells).  Those clouds are plain inputs of fmm_eval, so the FMM parity tests do not depend on the rule;
+the BEM tests never take their quadrature from here: oracle/bem.py and the library each place the points
+with their own code, and a GPU test compares the two.  Every generator takes an explicit seed and uses
 numpy.random.default_rng.
 
 Shapes:
