@@ -300,6 +300,21 @@ int ws_train(ws_net_t net, const float* feat, const double* x_mapped, const doub
 int ws_num_params(ws_net_t net, int64_t* n);
 int ws_get_params(ws_net_t net, float* host);
 int ws_set_params(ws_net_t net, const float* host);
+/*
+ * ws_train_noalloc -- ws_train for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation).  Same arguments, kernels and results
+ * as ws_train, but the per-call work buffers (activations, gradients, residual targets, partial sums)
+ * live in a static device array of the library (128 MiB, one copy per GPU, held until the process ends)
+ * instead of memory the network allocates on first use; the call allocates nothing.
+ *   n  1 <= n <= KFMM_WS_NOALLOC_MAX_ROWS (larger n: KFMM_E_ARG, nothing runs)
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (several streams or
+ * host threads) race and must be serialised by the caller.  Each call writes every word of the array
+ * it reads before reading it, so nothing carries over from an earlier call.  Synchronises the stream
+ * (it returns the loss).
+ */
+#define KFMM_WS_NOALLOC_MAX_ROWS 40000
+int ws_train_noalloc(ws_net_t net, const float* feat, const double* x_mapped, const double* x_target, int64_t n,
+                     double scale, int epochs, float lr, float* loss /* host, may be NULL */, void* stream);
 /* Test hook: loss and gradient (host, ws_num_params entries) for features X and residual targets R
  * (device FP32, n x 16 and n x 3). */
 int ws_loss_grad(ws_net_t net, const float* X, const float* R, int64_t n, float* loss, float* grad, void* stream);

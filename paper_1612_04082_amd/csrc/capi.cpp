@@ -301,6 +301,19 @@ extern "C" int ws_train(ws_net_t net, const float* feat, const double* x_mapped,
   });
 }
 
+extern "C" int ws_train_noalloc(ws_net_t net, const float* feat, const double* x_mapped, const double* x_target,
+                                int64_t n, double scale, int epochs, float lr, float* loss, void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(n > 0 && feat && x_mapped && x_target && epochs >= 0 && lr > 0, "bad arguments");
+    KFMM_REQUIRE(std::isfinite(scale) && scale > 0, "scale must be positive");
+    KFMM_REQUIRE(n <= KFMM_WS_NOALLOC_MAX_ROWS, "n exceeds KFMM_WS_NOALLOC_MAX_ROWS (static scratch size)");
+    WsNet& w = net_of(net);
+    WsWork b = ws_noalloc_work(w, n);
+    float L = w.train(feat, x_mapped, x_target, n, scale, epochs, lr, b, (hipStream_t)stream);
+    if (loss) *loss = L;
+  });
+}
+
 extern "C" int ws_num_params(ws_net_t net, int64_t* n) {
   return guarded([&] {
     KFMM_REQUIRE(n != nullptr, "NULL argument");

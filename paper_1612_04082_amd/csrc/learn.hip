@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/kfmm.h"
@@ -445,48 +446,108 @@ WsNet::WsNet(int din_, int width_, uint64_t seed) : din(din_), width(width_) {
   step = 0;
 }
 
+// The buffers of WsWork for n rows, in one fixed order from `take`.
+template <typename Take>
+static WsWork carve_work(int64_t n, int W, Take&& take) {
+  WsWork b;
+  b.Z1 = take(n * W);
+  b.H1 = take(n * W);
+  b.Z2 = take(n * W);
+  b.H2 = take(n * W);
+  b.Y = take(n * 3);
+  b.dY = take(n * 3);
+  b.dA = take(n * W);
+  b.dB = take(n * W);
+  b.Rt = take(n * 3);
+  b.pW = take((int64_t)kGradChunks * (W * W + W));
+  b.lpart = take(1024);
+  return b;
+}
+
 void WsNet::ensure(int64_t n) {
   if (n <= rows) return;
   work.release();
   rows = n;
-  const int W = width;
-  Z1 = work.get<float>(n * W);
-  H1 = work.get<float>(n * W);
-  Z2 = work.get<float>(n * W);
-  H2 = work.get<float>(n * W);
-  Y = work.get<float>(n * 3);
-  dY = work.get<float>(n * 3);
-  dA = work.get<float>(n * W);
-  dB = work.get<float>(n * W);
-  Rt = work.get<float>(n * 3);
-  pW = work.get<float>((size_t)kGradChunks * (W * W + W));
-  lpart = work.get<float>(1024);
+  buf = carve_work(n, width, [&](int64_t cnt) { return work.get<float>((size_t)cnt); });
+}
+
+// ------------------------------------------------------------------------- allocation-free training
+
+// Scratch memory of ws_train_noalloc, for callers that cannot allocate device memory: file-scope device
+// data, one copy per GPU, held until the process ends.  In host code the array's name is not a device
+// address; host code uses the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kWsScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) float scratch[kWsScratchBytes / sizeof(float)];
+
+static constexpr int64_t align_floats(int64_t n) { return (n + 63) / 64 * 64; }  // 256-byte pieces
+
+// floats that carve_work takes for n rows at width W, each piece rounded up to 256 bytes
+static constexpr int64_t noalloc_floats(int64_t n, int W) {
+  return 4 * align_floats(n * W) + 2 * align_floats(n * W) + 3 * align_floats(n * 3) +
+         align_floats((int64_t)kGradChunks * (W * W + W)) + align_floats(1024);
+}
+static_assert(noalloc_floats(KFMM_WS_NOALLOC_MAX_ROWS, 128) * (int64_t)sizeof(float) <= (int64_t)kWsScratchBytes,
+              "KFMM_WS_NOALLOC_MAX_ROWS rows of width 128 must fit the static scratch");
+
+static float* scratch_address() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static float* addr[kMaxDevices] = {};
+  int dev = 0;
+  KFMM_HIP(hipGetDevice(&dev));
+  KFMM_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    KFMM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    KFMM_REQUIRE(p != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+    addr[dev] = (float*)p;
+  }
+  return addr[dev];
+}
+
+WsWork ws_noalloc_work(const WsNet& net, int64_t n) {
+  KFMM_REQUIRE(n > 0 && n <= KFMM_WS_NOALLOC_MAX_ROWS,
+               "ws_train_noalloc: n must be in [1, KFMM_WS_NOALLOC_MAX_ROWS] (static scratch size)");
+  KFMM_REQUIRE(noalloc_floats(n, net.width) * (int64_t)sizeof(float) <= (int64_t)kWsScratchBytes,
+               "ws_train_noalloc: the network does not fit the static scratch");
+  float* base = scratch_address();
+  int64_t used = 0;
+  return carve_work(n, net.width, [&](int64_t cnt) {
+    float* p = base + used;
+    used += align_floats(cnt);
+    return p;
+  });
 }
 
 // loss and gradients for features X and residual targets Rt (device, FP32), gradients into `grads`
 float WsNet::loss_grad(const float* X, const float* R, int64_t n, hipStream_t s) {
   ensure(n);
+  return loss_grad(X, R, n, buf, s);
+}
+
+float WsNet::loss_grad(const float* X, const float* R, int64_t n, const WsWork& b, hipStream_t s) {
   const int W = width;
   float* P = params;
   unsigned nr = nb(n, 16);
-  hipLaunchKernelGGL(k_dense_fwd<true>, dim3(nr), dim3(128), 0, s, X, n, din, P + oW1, P + ob1, W, Z1, H1);
-  hipLaunchKernelGGL(k_dense_fwd<true>, dim3(nr), dim3(128), 0, s, H1, n, W, P + oW2, P + ob2, W, Z2, H2);
-  hipLaunchKernelGGL(k_dense_fwd<false>, dim3(nr), dim3(128), 0, s, H2, n, W, P + oW3, P + ob3, 3, (float*)nullptr,
-                     Y);
-  int lb = 256;
-  hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, Y, R, n * 3, dY, lpart);
+  hipLaunchKernelGGL(k_dense_fwd<true>, dim3(nr), dim3(128), 0, s, X, n, din, P + oW1, P + ob1, W, b.Z1, b.H1);
+  hipLaunchKernelGGL(k_dense_fwd<true>, dim3(nr), dim3(128), 0, s, b.H1, n, W, P + oW2, P + ob2, W, b.Z2, b.H2);
+  hipLaunchKernelGGL(k_dense_fwd<false>, dim3(nr), dim3(128), 0, s, b.H2, n, W, P + oW3, P + ob3, 3, (float*)nullptr,
+                     b.Y);
+  constexpr int lb = 256;
+  hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, b.Y, R, n * 3, b.dY, b.lpart);
   auto wg = [&](const float* A, const float* dZ, int k, int m, int oW) {
-    hipLaunchKernelGGL(k_weight_grad, dim3(kGradChunks), dim3(256), 0, s, A, dZ, n, k, m, pW);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(nb(k * m + m)), dim3(256), 0, s, pW, k * m + m, grads + oW);
+    hipLaunchKernelGGL(k_weight_grad, dim3(kGradChunks), dim3(256), 0, s, A, dZ, n, k, m, b.pW);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(nb(k * m + m)), dim3(256), 0, s, b.pW, k * m + m, grads + oW);
   };
-  wg(H2, dY, W, 3, oW3);
-  hipLaunchKernelGGL(k_dense_bwd, dim3(nr), dim3(128), 0, s, dY, n, 3, P + oW3, W, Z2, dA);  // dZ2
-  wg(H1, dA, W, W, oW2);
-  hipLaunchKernelGGL(k_dense_bwd, dim3(nr), dim3(128), 0, s, dA, n, W, P + oW2, W, Z1, dB);  // dZ1
-  wg(X, dB, din, W, oW1);
+  wg(b.H2, b.dY, W, 3, oW3);
+  hipLaunchKernelGGL(k_dense_bwd, dim3(nr), dim3(128), 0, s, b.dY, n, 3, P + oW3, W, b.Z2, b.dA);  // dZ2
+  wg(b.H1, b.dA, W, W, oW2);
+  hipLaunchKernelGGL(k_dense_bwd, dim3(nr), dim3(128), 0, s, b.dA, n, W, P + oW2, W, b.Z1, b.dB);  // dZ1
+  wg(X, b.dB, din, W, oW1);
   KFMM_HIP(hipGetLastError());
-  std::vector<float> lp(lb);
-  KFMM_HIP(hipMemcpyAsync(lp.data(), lpart, sizeof(float) * lb, hipMemcpyDeviceToHost, s));
+  float lp[lb];
+  KFMM_HIP(hipMemcpyAsync(lp, b.lpart, sizeof(float) * lb, hipMemcpyDeviceToHost, s));
   KFMM_HIP(hipStreamSynchronize(s));
   double L = 0;
   for (float v : lp) L += v;
@@ -516,10 +577,16 @@ void WsNet::predict(const float* X, int64_t n, const double* xm, double scale, d
 float WsNet::train(const float* X, const double* xm, const double* xt, int64_t n, double scale, int epochs, float lr,
                    hipStream_t s) {
   ensure(n);
-  hipLaunchKernelGGL(k_residual_target, dim3(nb(3 * n)), dim3(256), 0, s, 3 * n, xt, xm, 1.0 / scale, Rt);
+  return train(X, xm, xt, n, scale, epochs, lr, buf, s);
+}
+
+float WsNet::train(const float* X, const double* xm, const double* xt, int64_t n, double scale, int epochs, float lr,
+                   const WsWork& b, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_target, dim3(nb(3 * n)), dim3(256), 0, s, 3 * n, xt, xm, 1.0 / scale, b.Rt);
+  KFMM_HIP(hipGetLastError());
   float L = 0;
   for (int e = 0; e < epochs; ++e) {
-    L = loss_grad(X, Rt, n, s);
+    L = loss_grad(X, b.Rt, n, b, s);
     adam(lr, s);
   }
   return L;

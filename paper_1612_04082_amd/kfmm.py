@@ -106,13 +106,16 @@ def load_library():
     L.ws_predict.argtypes = [vp, fp, i64, vp, ctypes.c_double, vp, vp]
     L.ws_train.argtypes = [vp, fp, vp, vp, i64, ctypes.c_double, ctypes.c_int, ctypes.c_float,
                            ctypes.POINTER(ctypes.c_float), vp]
+    L.ws_train_noalloc.argtypes = [vp, fp, vp, vp, i64, ctypes.c_double, ctypes.c_int, ctypes.c_float,
+                                   ctypes.POINTER(ctypes.c_float), vp]
     L.ws_num_params.argtypes = [vp, ctypes.POINTER(i64)]
     L.ws_get_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     L.ws_set_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
     L.ws_loss_grad.argtypes = [vp, fp, fp, i64, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), vp]
     L.ws_save.argtypes = [vp, ctypes.c_char_p]
     L.ws_load.argtypes = [vp, ctypes.c_char_p]
-    for f in ("ws_create", "ws_destroy", "ws_features", "ws_predict", "ws_train", "ws_num_params", "ws_get_params",
+    for f in ("ws_create", "ws_destroy", "ws_features", "ws_predict", "ws_train", "ws_train_noalloc", "ws_num_params",
+              "ws_get_params",
               "ws_set_params", "ws_loss_grad", "ws_save", "ws_load"):
         getattr(L, f).restype = ctypes.c_int
     ip = ctypes.POINTER(ctypes.c_int)
@@ -344,6 +347,7 @@ def _fptr(t, name, last=None):
 
 
 WS_DIN = 16
+WS_NOALLOC_MAX_ROWS = 40000  # KFMM_WS_NOALLOC_MAX_ROWS
 
 
 class WarmStartNet:
@@ -394,6 +398,16 @@ class WarmStartNet:
         check(load_library().ws_train(self._h, _fptr(feat, "feat", WS_DIN), _dptr(x_mapped, "x_mapped", 3, n),
                                       _dptr(x_target, "x_target", 3, n), n, float(scale), int(epochs),
                                       float(lr), ctypes.byref(loss), _stream()))
+        return loss.value
+
+    def train_noalloc(self, feat, x_mapped, x_target, scale, epochs=50, lr=1e-3):
+        """ws_train_noalloc: as train(), with the work buffers in the library's static device scratch
+        (n <= WS_NOALLOC_MAX_ROWS); allocates no device memory."""
+        loss = ctypes.c_float()
+        n = int(feat.shape[0])
+        check(load_library().ws_train_noalloc(self._h, _fptr(feat, "feat", WS_DIN), _dptr(x_mapped, "x_mapped", 3, n),
+                                              _dptr(x_target, "x_target", 3, n), n, float(scale), int(epochs),
+                                              float(lr), ctypes.byref(loss), _stream()))
         return loss.value
 
     def save(self, path):
