@@ -13,18 +13,27 @@ A x = b of eq. num2 (the dense matrix of oracle.bem.DenseBEM, solver units):
     position of each triple; ties keep the element order;
   * fine blocks R_b: consecutive runs of 32 elements of that order (the last one shorter), each with
     the 3 unknowns of every element;
-  * coarse space Z: consecutive runs of 64 elements ("aggregates"); per aggregate and component one
-    column, the indicator of that component's unknowns of its elements (3 columns per aggregate).
+  * coarse space Z: consecutive runs of 64 elements ("aggregates").  Per aggregate six raw columns, in
+    this order: the three translations (component k of every unknown of its elements, displacement and
+    traction unknowns alike) and the three infinitesimal rotations about the mean centroid c_a of its
+    elements (the value (e_k x (c_e - c_a))_c at the displacement unknown (e, c), zero at traction
+    unknowns).  Local rigid motions are the near-null space of 1/2 I + P (on a closed surface a rigid
+    displacement gives zero traction), which is what makes the slender cantilevers converge slowly.
+    The six are orthonormalised by modified Gram-Schmidt, two passes, in that order; a column whose
+    norm after the passes is at most 1e-8 of its raw norm (or whose raw norm is zero: an aggregate with
+    no displacement unknown, or collinear ones) is dropped.
 
 GMRES is run on A M^-1 (right preconditioning), so the residual it reduces is the true ||b - A x||.
-Parity pinned by tests/test_oracle_precond.py (an explicit dense construction, the exactness of each
-level on its own subspace, and the Morton order of a regular grid).
+Parity pinned by tests/test_oracle_precond.py (an explicit dense construction from the raw columns,
+the exactness of each level on its own subspace, reproduction of rigid motions, and the Morton order of
+a regular grid).
 """
 import numpy as np
 
 QBITS = 14
 FINE = 32
 COARSE = 64
+DROP = 1e-8
 
 
 def morton_order(cen):
@@ -54,22 +63,61 @@ def unknowns(elems):
     return (3 * elems[:, None] + np.arange(3)[None, :]).reshape(-1)
 
 
-class TwoLevel:
-    """M^-1 of the module docstring for a dense A (3T x 3T) and the element centroids."""
+def raw_columns(elems, cen, disp):
+    """The six raw coarse columns of one aggregate, restricted to its unknowns (3|a| x 6)."""
+    elems = np.asarray(elems)
+    ca = cen[elems].mean(axis=0)
+    d = cen[elems] - ca
+    m = disp[unknowns(elems)].reshape(-1, 3)
+    C = np.zeros((3 * elems.size, 6))
+    for k in range(3):
+        tr = np.zeros((elems.size, 3))
+        tr[:, k] = 1.0
+        C[:, k] = tr.reshape(-1)
+        e = np.zeros(3)
+        e[k] = 1.0
+        C[:, 3 + k] = (np.cross(e, d) * m).reshape(-1)
+    return C
 
-    def __init__(self, A, cen, fine=FINE, coarse=COARSE):
+
+def orthonormal_columns(C):
+    """Modified Gram-Schmidt, two passes, in column order; dropped columns are left out."""
+    kept = []
+    for j in range(C.shape[1]):
+        v = C[:, j].copy()
+        raw = np.linalg.norm(v)
+        for _ in range(2):
+            for q in kept:
+                v = v - np.dot(q, v) * q
+        nv = np.linalg.norm(v)
+        if raw == 0.0 or nv <= DROP * raw:
+            continue
+        kept.append(v / nv)
+    return np.array(kept).T if kept else np.zeros((C.shape[0], 0))
+
+
+class TwoLevel:
+    """M^-1 of the module docstring for a dense A (3T x 3T), the element centroids and the mask of
+    displacement unknowns (True where the traction is prescribed)."""
+
+    def __init__(self, A, cen, disp, fine=FINE, coarse=COARSE):
         self.A = np.asarray(A, dtype=np.float64)
         T = self.A.shape[0] // 3
+        cen = np.asarray(cen, dtype=np.float64)
+        disp = np.asarray(disp, dtype=bool).reshape(-1)
         self.order = morton_order(cen)
         self.fine = []
         for bl in blocks(self.order, fine):
             idx = unknowns(bl)
             self.fine.append((idx, np.linalg.inv(self.A[np.ix_(idx, idx)])))
-        agg = blocks(self.order, coarse)
-        self.Z = np.zeros((3 * T, 3 * len(agg)))
-        for a, bl in enumerate(agg):
-            for c in range(3):
-                self.Z[3 * bl + c, 3 * a + c] = 1.0
+        cols = []
+        for bl in blocks(self.order, coarse):
+            Q = orthonormal_columns(raw_columns(bl, cen, disp))
+            for j in range(Q.shape[1]):
+                z = np.zeros(3 * T)
+                z[unknowns(bl)] = Q[:, j]
+                cols.append(z)
+        self.Z = np.array(cols).T
         self.E = self.Z.T @ self.A @ self.Z
         self.Einv = np.linalg.inv(self.E)
 
