@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--m2l-tol", type=float, default=3e-7, help="shared-basis M2L compression cutoff (FP32); 0 = dense")
     ap.add_argument("--svd-eps", type=float, default=0.0, help="pseudo-inverse cutoff (0: library default)")
     ap.add_argument("--rows", type=int, default=2000, help="oracle sample for the cantilever workload")
+    ap.add_argument("--precond", choices=["none", "two-level", "both"], default="both",
+                    help="GMRES preconditioning of the cantilever workload")
     ap.add_argument("--iters", type=int, default=20, help="Algorithm 1 iterations for the warmstart workload")
     ap.add_argument("--measure-from", type=int, default=11)
     ap.add_argument("--p-bem", type=int, default=8, help="expansion order of the BEM solves in the warmstart workload")

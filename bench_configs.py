@@ -5,8 +5,8 @@ cells       64 periodic-cell bodies (unit cube minus ellipsoids, 20k-200k points
             single + double layer, FP32 (BF16 M2L with --precision bf16; split FP16 with the compressed M2L with
             --precision split16); also 64 separate plans; oracle on
             1,000 targets per cell.
-cantilever  8:1:1 cantilever with 64 spherical holes (~965k quadrature points): bem_solve (FP64, tol 1e-6),
-            then the stress at the 128^3 interior lattice; oracle rows of the matrix-vector product and stress
+cantilever  8:1:1 cantilever with 64 spherical holes (~965k quadrature points): bem_solve (FP64, tol 1e-6)
+            without and with the two-level preconditioner (--precond), then the stress at the 128^3 interior lattice; oracle rows of the matrix-vector product and stress
             on sampled points.
 warmstart   Algorithm 1 on the 120 x 15 x 15 voxel beam for 20 iterations (C = 0.001: the load corner's stress
             concentration sets the TD range, and larger C removes a third of the beam at once); systems 11-20 solved
@@ -140,12 +140,25 @@ def cantilever(args):
     prob = geo.cantilever_problem(M, h)
     T = prob["tri"].shape[0]
     dtri, dbc, dval = _t(prob["tri"]), _t(prob["bc_type"], torch.int8), _t(prob["bc_val"])
-    torch.cuda.synchronize()
-    t0 = time.time()
-    x, u, t, st = kfmm.bem_solve(dtri, dbc, dval, K=K, G=G, tol=1e-6, restart=200, max_iter=3000, p=8,
-                                 leaf_max=128, precision=kfmm.FP64, svd_eps=args.svd_eps, allow_noconv=True)
-    torch.cuda.synchronize()
-    solve_s = time.time() - t0
+    # unpreconditioned and two-level preconditioned GMRES on the same system; the preconditioned solution
+    # feeds the stress stage
+    modes = {"none": [kfmm.PC_NONE], "two-level": [kfmm.PC_TWO_LEVEL],
+             "both": [kfmm.PC_NONE, kfmm.PC_TWO_LEVEL]}[args.precond]
+    solves = {}
+    for pcm in modes:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x, u, t, st = kfmm.bem_solve(dtri, dbc, dval, K=K, G=G, tol=1e-6, restart=200, max_iter=3000, p=8,
+                                     leaf_max=128, precision=kfmm.FP64, svd_eps=args.svd_eps, allow_noconv=True,
+                                     precond=pcm)
+        torch.cuda.synchronize()
+        solve_s = time.time() - t0
+        solves["two-level" if pcm == kfmm.PC_TWO_LEVEL else "none"] = dict(
+            seconds=solve_s, iters=st["iters"], converged=st["converged"], rel_res=st["rel_res"],
+            restarts=st["restarts"], t_setup_s=st["t_setup_s"], t_precond_s=st["t_precond_s"],
+            pc_coarse_dim=st["pc_coarse_dim"], t_solve_s=st["t_solve_s"],
+            ms_per_iteration=1e3 * st["t_solve_s"] / max(1, st["n_matvec"]))
+        print(json.dumps({"solve": solves}), flush=True)
     # oracle rows of the product for a random unknown vector (direct FP64 sums + closed-form self blocks);
     # at the solution itself A x ~ b is a 1e4-fold cancellation and the relative row error is inflated
     rng = np.random.default_rng(3)
@@ -185,12 +198,9 @@ def cantilever(args):
     return dict(metric="BEM solve time (s), cantilever 8:1:1 with 64 holes", value=solve_s, unit="s",
                 higher_is_better=False, dtype="f64",
                 config=dict(workload=f"cantilever [0,32]x[0,4]^2, h=2/9, 64 holes: {T} elements, {16 * T} quadrature "
-                                     f"points, {3 * T} unknowns; GMRES(200) tol 1e-6, FMM p=8 leaf<=128 FP64"),
-                svd_eps=args.svd_eps,
-                gmres=dict(iters=st["iters"], converged=st["converged"], rel_res=st["rel_res"],
-                           restarts=st["restarts"], res_estimate=st["res_estimate"],
-                           t_setup_s=st["t_setup_s"], t_solve_s=st["t_solve_s"],
-                           ms_per_iteration=1e3 * st["t_solve_s"] / max(1, st["n_matvec"])),
+                                     f"points, {3 * T} unknowns; GMRES(200) tol 1e-6, FMM p=8 leaf<=128 FP64",
+                            precond=args.precond),
+                svd_eps=args.svd_eps, gmres=solves,
                 matvec_rows_rel_err=matvec_err, oracle_rows_seconds=t_rows,
                 stress=dict(targets=int(lat.shape[0]), p=9, precision="fp32t64", seconds=stress_s,
                             seconds_first_call=stress_times[0], points_per_s=lat.shape[0] / stress_s,

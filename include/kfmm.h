@@ -208,7 +208,25 @@ typedef struct {
                            from the minimal-residual combination a x0 + c x0_alt (a alone without x0_alt),
                            from the products A x0, A x0_alt (one extra product); a start still worse than
                            zero is replaced by zero. */
+  int precond;     /* KFMM_PC_NONE or KFMM_PC_TWO_LEVEL (right preconditioning: the residual GMRES reduces and
+                      the stopping test stay the true ||b - A x||) */
+  int pc_fine;     /* elements per fine block, 1..32; 0 -> 32 */
+  int pc_coarse;   /* elements per coarse aggregate; 0 -> 64, doubled while 6 ceil(T / size) > 4096 */
 } bem_opts;
+
+/* Preconditioners of bem_solve (the paper leaves the preconditioning of mixed problems open, Sec. 5,
+ * "Discussion and future work"). */
+enum {
+  KFMM_PC_NONE = 0,
+  KFMM_PC_TWO_LEVEL = 1 /* two-level additive Schwarz: M^-1 = sum_b R_b^T (R_b A R_b^T)^-1 R_b + Z (Z^T A Z)^-1 Z^T.
+                           Elements ordered along the Morton curve of their centroids (14 bits per axis);
+                           fine blocks of pc_fine consecutive elements (their exact 3m x 3m blocks of A,
+                           inverted); aggregates of pc_coarse consecutive elements, each contributing its
+                           local rigid motions as coarse columns (three translations of every unknown, three
+                           rotations about the aggregate's mean centroid at the displacement unknowns),
+                           orthonormalised (modified Gram-Schmidt, two passes; a column keeping at most 1e-8
+                           of its raw norm is dropped); E = Z^T A Z summed directly in FP64 and inverted. */
+};
 
 typedef struct {   /* host */
   int iters, restarts, converged;
@@ -223,6 +241,8 @@ typedef struct {   /* host */
   double res_estimate; /* last GMRES estimate */
   double b_norm;
   double t_setup_s, t_solve_s;
+  double t_precond_s;   /* preconditioner set-up (included in t_setup_s) */
+  int64_t pc_coarse_dim; /* columns of Z kept (0 without the preconditioner) */
 } bem_stats;
 
 /*
@@ -250,6 +270,22 @@ int bem_stress(const bem_problem* prob, const double* u_full, const double* t_fu
  * x, y: T x 3 (device).  Builds a plan internally.  Synchronises the stream.
  */
 int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const double* x, double* y, void* stream);
+
+/* Sizes of a built preconditioner (host). */
+typedef struct {
+  int64_t n_fine_blocks, n_aggregates, n_coarse; /* n_coarse = 6 n_aggregates (dropped columns included) */
+  int fine, coarse, n_dropped;
+  double t_setup_s;
+} bem_pc_info;
+
+/*
+ * bem_precond_apply -- y = M^-1 v for the preconditioner opts->precond (KFMM_PC_TWO_LEVEL) of the system
+ * bem_solve builds for prob and opts (solver units: traction unknowns scaled by -l/G).  v, y: T x 3 (device,
+ * must not overlap).  info (host) may be NULL.  Builds the system and the preconditioner internally; returns
+ * KFMM_E_ARG for KFMM_PC_NONE, block sizes out of range, or a singular block.  Synchronises the stream.
+ */
+int bem_precond_apply(const bem_problem* prob, const bem_opts* opts, const double* v, double* y, bem_pc_info* info,
+                      void* stream);
 
 /* bem_quadrature -- the 16 quadrature points per triangle (device, 16T x 3), their normals (16T x 3),
  * weights (16T) and the collocation points (T x 3).  Synchronises the stream. */

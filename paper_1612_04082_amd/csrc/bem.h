@@ -9,6 +9,8 @@
 
 namespace kfmm {
 
+struct TwoLevelPC;
+
 struct BemSystem {
   hipStream_t stream;
   int64_t T = 0, n = 0;
@@ -23,6 +25,7 @@ struct BemSystem {
   double *a16 = nullptr, *b16 = nullptr, *ae = nullptr, *be = nullptr, *fmm_out = nullptr;
   double* partial = nullptr;
   std::unique_ptr<Plan> plan;
+  std::unique_ptr<TwoLevelPC> pc;  // right preconditioner of gmres (optional)
   int64_t n_apply = 0;
 
   BemSystem(const bem_problem& p, const fmm_opts& fo, hipStream_t s);

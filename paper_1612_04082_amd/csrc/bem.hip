@@ -16,7 +16,9 @@
 //    (positive definite), keeping the spectrum in the right half-plane.
 //  * Restarted GMRES(m): Arnoldi with classical Gram-Schmidt applied twice, FP64 vectors on the device,
 //    the small Hessenberg problem (Givens rotations) on the host; stop when ||b - A x|| / ||b|| <= tol,
-//    checked with a true residual at every restart.
+//    checked with a true residual at every restart.  With a preconditioner M (precond.hip) the Arnoldi
+//    process runs on A M^-1 and each cycle's correction is M^-1 V y (right preconditioning: the residual
+//    is still the true one).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -27,6 +29,7 @@
 #include "../../include/kfmm.h"
 #include "bem.h"
 #include "common.h"
+#include "precond.h"
 #include "plan.h"
 #include "tree.h"
 
@@ -411,6 +414,7 @@ bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, do
   double* w = arena.get<double>(n);
   double* V = arena.get<double>((size_t)(m + 1) * n);
   double* d_h = arena.get<double>(m + 2);
+  double* zb = pc ? arena.get<double>(n) : nullptr;  // M^-1 of an Arnoldi vector or of the correction
   double* part = scratch_partial();
   apply(1, nullptr, b);
   if (x0) {  // x0 in physical units -> traction unknowns divided by the column scale
@@ -523,7 +527,12 @@ bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, do
     int k = 0;
     for (int j = 0; j < m && it < max_iter; ++j) {
       double* vj1 = V + (size_t)(j + 1) * n;
-      apply(0, V + (size_t)j * n, vj1);
+      const double* vin = V + (size_t)j * n;
+      if (pc) {
+        pc->apply(vin, zb, s);
+        vin = zb;
+      }
+      apply(0, vin, vj1);
       ++it;
       // classical Gram-Schmidt, twice
       std::vector<double> hcol(j + 2, 0.0);
@@ -562,7 +571,14 @@ bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, do
       y[i] = H[(size_t)i * m + i] != 0 ? acc / H[(size_t)i * m + i] : 0.0;
     }
     KFMM_HIP(hipMemcpyAsync(d_h, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_add_many, dim3(nblk(n)), dim3(256), 0, s, V, (int64_t)n, k, d_h, x, n);
+    if (pc) {  // x += M^-1 (V y)
+      KFMM_HIP(hipMemsetAsync(w, 0, sizeof(double) * n, s));
+      hipLaunchKernelGGL(k_add_many, dim3(nblk(n)), dim3(256), 0, s, V, (int64_t)n, k, d_h, w, n);
+      pc->apply(w, zb, s);
+      hipLaunchKernelGGL(k_axpby, dim3(nblk(n)), dim3(256), 0, s, n, 1.0, zb, 1.0, x);
+    } else {
+      hipLaunchKernelGGL(k_add_many, dim3(nblk(n)), dim3(256), 0, s, V, (int64_t)n, k, d_h, x, n);
+    }
     KFMM_HIP(hipGetLastError());
     st.iters = it;
   }

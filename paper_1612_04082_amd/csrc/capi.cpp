@@ -10,6 +10,7 @@
 #include "common.h"
 #include "bem.h"
 #include "learn.h"
+#include "precond.h"
 #include "plan.h"
 
 namespace kfmm {
@@ -191,10 +192,19 @@ extern "C" int bem_solve(const bem_problem* prob, const bem_opts* opts, const do
                  "tol > 0, restart in [1, 500], max_iter >= 0 required");
     hipStream_t s = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
+    KFMM_REQUIRE(opts->precond == KFMM_PC_NONE || opts->precond == KFMM_PC_TWO_LEVEL, "unknown preconditioner");
     BemSystem sys(*prob, opts->fmm, s);
+    if (opts->precond == KFMM_PC_TWO_LEVEL) {
+      sys.pc = std::make_unique<TwoLevelPC>();
+      sys.pc->build(sys, opts->pc_fine, opts->pc_coarse);
+    }
     double t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bem_stats st = sys.gmres(x0, opts->x0_alt, x, opts->tol, opts->restart, opts->max_iter);
     st.t_setup_s = t_setup;
+    if (sys.pc) {
+      st.t_precond_s = sys.pc->t_setup_s;
+      st.pc_coarse_dim = sys.pc->nc - sys.pc->n_dropped;
+    }
     // traction unknowns back to physical units
     sys.split(x, u_full, t_full);
     scale_traction_unknowns(sys, x, sys.scale_t);
@@ -215,6 +225,31 @@ extern "C" int bem_stress(const bem_problem* prob, const double* u_full, const d
     KFMM_REQUIRE(M >= 0 && (M == 0 || (trg && out)), "bad targets");
     if (M == 0) return;
     stress_from_boundary(*prob, u_full, t_full, trg, M, out, *fmm, (hipStream_t)stream);
+  });
+}
+
+extern "C" int bem_precond_apply(const bem_problem* prob, const bem_opts* opts, const double* v, double* y,
+                                 bem_pc_info* info, void* stream) {
+  return guarded([&] {
+    check_problem(prob);
+    KFMM_REQUIRE(opts && v && y, "opts, v or y is NULL");
+    KFMM_REQUIRE(opts->precond == KFMM_PC_TWO_LEVEL, "bem_precond_apply needs opts->precond = KFMM_PC_TWO_LEVEL");
+    KFMM_REQUIRE(v != y, "v and y must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    BemSystem sys(*prob, opts->fmm, s);
+    TwoLevelPC pc;
+    pc.build(sys, opts->pc_fine, opts->pc_coarse);
+    pc.apply(v, y, s);
+    KFMM_HIP(hipStreamSynchronize(s));
+    if (info) {
+      info->n_fine_blocks = pc.nb;
+      info->n_aggregates = pc.na;
+      info->n_coarse = pc.nc;
+      info->fine = pc.fine;
+      info->coarse = pc.coarse;
+      info->n_dropped = pc.n_dropped;
+      info->t_setup_s = pc.t_setup_s;
+    }
   });
 }
 

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libkfmm.so")
 
 DISP, STRESS = 0, 1
 FP64, FP32, FP32_M2L_BF16, FP32_M2L_SPLIT16, FP32_TRANS64 = 0, 1, 2, 3, 4
+PC_NONE, PC_TWO_LEVEL = 0, 1
 PHASES = ("permute", "s2m", "uc2ue", "m2m", "m2l_prep", "m2l", "m2l_red", "s2l", "down", "near", "leaf")
 _STATUS = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_HIP", -4: "E_NOCONV", -5: "E_STATE"}
 
@@ -46,7 +47,14 @@ class BemProblem(ctypes.Structure):
 
 class BemOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("fmm", FmmOpts),
-                ("x0_alt", ctypes.c_void_p)]
+                ("x0_alt", ctypes.c_void_p), ("precond", ctypes.c_int), ("pc_fine", ctypes.c_int),
+                ("pc_coarse", ctypes.c_int)]
+
+
+class BemPcInfo(ctypes.Structure):
+    _fields_ = [("n_fine_blocks", ctypes.c_int64), ("n_aggregates", ctypes.c_int64), ("n_coarse", ctypes.c_int64),
+                ("fine", ctypes.c_int), ("coarse", ctypes.c_int), ("n_dropped", ctypes.c_int),
+                ("t_setup_s", ctypes.c_double)]
 
 
 class BemStats(ctypes.Structure):
@@ -54,7 +62,7 @@ class BemStats(ctypes.Structure):
                 ("used_alt", ctypes.c_int), ("used_zero", ctypes.c_int), ("rel_res_alt", ctypes.c_double),
                 ("rel_res_start", ctypes.c_double), ("start_coef", ctypes.c_double * 2), ("n_matvec", ctypes.c_int64), ("rel_res", ctypes.c_double), ("rel_res0", ctypes.c_double),
                 ("res_estimate", ctypes.c_double), ("b_norm", ctypes.c_double), ("t_setup_s", ctypes.c_double),
-                ("t_solve_s", ctypes.c_double)]
+                ("t_solve_s", ctypes.c_double), ("t_precond_s", ctypes.c_double), ("pc_coarse_dim", ctypes.c_int64)]
 
 
 _lib = None
@@ -92,6 +100,9 @@ def load_library():
     L.bem_solve.restype = ctypes.c_int
     L.bem_stress.argtypes = [ctypes.POINTER(BemProblem), vp, vp, vp, i64, vp, ctypes.POINTER(FmmOpts), vp]
     L.bem_stress.restype = ctypes.c_int
+    L.bem_precond_apply.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(BemOpts), vp, vp,
+                                    ctypes.POINTER(BemPcInfo), vp]
+    L.bem_precond_apply.restype = ctypes.c_int
     L.bem_matvec.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(FmmOpts), ctypes.c_int, vp, vp, vp]
     L.bem_matvec.restype = ctypes.c_int
     L.bem_quadrature.argtypes = [i64, vp, vp, vp, vp, vp, vp]
@@ -269,7 +280,8 @@ def _problem(tri, bc_type, bc_val, K, G):
 
 
 def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_iter=2000, x0=None, p=8,
-              leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False, x0_alt=None):
+              leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False, x0_alt=None,
+              precond=PC_NONE, pc_fine=0, pc_coarse=0):
     """bem_solve on torch tensors: tri (T,3,3) f64, bc_type (T,3) int8, bc_val (T,3) f64, all on the GPU.
 
     Returns (x, u, t, stats) with x the unknowns (physical units) and u, t the full boundary data."""
@@ -279,7 +291,7 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
     prob = _problem(tri, bc_type, bc_val, K, G)
     alt = _dptr(x0_alt, "x0_alt", 3, int(tri.shape[0]))
     opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0),
-                   alt.value if alt is not None else None)
+                   alt.value if alt is not None else None, precond, pc_fine, pc_coarse)
     T = int(tri.shape[0])
     x = torch.empty((T, 3), dtype=torch.float64, device=tri.device)
     u = torch.empty_like(x) if want_full else None
@@ -293,6 +305,24 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
         return x, u, t, stats
     check(rc)
     return x, u, t, stats
+
+
+def bem_precond_apply(tri, bc_type, bc_val, v, K=None, G=1.0, p=8, leaf_max=128, precision=FP32, svd_eps=0.0,
+                      pc_fine=0, pc_coarse=0):
+    """y = M^-1 v for the two-level preconditioner of the system bem_solve builds (v: (T,3) f64 on the GPU,
+    solver units).  Returns (y, info dict)."""
+    L = load_library()
+    if K is None:
+        K = moduli(G, 0.3)
+    prob = _problem(tri, bc_type, bc_val, K, G)
+    T = int(tri.shape[0])
+    opts = BemOpts(1e-6, 50, 0, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0), None, PC_TWO_LEVEL,
+                   pc_fine, pc_coarse)
+    y = torch.empty((T, 3), dtype=torch.float64, device=tri.device)
+    info = BemPcInfo()
+    check(L.bem_precond_apply(ctypes.byref(prob), ctypes.byref(opts), _dptr(v, "v", 3, T), _dptr(y, "y", 3),
+                              ctypes.byref(info), _stream()))
+    return y, {k: getattr(info, k) for k, _ in BemPcInfo._fields_}
 
 
 def bem_stress(tri, bc_type, bc_val, u, t, trg, K=None, G=1.0, p=8, leaf_max=128, precision=FP32, svd_eps=0.0):
