@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--rows", type=int, default=2000, help="oracle sample for the cantilever workload")
     ap.add_argument("--precond", choices=["none", "two-level", "both"], default="both",
                     help="GMRES preconditioning of the cantilever workload")
+    ap.add_argument("--full-residual", action="store_true",
+                    help="cantilever: the solution's residual with every row of the product by direct FP64 sums")
     ap.add_argument("--iters", type=int, default=20, help="Algorithm 1 iterations for the warmstart workload")
     ap.add_argument("--measure-from", type=int, default=11)
     ap.add_argument("--p-bem", type=int, default=8, help="expansion order of the BEM solves in the warmstart workload")

@@ -167,10 +167,30 @@ def cantilever(args):
     tc = time.time()
     ref_rows = ob.matvec_rows(prob["tri"], prob["bc_type"], xs, rows, K, G, nthreads=_cores())
     t_rows = time.time() - tc
-    gpu_rows = kfmm.bem_matvec(dtri, dbc, dval, x=_t(xs), which=0, K=K, G=G, p=8, precision=kfmm.FP64,
-                               svd_eps=args.svd_eps or 1e-7)
-    gpu_rows = gpu_rows.cpu().numpy()[rows]
+    gpu_full = kfmm.bem_matvec(dtri, dbc, dval, x=_t(xs), which=0, K=K, G=G, p=8, precision=kfmm.FP64,
+                               svd_eps=args.svd_eps or 1e-7).cpu().numpy()
+    gpu_rows = gpu_full[rows]
     matvec_err = float(np.linalg.norm(gpu_rows - ref_rows) / np.linalg.norm(ref_rows))
+    # residual floor of the solution measured with the exact operator: product error eps times
+    # ||A|| ||x|| / ||b|| (||A|| estimated as ||A x_r|| / ||x_r|| on the random x_r above)
+    scale_t = -G / ob.mean_edge(prob["tri"])
+    xsol = x.cpu().numpy().copy()
+    xsol[prob["bc_type"] == 0] /= scale_t  # solver units
+    b_gpu = kfmm.bem_matvec(dtri, dbc, dval, which=1, K=K, G=G, p=8, precision=kfmm.FP64,
+                            svd_eps=args.svd_eps or 1e-7).cpu().numpy()
+    kx = float(np.linalg.norm(gpu_full) / np.linalg.norm(xs) * np.linalg.norm(xsol) / np.linalg.norm(b_gpu))
+    residual = dict(norm_A_x_over_b=kx, product_err_random=matvec_err, floor_estimate=matvec_err * kx)
+    if args.full_residual:
+        # every row of b - A x by direct FP64 sums over all quadrature points on the host cores
+        tc = time.time()
+        allrows = np.arange(T)
+        ax_full = ob.matvec_rows(prob["tri"], prob["bc_type"], xsol, allrows, K, G, nthreads=_cores())
+        print(json.dumps({"direct_product_rows_done_s": time.time() - tc}), flush=True)
+        b_full = ob.rhs_rows(prob["tri"], prob["bc_type"], prob["bc_val"], allrows, K, G, nthreads=_cores())
+        residual.update(direct_rel_res=float(np.linalg.norm(b_full - ax_full) / np.linalg.norm(b_full)),
+                        direct_seconds=time.time() - tc,
+                        rhs_fmm_vs_direct=float(np.linalg.norm(b_gpu.reshape(-1, 3) - b_full) / np.linalg.norm(b_full)))
+        print(json.dumps({"residual": residual}), flush=True)
     # stress at the 128^3 lattice
     # stress at the 128^3 lattice: p = 9 (the derivative kernel needs one order more than displacement for
     # 1e-5 here: 9e-6 at p = 8, 3e-6 at p = 9 measured with random boundary data), FP32 M2L and near field
@@ -201,7 +221,7 @@ def cantilever(args):
                                      f"points, {3 * T} unknowns; GMRES(200) tol 1e-6, FMM p=8 leaf<=128 FP64",
                             precond=args.precond),
                 svd_eps=args.svd_eps, gmres=solves,
-                matvec_rows_rel_err=matvec_err, oracle_rows_seconds=t_rows,
+                matvec_rows_rel_err=matvec_err, oracle_rows_seconds=t_rows, residual_vs_exact=residual,
                 stress=dict(targets=int(lat.shape[0]), p=9, precision="fp32t64", seconds=stress_s,
                             seconds_first_call=stress_times[0], points_per_s=lat.shape[0] / stress_s,
                             rel_err=stress_err, oracle_seconds=t_sig),

@@ -208,22 +208,10 @@ def gmres(matvec, b, x0=None, tol=1e-6, restart=50, max_iter=2000):
         x = x + V[:k].T @ y
 
 
-def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0):
-    """Rows of A x (eq. num2, solver units as in DenseBEM) by direct FP64 sums, for large meshes.
-
-    For each collocation row t: the quadrature sum over every element's 16 points (coincident pair
-    skipped), with the element's own quadrature terms replaced by its closed-form self block, plus the
-    free term 1/2 u.  Unknown layout as DenseBEM: u where the traction is prescribed, t / scale_t where the
-    displacement is prescribed, scale_t = -G / l.
-    """
-    tri = np.ascontiguousarray(tri, dtype=np.float64)
-    T = tri.shape[0]
-    bc = np.asarray(bc_type).reshape(T, 3)
-    x = np.asarray(x, dtype=np.float64).reshape(T, 3)
-    scale_t = -G / mean_edge(tri)
-    t_unk = bc == 0
-    a_el = np.where(t_unk, -scale_t * x, 0.0)   # -t for traction unknowns
-    b_el = np.where(t_unk, 0.0, x)              #  u for displacement unknowns
+def _rows(tri, a_el, b_el, rows, K, G, nthreads):
+    """Rows of U(a) + P(b) + 1/2 b at the collocation points `rows`, element densities a_el, b_el (T x 3):
+    the quadrature sum over every element's 16 points (coincident pair skipped), with the element's own
+    quadrature terms replaced by its closed-form self block, plus the free term."""
     qp, qn, qw, qe = quadrature(tri)
     cen = tri_geometry(tri)[0]
     rows = np.asarray(rows)
@@ -234,3 +222,32 @@ def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0):
         Us, Ps = self_integrals(tri[r], K, G)
         out[i] += -own[0] + Us @ a_el[r] + Ps @ b_el[r] + 0.5 * b_el[r]
     return out
+
+
+def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0):
+    """Rows of A x (eq. num2, solver units as in DenseBEM) by direct FP64 sums, for large meshes.
+
+    Unknown layout as DenseBEM: u where the traction is prescribed, t / scale_t where the displacement is
+    prescribed, scale_t = -G / l; A x = 1/2 u_unk + P u_unk - U t_unk.
+    """
+    tri = np.ascontiguousarray(tri, dtype=np.float64)
+    T = tri.shape[0]
+    bc = np.asarray(bc_type).reshape(T, 3)
+    x = np.asarray(x, dtype=np.float64).reshape(T, 3)
+    scale_t = -G / mean_edge(tri)
+    t_unk = bc == 0
+    a_el = np.where(t_unk, -scale_t * x, 0.0)   # -t for traction unknowns
+    b_el = np.where(t_unk, 0.0, x)              #  u for displacement unknowns
+    return _rows(tri, a_el, b_el, rows, K, G, nthreads)
+
+
+def rhs_rows(tri, bc_type, bc_val, rows, K, G, nthreads=0):
+    """Rows of the right-hand side b = U t_known - P u_known - 1/2 u_known (eq. num2) by direct FP64 sums."""
+    tri = np.ascontiguousarray(tri, dtype=np.float64)
+    T = tri.shape[0]
+    bc = np.asarray(bc_type).reshape(T, 3)
+    y = np.asarray(bc_val, dtype=np.float64).reshape(T, 3)
+    u_known = bc == 0
+    a_el = np.where(u_known, 0.0, y)    # t where the traction is prescribed
+    b_el = np.where(u_known, -y, 0.0)   # -u where the displacement is prescribed
+    return _rows(tri, a_el, b_el, rows, K, G, nthreads)

@@ -213,3 +213,13 @@ def test_matvec_rows_equals_dense():
     got = ob.matvec_rows(p["tri"], p["bc_type"], x, rows, K, G)
     ref = (s.A @ x).reshape(-1, 3)[rows]
     assert np.abs(got - ref).max() < 1e-12 * np.abs(s.A @ x).max()
+
+
+def test_rhs_rows_equals_dense():
+    """Right-hand side by direct sums equals the dense B y of eq. num2 (columns of the prescribed values)."""
+    p = geo.cube_tension_problem(2)
+    s = ob.DenseBEM(p["tri"], p["bc_type"], p["bc_val"], K, G)
+    rows = np.array([0, 3, 22, 41, 95])
+    got = ob.rhs_rows(p["tri"], p["bc_type"], p["bc_val"], rows, K, G)
+    ref = s.b.reshape(-1, 3)[rows]
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(s.b).max()
