@@ -33,11 +33,11 @@ sys.path.insert(0, ROOT)
 # a phase runs on: the split-FP16 products at the FP16 dense matrix peak (the three FP16 products per
 # algorithmic product are the implementation's cost, reported apart as the matrix-pipe utilisation).
 HBM_TBS = 8.0
-VALU_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 157.3, "split16": 157.3, "fp32t64": 157.3}
-M2L_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "split16": 2500.0, "fp32t64": 157.3}
-TRANS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 78.6, "split16": 2500.0, "fp32t64": 78.6}
+VALU_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split16": 157.3, "fp32t64": 157.3}
+M2L_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split16": 2500.0, "fp32t64": 157.3}
+TRANS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split16": 2500.0, "fp32t64": 78.6}
 MFMA_PRODUCTS = {"split16": 3}  # matrix-core products per algorithmic product
-KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_gemm_f<float>", "bf16": "k_gemm_bf16",
+KERNELS = {"fp64": "k_gemm_f<double>", "fp32": "k_gemm_f<float>", "fp32t64": "k_gemm_f<float>",
            "split16": "k_gemm_h3 (FP16 high/low split, 3 MFMA products)"}
 PHASE_UNIT = {"permute": "hbm", "m2l_red": "hbm", "s2m": "valu", "s2l": "valu", "near": "valu", "leaf": "valu",
               "uc2ue": "trans", "m2m": "trans", "m2l_prep": "trans", "down": "trans", "m2l": "m2l"}
@@ -94,7 +94,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16", "split16", "fp32t64"], default="split16",
+    ap.add_argument("--precision", choices=["fp64", "fp32", "split16", "fp32t64"], default="split16",
                     help="fp32t64: FP32 M2L with FP64 pseudo-inverses and translations")
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=256)
@@ -141,8 +141,8 @@ def main():
     from workloads import geometry as geo
 
     dev = torch.device("cuda:0")
-    prec = {"fp64": kfmm.FP64, "fp32": kfmm.FP32, "bf16": kfmm.FP32_M2L_BF16,
-            "split16": kfmm.FP32_M2L_SPLIT16, "fp32t64": kfmm.FP32_TRANS64}[args.precision]
+    prec = {"fp64": kfmm.FP64, "fp32": kfmm.FP32, "split16": kfmm.FP32_M2L_SPLIT16,
+            "fp32t64": kfmm.FP32_TRANS64}[args.precision]
     c = geo.box_beam_cloud(seed=2)
     n = c["src"].shape[0]
     t = lambda x: torch.tensor(x, dtype=torch.float64, device=dev)
@@ -244,7 +244,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32+bf16", "split16": "f32+f16x2",
+        "dtype": {"fp64": "f64", "fp32": "f32", "split16": "f32+f16x2",
                   "fp32t64": "f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "box-beam 120x20x20 surface, 201344 quadrature points, single+double layer "

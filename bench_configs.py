@@ -2,12 +2,12 @@
 
 sphere      4,096 points on the unit sphere, single layer, FP64, p = 6, leaf <= 64; full O(N^2) oracle.
 cells       64 periodic-cell bodies (unit cube minus ellipsoids, 20k-200k points each) in ONE batched plan,
-            single + double layer, FP32 (BF16 M2L with --precision bf16; split FP16 with the compressed M2L with
-            --precision split16); also 64 separate plans; oracle on
-            1,000 targets per cell.
+            single + double layer, FP32 (split FP16 with the compressed M2L with --precision split16); also 64
+            separate plans; oracle on 1,000 targets per cell.
 cantilever  8:1:1 cantilever with 64 spherical holes (~965k quadrature points): bem_solve (FP64, tol 1e-6)
-            without and with the two-level preconditioner (--precond), then the stress at the 128^3 interior lattice; oracle rows of the matrix-vector product and stress
-            on sampled points.
+            without and with the two-level preconditioner (--precond), then the stress at the 128^3 interior
+            lattice; oracle rows of the matrix-vector product and stress on sampled points; with
+            --full-residual every row of b - A x by direct sums.
 warmstart   Algorithm 1 on the 120 x 15 x 15 voxel beam for 20 iterations (C = 0.001: the load corner's stress
             concentration sets the TD range, and larger C removes a third of the beam at once); systems 11-20 solved
             from zero, from the previous solution mapped onto the new surface, and from the learned network.
@@ -69,7 +69,7 @@ def sphere(args):
 
 def cells(args):
     from oracle import direct as od
-    prec = {"bf16": kfmm.FP32_M2L_BF16, "split16": kfmm.FP32_M2L_SPLIT16}.get(args.precision, kfmm.FP32)
+    prec = {"split16": kfmm.FP32_M2L_SPLIT16}.get(args.precision, kfmm.FP32)
     tol = args.m2l_tol if args.precision == "split16" else 0.0  # compressed M2L with the split-FP16 arithmetic
     cl = geo.cell_batch(64)
     src = np.concatenate([c["src"] for c in cl])
@@ -123,7 +123,7 @@ def cells(args):
     tcpu = time.time() - tc
     return dict(metric="FMM target points/s (64 cells, one batched plan)", value=n / (ms * 1e-3),
                 unit="target points/s", ms_per_step=ms,
-                dtype={kfmm.FP32_M2L_BF16: "f32+bf16", kfmm.FP32_M2L_SPLIT16: "f32+f16x2"}.get(prec, "f32"),
+                dtype={kfmm.FP32_M2L_SPLIT16: "f32+f16x2"}.get(prec, "f32"),
                 config=dict(workload=f"64 periodic-cell bodies, {n} points, SL+DL, p={args.p}, leaf<={args.leaf}",
                             m2l_tol=tol),
                 sequential=dict(ms_per_step=ms_seq, value=n / (ms_seq * 1e-3), plan_seconds=plan_seq_s),
@@ -233,9 +233,11 @@ def warmstart(args):
     from paper_1612_04082_amd.alg1 import warm_start_study
     M0 = np.ones((120, 15, 15), bool)
     log = []
+    pcm = kfmm.PC_NONE if args.precond == "none" else kfmm.PC_TWO_LEVEL
     rec = warm_start_study(M0, n_iter=args.iters, train_from=2, measure_from=args.measure_from, h=1.0, C=0.001,
                            tol_seq=1e-6, tol=1e-6, epochs=200, lr=1e-3, restart=200, p=args.p_bem, leaf_max=128,
-                           precision=kfmm.FP64, log=lambda r: (log.append(r), print(json.dumps(r), flush=True)))
+                           precision=kfmm.FP64, precond=pcm,
+                           log=lambda r: (log.append(r), print(json.dumps(r), flush=True)))
     meas = [r for r in rec if "zero" in r]
     summ = {}
     for mode in ("zero", "prev", "net"):
@@ -246,7 +248,7 @@ def warmstart(args):
     return dict(metric="BEM solve time learned vs plain (s per solve, mean over measured iterations)",
                 value=summ["net"]["seconds_mean"], unit="s", higher_is_better=False, dtype="f64",
                 config=dict(workload=f"Algorithm 1 on 120x15x15 voxels, C=0.001, tol 1e-6, GMRES(200), "
-                                     f"FMM p={args.p_bem} FP64"),
+                                     f"FMM p={args.p_bem} FP64", precond="none" if pcm == kfmm.PC_NONE else "two-level"),
                 summary=summ, speedup_vs_zero=summ["zero"]["seconds_mean"] / summ["net"]["seconds_mean"],
                 speedup_vs_prev=summ["prev"]["seconds_mean"] / summ["net"]["seconds_mean"],
                 iterations=[dict(iter=r["iter"], alpha=r.get("alpha"), T=r["T"]) for r in rec])

@@ -46,8 +46,10 @@ enum {
                              M2M/L2L chains run on scaled check potentials (smooth fields, no cancellation)
                              and the check-to-equivalent pseudo-inverses are applied in their SVD-factored
                              form (an orthogonal rotation, then a column-scaled one), once per box */
-  KFMM_FP32_M2L_BF16 = 2, /* near field, check/equivalent evaluations in FP32, M2L in BF16 on the matrix
-                             cores (FP32 accumulation), pseudo-inverse and M2M/L2L translations in FP64 */
+  KFMM_FP32_M2L_BF16 = 2, /* withdrawn: every call given it returns KFMM_E_ARG.  A BF16 M2L (8-bit operands,
+                             FP32 accumulation) measured ~1e-2 relative error against its 1e-3 target: the
+                             equivalent densities cancel strongly; KFMM_FP32_M2L_SPLIT16 uses the matrix cores
+                             at FP32 accuracy instead */
   KFMM_FP32_M2L_SPLIT16 = 3, /* as KFMM_FP32 but the M2L contractions, the M2M/L2L translations on check
                                potentials and the orthogonal factors of the pseudo-inverses on the FP16
                                matrix cores: every operator and every input vector, scaled by a power of
@@ -68,7 +70,7 @@ typedef struct {
   double K, G;        /* bulk and shear modulus */
   int p;              /* equivalent-surface order: p points per cube edge, 6(p-1)^2+2 points; 0 -> 6 */
   int leaf_max;       /* a box is split while it holds more than leaf_max sources + targets; 0 -> 64 */
-  int precision;      /* KFMM_FP64, KFMM_FP32, KFMM_FP32_M2L_BF16, KFMM_FP32_M2L_SPLIT16 or KFMM_FP32_TRANS64 */
+  int precision;      /* KFMM_FP64, KFMM_FP32, KFMM_FP32_M2L_SPLIT16 or KFMM_FP32_TRANS64 */
   double svd_eps;     /* relative singular-value cutoff of the check-to-equivalent pseudo-inverse; 0 -> 1e-8 */
   int max_depth;      /* deepest octree level; 0 -> 16 */
   size_t mem_limit;   /* bytes of device memory the plan may use; 0 = no limit */
@@ -233,7 +235,8 @@ typedef struct {   /* host */
   int used_alt;        /* 1 if x0_alt entered the start (c != 0) */
   int used_zero;       /* 1 if both given starts were worse than zero and zero was used */
   double rel_res_alt;  /* true relative residual of x0_alt (if given) */
-  double rel_res_start; /* relative residual of the minimal-residual start */
+  double rel_res_start; /* relative residual of the start GMRES iterates from (the minimal-residual combination,
+                            or 1 when the guard fell back to zero); 0 without a start */
   double start_coef[2]; /* the coefficients a, c of the start */
   int64_t n_matvec;
   double rel_res;      /* true relative residual of the returned x */
@@ -361,7 +364,7 @@ int ws_load(ws_net_t net, const char* path);
 /*
  * Test hook: one launch of the batched gather/scatter GEMM used by every translation,
  *   Y[:, out[j]] (=, +=, atomic +=) scale[j] * A[op[j]] * X[:, in[j]]
- * precision 0: A, X, Y FP64; 1: FP32; 2: A, X bfloat16 and Y FP32; 3: A, X, Y FP32 with the products on
+ * precision 0: A, X, Y FP64; 1: FP32; 3: A, X, Y FP32 with the products on
  * the FP16 matrix cores (A and X split into high and low FP16 parts, see KFMM_FP32_M2L_SPLIT16; NC a
  * multiple of 96 or 64).  A holds NC x NC row-major operators,
  * X and Y hold NC-vectors (stride NC).  op, in, out, scale (scale may be NULL) are HOST arrays of ncols

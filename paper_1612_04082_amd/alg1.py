@@ -57,7 +57,7 @@ class Problem:
 
 class Optimiser:
     def __init__(self, M0, h=1.0, load=(0.0, 0.0, -1.0), C=0.02, G=1.0, nu=0.3, tol=1e-8, restart=200, p=8,
-                 leaf_max=128, precision=0, max_iter=5000):
+                 leaf_max=128, precision=0, max_iter=5000, precond=0):
         from paper_1612_04082_amd import kfmm
         self.kfmm = kfmm
         self.M0 = np.asarray(M0, bool)
@@ -66,7 +66,7 @@ class Optimiser:
         self.K = kfmm.moduli(G, nu)
         self.E = 2 * G * (1 + nu)
         self.solve_kw = dict(K=self.K, G=G, tol=tol, restart=restart, p=p, leaf_max=leaf_max, precision=precision,
-                             max_iter=max_iter)
+                             max_iter=max_iter, precond=precond)
         self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=precision)
 
     def solve(self, prob, x0=None, x0_alt=None, **over):
@@ -156,6 +156,7 @@ def warm_start_study(M0, n_iter=20, train_from=2, measure_from=11, h=1.0, C=0.02
                         _, _, _, s2 = opt.solve(prob, x0=x0, x0_alt=xm, tol=tol)
                     sync()
                     r[mode] = dict(iters=s2["iters"], seconds=time.time() - t0 + extra, rel_res0=s2["rel_res0"],
+                                   rel_res_start=s2["rel_res_start"] if mode != "zero" else 1.0,
                                    converged=s2["converged"], used_alt=s2.get("used_alt", 0),
                                    used_zero=s2.get("used_zero", 0))
             if k + 1 >= train_from:

@@ -512,6 +512,7 @@ bem_stats BemSystem::gmres(const double* x0, const double* x0_alt, double* x, do
         rel = 1.0;
         beta = bnorm;
         st.used_zero = 1;
+        st.rel_res_start = 1.0;
       }
     }
     if (rel <= tol || it >= max_iter || !std::isfinite(rel)) break;

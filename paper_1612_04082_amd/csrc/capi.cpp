@@ -60,6 +60,7 @@ extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* s
     // trg_xyz NULL: the targets are the sources (n_trg == n_src), or there are none (n_trg == 0)
     if (trg_xyz == nullptr) KFMM_REQUIRE(n_trg == n_src || n_trg == 0, "aliased targets need n_trg == n_src");
     KFMM_REQUIRE(opts->precision >= KFMM_FP64 && opts->precision <= KFMM_FP32_TRANS64, "unknown precision");
+    KFMM_REQUIRE(opts->precision != KFMM_FP32_M2L_BF16, kBf16Withdrawn);
     KFMM_REQUIRE(opts->p == 0 || (opts->p >= 3 && opts->p <= 12), "p must be in [3, 12]");
     KFMM_REQUIRE(opts->leaf_max >= 0 && opts->max_depth >= 0, "negative leaf_max or max_depth");
     KFMM_REQUIRE(opts->m2l_tol >= 0 && opts->m2l_tol < 1, "m2l_tol must be in [0, 1)");
@@ -431,7 +432,8 @@ extern "C" int kfmm_selftest_gemm(int precision, const void* A, int NC, const vo
   return guarded([&] {
     const int kernel = precision >> 4;
     precision &= 15;
-    KFMM_REQUIRE(precision >= 0 && precision <= 3 && mode >= 0 && mode <= 2 && ncols >= 0, "bad arguments");
+    KFMM_REQUIRE((precision == 0 || precision == 1 || precision == 3) && mode >= 0 && mode <= 2 && ncols >= 0,
+                 "bad arguments");
     KFMM_REQUIRE(kernel >= 0 && kernel <= 4 && (kernel == 0 || precision <= 1 || (precision == 3 && kernel == 1)),
                  "bad kernel selector");
     KFMM_REQUIRE(NC > 0 && gemm_tm(NC) != 0, "NC must be a positive multiple of 96 or 128");

@@ -33,6 +33,11 @@ void set_last_error(const std::string& msg);
 
 constexpr double kPi = 3.14159265358979323846;
 
+// Message of the withdrawn BF16 M2L precision (precision value 2).
+constexpr const char* kBf16Withdrawn =
+    "KFMM_FP32_M2L_BF16 is withdrawn (BF16 M2L measured ~1e-2 relative error, above its 1e-3 target); "
+    "KFMM_FP32_M2L_SPLIT16 runs the M2L on the FP16 matrix cores at FP32 accuracy";
+
 // Elastic constants derived from (K, G) (Sec. 2, eq. elast): nu and the kernel prefactors.
 struct Elastic {
   double K, G, nu;

@@ -12,7 +12,6 @@
 //                caller's order (U or D kernel for far fields; U+P or D+S near field)
 // Coordinates are stored relative to the leaf centre; box-centre offsets are exact dyadic numbers
 // (power-of-two root), which keeps FP32 near-field differences accurate.
-#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -74,7 +73,6 @@ struct DeviceOps {
   uint16_t *vs_h3 = nullptr, *us_h3 = nullptr;  // split-FP16 copies (one scale each), made on first use
   float *vs_h3_scale = nullptr, *us_h3_scale = nullptr;
   float* m2l32 = nullptr;
-  __hip_bfloat16* m2l16 = nullptr;
   uint16_t* m2l_h3 = nullptr;     // m2l64 split into FP16 high / low parts, made on first use
   float* m2l_h3_scale = nullptr;  // power-of-two scale per operator
   // split-FP16 copies (one scale per operator) of M2M_q, L2L_q (8 each) and of the orthogonal pseudo-inverse
@@ -183,10 +181,6 @@ static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, 
       for (size_t i = 0; i < f.size(); ++i) f[i] = (float)m2l_all[i];
       d->m2l32 = d->arena.get<float>(f.size());
       KFMM_HIP(hipMemcpy(d->m2l32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-      std::vector<__hip_bfloat16> h(m2l_all.size());
-      for (size_t i = 0; i < h.size(); ++i) h[i] = __float2bfloat16((float)m2l_all[i]);
-      d->m2l16 = d->arena.get<__hip_bfloat16>(h.size());
-      KFMM_HIP(hipMemcpy(d->m2l16, h.data(), h.size() * sizeof(__hip_bfloat16), hipMemcpyHostToDevice));
     }
     g_ops[key] = d;
   }
@@ -260,12 +254,6 @@ template <typename TI, typename TO>
 __global__ void k_convert(int64_t n, const TI* in, TO* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (TO)in[i];
-}
-
-template <>
-__global__ void k_convert<double, __hip_bfloat16>(int64_t n, const double* in, __hip_bfloat16* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = __float2bfloat16((float)in[i]);
 }
 
 template <typename T>
@@ -983,6 +971,9 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
                   int64_t n_trg, const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, const fmm_opts& o,
                   hipStream_t s) {
   auto t_start = std::chrono::steady_clock::now();
+  KFMM_REQUIRE(o.precision == KFMM_FP64 || o.precision == KFMM_FP32 || o.precision == KFMM_FP32_M2L_SPLIT16 ||
+                   o.precision == KFMM_FP32_TRANS64,
+               o.precision == KFMM_FP32_M2L_BF16 ? kBf16Withdrawn : "unknown precision");
   std::unique_ptr<Plan> P(new Plan());
   P->opts = o;
   P->el = Elastic::make(o.K, o.G);
@@ -1285,7 +1276,6 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   if (!f64) {
     P->phi_up_lo = zalloc(nbc * 4);
     P->phi_dn_lo = zalloc(nbc * 4);
-    if (o.precision == KFMM_FP32_M2L_BF16) P->phi_up_bf = zalloc(nbc * 2);
   }
   KFMM_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
   for (hipEvent_t* e : {&P->fork_ev, &P->phi_ev, &P->x_ev, &P->join_ev})
@@ -1563,13 +1553,7 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
               (float*)P.m2l_slots, kStore, s);
       m2l_end();
     } else {
-      hipLaunchKernelGGL((k_convert<double, __hip_bfloat16>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
-                         (int64_t)nbc, P.phi_up, (__hip_bfloat16*)P.phi_up_bf);
-      mark(KFMM_PH_M2L);
-      m2l_begin();
-      gemm_bf16(P.job_m2l, D.m2l16, GemmDims::Sq(NC), (const __hip_bfloat16*)P.phi_up_bf, (float*)P.m2l_slots, kStore,
-                s);
-      m2l_end();
+      throw Error(KFMM_E_ARG, "unsupported M2L precision");
     }
     mark(KFMM_PH_M2L_RED);
     if (P.m2l_red_n) {
@@ -1693,7 +1677,7 @@ void plan_work(const Plan& P, int kind, bool sl, bool dl, double* flops, double*
   const bool f32t = P.f32t, comp = P.comp != nullptr;
   // bytes per coefficient of the translations and of the M2L (split FP16: hi + lo, 4 bytes)
   const double vb = f32t ? 4.0 : 8.0;
-  const double mb = P.prec == KFMM_FP64 ? 8.0 : P.prec == KFMM_FP32_M2L_BF16 ? 2.0 : 4.0;
+  const double mb = P.prec == KFMM_FP64 ? 8.0 : 4.0;
   const double r = comp ? (double)P.comp->r : n;
   const double f_src = sl && dl ? (kind == KFMM_DISP ? 65 : 130) : sl ? (kind == KFMM_DISP ? 29 : 50)
                                                                      : (kind == KFMM_DISP ? 45 : 90);

@@ -5,10 +5,8 @@
 // A_op are NC x NC row-major operators (op index per tile, stride NC*NC), X and Y hold one
 // NC-vector per box (box-major, stride NC).  Columns are grouped in tiles of <= 64 that share one
 // operator.  A workgroup of 4 waves computes a (16*TM) x 64 block: every wave owns 16 columns and
-// all rows; A and X tiles are staged in LDS, products use v_mfma_*_16x16x4 (FP64/FP32) or
-// v_mfma_f32_16x16x32_bf16 (BF16 inputs, FP32 accumulation).
+// all rows; A and X tiles are staged in LDS, products use v_mfma_*_16x16x4 (FP64/FP32).
 #pragma once
-#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -69,10 +67,6 @@ void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, fl
               int kernel = kGemmAuto);
 void gemm_f32(const GemmJob& job, const float* A, GemmDims d, const float* X, double* Y, int mode, hipStream_t s,
               int kernel = kGemmAuto);
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, float* Y, int mode,
-               hipStream_t s);
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, double* Y, int mode,
-               hipStream_t s);
 
 // Split-FP16 products (gemm_h3.hip).  split_h3 writes n_rows rows of len values (a multiple of 8, read at
 // stride ld) as split rows of 2 * len FP16 numbers, chunks of [hi of 8 values][lo of the same 8] after

@@ -1,4 +1,4 @@
-// Batched gather/scatter GEMM on the matrix cores (see gemm.h): FP64 and BF16 launches and the test hook.
+// Batched gather/scatter GEMM on the matrix cores (see gemm.h): FP64 launches and the test hook.
 // Compiled with the VGPR form of the MFMA instructions (see build.py).
 #include <algorithm>
 
@@ -10,28 +10,6 @@ void gemm_f64(const GemmJob& job, const double* A, GemmDims d, const double* X, 
               int kernel) {
   gemm_t(job, A, d, X, Y, mode, s, kernel);
 }
-template <typename TY>
-static void gemm_bf16_t(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, TY* Y,
-                        int mode, hipStream_t s) {
-  if (job.n_tiles == 0) return;
-  check_dims(d);
-  if (gemm_tm(d.M) == 6)
-    hipLaunchKernelGGL((k_gemm_bf16<TY, 6>), dim3(job.n_tiles, d.M / 96), dim3(256), 0, s, (const __bf16*)A, d,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
-  else
-    hipLaunchKernelGGL((k_gemm_bf16<TY, 8>), dim3(job.n_tiles, d.M / 128), dim3(256), 0, s, (const __bf16*)A, d,
-                       job.tiles, job.in_idx, job.out_idx, job.scale, (const __bf16*)X, Y, mode);
-  KFMM_HIP(hipGetLastError());
-}
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, float* Y, int mode,
-               hipStream_t s) {
-  gemm_bf16_t(job, A, d, X, Y, mode, s);
-}
-void gemm_bf16(const GemmJob& job, const __hip_bfloat16* A, GemmDims d, const __hip_bfloat16* X, double* Y, int mode,
-               hipStream_t s) {
-  gemm_bf16_t(job, A, d, X, Y, mode, s);
-}
-
 }  // namespace kfmm
 
 // ------------------------------------------------------------------ test hook (see kfmm_selftest_gemm)
@@ -77,10 +55,8 @@ void selftest_gemm(int precision, const void* A, int NC, const void* X, void* Y,
     gemm_h3(job, Ah, as, GemmDims{NC, NC, 2 * NC, NC}, Xh, xs, (float*)Y, mode, s);
   } else if (precision == 0)
     gemm_f64(job, (const double*)A, d, (const double*)X, (double*)Y, mode, s, kernel);
-  else if (precision == 1)
-    gemm_f32(job, (const float*)A, d, (const float*)X, (float*)Y, mode, s, kernel);
   else
-    gemm_bf16(job, (const __hip_bfloat16*)A, d, (const __hip_bfloat16*)X, (float*)Y, mode, s);
+    gemm_f32(job, (const float*)A, d, (const float*)X, (float*)Y, mode, s, kernel);
   KFMM_HIP(hipStreamSynchronize(s));
 }
 }  // namespace kfmm

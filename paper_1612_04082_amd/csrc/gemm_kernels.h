@@ -1,9 +1,8 @@
 // Kernels and launch helpers of the batched gather/scatter GEMM (see gemm.h), shared by gemm.hip (FP64,
-// BF16, test hook) and gemm_f32.hip (FP32), which are compiled with different MFMA register forms.
+// test hook) and gemm_f32.hip (FP32), which are compiled with different MFMA register forms.
 //
 // MFMA operand layout used (wave64, 16x16 output block):
 //   v_mfma_{f64,f32}_16x16x4 : lane l holds A[l%16][l/16], B[l/16][l%16];
-//   v_mfma_f32_16x16x32_bf16 : lane l holds A[l%16][8(l/16)+0..7], B[8(l/16)+0..7][l%16];
 //   accumulator (FP32 outputs): lane l holds C[4(l/16)+v][l%16], v = 0..3;
 //   accumulator (FP64 output) : lane l holds C[l/16+4v][l%16], v = 0..3.
 #pragma once
@@ -15,7 +14,6 @@ namespace kfmm {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 // The dispatcher hands workgroups to the 8 XCDs round-robin by linear id (x fastest).  Remapped so that
 // each XCD receives a contiguous range of logical ids: with the row block fastest in the logical order,
@@ -271,78 +269,6 @@ __global__ __launch_bounds__(256) void k_gemm_sk(const T* __restrict__ A, GemmDi
     const TY sc = scale ? (TY)scale[col] : TY(1);
     store_out(Y + (size_t)out_idx[col] * dm.ldy + r0 + row, sc * (TY)sum, mode);
   }
-}
-
-// BF16 inputs, FP32 accumulation: BK = 32 per LDS stage, one MFMA k-step.
-template <typename TY, int TM>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const __bf16* __restrict__ A, GemmDims dm, const int4* __restrict__ tiles,
-                                                   const int* __restrict__ in_idx, const int* __restrict__ out_idx,
-                                                   const double* __restrict__ scale, const __bf16* __restrict__ X,
-                                                   TY* __restrict__ Y, int mode) {
-  constexpr int BK = 32, BM = 16 * TM, BN = kGemmBN, PAD = 8;
-  static_assert(BM * 4 <= 512, "A tile: at most two 16-byte chunks per thread");
-  __shared__ __attribute__((aligned(16))) __bf16 As[BM][BK + PAD];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][BK + PAD];
-  const int lid = xcd_logical_id();
-  const int4 tile = tiles[lid / gridDim.y];
-  const int r0 = (lid % gridDim.y) * BM;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const __bf16* Aop = A + (size_t)tile.x * dm.M * dm.K;
-  // A tile: BM rows x 32 bf16 = BM*4 chunks of 8 (16 bytes), at most 2 per thread; B tile: 64 columns x 4
-  // chunks
-  const int bc = tid >> 2, bq = tid & 3;
-  const int col_ok = bc < tile.z;
-  const __bf16* xcol = X + (size_t)(col_ok ? in_idx[tile.y + bc] : 0) * dm.ldx;
-  uint4 ra[2], rb;
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      int lin = tid + 256 * e;
-      if (lin < BM * 4) {
-        int row = lin >> 2, q = lin & 3;
-        ra[e] = *(const uint4*)(Aop + (size_t)(r0 + row) * dm.K + k0 + 8 * q);
-      }
-    }
-    rb = col_ok ? *(const uint4*)(xcol + k0 + 8 * bq) : make_uint4(0, 0, 0, 0);
-  };
-  auto stash = [&]() {
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      int lin = tid + 256 * e;
-      if (lin < BM * 4) *(uint4*)&As[lin >> 2][8 * (lin & 3)] = ra[e];
-    }
-    *(uint4*)&Bs[bc][8 * bq] = rb;
-  };
-  float4_t acc[TM];
-#pragma unroll
-  for (int t = 0; t < TM; ++t) acc[t] = float4_t{0, 0, 0, 0};
-  const int nk = dm.K / BK;
-  load(0);
-  stash();
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) load((kt + 1) * BK);
-    bf16x8_t b = *(const bf16x8_t*)&Bs[wave * 16 + (lane & 15)][8 * (lane >> 4)];
-#pragma unroll
-    for (int t = 0; t < TM; ++t) {
-      bf16x8_t a = *(const bf16x8_t*)&As[t * 16 + (lane & 15)][8 * (lane >> 4)];
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-    }
-    __syncthreads();
-    if (kt + 1 < nk) {
-      stash();
-      __syncthreads();
-    }
-  }
-  const int c = wave * 16 + (lane & 15);
-  if (c >= tile.z) return;
-  const int col = tile.y + c;
-  TY* ycol = Y + (size_t)out_idx[col] * dm.ldy + r0;
-  const TY sc = scale ? (TY)scale[col] : TY(1);
-#pragma unroll
-  for (int t = 0; t < TM; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) store_out(ycol + t * 16 + 4 * (lane >> 4) + v, sc * (TY)acc[t][v], mode);
 }
 
 inline void check_dims(const GemmDims& d) {

@@ -72,7 +72,7 @@ struct Plan {
   // FP32 translations: check potentials (upward, then downward qhat), work rows, reduced compressed check
   // potentials (n_box x NCr) and X-list rows; the equivalent densities are phi_up_lo / phi_dn_lo
   float *q_f = nullptr, *tmp_f = nullptr, *q_t_f = nullptr, *qx_f = nullptr;
-  void *phi_up_lo = nullptr, *phi_dn_lo = nullptr, *phi_up_bf = nullptr;
+  void *phi_up_lo = nullptr, *phi_dn_lo = nullptr;
   // W pairs (CSR order of the W lists): one output slot of nt(B) x 6 doubles each
   int n_wp = 0;
   int *wp_b = nullptr, *wp_a = nullptr;

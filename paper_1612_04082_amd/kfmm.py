@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkfmm.so")
 
 DISP, STRESS = 0, 1
-FP64, FP32, FP32_M2L_BF16, FP32_M2L_SPLIT16, FP32_TRANS64 = 0, 1, 2, 3, 4
+FP64, FP32, FP32_M2L_BF16, FP32_M2L_SPLIT16, FP32_TRANS64 = 0, 1, 2, 3, 4  # FP32_M2L_BF16: withdrawn (E_ARG)
 PC_NONE, PC_TWO_LEVEL = 0, 1
 PHASES = ("permute", "s2m", "uc2ue", "m2m", "m2l_prep", "m2l", "m2l_red", "s2l", "down", "near", "leaf")
 _STATUS = {0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_HIP", -4: "E_NOCONV", -5: "E_STATE"}

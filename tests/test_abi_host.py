@@ -67,7 +67,8 @@ def test_plan_argument_errors(lib):
     assert call(ctypes.byref(plan), None) == KFMM_E_ARG
     assert last_error(lib) == "opts is NULL"
     for change, msg in ((dict(K=-1.0), "moduli"), (dict(G=float("nan")), "moduli"),
-                        (dict(precision=9), "unknown precision"), (dict(p=2), "p must be in"),
+                        (dict(precision=9), "unknown precision"), (dict(precision=2), "M2L_BF16 is withdrawn"),
+                        (dict(p=2), "p must be in"),
                         (dict(m2l_tol=1.5), "m2l_tol"), (dict(leaf_max=-4), "negative leaf_max")):
         opts = kfmm.FmmOpts(**{**good, **change})
         assert call(ctypes.byref(plan), ctypes.byref(opts)) == KFMM_E_ARG, change
@@ -85,9 +86,10 @@ def test_selftest_gemm_selector_errors(lib):
 
     assert call(7) == KFMM_E_ARG and last_error(lib) == "bad arguments"
     assert call(1, mode=3) == KFMM_E_ARG and last_error(lib) == "bad arguments"
-    # kernel selectors: FP64 / FP32 take 0..4, split FP16 only 0 and 1 (64-column tiles), BF16 only 0
+    # precision 2 (the withdrawn BF16 kernel) is refused
+    assert call(2) == KFMM_E_ARG and last_error(lib) == "bad arguments"
+    # kernel selectors: FP64 / FP32 take 0..4, split FP16 only 0 and 1 (64-column tiles)
     assert call(3 + 16 * 2) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
-    assert call(2 + 16 * 1) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
     assert call(1 + 16 * 5) == KFMM_E_ARG and last_error(lib) == "bad kernel selector"
     assert call(3, NC=100) == KFMM_E_ARG and "multiple of 96 or 128" in last_error(lib)
 

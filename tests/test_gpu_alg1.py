@@ -32,17 +32,22 @@ def test_alg1_small_beam(cuda):
     assert M[0].any() and M[-1].any()
 
 
-def test_warm_start_study_small(cuda):
+@pytest.mark.parametrize("precond", [0, 1])
+def test_warm_start_study_small(cuda, precond):
+    """The study loop (three starts per measured system) runs and every solve converges.  What the warm start
+    guarantees is its guard: the start GMRES uses (the minimal-residual combination of the given starts,
+    else zero) never has a larger residual than the zero start.  It does not guarantee fewer steps: on the
+    cantilever sequences the mapped previous solution and the network start measured no gain (the start
+    residuals are 1.2-5 ||b||, so the guard falls back to the zero start's residual or close to it)."""
     from paper_1612_04082_amd.alg1 import warm_start_study
     M0 = np.ones((16, 4, 4), bool)
     rec = warm_start_study(M0, n_iter=4, train_from=2, measure_from=3, h=0.5, C=0.005, tol_seq=1e-8, tol=1e-6,
-                           epochs=20, restart=100, p=6, precision=0, log=lambda r: None)
+                           epochs=20, restart=100, p=6, precision=0, precond=precond, log=lambda r: None)
     meas = [r for r in rec if "zero" in r]
     assert len(meas) == 2
     for r in meas:
+        print({m: (r[m]["iters"], round(r[m]["rel_res0"], 3), round(r[m]["rel_res_start"], 3)) for m in
+               ("zero", "prev", "net")})
         for mode in ("zero", "prev", "net"):
             assert r[mode]["converged"] == 1
-        # the start is never worse than zero in residual (minimal-residual projection, then the zero guard);
-        # GMRES step counts are not monotone in the starting residual, hence the slack
-        assert r["prev"]["iters"] <= 1.25 * r["zero"]["iters"] + 5
-        assert r["net"]["iters"] <= 1.25 * r["zero"]["iters"] + 5
+            assert r[mode]["rel_res_start"] <= 1.0 + 1e-12

@@ -17,8 +17,12 @@ def cells():
     return geo.cell_batch(6)
 
 
-@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("precision", [1, 3])
 def test_batched_equals_separate(cuda, cells, precision):
+    """Launches of the batched plan are larger, so some translation products run on another kernel (tiled
+    instead of split-K, or the k-split split-FP16 variant): the same sums grouped differently.  Two such
+    evaluations differ by at most the sum of their rounding errors, each about the distance of the separate
+    evaluation from the same plan in FP64, so the bound is 3x that distance (measured per geometry)."""
     src = np.concatenate([c["src"] for c in cells])
     nrm = np.concatenate([c["nrm"] for c in cells])
     w = np.concatenate([c["w"] for c in cells])
@@ -26,13 +30,13 @@ def test_batched_equals_separate(cuda, cells, precision):
     b = np.concatenate([c["b"] for c in cells])
     off = np.concatenate([[0], np.cumsum([c["src"].shape[0] for c in cells])])
     got = run_fmm(src, nrm, w, a, b, od.DISP, precision=precision, p=6, leaf_max=128, batch=list(off))
-    # Launches of the batched plan are larger, so some translation products run on the tiled GEMM instead
-    # of the split-K one: the same sums grouped differently, equal up to FP32 rounding.
     for g, c in enumerate(cells):
         one = run_fmm(c["src"], c["nrm"], c["w"], c["a"], c["b"], od.DISP, precision=precision, p=6, leaf_max=128)
+        one64 = run_fmm(c["src"], c["nrm"], c["w"], c["a"], c["b"], od.DISP, precision=0, p=6, leaf_max=128)
         d = rel_l2(got[off[g]:off[g + 1]], one)
-        print(f"geometry {g}: batched vs separate {d:.2e}")
-        assert d < 1e-4, (g, d)
+        e = rel_l2(one, one64)
+        print(f"geometry {g}: batched vs separate {d:.2e}; separate vs FP64 {e:.2e}")
+        assert d <= 3 * e, (g, d, e)
 
 
 def test_batched_matches_oracle(cuda, cells):

@@ -2,7 +2,7 @@
 
   * one-leaf trees: the method reduces to the direct sum (near field only) -> FP64 rounding level;
   * the unit-sphere cloud of 4096 points (plain KIFMM check): FP64 error small and falling with p;
-  * FP32, BF16-M2L and split-FP16-M2L precisions at their stated tolerances;
+  * FP32 and split-FP16-M2L precisions at their stated tolerances;
   * stress targets distinct from the sources;
   * the double-layer jump identity evaluated through the FMM (int P = -I at interior targets).
 """
@@ -48,7 +48,7 @@ def test_sphere_fp64_p_sweep(cuda):
     assert errs[6] < 1e-5
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 1e-4), (2, 1e-2)])
+@pytest.mark.parametrize("precision,tol", [(1, 1e-4)])
 def test_sphere_low_precision(cuda, precision, tol):
     c = geo.sphere_cloud(4096, seed=1)
     ref = run_oracle(c["src"], c["nrm"], c["w"], c["a"], c["a"][::-1].copy(), od.DISP)
