@@ -51,6 +51,12 @@ struct CompressedM2L {
   float* Gv32 = nullptr;   // U^T vs = G diag(sigma) (split FP16: phi~ = Gv (diag(inv_sig) fu1 qhat))
   uint16_t* Gv_h3 = nullptr;
   float* Gv_h3_scale = nullptr;
+  // U^T UC2UE (NCr x NC): phi~ straight from the upward check potentials in one product (split FP16); the
+  // pseudo-inverse's large entries 1/sigma sit on density modes that the far field barely sees, and
+  // projected onto the M2L basis they stay of the size of the result
+  float* Mu32 = nullptr;
+  uint16_t* Mu_h3 = nullptr;
+  float* Mu_h3_scale = nullptr;
   float* Ut32 = nullptr;   // NCr x NC
   float* C32 = nullptr;    // 316 x NCr x NCr row-major
   uint16_t* Ch3 = nullptr;      // C32 split into FP16 high / low parts (see split_h3), made on first use
@@ -480,6 +486,27 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
     c->Gv32 = d.arena.get<float>(gv32.size());
     KFMM_HIP(hipMemcpy(c->Gv32, gv32.data(), sizeof(float) * gv32.size(), hipMemcpyHostToDevice));
   }
+  {  // Mu = U^T UC2UE (NCr x NC): column c = U^T (UC2UE e_c), from the rows of UC2UE^T
+    std::vector<double> h((size_t)NC * NC), ht((size_t)NC * NC);
+    KFMM_HIP(hipMemcpy(h.data(), d.uc2ue, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < NC; ++i)
+      for (int j = 0; j < NC; ++j) ht[(size_t)j * NC + i] = h[(size_t)i * NC + j];
+    double* uct = tmp.get<double>(ht.size());
+    KFMM_HIP(hipMemcpy(uct, ht.data(), sizeof(double) * ht.size(), hipMemcpyHostToDevice));
+    GemmCols cm;
+    for (int c2 = 0; c2 < NC; ++c2) cm.add(0, c2, c2);
+    GemmJob jm = upload_job(tmp, cm, s, kGemmBN);
+    double* Ym = tmp.get<double>((size_t)NC * NCr);
+    gemm_f64(jm, c->Ut64, GemmDims{NCr, NC, NC, NCr}, uct, Ym, kStore, s);
+    std::vector<double> hm((size_t)NC * NCr);
+    KFMM_HIP(hipMemcpyAsync(hm.data(), Ym, sizeof(double) * hm.size(), hipMemcpyDeviceToHost, s));
+    KFMM_HIP(hipStreamSynchronize(s));
+    std::vector<float> m32((size_t)NCr * NC, 0.0f);
+    for (int c2 = 0; c2 < NC; ++c2)
+      for (int k = 0; k < NCr; ++k) m32[(size_t)k * NC + c2] = (float)hm[(size_t)c2 * NCr + k];
+    c->Mu32 = d.arena.get<float>(m32.size());
+    KFMM_HIP(hipMemcpy(c->Mu32, m32.data(), sizeof(float) * m32.size(), hipMemcpyHostToDevice));
+  }
   {  // U itself (NC x NCr, column k = k-th basis vector) for the FP32 translations
     std::vector<float> u32((size_t)NC * NCr, 0.0f);
     for (int k = 0; k < r; ++k)
@@ -522,6 +549,7 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     }
     split_set(c->U32, 1, (int64_t)d.NC * c->NCr, c->U_h3, c->U_h3_scale);
     split_set(c->Gv32, 1, (int64_t)c->NCr * d.NC, c->Gv_h3, c->Gv_h3_scale);
+    split_set(c->Mu32, 1, (int64_t)c->NCr * d.NC, c->Mu_h3, c->Mu_h3_scale);
     const int64_t len = (int64_t)c->NCr * c->NCr;
     c->Ch3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
     c->Ch3_scale = d.arena.get<float>(nops);
@@ -1265,6 +1293,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   if (P->f32t) {
     P->q_f = (float*)zalloc(nbc * 4);
     P->tmp_f = (float*)zalloc(nbc * 4);
+    if (P->comp && o.precision == KFMM_FP32_M2L_SPLIT16) P->tmp_w = (float*)zalloc(nbc * 4);
     P->qx_f = (float*)zalloc(nxc * 4);  // padding rows stay zero
   } else {
     P->q_up = (double*)zalloc(nbc * 8);
@@ -1278,7 +1307,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->phi_dn_lo = zalloc(nbc * 4);
   }
   KFMM_HIP(hipStreamCreateWithFlags(&P->near_stream, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&P->fork_ev, &P->phi_ev, &P->x_ev, &P->join_ev})
+  for (hipEvent_t* e : {&P->fork_ev, &P->phi_ev, &P->x_ev, &P->join_ev, &P->wq_ev})
     KFMM_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   KFMM_HIP(hipStreamSynchronize(s));
   P->plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -1463,7 +1492,16 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
                            U.n_par, t.child_first, t.child_count, t.src_b, t.src_e, P.tmp, P.phi_up, NC);
     }
   }
-  if (P.f32t) {  // phi_up = UC2UE qhat_up = fu2 (fu1 qhat_up); fu1 is orthogonal (split16 products)
+  // split FP16 with the compressed M2L: the M2L input phi~ = (U^T UC2UE) qhat comes in one product from the
+  // split check-potential rows (M2L prep below), and the full phi_up of the W-list source boxes, which only
+  // the W lists read, is made on the second stream (FP32 fu1 then fu2) ahead of the W evaluation
+  const bool merged = split16 && P.comp && P.tmp_w && sig_split;
+  if (merged) {
+    fork(P.phi_ev);
+    gemm_f32(P.job_up_w, D.fu1, GemmDims::Sq(NC), P.q_f, P.tmp_w, kStore, side);
+    if (overlap) KFMM_HIP(hipEventRecord(P.wq_ev, side));
+    gemm_f32(P.job_up_w, D.fu2, GemmDims::Sq(NC), P.tmp_w, phi_up_f, kStore, side);
+  } else if (P.f32t) {  // phi_up = UC2UE qhat_up = fu2 (fu1 qhat_up); fu1 is orthogonal (split16 products)
     if (split16)
       gemm_h3(P.job_up_all, D.fu1_h3, D.fu1_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, P.tmp_f, kStore,
               s);
@@ -1498,7 +1536,7 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     hipLaunchKernelGGL((k_convert<double, float>), dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s,
                        (int64_t)nbc, P.phi_up, (float*)P.phi_up_lo);
   KFMM_HIP(hipGetLastError());
-  fork(P.phi_ev);  // phi_up ready in the evaluation precision
+  if (!merged) fork(P.phi_ev);  // phi_up ready in the evaluation precision
   if (overlap) {
     w_eval(side);
     KFMM_HIP(hipEventRecord(P.join_ev, side));
@@ -1515,7 +1553,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   } else if (fused_down) {
     const CompressedM2L& C = *P.comp;
     const int NCr = C.NCr;
-    if (sig_split)  // phi~ = Gv (diag(inv_sig) fu1 qhat), the scaled rows split in the UC2UE step above
+    if (merged)  // phi~ = (U^T UC2UE) qhat from the split check-potential rows
+      gemm_h3(P.job_ut, C.Mu_h3, C.Mu_h3_scale, GemmDims{NCr, NC, 2 * NC, NCr}, xq, xq_scale, P.phi_t, kStore, s);
+    else if (sig_split)  // phi~ = Gv (diag(inv_sig) fu1 qhat), the scaled rows split in the UC2UE step above
       gemm_h3(P.job_ut, C.Gv_h3, C.Gv_h3_scale, GemmDims{NCr, NC, 2 * NC, NCr}, xq, xq_scale, P.phi_t, kStore, s);
     else if (P.f32t)  // phi~ = U^T UC2UE qhat = G (fu1 qhat)
       gemm_f32(P.job_ut, C.G32, GemmDims{NCr, NC, NC, NCr}, P.tmp_f, P.phi_t, kStore, s);
@@ -1582,6 +1622,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   }
   KFMM_HIP(hipGetLastError());
   mark(KFMM_PH_DOWN);
+  // the downward pass overwrites the upward check potentials (qhat_f is q_f): wait until the second stream
+  // has read the W-list boxes' rows
+  if (merged && overlap) KFMM_HIP(hipStreamWaitEvent(s, P.wq_ev, 0));
   if (P.f32t) {
     // downward pass in FP32 on check potentials: qhat = U q~ + X rows (compressed), qhat(child) +=
     // L2L_q qhat(parent) level by level, then phi_dn = DC2DE qhat = fd2 (fd1 qhat) at the target leaves
@@ -1656,7 +1699,7 @@ Plan::~Plan() {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : lev)
     if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t e : {fork_ev, phi_ev, x_ev, join_ev})
+  for (hipEvent_t e : {fork_ev, phi_ev, x_ev, join_ev, wq_ev})
     if (e) (void)hipEventDestroy(e);
   if (near_stream) (void)hipStreamDestroy(near_stream);
 }

@@ -72,6 +72,7 @@ struct Plan {
   // FP32 translations: check potentials (upward, then downward qhat), work rows, reduced compressed check
   // potentials (n_box x NCr) and X-list rows; the equivalent densities are phi_up_lo / phi_dn_lo
   float *q_f = nullptr, *tmp_f = nullptr, *q_t_f = nullptr, *qx_f = nullptr;
+  float* tmp_w = nullptr;  // fu1 qhat of the W-list source boxes (merged compressed path, second stream)
   void *phi_up_lo = nullptr, *phi_dn_lo = nullptr;
   // W pairs (CSR order of the W lists): one output slot of nt(B) x 6 doubles each
   int n_wp = 0;
@@ -88,6 +89,7 @@ struct Plan {
   // second stream (near field, X and W lists) and its fork / join events
   hipStream_t near_stream = nullptr;
   hipEvent_t fork_ev = nullptr, phi_ev = nullptr, x_ev = nullptr, join_ev = nullptr;
+  hipEvent_t wq_ev = nullptr;  // second stream done reading the upward check potentials
   // optional phase timing with HIP events (see fmm_profile); light: M2L launch only, events in a ring
   bool prof = false;
   bool light = false;
