@@ -207,3 +207,84 @@ int oracle_pair_kernels(double K, double G, const double* trg, const double* src
   }
   return 0;
 }
+
+/*
+ * Upsampled quadrature of near-singular blocks (Sec. 2.2, "Matrix-vector products": near the collocation
+ * point the element's 16-point rule loses accuracy, and an upsampled quadrature is used on the triangles
+ * close to it).  For each pair (t, e): the triangle e (tri + 9e, vertices v0 v1 v2) is split at its edge
+ * midpoints L + 1 times, each split giving the four children (v0, m01, m20), (m01, v1, m12),
+ * (m20, m12, v2), (m01, m12, m20) in that order; on each of the 4^(L+1) leaves the symmetric degree-3
+ * four-point rule (centroid weight -27/48; barycentric (3/5, 1/5, 1/5) and permutations, 25/48) is
+ * applied with weights (leaf area) x (rule weight).  L = 0 is the element's own 16-point rule.  Leaves
+ * are visited in the order of their base-4 child index (first split most significant).
+ *   U[9p + 3i + j] = sum_q U_ij(x_t, y_q) w_q,  P likewise with P_ij and the normal of e (right-hand rule).
+ * Coincident points are skipped.  Returns 0, or -1 on bad arguments.
+ */
+int oracle_near_blocks(double K, double G, const double* colloc, const double* tri, const int64_t* pairs,
+                       int64_t n, int L, double* U, double* P, int nthreads) {
+  if (!(K > 0.0) || !(G > 0.0) || L < 0 || L > 8) return -1;
+  double nu = poisson_ratio(K, G);
+  static const double bary[4][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {0.6, 0.2, 0.2}, {0.2, 0.6, 0.2}, {0.2, 0.2, 0.6}};
+  static const double rw[4] = {-27.0 / 48, 25.0 / 48, 25.0 / 48, 25.0 / 48};
+  int64_t nleaf = 1;
+  for (int d = 0; d <= L; ++d) nleaf *= 4;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t p = 0; p < n; ++p) {
+    const double* x = colloc + 3 * pairs[2 * p];
+    const double* v = tri + 9 * pairs[2 * p + 1];
+    double e1[3], e2[3], nr[3];
+    for (int d = 0; d < 3; ++d) {
+      e1[d] = v[3 + d] - v[d];
+      e2[d] = v[6 + d] - v[d];
+    }
+    nr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    nr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    nr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    double a2 = sqrt(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+    for (int d = 0; d < 3; ++d) nr[d] /= a2;
+    double leaf_area = 0.5 * a2 / (double)nleaf;
+    double Ua[3][3] = {{0}}, Pa[3][3] = {{0}};
+    for (int64_t k = 0; k < nleaf; ++k) {
+      double c[3][3];
+      memcpy(c, v, sizeof(c));
+      for (int64_t div = nleaf / 4; div >= 1; div /= 4) {
+        int child = (int)((k / div) % 4);
+        double m01[3], m12[3], m20[3];
+        for (int d = 0; d < 3; ++d) {
+          m01[d] = 0.5 * (c[0][d] + c[1][d]);
+          m12[d] = 0.5 * (c[1][d] + c[2][d]);
+          m20[d] = 0.5 * (c[2][d] + c[0][d]);
+        }
+        for (int d = 0; d < 3; ++d) {
+          double a = c[0][d], b = c[1][d], cc = c[2][d];
+          if (child == 0) { c[0][d] = a;       c[1][d] = m01[d]; c[2][d] = m20[d]; }
+          if (child == 1) { c[0][d] = m01[d];  c[1][d] = b;      c[2][d] = m12[d]; }
+          if (child == 2) { c[0][d] = m20[d];  c[1][d] = m12[d]; c[2][d] = cc;     }
+          if (child == 3) { c[0][d] = m01[d];  c[1][d] = m12[d]; c[2][d] = m20[d]; }
+        }
+      }
+      for (int q = 0; q < 4; ++q) {
+        double y[3], rh[3], r;
+        for (int d = 0; d < 3; ++d) y[d] = bary[q][0] * c[0][d] + bary[q][1] * c[1][d] + bary[q][2] * c[2][d];
+        if (!pair_geometry(x, y, rh, &r)) continue;
+        double Uq[3][3], Pq[3][3], w = leaf_area * rw[q];
+        kernel_U(rh, r, nu, G, Uq);
+        kernel_P(rh, r, nr, nu, Pq);
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            Ua[i][j] += Uq[i][j] * w;
+            Pa[i][j] += Pq[i][j] * w;
+          }
+      }
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        U[9 * p + 3 * i + j] = Ua[i][j];
+        P[9 * p + 3 * i + j] = Pa[i][j];
+      }
+  }
+  return 0;
+}

@@ -37,6 +37,9 @@ def lib():
         L.oracle_quad_blocks.restype = ctypes.c_int
         L.oracle_pair_kernels.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp, i64, dp, dp, dp, dp]
         L.oracle_pair_kernels.restype = ctypes.c_int
+        L.oracle_near_blocks.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_int64), i64,
+                                         ctypes.c_int, dp, dp, ctypes.c_int]
+        L.oracle_near_blocks.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -106,3 +109,20 @@ def pair_kernels(trg, src, nrm, K, G):
     if rc != 0:
         raise ValueError("oracle_pair_kernels: coincident pair or bad moduli")
     return U, P, D, S
+
+
+def near_blocks(colloc, tri, pairs, levels, K, G, nthreads=0):
+    """Upsampled quadrature blocks (see oracle_near_blocks in direct.c): for each pair (t, e) the 3x3 blocks
+    U, P of triangle e at collocation point t with the rule of `levels` extra midpoint splits.  Returns
+    U, P of shape (n, 3, 3)."""
+    colloc = _f64(colloc).reshape(-1, 3)
+    tri = _f64(tri).reshape(-1, 3, 3)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int64).reshape(-1, 2)
+    n = pairs.shape[0]
+    U = np.zeros((n, 3, 3))
+    P = np.zeros((n, 3, 3))
+    rc = lib().oracle_near_blocks(K, G, _p(colloc), _p(tri), pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  n, int(levels), _p(U), _p(P), nthreads)
+    if rc != 0:
+        raise ValueError("oracle_near_blocks: bad arguments")
+    return U, P
