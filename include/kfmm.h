@@ -198,6 +198,13 @@ typedef struct {
   const int8_t* bc_type;  /* T x 3 (device): 0 = displacement prescribed, 1 = traction prescribed */
   const double* bc_val;   /* T x 3 (device): prescribed displacement or traction */
   double K, G;            /* moduli */
+  int near_levels;        /* 0: every off-diagonal block by the 16-point rule.  L in 1..5: the blocks of the
+                             near pairs (below) by the upsampled rule of Sec. 2.2 ("Matrix-vector products"):
+                             the triangle split at its edge midpoints L more times, the element rule on each
+                             of the 4^L pieces (16 4^L points), added in the local pass as the difference to
+                             the 16-point blocks the fast summation applies */
+  double near_radius;     /* a pair (t, e), t != e, is near when |c_t - c_e|^2 < near_radius^2 l_e^2 (c:
+                             centroids, l_e: longest edge of e); 0 -> 1.5 */
 } bem_problem;
 
 typedef struct {
@@ -273,6 +280,14 @@ int bem_stress(const bem_problem* prob, const double* u_full, const double* t_fu
  * x, y: T x 3 (device).  Builds a plan internally.  Synchronises the stream.
  */
 int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const double* x, double* y, void* stream);
+
+/*
+ * bem_near_pairs -- the near pairs of prob (near_radius as in bem_problem; near_levels is ignored), sorted by
+ * collocation element t, then by source element e.  *count (host) receives their number; pairs (device,
+ * 2 x count int32 as (t, e) rows) may be NULL to query the count, else it must hold *count_capacity pairs
+ * (KFMM_E_ARG if fewer).  Synchronises the stream.
+ */
+int bem_near_pairs(const bem_problem* prob, int64_t* count, int32_t* pairs, int64_t count_capacity, void* stream);
 
 /* Sizes of a built preconditioner (host). */
 typedef struct {

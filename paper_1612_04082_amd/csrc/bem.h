@@ -11,6 +11,18 @@ namespace kfmm {
 
 struct TwoLevelPC;
 
+// Near pairs (t, e) of the near-singular quadrature (nearfield.hip): CSR by t (off[T + 1], idx sorted by e)
+// and the row of every entry.
+struct NearPairs {
+  int64_t n = 0;
+  int *off = nullptr, *idx = nullptr, *row = nullptr;
+};
+NearPairs find_near_pairs(const double* tri, const double* cen, int64_t T, double radius, Arena& arena,
+                          hipStream_t s);
+// dU, dP (n x 9 each): upsampled blocks (levels extra midpoint splits) minus the element's 16 quadrature points
+void near_blocks(const NearPairs& np, int levels, const double* tri, const double* cen, const double* qp,
+                 const double* qn, const double* qw, const Elastic& el, double* dU, double* dP, hipStream_t s);
+
 struct BemSystem {
   hipStream_t stream;
   int64_t T = 0, n = 0;
@@ -22,6 +34,9 @@ struct BemSystem {
   Arena arena;
   double *qp = nullptr, *qn = nullptr, *qw = nullptr, *cen = nullptr;  // quadrature sources, collocation points
   double *dU = nullptr, *dP = nullptr;                                 // local-pass blocks (T x 3 x 3)
+  int near_levels = 0;                                                 // upsampled near-singular quadrature
+  NearPairs near;
+  double *near_dU = nullptr, *near_dP = nullptr;                       // near.n x 3 x 3
   double *a16 = nullptr, *b16 = nullptr, *ae = nullptr, *be = nullptr, *fmm_out = nullptr;
   double* partial = nullptr;
   std::unique_ptr<Plan> plan;

@@ -215,14 +215,23 @@ __global__ void k_bem_densities(int64_t T, int mode, const double* __restrict__ 
 
 // Local pass and free term:  out_k = fmm_k + dU_k ae_k + dP_k be_k + half * (+-1/2 u)
 //   mode 0: + 1/2 u_unk (= be);  mode 1: - 1/2 u_known (= be, which holds -u_known).
+// With the near-singular quadrature (near_off != NULL) also sum_{e near k} nU_ke ae_e + nP_ke be_e, in the
+// order of e.
 __global__ void k_bem_local(int64_t T, const double* __restrict__ fmm, const double* __restrict__ dU,
                             const double* __restrict__ dP, const double* __restrict__ ae,
-                            const double* __restrict__ be, double* __restrict__ out) {
+                            const double* __restrict__ be, const int* __restrict__ near_off,
+                            const int* __restrict__ near_idx, const double* __restrict__ nU,
+                            const double* __restrict__ nP, double* __restrict__ out) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= T) return;
   for (int i = 0; i < 3; ++i) {
     double v = fmm[3 * k + i];
     for (int j = 0; j < 3; ++j) v += dU[9 * k + 3 * i + j] * ae[3 * k + j] + dP[9 * k + 3 * i + j] * be[3 * k + j];
+    if (near_off)
+      for (int p = near_off[k]; p < near_off[k + 1]; ++p) {
+        const int64_t e = near_idx[p];
+        for (int j = 0; j < 3; ++j) v += nU[9 * p + 3 * i + j] * ae[3 * e + j] + nP[9 * p + 3 * i + j] * be[3 * e + j];
+      }
     v += 0.5 * be[3 * k + i];
     out[3 * k + i] = v;
   }
@@ -347,6 +356,13 @@ BemSystem::BemSystem(const bem_problem& p, const fmm_opts& fo, hipStream_t s) : 
   dP = arena.get<double>(9 * T);
   hipLaunchKernelGGL(k_bem_self, dim3(nblk(T, 128)), dim3(128), 0, s, T, tri, qp, qw, el, dU, dP);
   KFMM_HIP(hipGetLastError());
+  near_levels = p.near_levels;
+  if (near_levels > 0) {
+    near = find_near_pairs(tri, cen, T, p.near_radius > 0 ? p.near_radius : 1.5, arena, s);
+    near_dU = arena.get<double>((size_t)9 * std::max<int64_t>(near.n, 1));
+    near_dP = arena.get<double>((size_t)9 * std::max<int64_t>(near.n, 1));
+    near_blocks(near, near_levels, tri, cen, qp, qn, qw, el, near_dU, near_dP, s);
+  }
   fmm_opts o = fo;
   o.K = p.K;
   o.G = p.G;
@@ -372,7 +388,8 @@ void BemSystem::apply(int mode, const double* xin, double* out) {
                      b16, ae, be);
   KFMM_HIP(hipGetLastError());
   plan_eval(*plan, KFMM_DISP, a16, b16, fmm_out, s);
-  hipLaunchKernelGGL(k_bem_local, dim3(nblk(T)), dim3(256), 0, s, T, fmm_out, dU, dP, ae, be, out);
+  hipLaunchKernelGGL(k_bem_local, dim3(nblk(T)), dim3(256), 0, s, T, fmm_out, dU, dP, ae, be,
+                     near_levels > 0 ? near.off : nullptr, near.idx, near_dU, near_dP, out);
   KFMM_HIP(hipGetLastError());
   ++n_apply;
 }

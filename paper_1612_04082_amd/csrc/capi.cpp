@@ -181,6 +181,46 @@ static void check_problem(const bem_problem* p) {
   KFMM_REQUIRE(p->n_tri > 0 && p->n_tri < ((int64_t)1 << 27), "n_tri must be in [1, 2^27)");
   KFMM_REQUIRE(p->tri_xyz && p->bc_type && p->bc_val, "problem arrays are NULL");
   check_moduli(p->K, p->G);
+  KFMM_REQUIRE(p->near_levels >= 0 && p->near_levels <= 5, "near_levels must be in [0, 5]");
+  KFMM_REQUIRE(std::isfinite(p->near_radius) && p->near_radius >= 0 && p->near_radius < 16,
+               "near_radius must be in [0, 16)");
+}
+
+extern "C" int bem_near_pairs(const bem_problem* prob, int64_t* count, int32_t* pairs, int64_t count_capacity,
+                              void* stream) {
+  return guarded([&] {
+    KFMM_REQUIRE(prob != nullptr && prob->n_tri > 0 && prob->n_tri < ((int64_t)1 << 27) && prob->tri_xyz,
+                 "problem with triangles required");
+    KFMM_REQUIRE(std::isfinite(prob->near_radius) && prob->near_radius >= 0 && prob->near_radius < 16,
+                 "near_radius must be in [0, 16)");
+    KFMM_REQUIRE(count != nullptr, "count is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t T = prob->n_tri, NQ = 16 * T;
+    Arena a;
+    double* qp = a.get<double>(3 * NQ);
+    double* qn = a.get<double>(3 * NQ);
+    double* qw = a.get<double>(NQ);
+    double* cen = a.get<double>(3 * T);
+    bem_expand(T, prob->tri_xyz, qp, qn, qw, cen, s);
+    NearPairs np = find_near_pairs(prob->tri_xyz, cen, T, prob->near_radius > 0 ? prob->near_radius : 1.5, a, s);
+    *count = np.n;
+    if (pairs) {
+      KFMM_REQUIRE(count_capacity >= np.n, "pairs holds fewer than count pairs");
+      std::vector<int32_t> h(2 * std::max<int64_t>(np.n, 1));
+      std::vector<int32_t> r(np.n), c(np.n);
+      if (np.n) {
+        KFMM_HIP(hipMemcpyAsync(r.data(), np.row, sizeof(int32_t) * np.n, hipMemcpyDeviceToHost, s));
+        KFMM_HIP(hipMemcpyAsync(c.data(), np.idx, sizeof(int32_t) * np.n, hipMemcpyDeviceToHost, s));
+        KFMM_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < np.n; ++i) {
+          h[2 * i] = r[i];
+          h[2 * i + 1] = c[i];
+        }
+        KFMM_HIP(hipMemcpyAsync(pairs, h.data(), sizeof(int32_t) * 2 * np.n, hipMemcpyHostToDevice, s));
+      }
+    }
+    KFMM_HIP(hipStreamSynchronize(s));
+  });
 }
 
 extern "C" int bem_solve(const bem_problem* prob, const bem_opts* opts, const double* x0, double* x, double* u_full,

@@ -7,9 +7,9 @@
 //  * Elements are ordered along a Morton curve of their centroids (14 bits per axis over the centroids'
 //    bounding cube, x in the lowest bit of each triple, ties in element order).
 //  * Fine level: runs of `fine` (<= 32) consecutive elements of that order; each block of A (3m x 3m: the
-//    16-point quadrature between the block's elements, closed-form self blocks and the free term on the
-//    diagonal, the traction columns scaled like the system's) is assembled and inverted (Gauss-Jordan,
-//    partial pivoting, FP64) in LDS by one workgroup.
+//    16-point quadrature between the block's elements, the near-singular corrections of its near pairs,
+//    closed-form self blocks and the free term on the diagonal, the traction columns scaled like the
+//    system's) is assembled and inverted (Gauss-Jordan, partial pivoting, FP64) in LDS by one workgroup.
 //  * Coarse level: runs of `coarse` elements ("aggregates"), each with the local rigid motions as columns:
 //    three translations (every unknown of a component) and three rotations about the aggregate's mean
 //    centroid (at the displacement unknowns only), orthonormalised by two passes of modified Gram-Schmidt;
@@ -70,9 +70,22 @@ struct BlockArgs {
   const int8_t* bc_type;
   double scale_t;
   Elastic el;
+  // near-singular quadrature (NULL when off): CSR of near pairs and their corrections
+  const int *near_off, *near_idx;
+  const double *near_dU, *near_dP;
 };
 
-__device__ void system_block(const BlockArgs& a, int64_t i, int64_t j, double M[3][3]) {
+// 3x3 block M[u][v] from the kernel sums KU, KP: traction-unknown columns -scale_t U, others P
+__device__ __forceinline__ void column_map(const BlockArgs& a, int64_t j, const double KU[3][3], const double KP[3][3],
+                                           double M[3][3]) {
+  for (int v = 0; v < 3; ++v) {
+    const bool t_unknown = a.bc_type[3 * j + v] == 0;
+    for (int u = 0; u < 3; ++u) M[u][v] = t_unknown ? -a.scale_t * KU[u][v] : KP[u][v];
+  }
+}
+
+// The block of the pair (i, j) with its near-singular correction when with_near and (i, j) is a near pair.
+__device__ void system_block(const BlockArgs& a, int64_t i, int64_t j, double M[3][3], bool with_near) {
   double KU[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, KP[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   const double c[3] = {a.cen[3 * i], a.cen[3 * i + 1], a.cen[3 * i + 2]};
   const double n[3] = {a.qn[3 * kQ * j], a.qn[3 * kQ * j + 1], a.qn[3 * kQ * j + 2]};
@@ -90,10 +103,17 @@ __device__ void system_block(const BlockArgs& a, int64_t i, int64_t j, double M[
         KP[u][v] += a.dP[9 * i + 3 * u + v] + (u == v ? 0.5 : 0.0);
       }
   }
-  for (int v = 0; v < 3; ++v) {
-    const bool t_unknown = a.bc_type[3 * j + v] == 0;
-    for (int u = 0; u < 3; ++u) M[u][v] = t_unknown ? -a.scale_t * KU[u][v] : KP[u][v];
-  }
+  if (with_near && a.near_off)
+    for (int p = a.near_off[i]; p < a.near_off[i + 1]; ++p)
+      if (a.near_idx[p] == j) {
+        for (int u = 0; u < 3; ++u)
+          for (int v = 0; v < 3; ++v) {
+            KU[u][v] += a.near_dU[9 * p + 3 * u + v];
+            KP[u][v] += a.near_dP[9 * p + 3 * u + v];
+          }
+        break;
+      }
+  column_map(a, j, KU, KP, M);
 }
 
 // ------------------------------------------------------------------------------------------- order
@@ -168,7 +188,7 @@ __global__ __launch_bounds__(256) void k_pc_fine(BlockArgs a, const int* __restr
   for (int pr = tid; pr < m * m; pr += blockDim.x) {
     const int bi = pr / m, bj = pr % m;
     double M[3][3];
-    system_block(a, order[first + bi], order[first + bj], M);
+    system_block(a, order[first + bi], order[first + bj], M, true);
     for (int u = 0; u < 3; ++u)
       for (int v = 0; v < 3; ++v) A[3 * bi + u][3 * bj + v] = M[u][v];
   }
@@ -329,7 +349,7 @@ __global__ __launch_bounds__(64) void k_pc_coarse_E(BlockArgs a, const int* __re
     for (int sj = 0; sj < ms; ++sj) {
       const int64_t j = order[src_first + sj];
       double M[3][3];
-      system_block(a, i, j, M);
+      system_block(a, i, j, M, false);  // near corrections are added by k_pc_coarse_E_near
       for (int cj = 0; cj < 3; ++cj)
         for (int k2 = 0; k2 < kPcCols; ++k2) {
           const double zz = z[(3 * j + cj) * kPcCols + k2];
@@ -347,6 +367,46 @@ __global__ __launch_bounds__(64) void k_pc_coarse_E(BlockArgs a, const int* __re
       const double v = wave_sum(acc[k][k2]);
       if (lane == 0) E[(blockIdx.y * kPcCols + k) * nc + blockIdx.x * kPcCols + k2] = v;
     }
+}
+
+// Near-singular corrections of E: for the elements i of aggregate a (one wave) and their near elements j,
+// E[(a, k), (agg j, k')] += z_i[., k]^T dM_ij z_j[., k'].  Lane k * 6 + k' owns those entries of row block a
+// and applies the pairs in order (i by position, j by index), so the sums are deterministic.
+__global__ __launch_bounds__(64) void k_pc_coarse_E_near(BlockArgs a, const int* __restrict__ order,
+                                                         const int* __restrict__ rank, int64_t T, int coarse,
+                                                         const double* __restrict__ z, int64_t nc,
+                                                         double* __restrict__ E) {
+  const int64_t first = (int64_t)blockIdx.x * coarse;
+  const int m = (int)min((int64_t)coarse, T - first);
+  const int lane = threadIdx.x;
+  if (lane >= kPcCols * kPcCols) return;
+  const int k = lane / kPcCols, k2 = lane % kPcCols;
+  for (int ti = 0; ti < m; ++ti) {
+    const int64_t i = order[first + ti];
+    for (int p = a.near_off[i]; p < a.near_off[i + 1]; ++p) {
+      const int64_t j = a.near_idx[p];
+      double KU[3][3], KP[3][3], M[3][3];
+      for (int u = 0; u < 3; ++u)
+        for (int v = 0; v < 3; ++v) {
+          KU[u][v] = a.near_dU[9 * p + 3 * u + v];
+          KP[u][v] = a.near_dP[9 * p + 3 * u + v];
+        }
+      column_map(a, j, KU, KP, M);
+      double acc = 0.0;
+      for (int u = 0; u < 3; ++u) {
+        double t = 0.0;
+        for (int v = 0; v < 3; ++v) t += M[u][v] * z[(3 * j + v) * kPcCols + k2];
+        acc += z[(3 * i + u) * kPcCols + k] * t;
+      }
+      const int64_t aj = rank[j] / coarse;
+      E[(blockIdx.x * kPcCols + k) * nc + aj * kPcCols + k2] += acc;
+    }
+  }
+}
+
+__global__ void k_pc_rank(const int* __restrict__ order, int64_t T, int* __restrict__ rank) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < T) rank[order[p]] = (int)p;
 }
 
 // Dropped columns: identity on their row and column (both are zero), so E stays invertible and the
@@ -518,7 +578,14 @@ void TwoLevelPC::build(const BemSystem& sys, int fine_, int coarse_) {
   order = arena.get<int>(T);
   KFMM_HIP(hipMemcpyAsync(order, idx, sizeof(int) * T, hipMemcpyDeviceToDevice, st));
 
-  BlockArgs a{sys.qp, sys.qn, sys.qw, sys.cen, sys.dU, sys.dP, sys.bc_type, sys.scale_t, sys.el};
+  const bool with_near = sys.near_levels > 0 && sys.near.n > 0;
+  BlockArgs a{sys.qp,      sys.qn,
+              sys.qw,      sys.cen,
+              sys.dU,      sys.dP,
+              sys.bc_type, sys.scale_t,
+              sys.el,      with_near ? sys.near.off : nullptr,
+              sys.near.idx, sys.near_dU,
+              sys.near_dP};
   int* singular = scratch.get<int>(2);
   KFMM_HIP(hipMemsetAsync(singular, 0, 2 * sizeof(int), st));
   binv_t = arena.get<double>((size_t)nb * kFineN * kFineN);
@@ -534,6 +601,13 @@ void TwoLevelPC::build(const BemSystem& sys, int fine_, int coarse_) {
   hipLaunchKernelGGL(k_pc_coarse_E, dim3((unsigned)na, (unsigned)na), dim3(64), 0, st, a, order, T, coarse, z, nc,
                      einv);
   KFMM_HIP(hipGetLastError());
+  if (with_near) {
+    int* rank = scratch.get<int>(T);
+    hipLaunchKernelGGL(k_pc_rank, dim3(nblocks(T, 256)), dim3(256), 0, st, order, T, rank);
+    hipLaunchKernelGGL(k_pc_coarse_E_near, dim3((unsigned)na), dim3(64), 0, st, a, order, rank, T, coarse, z, nc,
+                       einv);
+    KFMM_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_pc_pad, dim3(nblocks(nc, 256)), dim3(256), 0, st, kept, nc, einv);
   int* piv = scratch.get<int>(nc);
   double* col = scratch.get<double>(nc);

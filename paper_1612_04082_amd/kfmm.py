@@ -42,7 +42,8 @@ class FmmInfo(ctypes.Structure):
 
 class BemProblem(ctypes.Structure):
     _fields_ = [("n_tri", ctypes.c_int64), ("tri_xyz", ctypes.c_void_p), ("bc_type", ctypes.c_void_p),
-                ("bc_val", ctypes.c_void_p), ("K", ctypes.c_double), ("G", ctypes.c_double)]
+                ("bc_val", ctypes.c_void_p), ("K", ctypes.c_double), ("G", ctypes.c_double),
+                ("near_levels", ctypes.c_int), ("near_radius", ctypes.c_double)]
 
 
 class BemOpts(ctypes.Structure):
@@ -104,6 +105,8 @@ def load_library():
                                     ctypes.POINTER(BemPcInfo), vp]
     L.bem_precond_apply.restype = ctypes.c_int
     L.bem_matvec.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(FmmOpts), ctypes.c_int, vp, vp, vp]
+    L.bem_near_pairs.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(i64), vp, i64, vp]
+    L.bem_near_pairs.restype = ctypes.c_int
     L.bem_matvec.restype = ctypes.c_int
     L.bem_quadrature.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     L.bem_quadrature.restype = ctypes.c_int
@@ -269,26 +272,26 @@ def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0,
                                _stream()))
 
 
-def _problem(tri, bc_type, bc_val, K, G):
+def _problem(tri, bc_type, bc_val, K, G, near_levels=0, near_radius=0.0):
     if not (bc_type.is_cuda and bc_type.dtype == torch.int8 and bc_type.is_contiguous()):
         raise TypeError("bc_type must be a contiguous int8 CUDA tensor")
     T = int(tri.shape[0])
     if tuple(tri.shape[1:]) != (3, 3) or tuple(bc_type.shape) != (T, 3):
         raise ValueError("tri must be (T,3,3) and bc_type (T,3)")
     return BemProblem(T, _dptr(tri, "tri").value, ctypes.c_void_p(bc_type.data_ptr()).value,
-                      _dptr(bc_val, "bc_val", 3, T).value, K, G)
+                      _dptr(bc_val, "bc_val", 3, T).value, K, G, near_levels, near_radius)
 
 
 def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_iter=2000, x0=None, p=8,
               leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False, x0_alt=None,
-              precond=PC_NONE, pc_fine=0, pc_coarse=0):
+              precond=PC_NONE, pc_fine=0, pc_coarse=0, near_levels=0, near_radius=0.0):
     """bem_solve on torch tensors: tri (T,3,3) f64, bc_type (T,3) int8, bc_val (T,3) f64, all on the GPU.
 
     Returns (x, u, t, stats) with x the unknowns (physical units) and u, t the full boundary data."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
-    prob = _problem(tri, bc_type, bc_val, K, G)
+    prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius)
     alt = _dptr(x0_alt, "x0_alt", 3, int(tri.shape[0]))
     opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0),
                    alt.value if alt is not None else None, precond, pc_fine, pc_coarse)
@@ -308,13 +311,13 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
 
 
 def bem_precond_apply(tri, bc_type, bc_val, v, K=None, G=1.0, p=8, leaf_max=128, precision=FP32, svd_eps=0.0,
-                      pc_fine=0, pc_coarse=0):
+                      pc_fine=0, pc_coarse=0, near_levels=0, near_radius=0.0):
     """y = M^-1 v for the two-level preconditioner of the system bem_solve builds (v: (T,3) f64 on the GPU,
     solver units).  Returns (y, info dict)."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
-    prob = _problem(tri, bc_type, bc_val, K, G)
+    prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius)
     T = int(tri.shape[0])
     opts = BemOpts(1e-6, 50, 0, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0), None, PC_TWO_LEVEL,
                    pc_fine, pc_coarse)
@@ -355,17 +358,32 @@ def bem_quadrature(tri):
 
 
 def bem_matvec(tri, bc_type, bc_val, x=None, which=0, K=None, G=1.0, p=8, leaf_max=128, precision=FP32,
-               svd_eps=0.0):
+               svd_eps=0.0, near_levels=0, near_radius=0.0):
     """y = A x (which=0, x in solver units) or the right-hand side B y (which=1)."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
-    prob = _problem(tri, bc_type, bc_val, K, G)
+    prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius)
     fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
     y = torch.empty((int(tri.shape[0]), 3), dtype=torch.float64, device=tri.device)
     check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3, int(tri.shape[0])),
                        _dptr(y, "y", 3), _stream()))
     return y
+
+
+def bem_near_pairs(tri, near_radius=0.0):
+    """Near pairs (t, e) of the triangles (int32 (n, 2) on the GPU), sorted by t then e."""
+    L = load_library()
+    T = int(tri.shape[0])
+    bc = torch.zeros((T, 3), dtype=torch.int8, device=tri.device)
+    val = torch.zeros((T, 3), dtype=torch.float64, device=tri.device)
+    prob = _problem(tri, bc, val, 1.0, 1.0, 0, near_radius)
+    n = ctypes.c_int64(0)
+    check(L.bem_near_pairs(ctypes.byref(prob), ctypes.byref(n), None, 0, _stream()))
+    out = torch.empty((max(n.value, 1), 2), dtype=torch.int32, device=tri.device)
+    check(L.bem_near_pairs(ctypes.byref(prob), ctypes.byref(n), ctypes.c_void_p(out.data_ptr()), n.value,
+                           _stream()))
+    return out[:n.value]
 
 
 def _fptr(t, name, last=None):

@@ -147,3 +147,29 @@ def test_other_entry_points_check_arguments_first(lib):
     assert td(None, 0, 1.0, 1.0, None, None) == 0
     assert td(None, 0, -1.0, 1.0, None, None) == KFMM_E_ARG and "moduli" in last_error(lib)
     assert td(None, 5, 1.0, 1.0, None, None) == KFMM_E_ARG and last_error(lib) == "bad arguments"
+
+
+def test_bem_entry_points_check_problem_and_options_first(lib):
+    """BEM calls validate the problem (near-singular quadrature settings included) and their options before
+    any device work: device pointers that are never dereferenced stand in for the arrays."""
+    from paper_1612_04082_amd import kfmm
+    fake = 0x1000  # a non-NULL address that no check dereferences
+    prob = kfmm.BemProblem(10, fake, fake, fake, 2.0, 1.0, 0, 0.0)
+    fo = kfmm.FmmOpts(2.0, 1.0, 6, 64, kfmm.FP64, 0.0, 0, 0, 0.0)
+    for change, msg in ((dict(near_levels=6), "near_levels"), (dict(near_levels=-1), "near_levels"),
+                        (dict(near_radius=-1.0), "near_radius"), (dict(near_radius=float("nan")), "near_radius"),
+                        (dict(n_tri=0), "n_tri"), (dict(K=-1.0), "moduli")):
+        p = kfmm.BemProblem(10, fake, fake, fake, 2.0, 1.0, 0, 0.0)
+        for k, v in change.items():
+            setattr(p, k, v)
+        rc = lib.bem_matvec(ctypes.byref(p), ctypes.byref(fo), 0, ctypes.c_void_p(fake), ctypes.c_void_p(fake), None)
+        assert rc == KFMM_E_ARG and msg in last_error(lib), (change, last_error(lib))
+    assert lib.bem_near_pairs(ctypes.byref(prob), None, None, 0, None) == KFMM_E_ARG
+    assert last_error(lib) == "count is NULL"
+    opts = kfmm.BemOpts(1e-6, 50, 10, fo, None, kfmm.PC_NONE, 0, 0)
+    assert lib.bem_precond_apply(ctypes.byref(prob), ctypes.byref(opts), ctypes.c_void_p(fake),
+                                 ctypes.c_void_p(fake + 64), None, None) == KFMM_E_ARG
+    assert "KFMM_PC_TWO_LEVEL" in last_error(lib)
+    opts.precond = 7
+    assert lib.bem_solve(ctypes.byref(prob), ctypes.byref(opts), None, ctypes.c_void_p(fake), None, None, None,
+                         None) == KFMM_E_ARG and "preconditioner" in last_error(lib)
