@@ -289,6 +289,61 @@ int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const do
  */
 int bem_near_pairs(const bem_problem* prob, int64_t* count, int32_t* pairs, int64_t count_capacity, void* stream);
 
+/* ---------------------------------------------------------------------------------------------------
+ * Algorithm 1 (Sec. 2.3) on the device: the voxel steps of an optimisation iteration and the adaptive
+ * sampling of the interior (Sec. 2.2 end, Sec. 5 "adaptive grid").  A design is a uint8 array (device,
+ * nonzero = material) of nx x ny x nz voxels of edge h in C order (i slowest), origin at 0; voxel (i, j, k)
+ * spans [i h, (i + 1) h] x [j h, (j + 1) h] x [k h, (k + 1) h].  Outputs follow linear voxel order and are
+ * bitwise reproducible.  Calls that return a count take NULL outputs to query it; capacity is the number
+ * of rows the output holds (KFMM_E_ARG if fewer).  All synchronise the stream.
+ */
+typedef struct {
+  int nx, ny, nz; /* voxels per axis, nx * ny * nz < 2^31 */
+  double h;       /* voxel edge */
+} alg1_grid;
+
+/* alg1_surface -- the boundary of the material as triangles with the cantilever's conditions.  Every face of
+ * a filled voxel whose neighbour across it is empty or outside gives four triangles (q_e, q_{e+1}, centre),
+ * e = 0..3, counter-clockwise seen from outside; faces in six classes (axis 0, +), (axis 0, -), (axis 1, +),
+ * ..., each in linear voxel order; corners h p for the grid points p of the face from (0,0), (1,0), (1,1),
+ * (0,1) along the axes a + 1, a + 2 (reversed on - faces), centre (((q0 + q1) + q2) + q3) / 4.  The x = 0
+ * faces of the voxels with i = 0 are clamped (bc_type 0, value 0), the +x faces of the voxels with
+ * i = nx - 1 carry the traction load (host, 3; NULL -> (0, 0, -1)), all other faces are traction-free.
+ * tri: T x 3 x 3, bc_type T x 3, bc_val T x 3, owner T x 3 (int32 voxel index, may be NULL). */
+int alg1_surface(const alg1_grid* grid, const uint8_t* vox, const double* load, int64_t* n_tri, double* tri,
+                 int8_t* bc_type, double* bc_val, int32_t* owner, int64_t capacity, void* stream);
+
+/* alg1_centres -- centres (idx + 1/2) h of the filled voxels (n x 3), the interior points of eq. stress_1. */
+int alg1_centres(const alg1_grid* grid, const uint8_t* vox, int64_t* n, double* pts, int64_t capacity, void* stream);
+
+/* alg1_update -- the removal rule of Algorithm 1 with post-processing: td holds one topological derivative
+ * per filled voxel (linear order; n_td must equal their number, else KFMM_E_ARG); a filled voxel becomes empty when td < D_min + C (D_max - D_min) (strict),
+ * except in the layers i = 0 and i = nx - 1 (the supports); then only the material face-connected to both
+ * of those layers is kept.  out (device, nx ny nz, must not alias vox) receives the new design, *n_filled
+ * (host, may be NULL) its number of filled voxels. */
+int alg1_update(const alg1_grid* grid, const uint8_t* vox, const double* td, int64_t n_td, double C, uint8_t* out,
+                int64_t* n_filled, void* stream);
+
+/* Adaptive sampling with blocks of b^3 voxels (block grid ceil(n / b) per axis, linear order):
+ * alg1_coarse_blocks -- centres ((I + 1/2) b h, ...) of the blocks all of whose voxels are filled.
+ * alg1_refine -- with td_coarse (one value per full block, in that order): a block is refined unless it is
+ *   full and its six face neighbours are full blocks with the same decision td < lo + C (hi - lo) (lo, hi
+ *   over td_coarse; n_coarse must equal the number of full blocks); returns the centres of the filled voxels of refined blocks (linear order) and, when
+ *   refined (device, one byte per block) is not NULL, the mask.
+ * alg1_expand -- one value per filled voxel (linear order): its own value from td_fine (in alg1_refine's
+ *   order; n_fine must equal their number) in a refined block, else its block's coarse value; alg1_update applies the rule to this field. */
+int alg1_coarse_blocks(const alg1_grid* grid, const uint8_t* vox, int block, int64_t* n, double* pts,
+                       int64_t capacity, void* stream);
+int alg1_refine(const alg1_grid* grid, const uint8_t* vox, int block, const double* td_coarse, int64_t n_coarse,
+                double C, int64_t* n, double* pts, int64_t capacity, uint8_t* refined, void* stream);
+int alg1_expand(const alg1_grid* grid, const uint8_t* vox, int block, const double* td_coarse, int64_t n_coarse,
+                double C, const double* td_fine, int64_t n_fine, double* td_out, void* stream);
+
+/* alg1_energy -- compliance integrand: *psi (host) = sum over the n stresses (n x 6, device) of
+ * (1 / 2E) [(1 + nu) sigma:sigma - nu (tr sigma)^2] (fixed summation order); times h^3 it is the compliance
+ * of a voxel design evaluated at the voxel centres. */
+int alg1_energy(const double* sig6, int64_t n, double K, double G, double* psi, void* stream);
+
 /* Sizes of a built preconditioner (host). */
 typedef struct {
   int64_t n_fine_blocks, n_aggregates, n_coarse; /* n_coarse = 6 n_aggregates (dropped columns included) */

@@ -9,6 +9,9 @@ Readings where the paper is silent: the first and last voxel layers along the be
 ends) are protected from removal; post-processing keeps the voxels face-connected to both protected
 layers (a floating piece would make the elastic problem singular).
 
+DeviceOptimiser runs the same iteration with every step in the library (boundary extraction, targets, the
+adaptive two-scale sampling of Sec. 5, removal and post-processing), the design kept on the device.
+
 The warm-start study (`warm_start_study`) re-solves the systems of a fixed sequence with three starting
 points -- zero, the previous solution mapped onto the new surface, and the learned network (with the
 residual guard) -- and reports GMRES iterations and times.
@@ -113,6 +116,61 @@ class Optimiser:
                 break
             M = M_next
         return M, hist
+
+
+class DeviceOptimiser(Optimiser):
+    """Algorithm 1 with every step in the library: boundary extraction (alg1_surface), the solve, stress at
+    the voxel centres (alg1_centres, or the adaptive two-round sampling with blocks of `block` voxels:
+    alg1_coarse_blocks, alg1_refine, alg1_expand), the topological derivative and the removal rule with
+    post-processing (alg1_update).  The design stays on the device; the host only sequences the calls."""
+
+    def __init__(self, M0, block=0, **kw):
+        super().__init__(M0, **kw)
+        self.block = int(block)
+
+    def step_fields(self, vox, prob, u, t):
+        """TD per filled voxel (linear order), the number of stress points evaluated, and the compliance
+        (uniform sampling only; None with the adaptive sampling)."""
+        k = self.kfmm
+        args = (prob["tri"], prob["bc_type"], prob["bc_val"])
+        if self.block <= 1:
+            trg = k.alg1_centres(vox, self.h)
+            sig = k.bem_stress(*args, u, t, trg, **self.fmm_kw)
+            td = k.topological_derivative(sig, K=self.K, G=self.G)
+            return td, int(trg.shape[0]), k.alg1_energy(sig, self.K, self.G) * self.h ** 3
+        b = self.block
+        tc = k.alg1_coarse_blocks(vox, self.h, b)
+        td_c = (k.topological_derivative(k.bem_stress(*args, u, t, tc, **self.fmm_kw), K=self.K, G=self.G)
+                if tc.shape[0] else torch.empty(0, dtype=torch.float64, device=vox.device))
+        tf, _ = k.alg1_refine(vox, self.h, b, td_c, self.C)
+        td_f = (k.topological_derivative(k.bem_stress(*args, u, t, tf, **self.fmm_kw), K=self.K, G=self.G)
+                if tf.shape[0] else torch.empty(0, dtype=torch.float64, device=vox.device))
+        td = k.alg1_expand(vox, self.h, b, td_c, self.C, td_f)
+        return td, int(tc.shape[0] + tf.shape[0]), None
+
+    def run(self, n_iter, alpha_c=0.0, callback=None):
+        k = self.kfmm
+        vox = torch.tensor(np.ascontiguousarray(self.M0), dtype=torch.uint8, device="cuda")
+        n0 = int(self.M0.sum())
+        hist = []
+        for it in range(n_iter):
+            prob = k.alg1_surface(vox, self.h, self.load)
+            x, u, t, st = k.bem_solve(prob["tri"], prob["bc_type"], prob["bc_val"], x0=None, allow_noconv=True,
+                                      **self.solve_kw)
+            td, n_eval, psi = self.step_fields(vox, prob, u, t)
+            n_filled = int(td.shape[0])
+            alpha = n_filled / n0
+            hist.append(dict(iter=it + 1, alpha=float(alpha), psi=psi, T=int(prob["tri"].shape[0]), gmres=st["iters"],
+                             rel_res=st["rel_res"], stress_points=n_eval))
+            if callback:
+                callback(it, vox, prob, x, u, t, st)
+            if alpha < alpha_c:
+                break
+            nxt, kept = k.alg1_update(vox, self.h, td, self.C)
+            if kept == 0:  # the rule would disconnect the supports: stop with the last design
+                break
+            vox = nxt
+        return vox.cpu().numpy().astype(bool), hist
 
 
 def warm_start_study(M0, n_iter=20, train_from=2, measure_from=11, h=1.0, C=0.02, tol_seq=1e-8, tol=1e-6,

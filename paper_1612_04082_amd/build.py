@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libkfmm.so")
 ARCH = os.environ.get("KFMM_ARCH", "gfx950")
 
 SOURCES = ["tree.hip", "gemm.hip", "gemm_f32.hip", "gemm_h3.hip", "split_h3.hip", "fmm.hip", "bem.hip", "precond.hip",
-           "nearfield.hip", "learn.hip", "operators.cpp", "capi.cpp"]
+           "nearfield.hip", "alg1.hip", "learn.hip", "operators.cpp", "capi.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
 

@@ -269,6 +269,66 @@ extern "C" int bem_stress(const bem_problem* prob, const double* u_full, const d
   });
 }
 
+namespace kfmm {
+void alg1_surface_impl(const alg1_grid*, const uint8_t*, const double*, int64_t*, double*, int8_t*, double*,
+                       int32_t*, int64_t, hipStream_t);
+void alg1_centres_impl(const alg1_grid*, const uint8_t*, int64_t*, double*, int64_t, hipStream_t);
+void alg1_update_impl(const alg1_grid*, const uint8_t*, const double*, int64_t, double, uint8_t*, int64_t*,
+                      hipStream_t);
+void alg1_coarse_impl(const alg1_grid*, const uint8_t*, int, int64_t*, double*, int64_t, hipStream_t);
+void alg1_refine_impl(const alg1_grid*, const uint8_t*, int, const double*, int64_t, double, int64_t*, double*,
+                      int64_t, uint8_t*, hipStream_t);
+void alg1_expand_impl(const alg1_grid*, const uint8_t*, int, const double*, int64_t, double, const double*, int64_t,
+                      double*, hipStream_t);
+void alg1_energy_impl(const double*, int64_t, double, double, double*, hipStream_t);
+}  // namespace kfmm
+
+extern "C" int alg1_surface(const alg1_grid* grid, const uint8_t* vox, const double* load, int64_t* n_tri, double* tri,
+                            int8_t* bc_type, double* bc_val, int32_t* owner, int64_t capacity, void* stream) {
+  return guarded([&] {
+    alg1_surface_impl(grid, vox, load, n_tri, tri, bc_type, bc_val, owner, capacity, (hipStream_t)stream);
+  });
+}
+
+extern "C" int alg1_centres(const alg1_grid* grid, const uint8_t* vox, int64_t* n, double* pts, int64_t capacity,
+                            void* stream) {
+  return guarded([&] { alg1_centres_impl(grid, vox, n, pts, capacity, (hipStream_t)stream); });
+}
+
+extern "C" int alg1_update(const alg1_grid* grid, const uint8_t* vox, const double* td, int64_t n_td, double C,
+                           uint8_t* out, int64_t* n_filled, void* stream) {
+  return guarded([&] { alg1_update_impl(grid, vox, td, n_td, C, out, n_filled, (hipStream_t)stream); });
+}
+
+extern "C" int alg1_coarse_blocks(const alg1_grid* grid, const uint8_t* vox, int block, int64_t* n, double* pts,
+                                  int64_t capacity, void* stream) {
+  return guarded([&] { alg1_coarse_impl(grid, vox, block, n, pts, capacity, (hipStream_t)stream); });
+}
+
+extern "C" int alg1_refine(const alg1_grid* grid, const uint8_t* vox, int block, const double* td_coarse,
+                           int64_t n_coarse, double C, int64_t* n, double* pts, int64_t capacity, uint8_t* refined,
+                           void* stream) {
+  return guarded([&] {
+    alg1_refine_impl(grid, vox, block, td_coarse, n_coarse, C, n, pts, capacity, refined, (hipStream_t)stream);
+  });
+}
+
+extern "C" int alg1_expand(const alg1_grid* grid, const uint8_t* vox, int block, const double* td_coarse,
+                           int64_t n_coarse, double C, const double* td_fine, int64_t n_fine, double* td_out,
+                           void* stream) {
+  return guarded([&] {
+    alg1_expand_impl(grid, vox, block, td_coarse, n_coarse, C, td_fine, n_fine, td_out, (hipStream_t)stream);
+  });
+}
+
+extern "C" int alg1_energy(const double* sig6, int64_t n, double K, double G, double* psi, void* stream) {
+  return guarded([&] {
+    check_moduli(K, G);
+    KFMM_REQUIRE(n >= 0, "negative size");
+    alg1_energy_impl(sig6, n, K, G, psi, (hipStream_t)stream);
+  });
+}
+
 extern "C" int bem_precond_apply(const bem_problem* prob, const bem_opts* opts, const double* v, double* y,
                                  bem_pc_info* info, void* stream) {
   return guarded([&] {

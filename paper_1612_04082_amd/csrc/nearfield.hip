@@ -25,9 +25,11 @@ namespace {
 
 unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// squared length without contraction: ((x*x) + (y*y)) + (z*z)
+// squared length ((x*x) + (y*y)) + (z*z), each operation rounded on its own (no fused multiply-add: the
+// device compiler contracts by default, and these sums decide which pairs are near)
 __device__ __forceinline__ double sq3(double x, double y, double z) {
-  return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+#pragma clang fp contract(off)
+  return x * x + y * y + z * z;
 }
 
 __global__ void k_near_l2(const double* __restrict__ tri, int64_t T, double* __restrict__ l2) {

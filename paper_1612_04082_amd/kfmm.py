@@ -107,6 +107,17 @@ def load_library():
     L.bem_matvec.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(FmmOpts), ctypes.c_int, vp, vp, vp]
     L.bem_near_pairs.argtypes = [ctypes.POINTER(BemProblem), ctypes.POINTER(i64), vp, i64, vp]
     L.bem_near_pairs.restype = ctypes.c_int
+    gp = ctypes.POINTER(Alg1Grid)
+    L.alg1_surface.argtypes = [gp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp, vp, vp, vp, i64, vp]
+    L.alg1_centres.argtypes = [gp, vp, ctypes.POINTER(i64), vp, i64, vp]
+    L.alg1_update.argtypes = [gp, vp, vp, i64, ctypes.c_double, vp, ctypes.POINTER(i64), vp]
+    L.alg1_coarse_blocks.argtypes = [gp, vp, ctypes.c_int, ctypes.POINTER(i64), vp, i64, vp]
+    L.alg1_refine.argtypes = [gp, vp, ctypes.c_int, vp, i64, ctypes.c_double, ctypes.POINTER(i64), vp, i64, vp, vp]
+    L.alg1_expand.argtypes = [gp, vp, ctypes.c_int, vp, i64, ctypes.c_double, vp, i64, vp, vp]
+    L.alg1_energy.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+    for f in ("alg1_surface", "alg1_centres", "alg1_update", "alg1_coarse_blocks", "alg1_refine", "alg1_expand",
+              "alg1_energy"):
+        getattr(L, f).restype = ctypes.c_int
     L.bem_matvec.restype = ctypes.c_int
     L.bem_quadrature.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     L.bem_quadrature.restype = ctypes.c_int
@@ -384,6 +395,119 @@ def bem_near_pairs(tri, near_radius=0.0):
     check(L.bem_near_pairs(ctypes.byref(prob), ctypes.byref(n), ctypes.c_void_p(out.data_ptr()), n.value,
                            _stream()))
     return out[:n.value]
+
+
+class Alg1Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("h", ctypes.c_double)]
+
+
+def _vox(vox):
+    if not (isinstance(vox, torch.Tensor) and vox.is_cuda and vox.dtype == torch.uint8 and vox.is_contiguous()
+            and vox.dim() == 3):
+        raise TypeError("vox must be a contiguous 3-D uint8 CUDA tensor")
+    return ctypes.c_void_p(vox.data_ptr())
+
+
+def _grid(vox, h):
+    return Alg1Grid(int(vox.shape[0]), int(vox.shape[1]), int(vox.shape[2]), float(h))
+
+
+def _count_then_fill(fn, rows, alloc):
+    """Two-call pattern of the alg1_* entry points: query the count, allocate, fill."""
+    n = ctypes.c_int64(0)
+    check(fn(ctypes.byref(n), None, 0))
+    out = alloc(max(n.value, 1))
+    check(fn(ctypes.byref(n), out, n.value))
+    return n.value, out
+
+
+def alg1_surface(vox, h, load=(0.0, 0.0, -1.0)):
+    """Boundary triangles of a voxel design with the cantilever's conditions (dict of device tensors)."""
+    L = load_library()
+    g = _grid(vox, h)
+    ld = (ctypes.c_double * 3)(*load)
+    n = ctypes.c_int64(0)
+    check(L.alg1_surface(ctypes.byref(g), _vox(vox), ld, ctypes.byref(n), None, None, None, None, 0, _stream()))
+    T = n.value
+    dev = vox.device
+    tri = torch.empty((max(T, 1), 3, 3), dtype=torch.float64, device=dev)
+    bct = torch.empty((max(T, 1), 3), dtype=torch.int8, device=dev)
+    bcv = torch.empty((max(T, 1), 3), dtype=torch.float64, device=dev)
+    own = torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
+    check(L.alg1_surface(ctypes.byref(g), _vox(vox), ld, ctypes.byref(n), ctypes.c_void_p(tri.data_ptr()),
+                         ctypes.c_void_p(bct.data_ptr()), ctypes.c_void_p(bcv.data_ptr()),
+                         ctypes.c_void_p(own.data_ptr()), T, _stream()))
+    return dict(tri=tri[:T], bc_type=bct[:T], bc_val=bcv[:T], owner=own[:T])
+
+
+def _points(vox):
+    return lambda m: torch.empty((m, 3), dtype=torch.float64, device=vox.device)
+
+
+def alg1_centres(vox, h):
+    L = load_library()
+    g = _grid(vox, h)
+    n, pts = _count_then_fill(lambda cnt, out, cap: L.alg1_centres(
+        ctypes.byref(g), _vox(vox), cnt, None if out is None else ctypes.c_void_p(out.data_ptr()), cap, _stream()),
+        3, _points(vox))
+    return pts[:n]
+
+
+def alg1_update(vox, h, td, C):
+    """New design after the removal rule and post-processing; returns (vox_new, n_filled)."""
+    L = load_library()
+    g = _grid(vox, h)
+    out = torch.empty_like(vox)
+    n = ctypes.c_int64(0)
+    check(L.alg1_update(ctypes.byref(g), _vox(vox), _dptr(td, "td"), int(td.numel()), float(C),
+                        ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), _stream()))
+    return out, n.value
+
+
+def alg1_coarse_blocks(vox, h, block):
+    L = load_library()
+    g = _grid(vox, h)
+    n, pts = _count_then_fill(lambda cnt, out, cap: L.alg1_coarse_blocks(
+        ctypes.byref(g), _vox(vox), int(block), cnt, None if out is None else ctypes.c_void_p(out.data_ptr()), cap,
+        _stream()), 3, _points(vox))
+    return pts[:n]
+
+
+def alg1_refine(vox, h, block, td_coarse, C):
+    """Centres of the voxels to evaluate in the second round and the refined-block mask (device tensors)."""
+    L = load_library()
+    g = _grid(vox, h)
+    nb = [-(-int(d) // int(block)) for d in vox.shape]
+    mask = torch.empty(nb, dtype=torch.uint8, device=vox.device)
+    tc = _dptr(td_coarse, "td_coarse") if td_coarse is not None and td_coarse.numel() else None
+    nc = 0 if td_coarse is None else int(td_coarse.numel())
+    n, pts = _count_then_fill(lambda cnt, out, cap: L.alg1_refine(
+        ctypes.byref(g), _vox(vox), int(block), tc, nc, float(C), cnt,
+        None if out is None else ctypes.c_void_p(out.data_ptr()), cap, ctypes.c_void_p(mask.data_ptr()), _stream()),
+        3, _points(vox))
+    return pts[:n], mask
+
+
+def alg1_expand(vox, h, block, td_coarse, C, td_fine):
+    L = load_library()
+    g = _grid(vox, h)
+    nf = int((vox != 0).sum().item())
+    out = torch.empty(max(nf, 1), dtype=torch.float64, device=vox.device)
+    tc = _dptr(td_coarse, "td_coarse") if td_coarse is not None and td_coarse.numel() else None
+    tf = _dptr(td_fine, "td_fine") if td_fine is not None and td_fine.numel() else None
+    nc = 0 if td_coarse is None else int(td_coarse.numel())
+    nfine = 0 if td_fine is None else int(td_fine.numel())
+    check(L.alg1_expand(ctypes.byref(g), _vox(vox), int(block), tc, nc, float(C), tf, nfine,
+                        ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out[:nf]
+
+
+def alg1_energy(sig, K, G):
+    L = load_library()
+    psi = ctypes.c_double(0.0)
+    n = int(sig.shape[0])
+    check(L.alg1_energy(_dptr(sig, "sig", 6) if n else None, n, float(K), float(G), ctypes.byref(psi), _stream()))
+    return psi.value
 
 
 def _fptr(t, name, last=None):
