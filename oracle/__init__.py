@@ -7,6 +7,7 @@ This package is TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()
 Modules
 -------
 direct   FP64 direct sums of the Kelvin kernels U, P, D, S (C, OpenMP) -- eq. fmm_summation.
+periodic FP64 periodic (Ewald) sums of the same kernels over a cubic lattice of cells (C) -- Sec. 4.3.
 bem      dense collocation BEM: quadrature, closed-form self integrals, LU and plain GMRES.
 mlp      FP64 point-MLP forward / backward / Adam for the warm-start network.
 td       topological derivative (eq. deriv) and the threshold rule of Algorithm 1.

@@ -1,4 +1,4 @@
-"""Compile the oracle's C code (oracle/direct.c) into oracle/_build/liboracle.so with gcc.
+"""Compile the oracle's C code (oracle/direct.c, oracle/ewald.c) into oracle/_build/liboracle.so with gcc.
 
 Plain -O2 with OpenMP; no fast-math, so the sums follow IEEE FP64 semantics.
 """
@@ -8,15 +8,16 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "liboracle.so")
+SOURCES = ("direct.c", "ewald.c")
 
 
 def build(force: bool = True) -> str:
-    src = os.path.join(HERE, "direct.c")
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(src):
+    srcs = [os.path.join(HERE, f) for f in SOURCES]
+    if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(f) for f in srcs):
         return LIB
     os.makedirs(BUILD, exist_ok=True)
     tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", src, "-o", tmp, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", *srcs, "-o", tmp, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -24,8 +24,9 @@ def lib():
         path = _build.LIB
         if not os.path.exists(path):
             raise ImportError(f"{path} not built: run __graft_entry__.build() or python -m oracle.build")
-        if os.path.getmtime(path) < os.path.getmtime(os.path.join(_build.HERE, "direct.c")):
-            raise ImportError(f"{path} is older than oracle/direct.c: rebuild it (python -m oracle.build)")
+        for f in _build.SOURCES:
+            if os.path.getmtime(path) < os.path.getmtime(os.path.join(_build.HERE, f)):
+                raise ImportError(f"{path} is older than oracle/{f}: rebuild it (python -m oracle.build)")
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         i64 = ctypes.c_int64
@@ -40,6 +41,10 @@ def lib():
         L.oracle_near_blocks.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, ctypes.POINTER(ctypes.c_int64), i64,
                                          ctypes.c_int, dp, dp, ctypes.c_int]
         L.oracle_near_blocks.restype = ctypes.c_int
+        L.oracle_periodic.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, i64, dp, dp,
+                                      dp, dp, dp, i64, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, dp, ctypes.c_int]
+        L.oracle_periodic.restype = ctypes.c_int
         _lib = L
     return _lib
 
