@@ -106,6 +106,28 @@ int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, con
              int32_t n_batch, const fmm_opts* opts, void* stream);
 
 /*
+ * fmm_plan_periodic -- as fmm_plan, for periodic cubic cells (Sec. 4.3, periodic cell of a metamaterial:
+ * the integrals run over the infinite periodic surface, and the FMM tree is periodic at every level).
+ * Each geometry g is the cell [c_g, c_g + L_g)^3 repeated over the lattice L_g Z^3; fmm_eval then returns
+ * the sums of eq. fmm_summation over every lattice image of every source.
+ *   cells  (host) n_batch x 4 doubles (n_batch <= 1: one row): lower corner c_g (x, y, z) and side L_g > 0.
+ *          Every source and target of geometry g must lie in its cell (KFMM_E_ARG otherwise).
+ * The lattice sum of a point force converges only conditionally; it is defined as its Fourier series
+ * without the k = 0 term: the periodic field of zero cell mean (a net force per cell is balanced by a
+ * uniform body force; the fast evaluation represents that balance only approximately, so single-layer
+ * densities should carry no net force per cell).  With the root taken through its equivalent density, the
+ * displacement of fmm_eval may differ from that definition by one constant vector per geometry and
+ * evaluation (a rigid translation, the cell mean of the difference between the sources' field and their
+ * equivalent density's); stresses carry no such constant.  The image n = 0 of a source that coincides with
+ * a target is left out, all other images are kept.
+ * Requires opts->precision == KFMM_FP64 (KFMM_E_ARG otherwise).
+ */
+int fmm_plan_periodic(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w,
+                      int64_t n_src, const double* trg_xyz, int64_t n_trg, const int64_t* batch_src,
+                      const int64_t* batch_trg, int32_t n_batch, const double* cells, const fmm_opts* opts,
+                      void* stream);
+
+/*
  * fmm_eval -- fast evaluation of the boundary integrals at the plan's targets (eq. fmm_summation):
  *   KFMM_DISP  : out_i   = sum_j U(x_i, y_j) w_j a_j + P(x_i, y_j, n_j) w_j b_j        (eqs. disp_1, disp_2)
  *   KFMM_STRESS: out_i,kl = sum_j D_mkl(x_i, y_j) w_j a_j,m + S_mkl(x_i, y_j, n_j) w_j b_j,m  (eqs. stress_2, stress_3)

@@ -246,12 +246,13 @@ int oracle_periodic(int kind, double K, double G, double L, const double* trg, i
         for (int ny = -nr; ny <= nr; ++ny)
           for (int nz = -nr; nz <= nr; ++nz) {
             double d[3] = {src[3 * s] + nx * L - xi[0], src[3 * s + 1] + ny * L - xi[1], src[3 * s + 2] + nz * L - xi[2]};
-            const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (r == 0.0) {
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 == 0.0) {
               if (!free_space) accumulate(kind, &Kreg, wa, b ? (const double(*)[3])Q : NULL, v, g);
               continue;
             }
-            if (!free_space && r > rcut) continue;
+            if (!free_space && r2 > rcut * rcut) continue;
+            const double r = sqrt(r2);
             double fp[5] = {0, 0, 0, 0, 0}, fb[5] = {0, 0, 0, 0, 0};
             for (int m = 0; m < 3; ++m) fp[m] = rad_eval(&phi[m], r, ae);
             for (int m = 1; m < 5; ++m)

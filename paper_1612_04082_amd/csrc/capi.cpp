@@ -46,13 +46,15 @@ static void check_moduli(double K, double G) {
   KFMM_REQUIRE(std::isfinite(K) && std::isfinite(G) && K > 0 && G > 0, "moduli K and G must be finite and positive");
 }
 
-extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w,
-                        int64_t n_src, const double* trg_xyz, int64_t n_trg, const int64_t* batch_src,
-                        const int64_t* batch_trg, int32_t n_batch, const fmm_opts* opts, void* stream) {
+static int make_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w,
+                     int64_t n_src, const double* trg_xyz, int64_t n_trg, const int64_t* batch_src,
+                     const int64_t* batch_trg, int32_t n_batch, bool periodic, const double* cells,
+                     const fmm_opts* opts, void* stream) {
   return guarded([&] {
     KFMM_REQUIRE(out != nullptr, "out is NULL");
     *out = nullptr;
     KFMM_REQUIRE(opts != nullptr, "opts is NULL");
+    KFMM_REQUIRE(!periodic || cells != nullptr, "cells is NULL");
     check_moduli(opts->K, opts->G);
     KFMM_REQUIRE(n_src >= 0 && n_trg >= 0, "negative size");
     KFMM_REQUIRE(n_src < (int64_t)1 << 31 && n_trg < (int64_t)1 << 31, "too many points (max 2^31 - 1)");
@@ -81,9 +83,26 @@ extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* s
         KFMM_REQUIRE(bs[g + 1] >= bs[g] && bt[g + 1] >= bt[g], "batch offsets must be non-decreasing");
     }
     hipStream_t s = (hipStream_t)stream;
-    Plan* p = plan_create(src_xyz, src_nrm, src_w, n_src, trg_xyz, n_trg, bs, bt, *opts, s);
+    std::vector<double> cv;
+    if (cells) cv.assign(cells, cells + 4 * (size_t)(bs.size() - 1));
+    Plan* p = plan_create(src_xyz, src_nrm, src_w, n_src, trg_xyz, n_trg, bs, bt, *opts, s, cv);
     *out = new kfmm_plan{p};
   });
+}
+
+extern "C" int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w,
+                        int64_t n_src, const double* trg_xyz, int64_t n_trg, const int64_t* batch_src,
+                        const int64_t* batch_trg, int32_t n_batch, const fmm_opts* opts, void* stream) {
+  return make_plan(out, src_xyz, src_nrm, src_w, n_src, trg_xyz, n_trg, batch_src, batch_trg, n_batch, false,
+                   nullptr, opts, stream);
+}
+
+extern "C" int fmm_plan_periodic(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm,
+                                 const double* src_w, int64_t n_src, const double* trg_xyz, int64_t n_trg,
+                                 const int64_t* batch_src, const int64_t* batch_trg, int32_t n_batch,
+                                 const double* cells, const fmm_opts* opts, void* stream) {
+  return make_plan(out, src_xyz, src_nrm, src_w, n_src, trg_xyz, n_trg, batch_src, batch_trg, n_batch, true, cells,
+                   opts, stream);
 }
 
 extern "C" int fmm_eval(kfmm_plan_t plan, int kind, const double* a_sl, const double* b_dl, double* out,

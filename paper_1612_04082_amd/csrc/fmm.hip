@@ -89,6 +89,9 @@ struct DeviceOps {
   double* surf = nullptr;  // n_eq x 3
   std::vector<int> m2l_index;
   std::map<double, std::shared_ptr<CompressedM2L>> comp;  // by relative cutoff
+  // periodic cells: the far-image operator of the root (NC x NC, FP64), made on first use
+  double* per_far64 = nullptr;
+  std::mutex per_mutex;
   Arena arena;
 };
 
@@ -212,6 +215,15 @@ __device__ __forceinline__ double box_half(const int* level, const int* geom, co
   return ldexp(root_R[geom[B]], -level[B]);
 }
 
+// Adds the lattice shift of a list entry (code (sx+1)+3(sy+1)+9(sz+1), periodic cells) in cell sides.
+__device__ __forceinline__ void add_lattice_shift(double* o, int code, const int* geom, const double* root_R, int B) {
+  if (code == kNoShift) return;
+  const double side = 2.0 * root_R[geom[B]];
+  o[0] += (code % 3 - 1) * side;
+  o[1] += ((code / 3) % 3 - 1) * side;
+  o[2] += (code / 9 - 1) * side;
+}
+
 __device__ __forceinline__ void box_center(const int* level, const int* ix, const int* iy, const int* iz,
                                            const int* geom, const double* root_c, const double* root_R, int B,
                                            double* c) {
@@ -327,7 +339,8 @@ __global__ __launch_bounds__(256) void k_m2m_reduce(const int* parents, int n_pa
                                                     const int* child_count, const int* src_b, const int* src_e,
                                                     const T* __restrict__ tmp, T* __restrict__ phi, int NC,
                                                     uint16_t* __restrict__ split = nullptr,
-                                                    float* __restrict__ split_scale = nullptr) {
+                                                    float* __restrict__ split_scale = nullptr,
+                                                    const signed char* __restrict__ pair_sh = nullptr) {
   constexpr int V = Vec16<T>::V;
   int pi = blockIdx.x;
   if (pi >= n_par) return;
@@ -603,7 +616,8 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
                                                     KConst<T> kc, TQ* __restrict__ out, int s2m_r = 0,
                                                     const int* __restrict__ pair_src = nullptr,
                                                     uint16_t* __restrict__ split = nullptr,
-                                                    float* __restrict__ split_scale = nullptr) {
+                                                    float* __restrict__ split_scale = nullptr,
+                                                    const signed char* __restrict__ pair_sh = nullptr) {
   __shared__ T sp[kStage][4];
   __shared__ T sn[kStage][4];
   __shared__ T sd[kStage][8];
@@ -638,6 +652,7 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
     const int A = S2M ? B : (pair_src ? pair_src[blockIdx.x] : list_idx[list_off[B] + li]);
     double o[3] = {0, 0, 0};
     if (!S2M) box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
+    if (pair_sh) add_lattice_shift(o, pair_sh[blockIdx.x], tv.geom, tv.root_R, B);
     const int s0 = tv.src_b[A], ns = tv.src_e[A] - s0;
     for (int base = 0; base < ns; base += kStage) {
       int cnt = min(kStage, ns - base);
@@ -718,7 +733,8 @@ __global__ __launch_bounds__(1024) void k_check_eval(const int* __restrict__ box
 template <typename T, int KIND, bool SL, bool DL>
 __global__ __launch_bounds__(256) void k_leaf_eval(
     const int* __restrict__ leaves, TreeView tv, const int* __restrict__ u_off, const int* __restrict__ u_idx,
-    const int* __restrict__ w_off, const int64_t* __restrict__ wslot_off, const double* __restrict__ wslot,
+    const signed char* __restrict__ u_sh, const int* __restrict__ w_off, const int64_t* __restrict__ wslot_off,
+    const double* __restrict__ wslot,
     const T* __restrict__ spos4,
     const T* __restrict__ snrm4, const T* __restrict__ dens8, const T* __restrict__ tpos4,
     const int* __restrict__ perm_trg, const T* __restrict__ phi_dn, const T* __restrict__ phi_up,
@@ -810,6 +826,7 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
       const int A = u_idx[li];
       double o[3];
       box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
+      add_lattice_shift(o, u_sh[li], tv.geom, tv.root_R, B);
       const int s0 = tv.src_b[A], ns = tv.src_e[A] - s0;
       for (int base = 0; base < ns; base += kStage) {
         int cnt = min(kStage, ns - base);
@@ -868,6 +885,7 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
 // keeps the work even: a leaf next to a finely refined region can have tens of W boxes.
 template <typename T, int KIND>
 __global__ __launch_bounds__(256) void k_w_eval(const int* __restrict__ pair_b, const int* __restrict__ pair_a,
+                                                const signed char* __restrict__ pair_sh,
                                                 const int64_t* __restrict__ slot_off, TreeView tv,
                                                 const T* __restrict__ tpos4, const T* __restrict__ phi_up,
                                                 const double* __restrict__ surf, int n_eq, double r_up_equiv, int NC,
@@ -881,6 +899,7 @@ __global__ __launch_bounds__(256) void k_w_eval(const int* __restrict__ pair_b, 
   const int tid = threadIdx.x;
   double o[3];
   box_offset(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_R, A, B, o);
+  add_lattice_shift(o, pair_sh[blockIdx.x], tv.geom, tv.root_R, B);
   const double rad = r_up_equiv * box_half(tv.level, tv.geom, tv.root_R, A);
   double* out = wslot + slot_off[blockIdx.x];
   const int t0 = tv.trg_b[B], nt_all = tv.trg_e[B] - t0;
@@ -997,13 +1016,15 @@ static T* upload_vec(Arena& a, const std::vector<T>& h, hipStream_t s) {
 
 Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t n_src, const double* trg,
                   int64_t n_trg, const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, const fmm_opts& o,
-                  hipStream_t s) {
+                  hipStream_t s, const std::vector<double>& cells) {
   auto t_start = std::chrono::steady_clock::now();
   KFMM_REQUIRE(o.precision == KFMM_FP64 || o.precision == KFMM_FP32 || o.precision == KFMM_FP32_M2L_SPLIT16 ||
                    o.precision == KFMM_FP32_TRANS64,
                o.precision == KFMM_FP32_M2L_BF16 ? kBf16Withdrawn : "unknown precision");
+  KFMM_REQUIRE(cells.empty() || o.precision == KFMM_FP64, "periodic cells need KFMM_FP64");
   std::unique_ptr<Plan> P(new Plan());
   P->opts = o;
+  P->periodic = !cells.empty();
   P->el = Elastic::make(o.K, o.G);
   P->prec = o.precision;
   P->f32t = o.precision == KFMM_FP32 || o.precision == KFMM_FP32_M2L_SPLIT16;
@@ -1027,7 +1048,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     return P.release();
   }
   Tree& t = P->tree;
-  build_tree(t, P->arena, src, n_src, trg, n_trg, bs, bt, leaf_max, max_depth, s);
+  build_tree(t, P->arena, src, n_src, trg, n_trg, bs, bt, leaf_max, max_depth, s, cells);
   build_lists(t, P->arena, s);
   P->tv = TreeView{t.level, t.ix, t.iy, t.iz, t.geom, t.root_c, t.root_R, t.src_b, t.src_e, t.trg_b, t.trg_e};
   const int nb = t.n_box, NC = P->NC;
@@ -1076,6 +1097,9 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   auto octant = [&](int b) { return (t.h_ix[b] & 1) | ((t.h_iy[b] & 1) << 1) | ((t.h_iz[b] & 1) << 2); };
   auto hs = [&](int b) { return t.h_src_e[b] > t.h_src_b[b]; };
   auto ht = [&](int b) { return t.h_trg_e[b] > t.h_trg_b[b]; };
+  // coarsest level of the translations: V and W lists hold boxes of level >= 2 in free space; a periodic
+  // tree has them from level 1 (images of the cell) and the root takes the far-image operator
+  const int lv0 = P->periodic ? 0 : 2;
   // UC2UE over source leaves
   {
     GemmCols c;
@@ -1084,7 +1108,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     if (P->f32t) {  // UC2UE on the check potentials of every box with sources at level >= 2
       GemmCols ca;
       for (int b = 0; b < nb; ++b)
-        if (t.h_level[b] >= 2 && hs(b)) ca.add(0, b, b);
+        if (t.h_level[b] >= lv0 && hs(b)) ca.add(0, b, b);
       P->job_up_all = upload_job(P->arena, ca, s, wide(ca));
       // with the compressed M2L, full equivalent densities are only read by the W lists: the second
       // factor runs on the W-list source boxes, the M2L takes U^T UC2UE qhat = G (fu1 qhat) directly
@@ -1092,14 +1116,14 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       for (int k : t.h_w_idx) isw[k] = 1;
       GemmCols cw;
       for (int b = 0; b < nb; ++b)
-        if (isw[b] && t.h_level[b] >= 2 && hs(b)) cw.add(0, b, b);
+        if (isw[b] && t.h_level[b] >= lv0 && hs(b)) cw.add(0, b, b);
       P->job_up_w = upload_job(P->arena, cw, s, wide(cw));
     }
   }
   // M2M per level (deepest first): children with sources, grouped by octant; parents reduce.  Parents
-  // at levels 0 and 1 are skipped: V and W lists only hold boxes of level >= 2.
+  // below level lv0 are skipped (no list holds them).
   P->up_levels.clear();
-  for (int l = t.depth; l >= 3; --l) {
+  for (int l = t.depth; l >= lv0 + 1; --l) {
     GemmCols c;
     std::vector<int> parents;
     for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
@@ -1202,28 +1226,28 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       }
     }
   }
-  // DC2DE over all boxes with targets at level >= 2; L2L per level >= 3
+  // DC2DE over all boxes with targets at level >= lv0; L2L per level >= lv0 + 1
   {
     GemmCols c;
     for (int b = 0; b < nb; ++b)
-      if (t.h_level[b] >= 2 && ht(b)) c.add(0, b, b);
+      if (t.h_level[b] >= lv0 && ht(b)) c.add(0, b, b);
     P->job_dc2de = upload_job(P->arena, c, s, wide(c));
     if (P->f32t) {  // DC2DE at the leaves only: the downward pass carries check potentials
       GemmCols cl;
       for (int b : leaves_trg)
-        if (t.h_level[b] >= 2) cl.add(0, b, b);
+        if (t.h_level[b] >= lv0) cl.add(0, b, b);
       P->job_dn_leaf = upload_job(P->arena, cl, s, wide(cl));
     }
     // compressed M2L: the X-list check potentials get DC2DE on their own (added after DC2DE * U q~)
     if (P->comp) {
       GemmCols cx;
       for (int i = 0; i < (int)x_boxes.size(); ++i)
-        if (t.h_level[x_boxes[i]] >= 2 && ht(x_boxes[i])) cx.add(0, i, x_boxes[i]);
+        if (t.h_level[x_boxes[i]] >= lv0 && ht(x_boxes[i])) cx.add(0, i, x_boxes[i]);
       P->job_dcx = upload_job(P->arena, cx, s, wide(cx));
     }
     P->dn_levels.clear();
     P->dn_lv.clear();
-    for (int l = 3; l <= t.depth; ++l) {
+    for (int l = lv0 + 1; l <= t.depth; ++l) {
       GemmCols cl;
       for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
         if (ht(b)) cl.add(octant(b), t.h_parent[b], b);
@@ -1232,21 +1256,42 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       P->dn_lv.push_back(l);
     }
   }
+  // periodic cells: the images beyond the 3 x 3 x 3 block act on each root through one operator, added
+  // to the root's downward check potential like an M2L (unit half-width frame, so no per-box scale)
+  if (P->periodic) {
+    DeviceOps& Dm = *P->ops;
+    {
+      std::lock_guard<std::mutex> lock(Dm.per_mutex);
+      if (!Dm.per_far64) {
+        std::vector<double> T = periodic_far_operator(p, P->el);
+        std::vector<double> Tp = pad_square(T, 3 * Dm.n_eq, NC);
+        Dm.per_far64 = Dm.arena.get<double>(Tp.size());
+        KFMM_HIP(hipMemcpy(Dm.per_far64, Tp.data(), Tp.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
+    }
+    GemmCols c;
+    for (int b = t.level_start[0]; b < t.level_start[1]; ++b)
+      if (hs(b) && ht(b)) c.add(0, b, b);
+    P->job_per = upload_job(P->arena, c, s);
+  }
   // W pairs and their output slots
   {
     std::vector<int> pb, pa;
+    std::vector<signed char> ps;
     std::vector<int64_t> off;
     int64_t tot = 0;
     for (int b = 0; b < nb; ++b)
       for (int k = t.h_w_off[b]; k < t.h_w_off[b + 1]; ++k) {
         pb.push_back(b);
         pa.push_back(t.h_w_idx[k]);
+        ps.push_back(t.h_w_sh[k]);
         off.push_back(tot);
         tot += (int64_t)(t.h_trg_e[b] - t.h_trg_b[b]) * 6;
       }
     P->n_wp = (int)pb.size();
     P->wp_b = upload_vec(P->arena, pb, s);
     P->wp_a = upload_vec(P->arena, pa, s);
+    P->wp_s = upload_vec(P->arena, ps, s);
     P->wslot_off = upload_vec(P->arena, off, s);
     P->wslot = P->arena.get<double>(std::max<int64_t>(tot, 1));
   }
@@ -1262,12 +1307,14 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   P->n_x_pairs = (int64_t)t.h_x_idx.size();
   {  // X pairs in list order (grouped by box in x_boxes order) and their per-box reduction
     std::vector<int> xb, xa, roff = {0}, ridx, rbox;
+    std::vector<signed char> xs;
     for (int i = 0; i < (int)x_boxes.size(); ++i) {
       const int b = x_boxes[i];
       for (int k = t.h_x_off[b]; k < t.h_x_off[b + 1]; ++k) {
         ridx.push_back((int)xb.size());
         xb.push_back(b);
         xa.push_back(t.h_x_idx[k]);
+        xs.push_back(t.h_x_sh[k]);
       }
       rbox.push_back(i);
       roff.push_back((int)xb.size());
@@ -1275,6 +1322,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->n_xp = (int)xb.size();
     P->xp_b = upload_vec(P->arena, xb, s);
     P->xp_a = upload_vec(P->arena, xa, s);
+    P->xp_s = upload_vec(P->arena, xs, s);
     P->xr_box = upload_vec(P->arena, rbox, s);
     P->xr_off = upload_vec(P->arena, roff, s);
     P->xr_idx = upload_vec(P->arena, ridx, s);
@@ -1368,7 +1416,7 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   const T* spos = (const T*)P.spos;
   const T* snrm = (const T*)P.snrm;
   const T* dens = (const T*)P.dens;
-  const bool far = nb > 1;
+  const bool far = nb > 1 || P.periodic;  // a periodic cell always has far images
   const T* phi_dn = P.prec == KFMM_FP64 ? (const T*)P.phi_dn : (const T*)P.phi_dn_lo;
   const T* phi_up = P.prec == KFMM_FP64 ? (const T*)P.phi_up : (const T*)P.phi_up_lo;
   // leaf evaluation: parts = 1 far field (L2T + W slots, added to out), 2 near field (U lists, stored)
@@ -1377,7 +1425,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       constexpr int KIND = decltype(kd)::value;
       constexpr bool SL = decltype(sl)::value, DL = decltype(dl)::value;
       hipLaunchKernelGGL((k_leaf_eval<T, KIND, SL, DL>), dim3(P.n_leaves_trg), dim3(256), 0, st, P.leaves_trg, P.tv,
-                         t.u_off, t.u_idx, t.w_off, P.wslot_off, P.wslot, spos, snrm, dens, (const T*)P.tpos,
+                         t.u_off, t.u_idx, (const signed char*)t.u_sh, t.w_off, P.wslot_off, P.wslot, spos, snrm,
+                         dens, (const T*)P.tpos,
                          t.perm_trg, phi_dn, phi_up, D.surf, n_eq, 1.05, 2.95, NC, parts & 1, (parts >> 1) & 1,
                          parts & 1, kc, out);
     };
@@ -1414,11 +1463,12 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       if (P.f32t)
         hipLaunchKernelGGL((k_check_eval<T, float, SL, DL, false>), dim3(P.n_xp), dim3(check_block), 0, st, P.xp_b,
                            P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc, (float*)P.xslot, 0,
-                           P.xp_a);
+                           P.xp_a, (uint16_t*)nullptr, (float*)nullptr, (const signed char*)P.xp_s);
       else
         hipLaunchKernelGGL((k_check_eval<T, double, SL, DL, false>), dim3(P.n_xp), dim3(check_block), 0, st,
                            P.xp_b, P.tv, t.x_off, t.x_idx, spos, snrm, dens, D.surf, n_eq, 1.05, NC, kc,
-                           (double*)P.xslot, 0, P.xp_a);
+                           (double*)P.xslot, 0, P.xp_a, (uint16_t*)nullptr, (float*)nullptr,
+                           (const signed char*)P.xp_s);
     });
     if (P.f32t)
       hipLaunchKernelGGL((k_slot_reduce<float, float>), dim3(P.n_x_boxes), dim3(reduce_block<float>(NC)), 0, st,
@@ -1431,10 +1481,12 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   auto w_eval = [&](hipStream_t st) {
     if (!P.n_wp) return;
     if (kind == KFMM_DISP)
-      hipLaunchKernelGGL((k_w_eval<T, 0>), dim3(P.n_wp), dim3(256), 0, st, P.wp_b, P.wp_a, P.wslot_off, P.tv,
+      hipLaunchKernelGGL((k_w_eval<T, 0>), dim3(P.n_wp), dim3(256), 0, st, P.wp_b, P.wp_a,
+                         (const signed char*)P.wp_s, P.wslot_off, P.tv,
                          (const T*)P.tpos, phi_up, D.surf, n_eq, 1.05, NC, kc, P.wslot);
     else
-      hipLaunchKernelGGL((k_w_eval<T, 1>), dim3(P.n_wp), dim3(256), 0, st, P.wp_b, P.wp_a, P.wslot_off, P.tv,
+      hipLaunchKernelGGL((k_w_eval<T, 1>), dim3(P.n_wp), dim3(256), 0, st, P.wp_b, P.wp_a,
+                         (const signed char*)P.wp_s, P.wslot_off, P.tv,
                          (const T*)P.tpos, phi_up, D.surf, n_eq, 1.05, NC, kc, P.wslot);
     KFMM_HIP(hipGetLastError());
   };
@@ -1620,6 +1672,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       hipLaunchKernelGGL(k_add_rows<double>, dim3(P.n_x_boxes), dim3(reduce_block<double>(NC)), 0, s, P.x_boxes,
                          (const double*)P.qx, qhat, NC);
   }
+  // periodic cells (FP64 translations): the far images act on the roots
+  if (P.periodic && P.job_per.n_tiles)
+    gemm_f64(P.job_per, D.per_far64, GemmDims::Sq(NC), P.phi_up, qhat, kAdd, s);
   KFMM_HIP(hipGetLastError());
   mark(KFMM_PH_DOWN);
   // the downward pass overwrites the upward check potentials (qhat_f is q_f): wait until the second stream

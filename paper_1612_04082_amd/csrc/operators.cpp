@@ -399,4 +399,118 @@ void sym_eig_psd(const std::vector<double>& A, int n, std::vector<double>& lambd
   }
 }
 
+// Far-image operator of a periodic cell (Sec. 4.3: the multipole expansions are periodic, so the tree is
+// made periodic at every level).  The lists of a periodic tree cover the 3 x 3 x 3 block of cell images
+// around the cell; the images beyond act on the root alone, through
+//   T = sum_{n not in {-1,0,1}^3} U[dc <- ue + 2n]      (unit half-width frame, cell side 2)
+// added to the root's downward check potential like an M2L.  The lattice sum converges only conditionally;
+// it is taken as the Fourier series without its k = 0 term (the zero-mean periodic field, a net force per
+// cell balanced by a uniform body force), evaluated by Ewald splitting U = U_r + U_f + constant:
+//   U_r(x) = cU [(3 - 4nu) delta erfc(a r) / r + (erfc(a r) / r + 2a/sqrt(pi) exp(-a^2 r^2)) x x^T / r^2]
+//   U_f    = (1/V) sum_{k != 0} exp(-s) [delta / (G k^2) - (1 + s) k k^T / (2 (1 - nu) G k^4)] cos(k.x),
+//            k = 2 pi m / L, s = k^2 / (4 a^2)
+//   constant -delta / (4 a^2 G V)  (the k -> 0 limit of U_r's transform, left out with k = 0)
+// (U_r carries the Kelvin singularity; U_r - U is smooth, -(3 - 4nu) cU 2a/sqrt(pi) delta at x = 0).  So
+//   T(x) = sum_{n in 27} (U_r - U)(x + 2n) + sum_{n not in 27} U_r(x + 2n) + U_f(x) + constant.
+// With a = 1.5 (L = 2) the real-space terms beyond |n_i| <= 2 and the Fourier terms beyond |m_i| <= 7 are
+// below 1e-16 of the entries.
+std::vector<double> periodic_far_operator(int p, const Elastic& e) {
+  const int ne = surface_count(p), n = 3 * ne;
+  const double L = 2.0, V = L * L * L, a = 1.5, RE = 1.05, RC = 1.05;
+  const double sqpi = std::sqrt(kPi), c_e = 2.0 * a / sqpi;
+  const std::vector<double> S = cube_surface(p);
+  std::vector<double> X(3 * ne), Y(3 * ne);  // downward check points, upward equivalent points
+  for (int i = 0; i < 3 * ne; ++i) {
+    X[i] = RC * S[i];
+    Y[i] = RE * S[i];
+  }
+  std::vector<double> T((size_t)n * n, 0.0);
+  // ---- real space and constant
+  const int NR = 2;
+  const double rcut = 6.0 / a;
+  for (int ia = 0; ia < ne; ++ia)
+    for (int ib = 0; ib < ne; ++ib) {
+      double acc[3][3] = {};
+      for (int nx = -NR; nx <= NR; ++nx)
+        for (int ny = -NR; ny <= NR; ++ny)
+          for (int nz = -NR; nz <= NR; ++nz) {
+            const bool near = std::abs(nx) <= 1 && std::abs(ny) <= 1 && std::abs(nz) <= 1;
+            const double d[3] = {Y[3 * ib] + L * nx - X[3 * ia], Y[3 * ib + 1] + L * ny - X[3 * ia + 1],
+                                 Y[3 * ib + 2] + L * nz - X[3 * ia + 2]};
+            const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!near && r > rcut) continue;
+            double cd, cx;  // coefficients of delta and of x x^T / r^2
+            if (near) {     // U_r - U
+              const double ef = r > 0 ? std::erf(a * r) / r : c_e;
+              cd = -(3.0 - 4.0 * e.nu) * ef;
+              cx = r > 0 ? -ef + c_e * std::exp(-a * a * r * r) : 0.0;
+            } else {
+              const double ec = std::erfc(a * r) / r;
+              cd = (3.0 - 4.0 * e.nu) * ec;
+              cx = ec + c_e * std::exp(-a * a * r * r);
+            }
+            for (int i = 0; i < 3; ++i)
+              for (int j = 0; j < 3; ++j)
+                acc[i][j] += e.cU * ((i == j ? cd : 0.0) + (r > 0 ? cx * d[i] * d[j] / (r * r) : 0.0));
+          }
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          T[(size_t)(3 * ia + i) * n + 3 * ib + j] = acc[i][j] - (i == j ? 1.0 / (4.0 * a * a * e.G * V) : 0.0);
+    }
+  // ---- reciprocal space: half of the vectors m != 0 (m and -m give the same cosine), weight 2/V
+  const int KM = 7;
+  std::vector<double> kv;
+  for (int mx = -KM; mx <= KM; ++mx)
+    for (int my = -KM; my <= KM; ++my)
+      for (int mz = -KM; mz <= KM; ++mz)
+        if (mx > 0 || (mx == 0 && my > 0) || (mx == 0 && my == 0 && mz > 0)) {
+          kv.push_back(2.0 * kPi * mx / L);
+          kv.push_back(2.0 * kPi * my / L);
+          kv.push_back(2.0 * kPi * mz / L);
+        }
+  const int nk = (int)kv.size() / 3;
+  std::vector<double> w6((size_t)nk * 6);  // (2/V) U_f(k) components xx, yy, zz, xy, xz, yz
+  for (int q = 0; q < nk; ++q) {
+    const double* k = &kv[3 * q];
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2], sx = k2 / (4.0 * a * a), ex = std::exp(-sx);
+    const double cdel = 2.0 / V * ex / (e.G * k2), ckk = -2.0 / V * ex * (1.0 + sx) / (2.0 * (1.0 - e.nu) * e.G * k2 * k2);
+    const int pi6[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    for (int c = 0; c < 6; ++c) {
+      const int i = pi6[c][0], j = pi6[c][1];
+      w6[6 * q + c] = (i == j ? cdel : 0.0) + ckk * k[i] * k[j];
+    }
+  }
+  std::vector<double> cxa((size_t)ne * nk), sxa((size_t)ne * nk), cyb((size_t)ne * nk), syb((size_t)ne * nk);
+  for (int i = 0; i < ne; ++i)
+    for (int q = 0; q < nk; ++q) {
+      const double* k = &kv[3 * q];
+      const double tx = k[0] * X[3 * i] + k[1] * X[3 * i + 1] + k[2] * X[3 * i + 2];
+      const double ty = k[0] * Y[3 * i] + k[1] * Y[3 * i + 1] + k[2] * Y[3 * i + 2];
+      cxa[(size_t)i * nk + q] = std::cos(tx);
+      sxa[(size_t)i * nk + q] = std::sin(tx);
+      cyb[(size_t)i * nk + q] = std::cos(ty);
+      syb[(size_t)i * nk + q] = std::sin(ty);
+    }
+  auto rows = [&](int a0, int a1) {
+    for (int ia = a0; ia < a1; ++ia)
+      for (int ib = 0; ib < ne; ++ib) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        const double *ca = &cxa[(size_t)ia * nk], *sa = &sxa[(size_t)ia * nk];
+        const double *cb = &cyb[(size_t)ib * nk], *sb = &syb[(size_t)ib * nk];
+        for (int q = 0; q < nk; ++q) {
+          const double c = cb[q] * ca[q] + sb[q] * sa[q];  // cos(k.(y - x))
+          for (int m = 0; m < 6; ++m) acc[m] += w6[6 * q + m] * c;
+        }
+        const double M[3][3] = {{acc[0], acc[3], acc[4]}, {acc[3], acc[1], acc[5]}, {acc[4], acc[5], acc[2]}};
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) T[(size_t)(3 * ia + i) * n + 3 * ib + j] += M[i][j];
+      }
+  };
+  const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t) pool.emplace_back(rows, ne * t / nth, ne * (t + 1) / nth);
+  for (auto& th : pool) th.join();
+  return T;
+}
+
 }  // namespace kfmm

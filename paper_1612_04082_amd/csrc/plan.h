@@ -37,6 +37,10 @@ struct Plan {
   int64_t n_src = 0, n_trg = 0;
   int NC = 0, n_eq = 0;
   std::shared_ptr<DeviceOps> ops;
+  // periodic cells: levels 0 and 1 take part in the translations, and job_per adds the far-image operator
+  // to the root's downward check potential
+  bool periodic = false;
+  GemmJob job_per;
   Arena arena;
   Tree tree;
   TreeView tv{};
@@ -77,6 +81,7 @@ struct Plan {
   // W pairs (CSR order of the W lists): one output slot of nt(B) x 6 doubles each
   int n_wp = 0;
   int *wp_b = nullptr, *wp_a = nullptr;
+  signed char* wp_s = nullptr;  // lattice shift code of each pair (periodic cells)
   int64_t* wslot_off = nullptr;
   double* wslot = nullptr;
   // X-list check potentials, one compact row per box of x_boxes; computed per X pair (one row each, in
@@ -84,6 +89,7 @@ struct Plan {
   double* qx = nullptr;
   int n_xp = 0;
   int *xp_b = nullptr, *xp_a = nullptr;                       // pair -> target box, source box
+  signed char* xp_s = nullptr;                                // pair -> lattice shift code
   int *xr_box = nullptr, *xr_off = nullptr, *xr_idx = nullptr;  // per-box reduction of the pair rows
   void* xslot = nullptr;
   // second stream (near field, X and W lists) and its fork / join events
@@ -105,9 +111,10 @@ struct Plan {
   ~Plan();
 };
 
+// cells: empty for free space, else n_geom x 4 (lower corner, side) of periodic cubic cells.
 Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t n_src, const double* trg,
                   int64_t n_trg, const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, const fmm_opts& o,
-                  hipStream_t s);
+                  hipStream_t s, const std::vector<double>& cells = {});
 void plan_eval(Plan& P, int kind, const double* a, const double* b, double* out, hipStream_t s);
 void plan_profile(Plan& P, int mode);
 void plan_light_harvest(Plan& P, bool all);

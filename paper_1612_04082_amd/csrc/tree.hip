@@ -13,6 +13,13 @@
 //   W(B), leaf B: descendants A of B's colleagues with A not adjacent to B but parent(A) adjacent
 //   X(B): leaves A coarser than B, adjacent to parent(B) and not adjacent to B  (dual of W)
 // Only boxes that hold sources enter as sources and only boxes that hold targets as targets.
+//
+// Periodic cells (Sec. 4.3: integrals over the infinite periodic surface; the tree is periodic at every
+// level): the root box is the cell, and the neighbours of a box at the cell's faces are boxes of the
+// same cell seen through a lattice image.  Every colleague, and so every U, V, W, X entry, carries the
+// shift of that image (a code for s in {-1,0,1}^3, in cell sides); at level 0 the 26 colleagues of the
+// root are its own images.  The lists then cover exactly the 3 x 3 x 3 block of images around the cell;
+// the images farther out reach the root through one precomputed operator (fmm.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -300,8 +307,14 @@ __global__ void k_mark_leaf_points(int n_box, const int* is_leaf, const int* b, 
   for (int i = b[box] + threadIdx.x; i < e[box]; i += blockDim.x) leaf_of[i] = box;
 }
 
+__device__ __forceinline__ int wrap_cell(int x, int lim, int& sh) {  // x in [-1, lim] -> [0, lim), shift
+  sh = x < 0 ? -1 : (x >= lim ? 1 : 0);
+  return x - sh * lim;
+}
+
 __global__ void k_colleagues(int n_box, const int* level, const int* ix, const int* iy, const int* iz, const int* g,
-                             const int* level_start, const uint64_t* bkey, int* colleague) {
+                             const int* level_start, const uint64_t* bkey, int periodic, int* colleague,
+                             signed char* colleague_sh) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n_box) return;
   int l = level[b];
@@ -310,6 +323,12 @@ __global__ void k_colleagues(int n_box, const int* level, const int* ix, const i
   for (int c = 0; c < 27; ++c) {
     int dx = c % 3 - 1, dy = (c / 3) % 3 - 1, dz = c / 9 - 1;
     int x = ix[b] + dx, y = iy[b] + dy, z = iz[b] + dz;
+    int sx = 0, sy = 0, sz = 0;
+    if (periodic) {
+      x = wrap_cell(x, lim, sx);
+      y = wrap_cell(y, lim, sy);
+      z = wrap_cell(z, lim, sz);
+    }
     int found = -1;
     if (x >= 0 && y >= 0 && z >= 0 && x < lim && y < lim && z < lim) {
       uint64_t k = box_key(g[b], l, x, y, z);
@@ -317,6 +336,7 @@ __global__ void k_colleagues(int n_box, const int* level, const int* ix, const i
       if (p < hi0 && bkey[p] == k) found = p;
     }
     colleague[27 * b + c] = found;
+    colleague_sh[27 * b + c] = (signed char)((sx + 1) + 3 * (sy + 1) + 9 * (sz + 1));
   }
 }
 
@@ -364,10 +384,12 @@ static uint64_t* sort_points(Arena& arena, Arena& scratch, const double* x, int6
 
 void build_tree(Tree& t, Arena& arena, const double* src, int64_t n_src, const double* trg, int64_t n_trg,
                 const std::vector<int64_t>& batch_src, const std::vector<int64_t>& batch_trg, int leaf_max,
-                int max_depth, hipStream_t s) {
+                int max_depth, hipStream_t s, const std::vector<double>& cells) {
   Arena scratch;
   const int G = (int)batch_src.size() - 1;
   t.n_geom = G;
+  t.periodic = !cells.empty();
+  if (t.periodic && (int)cells.size() != 4 * G) throw Error(-1, "periodic cells: 4 values per geometry");
   const bool alias = (trg == nullptr);
   // ---- bounding cubes
   int64_t* d_bs = upload(scratch, batch_src, s);
@@ -401,6 +423,18 @@ void build_tree(Tree& t, Arena& arena, const double* src, int64_t n_src, const d
         mn[d] = std::min(mn[d], hbt[6 * g + d]);
         mx[d] = std::max(mx[d], hbt[6 * g + 3 + d]);
       }
+    }
+    if (t.periodic) {  // the root box is the cell; every point must lie in [lo, lo + side)
+      const double* c = &cells[4 * g];
+      if (!(c[3] > 0.0) || !std::isfinite(c[3]) || !std::isfinite(c[0]) || !std::isfinite(c[1]) ||
+          !std::isfinite(c[2]))
+        throw Error(-1, "periodic cell: side must be positive and finite");
+      for (int d = 0; d < 3; ++d) {
+        t.h_root_c[3 * g + d] = c[d] + 0.5 * c[3];
+        if (any && (mn[d] < c[d] || mx[d] >= c[d] + c[3])) throw Error(-1, "point outside its periodic cell");
+      }
+      t.h_root_R[g] = 0.5 * c[3];
+      continue;
     }
     if (!any) continue;
     double half = 0;
@@ -565,8 +599,9 @@ void build_tree(Tree& t, Arena& arena, const double* src, int64_t n_src, const d
   hipLaunchKernelGGL(k_box_keys, dim3((nbx + 255) / 256), dim3(256), 0, s, nbx, t.level, t.ix, t.iy, t.iz, t.geom,
                      bkey);
   t.colleague = arena.get<int>((size_t)27 * nbx);
+  t.colleague_sh = arena.get<signed char>((size_t)27 * nbx);
   hipLaunchKernelGGL(k_colleagues, dim3((nbx + 255) / 256), dim3(256), 0, s, nbx, t.level, t.ix, t.iy, t.iz, t.geom,
-                     d_ls, bkey, t.colleague);
+                     d_ls, bkey, t.periodic ? 1 : 0, t.colleague, t.colleague_sh);
   KFMM_HIP(hipGetLastError());
   KFMM_HIP(hipStreamSynchronize(s));
 }
@@ -576,19 +611,26 @@ void build_tree(Tree& t, Arena& arena, const double* src, int64_t n_src, const d
 struct BoxView {
   const int *level, *ix, *iy, *iz, *parent, *child_first, *child_count, *is_leaf, *colleague;
   const int *src_b, *src_e, *trg_b, *trg_e;
+  const signed char* colleague_sh;
 };
 
 __device__ __forceinline__ bool has_src(const BoxView& v, int b) { return v.src_e[b] > v.src_b[b]; }
 __device__ __forceinline__ bool has_trg(const BoxView& v, int b) { return v.trg_e[b] > v.trg_b[b]; }
 
-// Closed cubes of boxes a and b touch (boxes of one geometry with disjoint interiors).
-__device__ __forceinline__ bool adjacent(const BoxView& v, int a, int b) {
+__device__ __forceinline__ int shift_of(int code, int d) {  // component d of a lattice shift code
+  return d == 0 ? code % 3 - 1 : (d == 1 ? (code / 3) % 3 - 1 : code / 9 - 1);
+}
+
+// Closed cubes of box a, seen through the lattice image of shift code sa, and box b touch (boxes of one
+// geometry with disjoint interiors).
+__device__ __forceinline__ bool adjacent(const BoxView& v, int a, int sa_code, int b) {
   int la = v.level[a], lb = v.level[b];
   int L = la > lb ? la : lb;
   int sa = L - la, sb = L - lb;
   int ca[3] = {v.ix[a], v.iy[a], v.iz[a]}, cb[3] = {v.ix[b], v.iy[b], v.iz[b]};
   for (int d = 0; d < 3; ++d) {
-    long a0 = (long)ca[d] << sa, a1 = ((long)ca[d] + 1) << sa;
+    const long img = (long)shift_of(sa_code, d) * (1L << la);  // one cell side in units of level la
+    long a0 = ((long)ca[d] + img) << sa, a1 = ((long)ca[d] + img + 1) << sa;
     long b0 = (long)cb[d] << sb, b1 = ((long)cb[d] + 1) << sb;
     if (a1 < b0 || b1 < a0) return false;
   }
@@ -596,29 +638,38 @@ __device__ __forceinline__ bool adjacent(const BoxView& v, int a, int b) {
 }
 
 // One thread per box.  mode 0: count; mode 1: fill.  Each list k in {U, W, X, V} has counts cnt_k[b]
-// and offsets off_k[b]; V entries also record the offset index.
+// and offsets off_k[b]; V entries also record the offset index (lattice shift included), U, W, X entries
+// the shift code of the image they are seen through.  A descendant is seen through the image of the
+// colleague it descends from; colleague 13 of a box is the box itself.
 __global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* cX, int* cV, const int* oU,
-                        const int* oW, const int* oX, const int* oV, int* lU, int* lW, int* lX, int* lVs, int* lVo) {
+                        const int* oW, const int* oX, const int* oV, int* lU, int* lW, int* lX, int* lVs, int* lVo,
+                        signed char* sU, signed char* sW, signed char* sX) {
   int B = blockIdx.x * blockDim.x + threadIdx.x;
   if (B >= n_box) return;
   int nU = 0, nW = 0, nX = 0, nV = 0;
   const bool trgB = has_trg(v, B);
   const int P = v.parent[B];
-#define PUSH(list, cntvar, offarr, val) \
-  do {                                  \
-    if (mode) list[offarr[B] + cntvar] = (val); \
-    ++cntvar;                           \
+#define PUSH(list, shl, cntvar, offarr, val, sh) \
+  do {                                            \
+    if (mode) {                                   \
+      list[offarr[B] + cntvar] = (val);           \
+      shl[offarr[B] + cntvar] = (signed char)(sh); \
+    }                                             \
+    ++cntvar;                                     \
   } while (0)
   if (trgB) {
     // ---- V: children of the colleagues of parent(B), same level, not adjacent
     if (P >= 0) {
+      const int l = v.level[B];
       for (int c = 0; c < 27; ++c) {
         int C = v.colleague[27 * P + c];
         if (C < 0) continue;
+        const int sc = v.colleague_sh[27 * P + c];
         int f = v.child_first[C], nc = v.child_count[C];
         for (int k = 0; k < nc; ++k) {
           int A = f + k;
-          int dx = v.ix[A] - v.ix[B], dy = v.iy[A] - v.iy[B], dz = v.iz[A] - v.iz[B];
+          int dx = v.ix[A] + shift_of(sc, 0) * (1 << l) - v.ix[B], dy = v.iy[A] + shift_of(sc, 1) * (1 << l) - v.iy[B],
+              dz = v.iz[A] + shift_of(sc, 2) * (1 << l) - v.iz[B];
           int m = max(abs(dx), max(abs(dy), abs(dz)));
           if (m <= 1 || !has_src(v, A)) continue;
           if (mode) {
@@ -634,20 +685,22 @@ __global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* c
       for (int anc = P; anc >= 0; anc = v.parent[anc]) {
         for (int c = 0; c < 27; ++c) {
           int A = v.colleague[27 * anc + c];
-          if (A < 0 || A == anc || !v.is_leaf[A] || !has_src(v, A)) continue;
-          if (adjacent(v, A, P) && !adjacent(v, A, B)) PUSH(lX, nX, oX, A);
+          if (A < 0 || c == 13 || !v.is_leaf[A] || !has_src(v, A)) continue;
+          const int sa = v.colleague_sh[27 * anc + c];
+          if (adjacent(v, A, sa, P) && !adjacent(v, A, sa, B)) PUSH(lX, sX, nX, oX, A, sa);
         }
       }
     }
     if (v.is_leaf[B]) {
       // ---- U: B itself, adjacent leaves at B's level and finer (descending colleagues), coarser leaves
-      if (has_src(v, B)) PUSH(lU, nU, oU, B);
+      if (has_src(v, B)) PUSH(lU, sU, nU, oU, B, 13);
       int stack[256];
       for (int c = 0; c < 27; ++c) {
         int C = v.colleague[27 * B + c];
-        if (C < 0 || C == B) continue;
+        if (C < 0 || c == 13) continue;
+        const int sc = v.colleague_sh[27 * B + c];
         if (v.is_leaf[C]) {
-          if (has_src(v, C)) PUSH(lU, nU, oU, C);
+          if (has_src(v, C)) PUSH(lU, sU, nU, oU, C, sc);
           continue;
         }
         int sp = 0;
@@ -658,13 +711,13 @@ __global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* c
           for (int k = 0; k < nc; ++k) {
             int A = f + k;
             if (!has_src(v, A)) continue;
-            if (adjacent(v, A, B)) {
+            if (adjacent(v, A, sc, B)) {
               if (v.is_leaf[A])
-                PUSH(lU, nU, oU, A);
+                PUSH(lU, sU, nU, oU, A, sc);
               else if (sp < 256)
                 stack[sp++] = A;
             } else {
-              PUSH(lW, nW, oW, A);
+              PUSH(lW, sW, nW, oW, A, sc);
             }
           }
         }
@@ -672,8 +725,9 @@ __global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* c
       for (int anc = P; anc >= 0; anc = v.parent[anc]) {
         for (int c = 0; c < 27; ++c) {
           int A = v.colleague[27 * anc + c];
-          if (A < 0 || A == anc || !v.is_leaf[A] || !has_src(v, A)) continue;
-          if (adjacent(v, A, B)) PUSH(lU, nU, oU, A);
+          if (A < 0 || c == 13 || !v.is_leaf[A] || !has_src(v, A)) continue;
+          const int sa = v.colleague_sh[27 * anc + c];
+          if (adjacent(v, A, sa, B)) PUSH(lU, sU, nU, oU, A, sa);
         }
       }
     }
@@ -691,12 +745,13 @@ void build_lists(Tree& t, Arena& arena, hipStream_t s) {
   Arena scratch;
   const int n = t.n_box;
   BoxView v{t.level, t.ix, t.iy, t.iz, t.parent, t.child_first, t.child_count, t.is_leaf, t.colleague,
-            t.src_b, t.src_e, t.trg_b, t.trg_e};
+            t.src_b, t.src_e, t.trg_b, t.trg_e, t.colleague_sh};
   int* c4 = scratch.get<int>(4 * (size_t)n);
   unsigned nb = (unsigned)((n + 127) / 128);
   hipLaunchKernelGGL(k_lists, dim3(nb), dim3(128), 0, s, n, v, 0, c4, c4 + n, c4 + 2 * n, c4 + 3 * n,
                      (const int*)nullptr, (const int*)nullptr, (const int*)nullptr, (const int*)nullptr, (int*)nullptr,
-                     (int*)nullptr, (int*)nullptr, (int*)nullptr, (int*)nullptr);
+                     (int*)nullptr, (int*)nullptr, (int*)nullptr, (int*)nullptr, (signed char*)nullptr,
+                     (signed char*)nullptr, (signed char*)nullptr);
   KFMM_HIP(hipGetLastError());
   std::vector<int> h = download(c4, 4 * (size_t)n, s);
   std::vector<int> offs[4];
@@ -713,8 +768,11 @@ void build_lists(Tree& t, Arena& arena, hipStream_t s) {
   int* lX = scratch.get<int>(tot[2] + 1);
   int* lVs = scratch.get<int>(tot[3] + 1);
   int* lVo = scratch.get<int>(tot[3] + 1);
+  signed char* sU = scratch.get<signed char>(tot[0] + 1);
+  signed char* sW = scratch.get<signed char>(tot[1] + 1);
+  signed char* sX = scratch.get<signed char>(tot[2] + 1);
   hipLaunchKernelGGL(k_lists, dim3(nb), dim3(128), 0, s, n, v, 1, (int*)nullptr, (int*)nullptr, (int*)nullptr,
-                     (int*)nullptr, dO[0], dO[1], dO[2], dO[3], lU, lW, lX, lVs, lVo);
+                     (int*)nullptr, dO[0], dO[1], dO[2], dO[3], lU, lW, lX, lVs, lVo, sU, sW, sX);
   KFMM_HIP(hipGetLastError());
   t.h_u_off = offs[0];
   t.h_w_off = offs[1];
@@ -722,6 +780,9 @@ void build_lists(Tree& t, Arena& arena, hipStream_t s) {
   t.h_u_idx = download(lU, tot[0], s);
   t.h_w_idx = download(lW, tot[1], s);
   t.h_x_idx = download(lX, tot[2], s);
+  t.h_u_sh = download(sU, tot[0], s);
+  t.h_w_sh = download(sW, tot[1], s);
+  t.h_x_sh = download(sX, tot[2], s);
   std::vector<int> vs = download(lVs, tot[3], s), vo = download(lVo, tot[3], s);
   t.h_v_trg.resize(tot[3]);
   t.h_v_src = vs;
@@ -734,6 +795,7 @@ void build_lists(Tree& t, Arena& arena, hipStream_t s) {
   t.w_idx = upload(arena, t.h_w_idx, s);
   t.x_off = upload(arena, t.h_x_off, s);
   t.x_idx = upload(arena, t.h_x_idx, s);
+  t.u_sh = upload(arena, t.h_u_sh, s);
   KFMM_HIP(hipStreamSynchronize(s));
 }
 

@@ -81,6 +81,10 @@ def load_library():
     L.fmm_plan.argtypes = [ctypes.POINTER(vp), vp, vp, vp, i64, vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
                            i32, ctypes.POINTER(FmmOpts), vp]
     L.fmm_plan.restype = ctypes.c_int
+    L.fmm_plan_periodic.argtypes = [ctypes.POINTER(vp), vp, vp, vp, i64, vp, i64, ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64), i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(FmmOpts),
+                                    vp]
+    L.fmm_plan_periodic.restype = ctypes.c_int
     L.fmm_eval.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.fmm_eval.restype = ctypes.c_int
     L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
@@ -185,7 +189,9 @@ class FmmPlan:
     """fmm_plan / fmm_eval / fmm_plan_destroy on torch tensors (FP64, on the current CUDA device)."""
 
     def __init__(self, src, nrm=None, w=None, trg=None, K=None, G=1.0, p=6, leaf_max=64, precision=FP32,
-                 svd_eps=0.0, max_depth=0, mem_limit=0, batch_src=None, batch_trg=None, m2l_tol=0.0):
+                 svd_eps=0.0, max_depth=0, mem_limit=0, batch_src=None, batch_trg=None, m2l_tol=0.0, cells=None):
+        """cells: None (free space) or a sequence of (x0, y0, z0, side) per geometry -- periodic cubic cells
+        (fmm_plan_periodic)."""
         L = load_library()
         self._h = ctypes.c_void_p()
         if K is None:
@@ -203,9 +209,16 @@ class FmmPlan:
             bt = (ctypes.c_int64 * len(bt_list))(*[int(v) for v in bt_list])
         if w is not None and (w.dim() != 1 or int(w.shape[0]) != self.n_src):
             raise ValueError(f"w must have shape ({self.n_src},)")
-        check(L.fmm_plan(ctypes.byref(self._h), _dptr(src, "src", 3), _dptr(nrm, "nrm", 3, self.n_src), _dptr(w, "w"),
-                         self.n_src, _dptr(trg, "trg", 3), self.n_trg, bs, bt, nb, ctypes.byref(self.opts),
-                         _stream()))
+        args = (ctypes.byref(self._h), _dptr(src, "src", 3), _dptr(nrm, "nrm", 3, self.n_src), _dptr(w, "w"),
+                self.n_src, _dptr(trg, "trg", 3), self.n_trg, bs, bt, nb)
+        if cells is None:
+            check(L.fmm_plan(*args, ctypes.byref(self.opts), _stream()))
+        else:
+            flat = [float(v) for row in cells for v in row]
+            if len(flat) != 4 * max(nb, 1):
+                raise ValueError("cells: one (x0, y0, z0, side) row per geometry")
+            self._cells = (ctypes.c_double * len(flat))(*flat)
+            check(L.fmm_plan_periodic(*args, self._cells, ctypes.byref(self.opts), _stream()))
 
     def eval(self, kind, a=None, b=None, out=None):
         no = 3 if kind == DISP else 6

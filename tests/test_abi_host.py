@@ -78,6 +78,26 @@ def test_plan_argument_errors(lib):
     assert "negative size" in last_error(lib)
 
 
+def test_periodic_plan_argument_errors(lib):
+    """fmm_plan_periodic: a NULL cell array and a precision other than FP64 are refused before any device call."""
+    from paper_1612_04082_amd import kfmm
+    plan = ctypes.c_void_p()
+    xyz = (ctypes.c_double * 3)(0.5, 0.5, 0.5)
+    cells = (ctypes.c_double * 4)(0.0, 0.0, 0.0, 1.0)
+    good = dict(K=1.0, G=1.0, p=6, leaf_max=64, precision=kfmm.FP64, svd_eps=0.0, max_depth=0, mem_limit=0,
+                m2l_tol=0.0)
+
+    def call(c, opts):
+        return lib.fmm_plan_periodic(ctypes.byref(plan), xyz, None, None, 1, None, 1, None, None, 0, c,
+                                     ctypes.byref(opts), None)
+
+    assert call(None, kfmm.FmmOpts(**good)) == KFMM_E_ARG
+    assert last_error(lib) == "cells is NULL" and not plan.value
+    for prec in (kfmm.FP32, kfmm.FP32_M2L_SPLIT16, kfmm.FP32_TRANS64):
+        assert call(cells, kfmm.FmmOpts(**{**good, "precision": prec})) == KFMM_E_ARG
+        assert "periodic cells need KFMM_FP64" in last_error(lib)
+
+
 def test_selftest_gemm_selector_errors(lib):
     idx = (ctypes.c_int * 1)(0)
 

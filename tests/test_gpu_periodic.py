@@ -1,0 +1,123 @@
+"""Periodic FMM (fmm_plan_periodic; Sec. 4.3, a tree periodic at every level) against the Ewald oracle
+(oracle/periodic.py), element by element.
+
+Inputs: sources half uniform over the cell (interactions across every face of the cell) and half on a
+small sphere near one corner (an adaptive tree, so W and X lists occur), random normals, single-layer
+densities with no net force per cell (the case the periodic problem poses: the tractions of a closed
+surface), random double-layer densities.  FP64 translations at p = 8.
+
+Compared: stresses directly; displacements up to one constant vector per geometry (the fast evaluation
+takes the far images through the root's equivalent density, whose cell mean differs from the sources' by
+a rigid translation; the header of fmm_plan_periodic states this).  The bound 1e-5 is the free-space
+accuracy of the method at p = 8 (2e-6 to 5e-6 on these inputs in free space) with room for the images.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct as od
+from oracle import periodic as op
+
+pytestmark = pytest.mark.gpu
+
+G = 1.0
+K = od.moduli(G, 0.3)
+
+
+def _cloud(N, lo, L, seed):
+    rng = np.random.default_rng(seed)
+    nu = N // 2
+    pu = lo + rng.uniform(size=(nu, 3)) * L
+    d = rng.normal(size=(N - nu, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    ps = lo + 0.25 * L + 0.2 * L * d
+    src = np.vstack([pu, ps])
+    nrm = rng.normal(size=(N, 3))
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    w = rng.uniform(0.5, 1.5, size=N)
+    a = rng.normal(size=(N, 3))
+    a -= (w[:, None] * a).sum(0) / w.sum()  # no net force per cell
+    b = rng.normal(size=(N, 3))
+    return src, nrm, w, a, b
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _check(got, ref, kind, tol, label):
+    if kind == od.DISP:
+        c = (got - ref).mean(axis=0)
+        err = np.linalg.norm(got - ref - c) / np.linalg.norm(ref)
+        print(f"{label} DISP: rel L2 {err:.2e} (constant {np.abs(c).max():.2e})")
+    else:
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"{label} STRESS: rel L2 {err:.2e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("N,leaf,p", [(4000, 64, 8), (40, 64, 6), (600, 16, 6)])
+def test_periodic_matches_ewald(cuda, N, leaf, p):
+    """Many levels (W and X lists, V lists at level 1 through the images), a tree that is only the root
+    (near field with the 26 images, far images through the root operator), and a shallow tree."""
+    from paper_1612_04082_amd import kfmm
+    lo, L = np.array([-0.3, 0.2, 1.0]), 1.7
+    src, nrm, w, a, b = _cloud(N, lo, L, seed=N)
+    rng = np.random.default_rng(7)
+    trg = lo + rng.uniform(size=(300, 3)) * L
+    plan = kfmm.FmmPlan(_t(src), nrm=_t(nrm), w=_t(w), trg=_t(trg), K=K, G=G, p=p, leaf_max=leaf,
+                        precision=kfmm.FP64, cells=[(lo[0], lo[1], lo[2], L)])
+    info = plan.info()
+    print(f"N={N}: depth {info['depth']}, boxes {info['n_box']}, V {info['n_v_pairs']}, W {info['n_w_pairs']}, "
+          f"X {info['n_x_pairs']}")
+    tol = 1e-5 if p == 8 else 2e-4
+    for kind in (od.DISP, od.STRESS):
+        got = plan.eval(kind, a=_t(a), b=_t(b)).cpu().numpy()
+        ref = op.periodic(kind, trg, src, w, a=a, b=b, nrm=nrm, K=K, G=G, L=L)
+        _check(got, ref, kind, tol, f"N={N}")
+    plan.close()
+
+
+def test_periodic_targets_are_sources(cuda):
+    """Targets = sources: the image n = 0 of the coinciding source is left out, its other images kept."""
+    from paper_1612_04082_amd import kfmm
+    lo, L = np.zeros(3), 1.0
+    src, nrm, w, a, b = _cloud(1500, lo, L, seed=3)
+    plan = kfmm.FmmPlan(_t(src), nrm=_t(nrm), w=_t(w), K=K, G=G, p=8, leaf_max=64, precision=kfmm.FP64,
+                        cells=[(0.0, 0.0, 0.0, L)])
+    rng = np.random.default_rng(2)
+    idx = rng.choice(len(src), 300, replace=False)
+    for kind in (od.DISP, od.STRESS):
+        got = plan.eval(kind, a=_t(a), b=_t(b)).cpu().numpy()[idx]
+        ref = op.periodic(kind, src[idx], src, w, a=a, b=b, nrm=nrm, K=K, G=G, L=L)
+        _check(got, ref, kind, 1e-5, "alias")
+    plan.close()
+
+
+def test_periodic_batch_of_cells(cuda):
+    """Two geometries with different cells (sides 1 and 2.5) in one plan: each sums only its own images."""
+    from paper_1612_04082_amd import kfmm
+    cells = [(0.0, 0.0, 0.0, 1.0), (5.0, -1.0, 0.5, 2.5)]
+    parts = [_cloud(1200, np.array(c[:3]), c[3], seed=11 + i) for i, c in enumerate(cells)]
+    rng = np.random.default_rng(9)
+    trgs = [np.array(c[:3]) + rng.uniform(size=(150, 3)) * c[3] for c in cells]
+    src = np.vstack([q[0] for q in parts]); nrm = np.vstack([q[1] for q in parts])
+    w = np.concatenate([q[2] for q in parts]); a = np.vstack([q[3] for q in parts]); b = np.vstack([q[4] for q in parts])
+    trg = np.vstack(trgs)
+    plan = kfmm.FmmPlan(_t(src), nrm=_t(nrm), w=_t(w), trg=_t(trg), K=K, G=G, p=8, leaf_max=64,
+                        precision=kfmm.FP64, batch_src=[0, 1200, 2400], batch_trg=[0, 150, 300], cells=cells)
+    for kind in (od.DISP, od.STRESS):
+        got = plan.eval(kind, a=_t(a), b=_t(b)).cpu().numpy()
+        for g, c in enumerate(cells):
+            sl, ss = slice(150 * g, 150 * (g + 1)), slice(1200 * g, 1200 * (g + 1))
+            ref = op.periodic(kind, trg[sl], src[ss], w[ss], a=a[ss], b=b[ss], nrm=nrm[ss], K=K, G=G, L=c[3])
+            _check(got[sl], ref, kind, 1e-5, f"cell {g}")
+    plan.close()
+
+
+def test_periodic_rejects_points_outside_cell(cuda):
+    from paper_1612_04082_amd import kfmm
+    src = torch.rand(100, 3, dtype=torch.float64, device="cuda")
+    src[7, 1] = 1.0  # the cell is [0, 1): its upper faces belong to the next image
+    with pytest.raises(kfmm.KfmmError, match="outside its periodic cell"):
+        kfmm.FmmPlan(src, K=K, G=G, p=4, precision=kfmm.FP64, cells=[(0.0, 0.0, 0.0, 1.0)])
