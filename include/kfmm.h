@@ -115,11 +115,8 @@ int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, con
  * The lattice sum of a point force converges only conditionally; it is defined as its Fourier series
  * without the k = 0 term: the periodic field of zero cell mean (a net force per cell is balanced by a
  * uniform body force; the fast evaluation represents that balance only approximately, so single-layer
- * densities should carry no net force per cell).  With the root taken through its equivalent density, the
- * displacement of fmm_eval may differ from that definition by one constant vector per geometry and
- * evaluation (a rigid translation, the cell mean of the difference between the sources' field and their
- * equivalent density's); stresses carry no such constant.  The image n = 0 of a source that coincides with
- * a target is left out, all other images are kept.
+ * densities should carry no net force per cell).  The image n = 0 of a source that coincides with a
+ * target is left out, all other images are kept.
  * Requires opts->precision == KFMM_FP64 (KFMM_E_ARG otherwise).
  */
 int fmm_plan_periodic(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w,

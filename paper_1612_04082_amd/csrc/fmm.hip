@@ -965,6 +965,112 @@ __global__ __launch_bounds__(256) void k_w_eval(const int* __restrict__ pair_b, 
   }
 }
 
+// ----------------------------------------------------------------------- periodic cell-mean constant
+
+// Periodic cells, displacement.  The images beyond the 3 x 3 x 3 block reach the root through its upward
+// equivalent density.  Image by image that is exact outside the equivalent surface, but the zero-mean
+// lattice sum (k = 0 left out) also depends on the field inside: the fast sum exceeds the exact one by
+// the cell mean (1/V) int D of D = (field of the sources) - (field of the equivalent density), a field
+// that vanishes outside the equivalent surface.  Its transform at k -> 0 follows from the force
+// distributions' second moments m2_lbc = sum f_l y_b y_c (y from the root centre; the equivalent density
+// matches the lower moments): with Uhat(k) = [delta/k^2 - k k^T / (2 (1-nu) k^4)] / G and averaging over
+// the directions of k (the limit does not depend on them),
+//   int D_m = -(1 / (2 G)) [dt_m / 3 - (dt_m + 2 ds_m) / (30 (1 - nu))],
+//   t_m = sum_b m2_mbb,  s_m = sum_l m2_lml,  d = sources minus equivalent density.
+// Point forces f at y give t = f |y|^2, s = y (f . y); a double-layer source, a force dipole of tensor
+// Q = C : (w b) (x) n (f = -div(Q delta_y)), gives t = 2 Q y and s = Q y + tr(Q) y.
+// k_per_moments: one workgroup per chunk of a root's sources, the chunk's (t, s) into part[6 * chunk].
+template <typename T>
+__global__ __launch_bounds__(256) void k_per_moments(const int* __restrict__ chunk_root,
+                                                     const int* __restrict__ chunk_b, const int* __restrict__ chunk_e,
+                                                     TreeView tv, const int* __restrict__ leaf_of,
+                                                     const T* __restrict__ spos4, const T* __restrict__ snrm4,
+                                                     const T* __restrict__ dens8, double lam, double G,
+                                                     double* __restrict__ part) {
+  __shared__ double red[256][6];
+  const int c = blockIdx.x, root = chunk_root[c];
+  const int g = tv.geom[root];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = chunk_b[c] + (int)threadIdx.x; i < chunk_e[c]; i += blockDim.x) {
+    double cen[3];
+    box_center(tv.level, tv.ix, tv.iy, tv.iz, tv.geom, tv.root_c, tv.root_R, leaf_of[i], cen);
+    double y[3], f[3];
+    for (int d = 0; d < 3; ++d) {
+      y[d] = cen[d] - tv.root_c[3 * g + d] + (double)spos4[4 * (int64_t)i + d];
+      f[d] = (double)dens8[8 * (int64_t)i + d];
+    }
+    const double yy = y[0] * y[0] + y[1] * y[1] + y[2] * y[2], fy = f[0] * y[0] + f[1] * y[1] + f[2] * y[2];
+    for (int d = 0; d < 3; ++d) {
+      acc[d] += f[d] * yy;
+      acc[3 + d] += y[d] * fy;
+    }
+    if (snrm4) {
+      double wb[3], n[3], bn = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        wb[d] = (double)dens8[8 * (int64_t)i + 4 + d];
+        n[d] = (double)snrm4[4 * (int64_t)i + d];
+        bn += wb[d] * n[d];
+      }
+      double Qy[3];
+      for (int l = 0; l < 3; ++l) {
+        Qy[l] = 0.0;
+        for (int m = 0; m < 3; ++m) Qy[l] += (lam * (l == m ? bn : 0.0) + G * (wb[l] * n[m] + wb[m] * n[l])) * y[m];
+      }
+      const double trQ = 3.0 * lam * bn + 2.0 * G * bn;
+      for (int d = 0; d < 3; ++d) {
+        acc[d] += 2.0 * Qy[d];
+        acc[3 + d] += Qy[d] + trQ * y[d];
+      }
+    }
+  }
+  for (int k = 0; k < 6; ++k) red[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 6; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 6; ++k) part[6 * c + k] = red[0][k];
+}
+
+// One workgroup per root: the chunk sums in a fixed order, minus the equivalent density's moments (point
+// forces phi_e at r_up_equiv * R * surf_e), give the constant, subtracted from the root's target rows of
+// out (caller order [trg_b, trg_e), 3 per row).
+__global__ __launch_bounds__(256) void k_per_shift(const int* __restrict__ roots, const int* __restrict__ chunk_off,
+                                                   const int* __restrict__ trg_b, const int* __restrict__ trg_e,
+                                                   const double* __restrict__ part, TreeView tv,
+                                                   const double* __restrict__ phi_up, const double* __restrict__ surf,
+                                                   int n_eq, int NC, double r_up_equiv, double nu, double G,
+                                                   double* __restrict__ out) {
+  __shared__ double sc[3];
+  const int r = blockIdx.x, root = roots[r];
+  const double R = tv.root_R[tv.geom[root]];
+  if (threadIdx.x == 0) {
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    for (int c = chunk_off[r]; c < chunk_off[r + 1]; ++c)
+      for (int k = 0; k < 6; ++k) m[k] += part[6 * c + k];
+    for (int e = 0; e < n_eq; ++e) {
+      double z[3], f[3];
+      for (int d = 0; d < 3; ++d) {
+        z[d] = r_up_equiv * R * surf[3 * e + d];
+        f[d] = phi_up[(size_t)root * NC + 3 * e + d];
+      }
+      const double zz = z[0] * z[0] + z[1] * z[1] + z[2] * z[2], fz = f[0] * z[0] + f[1] * z[1] + f[2] * z[2];
+      for (int d = 0; d < 3; ++d) {
+        m[d] -= f[d] * zz;
+        m[3 + d] -= z[d] * fz;
+      }
+    }
+    const double V = 8.0 * R * R * R;
+    for (int d = 0; d < 3; ++d)
+      sc[d] = -(m[d] / 3.0 - (m[d] + 2.0 * m[3 + d]) / (30.0 * (1.0 - nu))) / (2.0 * G * V);
+  }
+  __syncthreads();
+  for (int i = trg_b[r] + (int)threadIdx.x; i < trg_e[r]; i += blockDim.x)
+    for (int d = 0; d < 3; ++d) out[3 * (int64_t)i + d] -= sc[d];
+}
+
 // ------------------------------------------------------------------------------------------ plan
 
 static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int tile_cols = kGemmBN) {
@@ -1273,6 +1379,33 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     for (int b = t.level_start[0]; b < t.level_start[1]; ++b)
       if (hs(b) && ht(b)) c.add(0, b, b);
     P->job_per = upload_job(P->arena, c, s);
+    // cell-mean constant of the displacement: roots with sources and targets, their sources in chunks
+    std::vector<int> roots, coff = {0}, tb_, te_, cb, ce, cr;
+    const int kChunk = 8192;
+    for (int b = t.level_start[0]; b < t.level_start[1]; ++b) {
+      if (!hs(b) || !ht(b)) continue;
+      const int g = t.h_geom[b];
+      const std::vector<int64_t>& bt2 = P->alias ? bs : bt;
+      roots.push_back(b);
+      tb_.push_back((int)bt2[g]);
+      te_.push_back((int)bt2[g + 1]);
+      for (int i0 = t.h_src_b[b]; i0 < t.h_src_e[b]; i0 += kChunk) {
+        cb.push_back(i0);
+        ce.push_back(std::min(i0 + kChunk, t.h_src_e[b]));
+        cr.push_back(b);
+      }
+      coff.push_back((int)cb.size());
+    }
+    P->per_n_roots = (int)roots.size();
+    P->per_n_chunks = (int)cb.size();
+    P->per_root = upload_vec(P->arena, roots, s);
+    P->per_chunk_off = upload_vec(P->arena, coff, s);
+    P->per_trg_b = upload_vec(P->arena, tb_, s);
+    P->per_trg_e = upload_vec(P->arena, te_, s);
+    P->per_chunk_b = upload_vec(P->arena, cb, s);
+    P->per_chunk_e = upload_vec(P->arena, ce, s);
+    P->per_chunk_root = upload_vec(P->arena, cr, s);
+    P->per_part = P->arena.get<double>(6 * (size_t)std::max(1, P->per_n_chunks));
   }
   // W pairs and their output slots
   {
@@ -1745,6 +1878,15 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   else
     w_eval(s);
   leaf_eval(1, s);
+  if (P.periodic && kind == KFMM_DISP && P.per_n_roots) {  // zero cell mean (the k = 0 term left out)
+    hipLaunchKernelGGL(k_per_moments<T>, dim3(P.per_n_chunks), dim3(256), 0, s, P.per_chunk_root, P.per_chunk_b,
+                       P.per_chunk_e, P.tv, t.leaf_of_src, spos, P.has_nrm ? snrm : (const T*)nullptr, dens,
+                       P.el.K - 2.0 * P.el.G / 3.0, P.el.G, P.per_part);
+    hipLaunchKernelGGL(k_per_shift, dim3(P.per_n_roots), dim3(256), 0, s, P.per_root, P.per_chunk_off, P.per_trg_b,
+                       P.per_trg_e, P.per_part, P.tv, (const double*)P.phi_up, D.surf, n_eq, NC, 1.05, P.el.nu,
+                       P.el.G, out);
+    KFMM_HIP(hipGetLastError());
+  }
   mark(KFMM_N_PHASES);
   finish_profile(P);
 }

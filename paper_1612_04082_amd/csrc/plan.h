@@ -41,6 +41,12 @@ struct Plan {
   // to the root's downward check potential
   bool periodic = false;
   GemmJob job_per;
+  // periodic displacement: the cell-mean constant per root (second moments of the sources in chunks of
+  // sources, then per root with the equivalent density), subtracted from the root's target rows
+  int per_n_roots = 0, per_n_chunks = 0;
+  int *per_root = nullptr, *per_chunk_off = nullptr, *per_trg_b = nullptr, *per_trg_e = nullptr;
+  int *per_chunk_b = nullptr, *per_chunk_e = nullptr, *per_chunk_root = nullptr;
+  double* per_part = nullptr;  // 6 per chunk
   Arena arena;
   Tree tree;
   TreeView tv{};
