@@ -224,6 +224,16 @@ typedef struct {
                              the 16-point blocks the fast summation applies */
   double near_radius;     /* a pair (t, e), t != e, is near when |c_t - c_e|^2 < near_radius^2 l_e^2 (c:
                              centroids, l_e: longest edge of e); 0 -> 1.5 */
+  const double* cell;     /* (host) NULL for a body in free space, or 4 doubles (lower corner x, y, z, side L):
+                             the surface repeats over the lattice L Z^3 and every integral runs over the
+                             infinite periodic surface (Sec. 4.3, periodic cell of a metamaterial; products
+                             through fmm_plan_periodic, so fmm.precision must be KFMM_FP64).  With the
+                             superposition formulation a cell of cavities under a homogeneous stress s^h is
+                             the pure traction problem with bc_val = -s^h n on every element: its solution is
+                             the periodic fluctuation field (zero cell mean), added to s^h for the total
+                             stress.  Every quadrature point and centroid must lie in [c, c + L)^3 (a
+                             face on an upper face of the cell is given on the lower one); near_levels must
+                             be 0 and precond KFMM_PC_NONE (both are built for free space). */
 } bem_problem;
 
 typedef struct {
@@ -301,8 +311,9 @@ int bem_stress(const bem_problem* prob, const double* u_full, const double* t_fu
 int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const double* x, double* y, void* stream);
 
 /*
- * bem_near_pairs -- the near pairs of prob (near_radius as in bem_problem; near_levels is ignored), sorted by
- * collocation element t, then by source element e.  *count (host) receives their number; pairs (device,
+ * bem_near_pairs -- the near pairs of prob (near_radius as in bem_problem; near_levels is ignored; a periodic
+ * cell is KFMM_E_ARG: pairs across the cell faces are not searched), sorted by collocation element t, then by
+ * source element e.  *count (host) receives their number; pairs (device,
  * 2 x count int32 as (t, e) rows) may be NULL to query the count, else it must hold *count_capacity pairs
  * (KFMM_E_ARG if fewer).  Synchronises the stream.
  */

@@ -242,14 +242,21 @@ def gmres(matvec, b, x0=None, tol=1e-6, restart=50, max_iter=2000):
         x = x + V[:k].T @ y
 
 
-def _rows(tri, a_el, b_el, rows, K, G, nthreads):
+def _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L=None):
     """Rows of U(a) + P(b) + 1/2 b at the collocation points `rows`, element densities a_el, b_el (T x 3):
     the quadrature sum over every element's 16 points (coincident pair skipped), with the element's own
-    quadrature terms replaced by its closed-form self block, plus the free term."""
+    quadrature terms replaced by its closed-form self block, plus the free term.  cell_L: the surface
+    repeats with period cell_L (Sec. 4.3): the quadrature sum runs over every lattice image (oracle.periodic,
+    the k = 0 reading) and only the element's own n = 0 terms are replaced."""
     qp, qn, qw, qe = quadrature(tri)
     cen = tri_geometry(tri)[0]
     rows = np.asarray(rows)
-    out = od.direct(od.DISP, cen[rows], qp, qw, a=a_el[qe], b=b_el[qe], nrm=qn, K=K, G=G, nthreads=nthreads)
+    if cell_L is None:
+        out = od.direct(od.DISP, cen[rows], qp, qw, a=a_el[qe], b=b_el[qe], nrm=qn, K=K, G=G, nthreads=nthreads)
+    else:
+        from . import periodic as opd
+        out = opd.periodic(od.DISP, cen[rows], qp, qw, a=a_el[qe], b=b_el[qe], nrm=qn, K=K, G=G, L=cell_L,
+                           nthreads=nthreads)
     for i, r in enumerate(rows):
         sl = slice(16 * r, 16 * r + 16)
         own = od.direct(od.DISP, cen[r:r + 1], qp[sl], qw[sl], a=a_el[qe[sl]], b=b_el[qe[sl]], nrm=qn[sl], K=K, G=G)
@@ -258,8 +265,9 @@ def _rows(tri, a_el, b_el, rows, K, G, nthreads):
     return out
 
 
-def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0):
-    """Rows of A x (eq. num2, solver units as in DenseBEM) by direct FP64 sums, for large meshes.
+def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0, cell_L=None):
+    """Rows of A x (eq. num2, solver units as in DenseBEM) by direct FP64 sums, for large meshes (cell_L: the
+    periodic surface of a cell of that side, see _rows).
 
     Unknown layout as DenseBEM: u where the traction is prescribed, t / scale_t where the displacement is
     prescribed, scale_t = -G / l; A x = 1/2 u_unk + P u_unk - U t_unk.
@@ -272,11 +280,12 @@ def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0):
     t_unk = bc == 0
     a_el = np.where(t_unk, -scale_t * x, 0.0)   # -t for traction unknowns
     b_el = np.where(t_unk, 0.0, x)              #  u for displacement unknowns
-    return _rows(tri, a_el, b_el, rows, K, G, nthreads)
+    return _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L)
 
 
-def rhs_rows(tri, bc_type, bc_val, rows, K, G, nthreads=0):
-    """Rows of the right-hand side b = U t_known - P u_known - 1/2 u_known (eq. num2) by direct FP64 sums."""
+def rhs_rows(tri, bc_type, bc_val, rows, K, G, nthreads=0, cell_L=None):
+    """Rows of the right-hand side b = U t_known - P u_known - 1/2 u_known (eq. num2) by direct FP64 sums
+    (cell_L as in matvec_rows)."""
     tri = np.ascontiguousarray(tri, dtype=np.float64)
     T = tri.shape[0]
     bc = np.asarray(bc_type).reshape(T, 3)
@@ -284,4 +293,4 @@ def rhs_rows(tri, bc_type, bc_val, rows, K, G, nthreads=0):
     u_known = bc == 0
     a_el = np.where(u_known, 0.0, y)    # t where the traction is prescribed
     b_el = np.where(u_known, -y, 0.0)   # -u where the displacement is prescribed
-    return _rows(tri, a_el, b_el, rows, K, G, nthreads)
+    return _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L)

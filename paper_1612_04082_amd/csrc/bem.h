@@ -1,6 +1,7 @@
 // Collocation BEM system on the device (see bem.hip).
 #pragma once
 #include <memory>
+#include <vector>
 
 #include "../../include/kfmm.h"
 #include "common.h"
@@ -10,6 +11,11 @@
 namespace kfmm {
 
 struct TwoLevelPC;
+
+// The plan's cell list of a problem: empty in free space, the periodic cell otherwise.
+inline std::vector<double> problem_cells(const bem_problem& p) {
+  return p.cell ? std::vector<double>(p.cell, p.cell + 4) : std::vector<double>();
+}
 
 // Near pairs (t, e) of the near-singular quadrature (nearfield.hip): CSR by t (off[T + 1], idx sorted by e)
 // and the row of every entry.

@@ -371,7 +371,7 @@ BemSystem::BemSystem(const bem_problem& p, const fmm_opts& fo, hipStream_t s) : 
   // 61k-element cantilever stalls near 2.6e-6, with 1e-7 GMRES reaches 1e-6 in 157 steps.
   if (o.svd_eps == 0) o.svd_eps = 1e-7;
   std::vector<int64_t> bsrc = {0, NQ}, btrg = {0, T};
-  plan.reset(plan_create(qp, qn, qw, NQ, cen, T, bsrc, btrg, o, s));
+  plan.reset(plan_create(qp, qn, qw, NQ, cen, T, bsrc, btrg, o, s, problem_cells(p)));
   a16 = arena.get<double>(3 * NQ);
   b16 = arena.get<double>(3 * NQ);
   ae = arena.get<double>(n);
@@ -652,7 +652,7 @@ void stress_from_boundary(const bem_problem& p, const double* u, const double* t
   o.K = p.K;
   o.G = p.G;
   std::vector<int64_t> bs = {0, NQ}, bt = {0, M};
-  std::unique_ptr<Plan> plan(plan_create(qp, qn, qw, NQ, trg, M, bs, bt, o, s));
+  std::unique_ptr<Plan> plan(plan_create(qp, qn, qw, NQ, trg, M, bs, bt, o, s, problem_cells(p)));
   plan_eval(*plan, KFMM_STRESS, da, db, out, s);
   KFMM_HIP(hipStreamSynchronize(s));
 }

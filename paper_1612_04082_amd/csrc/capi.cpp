@@ -203,6 +203,12 @@ static void check_problem(const bem_problem* p) {
   KFMM_REQUIRE(p->near_levels >= 0 && p->near_levels <= 5, "near_levels must be in [0, 5]");
   KFMM_REQUIRE(std::isfinite(p->near_radius) && p->near_radius >= 0 && p->near_radius < 16,
                "near_radius must be in [0, 16)");
+  if (p->cell) {
+    KFMM_REQUIRE(std::isfinite(p->cell[0]) && std::isfinite(p->cell[1]) && std::isfinite(p->cell[2]) &&
+                     std::isfinite(p->cell[3]) && p->cell[3] > 0,
+                 "cell: finite lower corner and side > 0 required");
+    KFMM_REQUIRE(p->near_levels == 0, "near_levels must be 0 for a periodic cell");
+  }
 }
 
 extern "C" int bem_near_pairs(const bem_problem* prob, int64_t* count, int32_t* pairs, int64_t count_capacity,
@@ -213,6 +219,7 @@ extern "C" int bem_near_pairs(const bem_problem* prob, int64_t* count, int32_t* 
     KFMM_REQUIRE(std::isfinite(prob->near_radius) && prob->near_radius >= 0 && prob->near_radius < 16,
                  "near_radius must be in [0, 16)");
     KFMM_REQUIRE(count != nullptr, "count is NULL");
+    KFMM_REQUIRE(prob->cell == nullptr, "near pairs are not searched across the faces of a periodic cell");
     hipStream_t s = (hipStream_t)stream;
     const int64_t T = prob->n_tri, NQ = 16 * T;
     Arena a;
@@ -253,6 +260,8 @@ extern "C" int bem_solve(const bem_problem* prob, const bem_opts* opts, const do
     hipStream_t s = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
     KFMM_REQUIRE(opts->precond == KFMM_PC_NONE || opts->precond == KFMM_PC_TWO_LEVEL, "unknown preconditioner");
+    KFMM_REQUIRE(opts->precond == KFMM_PC_NONE || prob->cell == nullptr,
+                 "the two-level preconditioner is built for free space (cell must be NULL)");
     BemSystem sys(*prob, opts->fmm, s);
     if (opts->precond == KFMM_PC_TWO_LEVEL) {
       sys.pc = std::make_unique<TwoLevelPC>();
@@ -354,6 +363,7 @@ extern "C" int bem_precond_apply(const bem_problem* prob, const bem_opts* opts, 
     check_problem(prob);
     KFMM_REQUIRE(opts && v && y, "opts, v or y is NULL");
     KFMM_REQUIRE(opts->precond == KFMM_PC_TWO_LEVEL, "bem_precond_apply needs opts->precond = KFMM_PC_TWO_LEVEL");
+    KFMM_REQUIRE(prob->cell == nullptr, "the two-level preconditioner is built for free space (cell must be NULL)");
     KFMM_REQUIRE(v != y, "v and y must not overlap");
     hipStream_t s = (hipStream_t)stream;
     BemSystem sys(*prob, opts->fmm, s);

@@ -43,7 +43,8 @@ class FmmInfo(ctypes.Structure):
 class BemProblem(ctypes.Structure):
     _fields_ = [("n_tri", ctypes.c_int64), ("tri_xyz", ctypes.c_void_p), ("bc_type", ctypes.c_void_p),
                 ("bc_val", ctypes.c_void_p), ("K", ctypes.c_double), ("G", ctypes.c_double),
-                ("near_levels", ctypes.c_int), ("near_radius", ctypes.c_double)]
+                ("near_levels", ctypes.c_int), ("near_radius", ctypes.c_double),
+                ("cell", ctypes.POINTER(ctypes.c_double))]
 
 
 class BemOpts(ctypes.Structure):
@@ -296,26 +297,36 @@ def selftest_gemm(precision, A, X, Y, op, cols_in, cols_out, scale=None, mode=0,
                                _stream()))
 
 
-def _problem(tri, bc_type, bc_val, K, G, near_levels=0, near_radius=0.0):
+def _problem(tri, bc_type, bc_val, K, G, near_levels=0, near_radius=0.0, cell=None):
+    """cell: None (free space) or (x0, y0, z0, side) of a periodic cubic cell."""
     if not (bc_type.is_cuda and bc_type.dtype == torch.int8 and bc_type.is_contiguous()):
         raise TypeError("bc_type must be a contiguous int8 CUDA tensor")
     T = int(tri.shape[0])
     if tuple(tri.shape[1:]) != (3, 3) or tuple(bc_type.shape) != (T, 3):
         raise ValueError("tri must be (T,3,3) and bc_type (T,3)")
-    return BemProblem(T, _dptr(tri, "tri").value, ctypes.c_void_p(bc_type.data_ptr()).value,
-                      _dptr(bc_val, "bc_val", 3, T).value, K, G, near_levels, near_radius)
+    cell_arr = None
+    if cell is not None:
+        if len(cell) != 4:
+            raise ValueError("cell must be (x0, y0, z0, side)")
+        cell_arr = (ctypes.c_double * 4)(*[float(v) for v in cell])
+    pr = BemProblem(T, _dptr(tri, "tri").value, ctypes.c_void_p(bc_type.data_ptr()).value,
+                    _dptr(bc_val, "bc_val", 3, T).value, K, G, near_levels, near_radius,
+                    ctypes.cast(cell_arr, ctypes.POINTER(ctypes.c_double)) if cell_arr is not None else None)
+    pr._cell_keep = cell_arr  # the C side reads the cell through this pointer
+    return pr
 
 
 def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_iter=2000, x0=None, p=8,
               leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False, x0_alt=None,
-              precond=PC_NONE, pc_fine=0, pc_coarse=0, near_levels=0, near_radius=0.0):
+              precond=PC_NONE, pc_fine=0, pc_coarse=0, near_levels=0, near_radius=0.0, cell=None):
     """bem_solve on torch tensors: tri (T,3,3) f64, bc_type (T,3) int8, bc_val (T,3) f64, all on the GPU.
+    cell: None, or (x0, y0, z0, side) of a periodic cell (needs precision=FP64).
 
     Returns (x, u, t, stats) with x the unknowns (physical units) and u, t the full boundary data."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
-    prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius)
+    prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius, cell)
     alt = _dptr(x0_alt, "x0_alt", 3, int(tri.shape[0]))
     opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0),
                    alt.value if alt is not None else None, precond, pc_fine, pc_coarse)
@@ -352,12 +363,13 @@ def bem_precond_apply(tri, bc_type, bc_val, v, K=None, G=1.0, p=8, leaf_max=128,
     return y, {k: getattr(info, k) for k, _ in BemPcInfo._fields_}
 
 
-def bem_stress(tri, bc_type, bc_val, u, t, trg, K=None, G=1.0, p=8, leaf_max=128, precision=FP32, svd_eps=0.0):
-    """Interior stress (M,6) from boundary u, t (eq. stress_1) at trg (M,3)."""
+def bem_stress(tri, bc_type, bc_val, u, t, trg, K=None, G=1.0, p=8, leaf_max=128, precision=FP32, svd_eps=0.0,
+               cell=None):
+    """Interior stress (M,6) from boundary u, t (eq. stress_1) at trg (M,3); cell as in bem_solve."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
-    prob = _problem(tri, bc_type, bc_val, K, G)
+    prob = _problem(tri, bc_type, bc_val, K, G, cell=cell)
     fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
     M = int(trg.shape[0])
     out = torch.empty((M, 6), dtype=torch.float64, device=trg.device)
@@ -382,12 +394,12 @@ def bem_quadrature(tri):
 
 
 def bem_matvec(tri, bc_type, bc_val, x=None, which=0, K=None, G=1.0, p=8, leaf_max=128, precision=FP32,
-               svd_eps=0.0, near_levels=0, near_radius=0.0):
-    """y = A x (which=0, x in solver units) or the right-hand side B y (which=1)."""
+               svd_eps=0.0, near_levels=0, near_radius=0.0, cell=None):
+    """y = A x (which=0, x in solver units) or the right-hand side B y (which=1); cell as in bem_solve."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
-    prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius)
+    prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius, cell)
     fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
     y = torch.empty((int(tri.shape[0]), 3), dtype=torch.float64, device=tri.device)
     check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3, int(tri.shape[0])),

@@ -16,7 +16,10 @@ Shapes:
                                centre into 4 triangles (Sec. 3: 24 N^2 triangles for the N-cube);
   * box beam                -- the 120 x 20 x 20 beam tiled by squares of side 20/11;
   * cantilever with holes   -- 8:1:1 beam voxelised, random spherical holes (Sec. 4.1 shape family);
-  * periodic-cell bodies    -- unit cube minus random ellipsoidal inclusions (Sec. 4.3 shape family).
+  * periodic-cell bodies    -- unit cube minus random ellipsoidal inclusions (Sec. 4.3 shape family);
+  * periodic cavity surface -- the void/solid faces of a voxel cell repeated over the lattice (Sec. 4.3:
+                               the cell's own faces are not boundary), with a spherical cavity as the
+                               paper's initial guess.
 """
 import numpy as np
 
@@ -88,6 +91,52 @@ def surface_from_voxels(M, h=1.0, origin=(0.0, 0.0, 0.0)):
     tris = quads_to_tris(quads)
     rep = lambda x: np.repeat(x, 4, axis=0)
     return dict(tri=tris, axis=rep(axes), sign=rep(signs), owner=rep(owners))
+
+
+def periodic_voxel_surface(M, h=1.0, origin=(0.0, 0.0, 0.0)):
+    """Faces between filled and empty voxels of a cell repeated periodically (neighbours wrap around), split
+    into 4 triangles each, counter-clockwise seen from the void (normals point out of the material).  A
+    face on the upper plane of an axis (between the last layer and the first layer's image) is placed on
+    the lower plane, so every face lies in [origin, origin + n h) up to its edges."""
+    M = np.asarray(M, dtype=bool)
+    origin = np.asarray(origin, dtype=np.float64)
+    quads, axes, signs, owners = [], [], [], []
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for s in (+1, -1):
+            nb = np.roll(M, -s, axis=a)  # periodic neighbour across the face
+            idx = np.argwhere(M & ~nb)
+            if idx.size == 0:
+                continue
+            base = idx.astype(np.float64)
+            base[:, a] += 1.0 if s > 0 else 0.0
+            base[:, a] = np.where(base[:, a] >= M.shape[a], base[:, a] - M.shape[a], base[:, a])
+            corners = np.zeros((idx.shape[0], 4, 3))
+            offs = [(0, 0), (1, 0), (1, 1), (0, 1)]
+            if s < 0:
+                offs = offs[::-1]
+            for q, (db, dc) in enumerate(offs):
+                p = base.copy()
+                p[:, b] += db
+                p[:, c] += dc
+                corners[:, q] = origin + h * p
+            quads.append(corners)
+            axes.append(np.full(idx.shape[0], a))
+            signs.append(np.full(idx.shape[0], s))
+            owners.append(idx)
+    quads = np.concatenate(quads)
+    rep = lambda x: np.repeat(np.concatenate(x), 4, axis=0)
+    return dict(tri=quads_to_tris(quads), axis=rep(axes), sign=rep(signs), owner=rep(owners))
+
+
+def cavity_cell(n, radius, center=(0.5, 0.5, 0.5)):
+    """n^3 voxels of a unit cell, solid except a ball of the given radius (voxel centres inside it are
+    void; the ball wraps around the cell faces when it crosses them)."""
+    xs = (np.arange(n) + 0.5) / n
+    X, Y, Z = np.meshgrid(xs, xs, xs, indexing="ij")
+    d = [np.abs(P - c) for P, c in zip((X, Y, Z), center)]
+    d = [np.minimum(q, 1.0 - q) for q in d]  # periodic distance
+    return (d[0] ** 2 + d[1] ** 2 + d[2] ** 2) > radius * radius
 
 
 def cube_mesh(N):
