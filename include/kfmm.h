@@ -369,6 +369,26 @@ int alg1_refine(const alg1_grid* grid, const uint8_t* vox, int block, const doub
 int alg1_expand(const alg1_grid* grid, const uint8_t* vox, int block, const double* td_coarse, int64_t n_coarse,
                 double C, const double* td_fine, int64_t n_fine, double* td_out, void* stream);
 
+/* Periodic cell of a metamaterial (Sec. 4.3), the design a cubic cell [0, nx h) x [0, ny h) x [0, nz h)
+ * repeated over the lattice (the cell's own faces are not boundary):
+ * alg1_cell_surface -- the void/material faces with neighbours taken periodically (a voxel of the last layer
+ *   faces the first layer's image), in alg1_surface's classes, order and corner convention; a face on an
+ *   upper plane of the cell is emitted on the lower one (coordinate 0), so every quadrature point and
+ *   centroid lies in the cell.  Every element gets the traction of the superposition formulation,
+ *   bc_type 1, bc_val = -sig_h n (sig_h host, 6 values xx, yy, zz, yz, xz, xy; n the face normal out of
+ *   the material): the problem of the fluctuation field under the homogeneous stress sig_h.
+ * alg1_cell_td -- the topological derivative (eq. deriv) of the total stress sig6 + sig_h at M points.
+ * alg1_cell_update -- the single-iteration rule of the paper's metamaterial example: keep the material
+ *   with the largest td so that round(alpha nx ny nz) voxels stay filled (td one value per filled voxel in
+ *   linear order, n_td their number; ties by linear order; nothing is removed when the design already
+ *   holds no more).  out (device, must not alias vox) receives the new design, *n_filled (host, may be
+ *   NULL) its number of filled voxels. */
+int alg1_cell_surface(const alg1_grid* grid, const uint8_t* vox, const double* sig_h, int64_t* n_tri, double* tri,
+                      int8_t* bc_type, double* bc_val, int32_t* owner, int64_t capacity, void* stream);
+int alg1_cell_td(const double* sig6, int64_t M, const double* sig_h, double K, double G, double* td, void* stream);
+int alg1_cell_update(const alg1_grid* grid, const uint8_t* vox, const double* td, int64_t n_td, double alpha,
+                     uint8_t* out, int64_t* n_filled, void* stream);
+
 /* alg1_energy -- compliance integrand: *psi (host) = sum over the n stresses (n x 6, device) of
  * (1 / 2E) [(1 + nu) sigma:sigma - nu (tr sigma)^2] (fixed summation order); times h^3 it is the compliance
  * of a voxel design evaluated at the voxel centres. */

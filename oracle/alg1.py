@@ -34,6 +34,17 @@ adaptive sampling with blocks of b^3 voxels (the paper's two-scale grid, coarse 
     expand(M, b, td_coarse, refined, td_fine)
                           one value per filled voxel: its own fine value in a refined block, else its block's
                           coarse value; update() then applies the rule to this field.
+Periodic cell of a metamaterial (Sec. 4.3; the cell repeats over the lattice and its own faces are no
+boundary):
+cell_surface(M, h, sig_h)
+    The faces of surface() with the neighbour across a face taken periodically (index modulo the cell size),
+    a face on the upper plane of an axis emitted on the lower plane (coordinate 0; the same face of the
+    periodic surface), and every element loaded with the superposition traction -sig_h n (sig_h a 3 x 3
+    stress, n = s e_a the normal out of the material): the problem of the fluctuation field.
+cell_update(M, td, alpha)
+    The single-iteration rule of the paper's metamaterial example (reading: the volume fraction alpha_c is
+    met exactly): the filled voxels sorted by (td, linear index), the first ones removed until
+    round(alpha n) stay filled (none when no more are filled).
 """
 from collections import deque
 
@@ -201,3 +212,61 @@ def expand(M, b, td_coarse, refined, td_fine):
         blk = (i // b, j // b, k // b)
         out.append(next(it) if refined[blk] else coarse_val[blk])
     return np.array(out, dtype=np.float64)
+
+
+def cell_surface(M, h, sig_h):
+    M = np.asarray(M, dtype=bool)
+    sig_h = np.asarray(sig_h, dtype=np.float64).reshape(3, 3)
+    dims = M.shape
+    tris, vals, owners = [], [], []
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for s in (1, -1):
+            for i in range(dims[0]):
+                for j in range(dims[1]):
+                    for k in range(dims[2]):
+                        if not M[i, j, k]:
+                            continue
+                        idx = [i, j, k]
+                        nb = list(idx)
+                        nb[a] = (nb[a] + s) % dims[a]
+                        if M[nb[0], nb[1], nb[2]]:
+                            continue
+                        base = list(idx)
+                        if s > 0:
+                            base[a] += 1
+                            if base[a] == dims[a]:
+                                base[a] = 0
+                        offs = [(0, 0), (1, 0), (1, 1), (0, 1)]
+                        if s < 0:
+                            offs = offs[::-1]
+                        q = []
+                        for db, dc in offs:
+                            p = list(base)
+                            p[b] += db
+                            p[c] += dc
+                            q.append(np.array([h * float(p[0]), h * float(p[1]), h * float(p[2])]))
+                        cen = (((q[0] + q[1]) + q[2]) + q[3]) / 4.0
+                        n = np.zeros(3)
+                        n[a] = float(s)
+                        t = -(sig_h @ n)
+                        for e in range(4):
+                            tris.append([q[e], q[(e + 1) % 4], cen])
+                            vals.append(t)
+                            owners.append(idx)
+    T = len(tris)
+    return dict(tri=np.array(tris).reshape(T, 3, 3), bc_type=np.ones((T, 3), np.int8),
+                bc_val=np.array(vals).reshape(T, 3), owner=np.array(owners, dtype=np.int64).reshape(T, 3))
+
+
+def cell_update(M, td, alpha):
+    M = np.asarray(M, dtype=bool)
+    td = np.asarray(td, dtype=np.float64)
+    lin = np.flatnonzero(M.reshape(-1))
+    assert td.shape == lin.shape
+    keep = int(round(alpha * M.size))
+    n_remove = max(0, lin.size - keep)
+    order = np.lexsort((np.arange(lin.size), td))  # by td, then linear order
+    out = M.reshape(-1).copy()
+    out[lin[order[:n_remove]]] = False
+    return out.reshape(M.shape)

@@ -19,6 +19,8 @@
 #include "common.h"
 #include "tree.h"
 
+#include <cmath>
+
 namespace kfmm {
 
 namespace {
@@ -74,23 +76,35 @@ __device__ __forceinline__ bool filled(const Grid& g, const uint8_t* vox, int i,
   return g.inside(i, j, k) && vox[g.lin(i, j, k)] != 0;
 }
 
+// Boundary conditions of the emitted faces.  Cantilever (periodic == 0): clamped x = 0 faces of the first
+// layer, the load on the +x faces of the last layer, traction-free elsewhere.  Periodic cell (periodic ==
+// 1): neighbours wrap around the cell, and every face carries the traction -sig n of the superposition
+// formulation (sig row-major 3 x 3, n the face normal out of the material).
+struct FaceBC {
+  int periodic;
+  double load[3];
+  double sig[9];
+};
+
 // flag[c * n + v] = 1 when voxel v has an exposed face of class c
-__global__ void k_face_flags(Grid g, const uint8_t* __restrict__ vox, int* __restrict__ flag) {
+__global__ void k_face_flags(Grid g, const uint8_t* __restrict__ vox, int periodic, int* __restrict__ flag) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= g.n()) return;
   int i, j, k;
   unlin(g, v, i, j, k);
   const bool f = vox[v] != 0;
+  const int dims[3] = {g.nx, g.ny, g.nz};
   for (int c = 0; c < kClasses; ++c) {
     const int a = c / 2, s = (c % 2 == 0) ? 1 : -1;
     int nb[3] = {i, j, k};
     nb[a] += s;
+    if (periodic) nb[a] = (nb[a] + dims[a]) % dims[a];
     flag[c * g.n() + v] = (f && !filled(g, vox, nb[0], nb[1], nb[2])) ? 1 : 0;
   }
 }
 
 __global__ void k_face_emit(Grid g, const uint8_t* __restrict__ vox, const int* __restrict__ flag,
-                            const int64_t* __restrict__ pos, double l0, double l1, double l2, double* __restrict__ tri,
+                            const int64_t* __restrict__ pos, FaceBC fb, double* __restrict__ tri,
                             int8_t* __restrict__ bct, double* __restrict__ bcv, int32_t* __restrict__ owner) {
   const int64_t cv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cv >= kClasses * g.n() || !flag[cv]) return;
@@ -101,6 +115,8 @@ __global__ void k_face_emit(Grid g, const uint8_t* __restrict__ vox, const int* 
   const int a = c / 2, s = (c % 2 == 0) ? 1 : -1, b = (a + 1) % 3, cc = (a + 2) % 3;
   int base[3] = {idx[0], idx[1], idx[2]};
   if (s > 0) base[a] += 1;
+  const int dims[3] = {g.nx, g.ny, g.nz};
+  if (fb.periodic && base[a] == dims[a]) base[a] = 0;  // the upper face of the cell is its lower face
   const int offs[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
   double q[4][3];
   for (int e = 0; e < 4; ++e) {
@@ -112,9 +128,10 @@ __global__ void k_face_emit(Grid g, const uint8_t* __restrict__ vox, const int* 
   }
   double cen[3];
   for (int d = 0; d < 3; ++d) cen[d] = (((q[0][d] + q[1][d]) + q[2][d]) + q[3][d]) / 4.0;
-  const bool clamp = a == 0 && s < 0 && idx[0] == 0;
-  const bool loaded = a == 0 && s > 0 && idx[0] == g.nx - 1;
-  const double load[3] = {l0, l1, l2};
+  const bool clamp = !fb.periodic && a == 0 && s < 0 && idx[0] == 0;
+  const bool loaded = !fb.periodic && a == 0 && s > 0 && idx[0] == g.nx - 1;
+  double val[3];
+  for (int d = 0; d < 3; ++d) val[d] = fb.periodic ? -(double)s * fb.sig[3 * d + a] : (loaded ? fb.load[d] : 0.0);
   const int64_t t0 = 4 * pos[cv];
   for (int e = 0; e < 4; ++e) {
     const int64_t t = t0 + e;
@@ -123,7 +140,7 @@ __global__ void k_face_emit(Grid g, const uint8_t* __restrict__ vox, const int* 
       tri[9 * t + 3 + d] = q[(e + 1) % 4][d];
       tri[9 * t + 6 + d] = cen[d];
       bct[3 * t + d] = clamp ? 0 : 1;
-      bcv[3 * t + d] = loaded ? load[d] : 0.0;
+      bcv[3 * t + d] = val[d];
       if (owner) owner[3 * t + d] = idx[d];
     }
   }
@@ -330,6 +347,41 @@ __global__ __launch_bounds__(256) void k_energy(const double* __restrict__ sig, 
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// ------------------------------------------------------------------ periodic cell: volume-fraction rule
+
+// Ascending keys <=> ascending values of finite doubles (sign-magnitude bits to an unsigned order; -0 is
+// taken as +0 first).
+__device__ __forceinline__ uint64_t order_key(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x + 0.0);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void k_td_keys(int64_t n, const double* __restrict__ td, uint64_t* __restrict__ key, int* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = order_key(td[i]);
+  idx[i] = (int)i;
+}
+
+// lin[rank] = linear index of the rank-th filled voxel
+__global__ void k_rank_lin(Grid g, const int* __restrict__ flag, const int64_t* __restrict__ pos,
+                           int64_t* __restrict__ lin) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < g.n() && flag[v]) lin[pos[v]] = v;
+}
+
+__global__ void k_copy_u8(int64_t n, const uint8_t* __restrict__ in, uint8_t* __restrict__ out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) out[v] = in[v] != 0 ? 1 : 0;
+}
+
+// the n_remove filled voxels first in (td, rank) order become empty
+__global__ void k_remove_lowest(int64_t n_remove, const int* __restrict__ order, const int64_t* __restrict__ lin,
+                                uint8_t* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_remove) out[lin[order[r]]] = 0;
+}
+
 Grid grid_of(const alg1_grid* g) {
   KFMM_REQUIRE(g != nullptr, "grid is NULL");
   KFMM_REQUIRE(g->nx > 0 && g->ny > 0 && g->nz > 0 && (int64_t)g->nx * g->ny * g->nz < ((int64_t)1 << 31),
@@ -355,13 +407,12 @@ int64_t scan(Arena& a, const int* flag, int64_t n, int64_t*& pos, hipStream_t s)
 
 }  // namespace
 
-void alg1_surface_impl(const alg1_grid* gp, const uint8_t* vox, const double* load, int64_t* n_tri, double* tri,
-                       int8_t* bct, double* bcv, int32_t* owner, int64_t capacity, hipStream_t s) {
-  const Grid g = grid_of(gp);
+static void surface(const Grid& g, const uint8_t* vox, const FaceBC& fb, int64_t* n_tri, double* tri, int8_t* bct,
+                    double* bcv, int32_t* owner, int64_t capacity, hipStream_t s) {
   KFMM_REQUIRE(vox && n_tri, "vox or n_tri is NULL");
   Arena a;
   int* flag = a.get<int>(kClasses * g.n());
-  hipLaunchKernelGGL(k_face_flags, dim3(nblk(g.n(), 256)), dim3(256), 0, s, g, vox, flag);
+  hipLaunchKernelGGL(k_face_flags, dim3(nblk(g.n(), 256)), dim3(256), 0, s, g, vox, fb.periodic, flag);
   KFMM_HIP(hipGetLastError());
   int64_t* pos = nullptr;
   const int64_t faces = scan(a, flag, kClasses * g.n(), pos, s);
@@ -369,11 +420,36 @@ void alg1_surface_impl(const alg1_grid* gp, const uint8_t* vox, const double* lo
   if (!tri) return;
   KFMM_REQUIRE(capacity >= 4 * faces, "output holds fewer triangles than the surface has");
   KFMM_REQUIRE(bct && bcv, "bc_type or bc_val is NULL");
-  const double l[3] = {load ? load[0] : 0.0, load ? load[1] : 0.0, load ? load[2] : -1.0};
-  hipLaunchKernelGGL(k_face_emit, dim3(nblk(kClasses * g.n(), 256)), dim3(256), 0, s, g, vox, flag, pos, l[0], l[1],
-                     l[2], tri, bct, bcv, owner);
+  hipLaunchKernelGGL(k_face_emit, dim3(nblk(kClasses * g.n(), 256)), dim3(256), 0, s, g, vox, flag, pos, fb, tri, bct,
+                     bcv, owner);
   KFMM_HIP(hipGetLastError());
   KFMM_HIP(hipStreamSynchronize(s));
+}
+
+void alg1_surface_impl(const alg1_grid* gp, const uint8_t* vox, const double* load, int64_t* n_tri, double* tri,
+                       int8_t* bct, double* bcv, int32_t* owner, int64_t capacity, hipStream_t s) {
+  const Grid g = grid_of(gp);
+  FaceBC fb{};
+  fb.periodic = 0;
+  fb.load[0] = load ? load[0] : 0.0;
+  fb.load[1] = load ? load[1] : 0.0;
+  fb.load[2] = load ? load[2] : -1.0;
+  surface(g, vox, fb, n_tri, tri, bct, bcv, owner, capacity, s);
+}
+
+void alg1_cell_surface_impl(const alg1_grid* gp, const uint8_t* vox, const double* sig_h, int64_t* n_tri,
+                            double* tri, int8_t* bct, double* bcv, int32_t* owner, int64_t capacity, hipStream_t s) {
+  const Grid g = grid_of(gp);
+  KFMM_REQUIRE(sig_h != nullptr, "sig_h is NULL");
+  FaceBC fb{};
+  fb.periodic = 1;
+  const int vi[6] = {0, 1, 2, 1, 0, 0}, vj[6] = {0, 1, 2, 2, 2, 1};  // Voigt xx, yy, zz, yz, xz, xy
+  for (int c = 0; c < 6; ++c) {
+    KFMM_REQUIRE(std::isfinite(sig_h[c]), "sig_h must be finite");
+    fb.sig[3 * vi[c] + vj[c]] = sig_h[c];
+    fb.sig[3 * vj[c] + vi[c]] = sig_h[c];
+  }
+  surface(g, vox, fb, n_tri, tri, bct, bcv, owner, capacity, s);
 }
 
 void alg1_centres_impl(const alg1_grid* gp, const uint8_t* vox, int64_t* n, double* pts, int64_t capacity,
@@ -436,6 +512,44 @@ void alg1_update_impl(const alg1_grid* gp, const uint8_t* vox, const double* td,
   int64_t* pos = nullptr;
   const int64_t kept = scan(a, flag, n, pos, s);
   if (n_out) *n_out = kept;
+}
+
+void alg1_cell_update_impl(const alg1_grid* gp, const uint8_t* vox, const double* td, int64_t n_td, double alpha,
+                           uint8_t* out, int64_t* n_out, hipStream_t s) {
+  const Grid g = grid_of(gp);
+  KFMM_REQUIRE(vox && td && out && vox != out, "vox, td or out is NULL, or out aliases vox");
+  KFMM_REQUIRE(std::isfinite(alpha) && alpha > 0 && alpha <= 1, "alpha must be in (0, 1]");
+  Arena a;
+  const int64_t n = g.n();
+  int* flag = a.get<int>(n);
+  hipLaunchKernelGGL(k_filled_flags, dim3(nblk(n, 256)), dim3(256), 0, s, n, vox, flag);
+  int64_t* rank = nullptr;
+  const int64_t nf = scan(a, flag, n, rank, s);
+  KFMM_REQUIRE(nf > 0, "the design holds no material");
+  KFMM_REQUIRE(n_td == nf, "td must hold one value per filled voxel");
+  double* mm = a.get<double>(2);
+  hipLaunchKernelGGL(k_minmax, dim3(1), dim3(256), 0, s, td, nf, mm);
+  double hmm[2];
+  KFMM_HIP(hipMemcpyAsync(hmm, mm, sizeof(hmm), hipMemcpyDeviceToHost, s));
+  KFMM_HIP(hipStreamSynchronize(s));
+  KFMM_REQUIRE(std::isfinite(hmm[0]) && std::isfinite(hmm[1]), "non-finite topological derivative");
+  const int64_t n_keep = std::llround(alpha * (double)n);
+  const int64_t n_remove = nf > n_keep ? nf - n_keep : 0;
+  int64_t n_pad = 2048;
+  while (n_pad < nf) n_pad *= 2;
+  uint64_t* key = a.get<uint64_t>(n_pad);
+  int* order = a.get<int>(n_pad);
+  hipLaunchKernelGGL(k_td_keys, dim3(nblk(nf, 256)), dim3(256), 0, s, nf, td, key, order);
+  KFMM_HIP(hipGetLastError());
+  sort_keys(key, order, nf, n_pad, s);
+  int64_t* lin = a.get<int64_t>(nf);
+  hipLaunchKernelGGL(k_rank_lin, dim3(nblk(n, 256)), dim3(256), 0, s, g, flag, rank, lin);
+  hipLaunchKernelGGL(k_copy_u8, dim3(nblk(n, 256)), dim3(256), 0, s, n, vox, out);
+  if (n_remove > 0)
+    hipLaunchKernelGGL(k_remove_lowest, dim3(nblk(n_remove, 256)), dim3(256), 0, s, n_remove, order, lin, out);
+  KFMM_HIP(hipGetLastError());
+  KFMM_HIP(hipStreamSynchronize(s));
+  if (n_out) *n_out = nf - n_remove;
 }
 
 void alg1_coarse_impl(const alg1_grid* gp, const uint8_t* vox, int block, int64_t* n, double* pts, int64_t capacity,

@@ -65,8 +65,9 @@ void scale_traction_unknowns(BemSystem& sys, double* x, double factor);
 void stress_from_boundary(const bem_problem& p, const double* u, const double* t, const double* trg, int64_t M,
                           double* out, const fmm_opts& fo, hipStream_t s);
 
-// Pointwise topological derivative (eq. deriv) of M stresses.
-void topological_derivative(const double* sig, int64_t M, const Elastic& el, double* td, hipStream_t s);
+// Pointwise topological derivative (eq. deriv) of M stresses, each plus sig_h (host, 6; NULL for none).
+void topological_derivative(const double* sig, int64_t M, const Elastic& el, double* td, hipStream_t s,
+                            const double* sig_h = nullptr);
 
 // Quadrature expansion only (16 points per triangle, normals, weights, centroids).
 void bem_expand(int64_t T, const double* tri, double* qp, double* qn, double* qw, double* cen, hipStream_t s);

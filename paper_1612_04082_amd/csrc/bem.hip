@@ -663,19 +663,28 @@ namespace kfmm {
 
 // Topological derivative of the compliance at a point with stress sig (eq. deriv; "tr sigma^2" read as the
 // square of the trace).
-__global__ void k_topo_derivative(const double* __restrict__ sig, int64_t M, double E, double nu,
+struct Stress6 {
+  double v[6];
+};
+
+__global__ void k_topo_derivative(const double* __restrict__ sig, int64_t M, double E, double nu, Stress6 off,
                                   double* __restrict__ td) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  const double* s = sig + 6 * i;
+  double s[6];
+  for (int c = 0; c < 6; ++c) s[c] = sig[6 * i + c] + off.v[c];
   double ss = s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
   double tr = s[0] + s[1] + s[2];
   td[i] = 3.0 * (1.0 - nu) / (4.0 * E * (7.0 - 5.0 * nu)) * (10.0 * (1.0 + nu) * ss - (1.0 + 5.0 * nu) * tr * tr);
 }
 
-void topological_derivative(const double* sig, int64_t M, const Elastic& el, double* td, hipStream_t s) {
+void topological_derivative(const double* sig, int64_t M, const Elastic& el, double* td, hipStream_t s,
+                            const double* sig_h) {
   const double E = 9.0 * el.K * el.G / (3.0 * el.K + el.G);
-  hipLaunchKernelGGL(k_topo_derivative, dim3(nblk(M)), dim3(256), 0, s, sig, M, E, el.nu, td);
+  Stress6 off{};
+  if (sig_h)
+    for (int c = 0; c < 6; ++c) off.v[c] = sig_h[c];
+  hipLaunchKernelGGL(k_topo_derivative, dim3(nblk(M)), dim3(256), 0, s, sig, M, E, el.nu, off, td);
   KFMM_HIP(hipGetLastError());
 }
 

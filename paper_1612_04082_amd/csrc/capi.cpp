@@ -303,6 +303,10 @@ void alg1_surface_impl(const alg1_grid*, const uint8_t*, const double*, int64_t*
 void alg1_centres_impl(const alg1_grid*, const uint8_t*, int64_t*, double*, int64_t, hipStream_t);
 void alg1_update_impl(const alg1_grid*, const uint8_t*, const double*, int64_t, double, uint8_t*, int64_t*,
                       hipStream_t);
+void alg1_cell_surface_impl(const alg1_grid*, const uint8_t*, const double*, int64_t*, double*, int8_t*, double*,
+                            int32_t*, int64_t, hipStream_t);
+void alg1_cell_update_impl(const alg1_grid*, const uint8_t*, const double*, int64_t, double, uint8_t*, int64_t*,
+                           hipStream_t);
 void alg1_coarse_impl(const alg1_grid*, const uint8_t*, int, int64_t*, double*, int64_t, hipStream_t);
 void alg1_refine_impl(const alg1_grid*, const uint8_t*, int, const double*, int64_t, double, int64_t*, double*,
                       int64_t, uint8_t*, hipStream_t);
@@ -321,6 +325,19 @@ extern "C" int alg1_surface(const alg1_grid* grid, const uint8_t* vox, const dou
 extern "C" int alg1_centres(const alg1_grid* grid, const uint8_t* vox, int64_t* n, double* pts, int64_t capacity,
                             void* stream) {
   return guarded([&] { alg1_centres_impl(grid, vox, n, pts, capacity, (hipStream_t)stream); });
+}
+
+extern "C" int alg1_cell_surface(const alg1_grid* grid, const uint8_t* vox, const double* sig_h, int64_t* n_tri,
+                                 double* tri, int8_t* bc_type, double* bc_val, int32_t* owner, int64_t capacity,
+                                 void* stream) {
+  return guarded([&] {
+    alg1_cell_surface_impl(grid, vox, sig_h, n_tri, tri, bc_type, bc_val, owner, capacity, (hipStream_t)stream);
+  });
+}
+
+extern "C" int alg1_cell_update(const alg1_grid* grid, const uint8_t* vox, const double* td, int64_t n_td,
+                                double alpha, uint8_t* out, int64_t* n_filled, void* stream) {
+  return guarded([&] { alg1_cell_update_impl(grid, vox, td, n_td, alpha, out, n_filled, (hipStream_t)stream); });
 }
 
 extern "C" int alg1_update(const alg1_grid* grid, const uint8_t* vox, const double* td, int64_t n_td, double C,
@@ -409,6 +426,17 @@ extern "C" int kfmm_topological_derivative(const double* sig6, int64_t M, double
     check_moduli(K, G);
     KFMM_REQUIRE(M >= 0 && (M == 0 || (sig6 && td)), "bad arguments");
     if (M) topological_derivative(sig6, M, Elastic::make(K, G), td, (hipStream_t)stream);
+  });
+}
+
+extern "C" int alg1_cell_td(const double* sig6, int64_t M, const double* sig_h, double K, double G, double* td,
+                            void* stream) {
+  return guarded([&] {
+    check_moduli(K, G);
+    KFMM_REQUIRE(sig_h != nullptr, "sig_h is NULL");
+    for (int c = 0; c < 6; ++c) KFMM_REQUIRE(std::isfinite(sig_h[c]), "sig_h must be finite");
+    KFMM_REQUIRE(M >= 0 && (M == 0 || (sig6 && td)), "bad arguments");
+    if (M) topological_derivative(sig6, M, Elastic::make(K, G), td, (hipStream_t)stream, sig_h);
   });
 }
 

@@ -120,8 +120,12 @@ def load_library():
     L.alg1_refine.argtypes = [gp, vp, ctypes.c_int, vp, i64, ctypes.c_double, ctypes.POINTER(i64), vp, i64, vp, vp]
     L.alg1_expand.argtypes = [gp, vp, ctypes.c_int, vp, i64, ctypes.c_double, vp, i64, vp, vp]
     L.alg1_energy.argtypes = [vp, i64, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+    L.alg1_cell_surface.argtypes = [gp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp, vp, vp, vp, i64,
+                                    vp]
+    L.alg1_cell_td.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double, vp, vp]
+    L.alg1_cell_update.argtypes = [gp, vp, vp, i64, ctypes.c_double, vp, ctypes.POINTER(i64), vp]
     for f in ("alg1_surface", "alg1_centres", "alg1_update", "alg1_coarse_blocks", "alg1_refine", "alg1_expand",
-              "alg1_energy"):
+              "alg1_energy", "alg1_cell_surface", "alg1_cell_td", "alg1_cell_update"):
         getattr(L, f).restype = ctypes.c_int
     L.bem_matvec.restype = ctypes.c_int
     L.bem_quadrature.argtypes = [i64, vp, vp, vp, vp, vp, vp]
@@ -463,6 +467,49 @@ def alg1_surface(vox, h, load=(0.0, 0.0, -1.0)):
                          ctypes.c_void_p(bct.data_ptr()), ctypes.c_void_p(bcv.data_ptr()),
                          ctypes.c_void_p(own.data_ptr()), T, _stream()))
     return dict(tri=tri[:T], bc_type=bct[:T], bc_val=bcv[:T], owner=own[:T])
+
+
+def alg1_cell_surface(vox, h, sig_h):
+    """Void/material faces of a periodic voxel cell with the superposition tractions -sig_h n (sig_h: 6 values
+    xx, yy, zz, yz, xz, xy) as a pure traction problem (dict of device tensors, as alg1_surface)."""
+    L = load_library()
+    g = _grid(vox, h)
+    sh = (ctypes.c_double * 6)(*[float(v) for v in sig_h])
+    n = ctypes.c_int64(0)
+    check(L.alg1_cell_surface(ctypes.byref(g), _vox(vox), sh, ctypes.byref(n), None, None, None, None, 0, _stream()))
+    T = n.value
+    dev = vox.device
+    tri = torch.empty((max(T, 1), 3, 3), dtype=torch.float64, device=dev)
+    bct = torch.empty((max(T, 1), 3), dtype=torch.int8, device=dev)
+    bcv = torch.empty((max(T, 1), 3), dtype=torch.float64, device=dev)
+    own = torch.empty((max(T, 1), 3), dtype=torch.int32, device=dev)
+    check(L.alg1_cell_surface(ctypes.byref(g), _vox(vox), sh, ctypes.byref(n), ctypes.c_void_p(tri.data_ptr()),
+                              ctypes.c_void_p(bct.data_ptr()), ctypes.c_void_p(bcv.data_ptr()),
+                              ctypes.c_void_p(own.data_ptr()), T, _stream()))
+    return dict(tri=tri[:T], bc_type=bct[:T], bc_val=bcv[:T], owner=own[:T])
+
+
+def alg1_cell_td(sig6, sig_h, K=None, G=1.0):
+    """Topological derivative (eq. deriv) of the total stresses sig6 + sig_h (device (M,6) -> (M,))."""
+    if K is None:
+        K = moduli(G, 0.3)
+    M = int(sig6.shape[0])
+    td = torch.empty((M,), dtype=torch.float64, device=sig6.device)
+    sh = (ctypes.c_double * 6)(*[float(v) for v in sig_h])
+    check(load_library().alg1_cell_td(_dptr(sig6, "sig6", 6) if M else None, M, sh, float(K), float(G),
+                                      _dptr(td, "td") if M else None, _stream()))
+    return td
+
+
+def alg1_cell_update(vox, h, td, alpha):
+    """Keep the material with the largest td at round(alpha n) filled voxels; returns (vox_new, n_filled)."""
+    L = load_library()
+    g = _grid(vox, h)
+    out = torch.empty_like(vox)
+    n = ctypes.c_int64(0)
+    check(L.alg1_cell_update(ctypes.byref(g), _vox(vox), _dptr(td, "td"), int(td.numel()), float(alpha),
+                             ctypes.c_void_p(out.data_ptr()), ctypes.byref(n), _stream()))
+    return out, n.value
 
 
 def _points(vox):

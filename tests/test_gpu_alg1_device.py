@@ -131,3 +131,37 @@ def test_adaptive_iterations_run(cuda):
     assert hist[0]["stress_points"] < M0.sum()
     assert hist[2]["alpha"] <= hist[1]["alpha"] <= hist[0]["alpha"] == 1.0
     assert M[0].any() and M[-1].any()
+
+
+@pytest.mark.parametrize("shape,seed,h", [((6, 5, 4), 21, 0.25), ((9, 3, 4), 22, 2.0 / 9.0)])
+def test_cell_surface_matches_oracle(cuda, shape, seed, h):
+    """Periodic cell (Sec. 4.3): random designs (material and voids touching every cell face), bit for bit."""
+    from paper_1612_04082_amd import kfmm
+    rng = np.random.default_rng(seed)
+    M = rng.uniform(size=shape) < 0.6
+    sig = np.array([[1.0, 0.2, -0.3], [0.2, 2.0, 0.5], [-0.3, 0.5, -1.0]])
+    v6 = [sig[0, 0], sig[1, 1], sig[2, 2], sig[1, 2], sig[0, 2], sig[0, 1]]
+    got = kfmm.alg1_cell_surface(_vox(M), h, v6)
+    ref = oa.cell_surface(M, h, sig)
+    print(f"{shape}: {ref['tri'].shape[0]} triangles")
+    for key in ("tri", "bc_type", "bc_val", "owner"):
+        assert np.array_equal(got[key].cpu().numpy(), ref[key]), key
+
+
+def test_cell_td_and_update_match_oracle(cuda):
+    from oracle import td as otd
+    from paper_1612_04082_amd import kfmm
+    rng = np.random.default_rng(23)
+    M = rng.uniform(size=(7, 6, 5)) < 0.8
+    n = int(M.sum())
+    sig = rng.normal(size=(n, 6))
+    sh = [1.0, 1.0, 1.0, 0.0, 0.0, 0.0]
+    K = kfmm.moduli(1.0, 0.3)
+    td = kfmm.alg1_cell_td(torch.tensor(sig, device="cuda"), sh, K=K, G=1.0)
+    ref = otd.topological_derivative(sig + np.array(sh), 2.0 * (1.0 + 0.3), 0.3)
+    assert np.abs(td.cpu().numpy() - ref).max() < 1e-13 * np.abs(ref).max()
+    tdq = np.round(td.cpu().numpy() * 4) / 4  # ties at the cut
+    for alpha in (0.3, 0.55, 0.79, 1.0):
+        out, kept = kfmm.alg1_cell_update(_vox(M), 0.1, torch.tensor(tdq, device="cuda"), alpha)
+        refM = oa.cell_update(M, tdq, alpha)
+        assert np.array_equal(out.cpu().numpy().astype(bool), refM) and kept == int(refM.sum())

@@ -142,3 +142,44 @@ def test_adaptive_matches_uniform_for_block_constant_fields():
     assert np.array_equal(field, td_all)
     assert np.array_equal(oa.update(M, field, 0.35), oa.update(M, td_all, 0.35))
     assert len(fine) < M.sum()
+
+
+@pytest.mark.parametrize("center", [(0.5, 0.5, 0.5), (0.05, 0.5, 0.9)])
+def test_cell_surface_closed_and_equal_to_independent_generator(center):
+    """Periodic cell (Sec. 4.3): the void/material faces of the repeated cell form closed surfaces (area
+    normals sum to zero), equal the separately written generator, and carry -sig_h n."""
+    M = geo.cavity_cell(8, 0.3, center=center)
+    h = 0.125
+    sig = np.array([[1.0, 0.2, -0.3], [0.2, 2.0, 0.5], [-0.3, 0.5, -1.0]])
+    s = oa.cell_surface(M, h, sig)
+    g = geo.periodic_voxel_surface(M, h)
+    assert np.allclose(s["tri"], g["tri"], rtol=0, atol=1e-15) and np.array_equal(s["owner"], g["owner"])
+    tri = s["tri"]
+    cr = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+    assert np.abs(cr.sum(axis=0)).max() < 1e-13
+    n = cr / np.linalg.norm(cr, axis=1)[:, None]
+    assert np.allclose(s["bc_val"], -n @ sig.T, atol=1e-15) and (s["bc_type"] == 1).all()
+    cen = tri.mean(axis=1)
+    assert (cen >= 0).all() and (cen < 1.0).all()  # every element inside the half-open cell
+    if center == (0.5, 0.5, 0.5):  # divergence theorem: the normals point into the cavity
+        assert np.isclose((cen * 0.5 * cr).sum() / 3.0, -(~M).sum() * h ** 3, rtol=1e-12)
+    # a face whose neighbour across the cell face is void: emitted on the lower plane
+    M2 = np.ones((3, 3, 3), bool)
+    M2[0, 1, 1] = False
+    s2 = oa.cell_surface(M2, 1.0, np.eye(3))
+    up = s2["owner"][:, 0] == 2  # voxel (2, 1, 1) faces the void (0, 1, 1) through the cell face x = 3 = 0
+    assert up.any() and np.allclose(s2["tri"][up][:, :, 0], 0.0)
+
+
+def test_cell_update_volume_fraction_and_ties():
+    M = np.ones((4, 3, 2), bool)
+    M[0, 0, 0] = False
+    lin = np.flatnonzero(M.reshape(-1))
+    td = np.array([5.0, 1.0, 1.0, 3.0] + [9.0] * (len(lin) - 4))
+    out = oa.cell_update(M, td, alpha=20.0 / 24.0)  # 23 filled, keep 20: remove the three smallest
+    removed = set(lin) - set(np.flatnonzero(out.reshape(-1)))
+    assert removed == {lin[1], lin[2], lin[3]}
+    out2 = oa.cell_update(M, td, alpha=21.0 / 24.0)  # remove two: the tied pair, by linear order
+    assert set(lin) - set(np.flatnonzero(out2.reshape(-1))) == {lin[1], lin[2]}
+    out3 = oa.cell_update(M, td, alpha=1.0)  # already below the target: nothing removed
+    assert np.array_equal(out3, M)
