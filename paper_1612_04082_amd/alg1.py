@@ -232,3 +232,87 @@ def warm_start_study(M0, n_iter=20, train_from=2, measure_from=11, h=1.0, C=0.02
         r.update(alpha=hh["alpha"], psi=hh["psi"])
     net.close()
     return rec
+
+
+# ---------------------------------------------------------------------------------- periodic cell (Sec. 4.3)
+
+def hashin_shtrikman_bulk(K, G, f_void):
+    """Hashin-Shtrikman upper bound of the bulk modulus of a porous isotropic material (void fraction f)."""
+    return K + f_void / (-1.0 / K + 3.0 * (1.0 - f_void) / (3.0 * K + 4.0 * G))
+
+
+class PeriodicCell:
+    """The metamaterial cell of Sec. 4.3 on the device: a cubic voxel cell repeated over the lattice, the
+    superposition formulation (the fluctuation field carries -s^h n on the void/material faces, the total
+    stress is s^h plus it), hydrostatic s^h for the bulk modulus.
+
+    single_iteration(alpha_c): the paper's single-iteration solution -- solve once on the initial design,
+    topological derivative (eq. deriv) of the total stress at every filled voxel centre, keep the largest
+    values at the volume fraction alpha_c (alg1_cell_surface, bem_solve and bem_stress on the periodic cell,
+    alg1_centres, alg1_cell_td, alg1_cell_update).
+    bulk_modulus(vox): effective bulk modulus of a design: <sigma> = C : [eps_h (1 - f) + (1/V) sum_e A_e
+    sym(u_e (x) n_e)] with the solution u on the faces (n_e out of the material, eps_h the matrix strain of
+    s^h; a rigid translation of u drops out on closed surfaces), K_eff = <sigma>_kk / (3 tr eps_h)."""
+
+    def __init__(self, n, h=None, K=None, G=1.0, p=8, leaf_max=64, tol=1e-6, restart=100, max_iter=400):
+        from paper_1612_04082_amd import kfmm
+        self.kfmm = kfmm
+        self.n = int(n)
+        self.h = 1.0 / n if h is None else float(h)
+        self.L = self.n * self.h
+        self.G = G
+        self.K = kfmm.moduli(G, 0.3) if K is None else K
+        self.cell = (0.0, 0.0, 0.0, self.L)
+        self.sig_h = (1.0, 1.0, 1.0, 0.0, 0.0, 0.0)
+        self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=kfmm.FP64, cell=self.cell)
+        self.solve_kw = dict(self.fmm_kw, tol=tol, restart=restart, max_iter=max_iter)
+
+    def _sync_time(self, t0):
+        torch.cuda.synchronize()
+        return time.time() - t0
+
+    def solve(self, vox):
+        k = self.kfmm
+        t0 = time.time()
+        prob = k.alg1_cell_surface(vox, self.h, self.sig_h)
+        t_surf = self._sync_time(t0)
+        t0 = time.time()
+        x, u, t, st = k.bem_solve(prob["tri"], prob["bc_type"], prob["bc_val"], allow_noconv=True, **self.solve_kw)
+        t_solve = self._sync_time(t0)
+        return prob, u, t, dict(T=int(prob["tri"].shape[0]), gmres=st["iters"], rel_res=st["rel_res"],
+                                converged=bool(st["converged"]), t_surface_s=t_surf, t_solve_s=t_solve)
+
+    def bulk_modulus(self, vox, prob=None, u=None):
+        if prob is None:
+            prob, u, _, rec = self.solve(vox)
+        else:
+            rec = {}
+        tri = prob["tri"].cpu().numpy()
+        uu = u.cpu().numpy()
+        cr = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
+        area_n = 0.5 * cr  # A_e n_e
+        f = 1.0 - float((vox != 0).float().mean().item())
+        V = self.L ** 3
+        eps_h = np.eye(3) / (3.0 * self.K)  # s^h = I
+        E = eps_h * (1.0 - f) + np.einsum("ei,ej->ij", uu, area_n) / V
+        E = 0.5 * (E + E.T)
+        K_eff = self.K * np.trace(E) / np.trace(eps_h)  # <sigma>_kk = 3 K tr E
+        rec.update(void_fraction=f, K_eff=float(K_eff), K_hs=float(hashin_shtrikman_bulk(self.K, self.G, f)))
+        return rec
+
+    def single_iteration(self, M0, alpha_c):
+        k = self.kfmm
+        vox = _dev(M0, torch.uint8)
+        prob, u, t, rec = self.solve(vox)
+        rec.update(self.bulk_modulus(vox, prob, u))
+        t0 = time.time()
+        pts = k.alg1_centres(vox, self.h)
+        sig = k.bem_stress(prob["tri"], prob["bc_type"], prob["bc_val"], u, t, pts, **self.fmm_kw)
+        rec["t_stress_s"] = self._sync_time(t0)
+        rec["stress_points"] = int(pts.shape[0])
+        t0 = time.time()
+        td = k.alg1_cell_td(sig, self.sig_h, K=self.K, G=self.G)
+        new, kept = k.alg1_cell_update(vox, self.h, td, alpha_c)
+        rec["t_update_s"] = self._sync_time(t0)
+        rec["kept"] = kept
+        return new, rec
