@@ -116,8 +116,7 @@ int fmm_plan(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, con
  * without the k = 0 term: the periodic field of zero cell mean (a net force per cell is balanced by a
  * uniform body force; the fast evaluation represents that balance only approximately, so single-layer
  * densities should carry no net force per cell).  The image n = 0 of a source that coincides with a
- * target is left out, all other images are kept.
- * Requires opts->precision == KFMM_FP64 (KFMM_E_ARG otherwise).
+ * target is left out, all other images are kept.  Every precision mode applies.
  */
 int fmm_plan_periodic(kfmm_plan_t* out, const double* src_xyz, const double* src_nrm, const double* src_w,
                       int64_t n_src, const double* trg_xyz, int64_t n_trg, const int64_t* batch_src,

@@ -22,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <tuple>
 
 #include "../../include/kfmm.h"
@@ -89,8 +90,12 @@ struct DeviceOps {
   double* surf = nullptr;  // n_eq x 3
   std::vector<int> m2l_index;
   std::map<double, std::shared_ptr<CompressedM2L>> comp;  // by relative cutoff
-  // periodic cells: the far-image operator of the root (NC x NC, FP64), made on first use
+  // periodic cells, made on first use: the far-image operator T of the root (NC x NC, FP64), the same on
+  // check potentials T UC2UE (FP32) and onto the downward density DC2DE T (FP64), and the second-moment rows
+  // of the upward equivalent density (6 x NC, unit half-width) on phi_up and on qhat_up (times UC2UE)
   double* per_far64 = nullptr;
+  float* per_farq32 = nullptr;
+  double *per_fardn64 = nullptr, *per_mom_phi = nullptr, *per_mom_q = nullptr;
   std::mutex per_mutex;
   Arena arena;
 };
@@ -1034,14 +1039,40 @@ __global__ __launch_bounds__(256) void k_per_moments(const int* __restrict__ chu
     for (int k = 0; k < 6; ++k) part[6 * c + k] = red[0][k];
 }
 
-// One workgroup per root: the chunk sums in a fixed order, minus the equivalent density's moments (point
-// forces phi_e at r_up_equiv * R * surf_e), give the constant, subtracted from the root's target rows of
-// out (caller order [trg_b, trg_e), 3 per row).
+// The equivalent density's (t, s) per root: linear in its upward vector (phi_up, or the check potential
+// qhat_up with UC2UE folded into the rows), eqm[6 r + k] = R^2 sum_j W[k][j] vec[root][j] (W at unit
+// half-width; one workgroup per root, 6 fixed-order block sums).  Taken before the downward pass reuses
+// the upward buffers.
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_per_eqm(const int* __restrict__ roots, const double* __restrict__ W,
+                                                 const TQ* __restrict__ vec, int NC, TreeView tv,
+                                                 double* __restrict__ eqm) {
+  __shared__ double red[256][6];
+  const int r = blockIdx.x, root = roots[r];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int j = threadIdx.x; j < NC; j += blockDim.x) {
+    const double v = (double)vec[(size_t)root * NC + j];
+    for (int k = 0; k < 6; ++k) acc[k] += W[(size_t)k * NC + j] * v;
+  }
+  for (int k = 0; k < 6; ++k) red[threadIdx.x][k] = acc[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 6; ++k) red[threadIdx.x][k] += red[threadIdx.x + st][k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double R = tv.root_R[tv.geom[root]];
+    for (int k = 0; k < 6; ++k) eqm[6 * r + k] = R * R * red[0][k];
+  }
+}
+
+// One workgroup per root: the chunk sums in a fixed order, minus the equivalent density's moments, give
+// the constant, subtracted from the root's target rows of out (caller order [trg_b, trg_e), 3 per row).
 __global__ __launch_bounds__(256) void k_per_shift(const int* __restrict__ roots, const int* __restrict__ chunk_off,
                                                    const int* __restrict__ trg_b, const int* __restrict__ trg_e,
                                                    const double* __restrict__ part, TreeView tv,
-                                                   const double* __restrict__ phi_up, const double* __restrict__ surf,
-                                                   int n_eq, int NC, double r_up_equiv, double nu, double G,
+                                                   const double* __restrict__ eqm, double nu, double G,
                                                    double* __restrict__ out) {
   __shared__ double sc[3];
   const int r = blockIdx.x, root = roots[r];
@@ -1050,18 +1081,7 @@ __global__ __launch_bounds__(256) void k_per_shift(const int* __restrict__ roots
     double m[6] = {0, 0, 0, 0, 0, 0};
     for (int c = chunk_off[r]; c < chunk_off[r + 1]; ++c)
       for (int k = 0; k < 6; ++k) m[k] += part[6 * c + k];
-    for (int e = 0; e < n_eq; ++e) {
-      double z[3], f[3];
-      for (int d = 0; d < 3; ++d) {
-        z[d] = r_up_equiv * R * surf[3 * e + d];
-        f[d] = phi_up[(size_t)root * NC + 3 * e + d];
-      }
-      const double zz = z[0] * z[0] + z[1] * z[1] + z[2] * z[2], fz = f[0] * z[0] + f[1] * z[1] + f[2] * z[2];
-      for (int d = 0; d < 3; ++d) {
-        m[d] -= f[d] * zz;
-        m[3 + d] -= z[d] * fz;
-      }
-    }
+    for (int k = 0; k < 6; ++k) m[k] -= eqm[6 * r + k];
     const double V = 8.0 * R * R * R;
     for (int d = 0; d < 3; ++d)
       sc[d] = -(m[d] / 3.0 - (m[d] + 2.0 * m[3 + d]) / (30.0 * (1.0 - nu))) / (2.0 * G * V);
@@ -1120,6 +1140,82 @@ static T* upload_vec(Arena& a, const std::vector<T>& h, hipStream_t s) {
   return d;
 }
 
+// C = A B for NC x NC row-major host matrices (threads over rows).
+static std::vector<double> host_matmul(const std::vector<double>& A, const std::vector<double>& B, int n) {
+  std::vector<double> C((size_t)n * n, 0.0);
+  auto rows = [&](int i0, int i1) {
+    for (int i = i0; i < i1; ++i)
+      for (int k = 0; k < n; ++k) {
+        const double a = A[(size_t)i * n + k];
+        if (a == 0.0) continue;
+        for (int j = 0; j < n; ++j) C[(size_t)i * n + j] += a * B[(size_t)k * n + j];
+      }
+  };
+  const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t) pool.emplace_back(rows, n * t / nth, n * (t + 1) / nth);
+  for (auto& th : pool) th.join();
+  return C;
+}
+
+// Periodic-cell operators of an operator set (once per set; see DeviceOps).  fp32: the check-potential
+// forms are needed; dn: the downward-density form (FP64 translations with the compressed M2L).
+static void ensure_periodic_ops(DeviceOps& D, int p, const Elastic& el, bool fp32, bool dn) {
+  std::lock_guard<std::mutex> lock(D.per_mutex);
+  const int NC = D.NC, n = 3 * D.n_eq;
+  std::vector<double> Tp;
+  auto far = [&]() -> const std::vector<double>& {
+    if (Tp.empty()) Tp = pad_square(periodic_far_operator(p, el), n, NC);
+    return Tp;
+  };
+  auto down = [&](const double* d) {
+    std::vector<double> h((size_t)NC * NC);
+    KFMM_HIP(hipMemcpy(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    return h;
+  };
+  if (!D.per_far64) {
+    D.per_far64 = D.arena.get<double>((size_t)NC * NC);
+    KFMM_HIP(hipMemcpy(D.per_far64, far().data(), (size_t)NC * NC * sizeof(double), hipMemcpyHostToDevice));
+    // second-moment rows on phi_up at unit half-width: t_m = sum_e phi_e,m |z_e|^2, s_m = sum_e z_e,m (phi_e . z_e)
+    std::vector<double> surf(3 * (size_t)D.n_eq), W(6 * (size_t)NC, 0.0);
+    KFMM_HIP(hipMemcpy(surf.data(), D.surf, surf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int e = 0; e < D.n_eq; ++e) {
+      double z[3];
+      for (int d = 0; d < 3; ++d) z[d] = 1.05 * surf[3 * e + d];
+      const double zz = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+      for (int m = 0; m < 3; ++m)
+        for (int d = 0; d < 3; ++d) {
+          if (m == d) W[(size_t)m * NC + 3 * e + d] = zz;
+          W[(size_t)(3 + m) * NC + 3 * e + d] = z[m] * z[d];
+        }
+    }
+    D.per_mom_phi = D.arena.get<double>(W.size());
+    KFMM_HIP(hipMemcpy(D.per_mom_phi, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (fp32 && !D.per_farq32) {
+    const std::vector<double> uc = down(D.uc2ue);
+    std::vector<double> Tq = host_matmul(far(), uc, NC);
+    std::vector<float> Tq32(Tq.begin(), Tq.end());
+    D.per_farq32 = D.arena.get<float>(Tq32.size());
+    KFMM_HIP(hipMemcpy(D.per_farq32, Tq32.data(), Tq32.size() * sizeof(float), hipMemcpyHostToDevice));
+    std::vector<double> Wp(6 * (size_t)NC), Wq(6 * (size_t)NC, 0.0);
+    KFMM_HIP(hipMemcpy(Wp.data(), D.per_mom_phi, Wp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int k = 0; k < 6; ++k)
+      for (int i = 0; i < NC; ++i) {
+        const double a = Wp[(size_t)k * NC + i];
+        if (a == 0.0) continue;
+        for (int j = 0; j < NC; ++j) Wq[(size_t)k * NC + j] += a * uc[(size_t)i * NC + j];
+      }
+    D.per_mom_q = D.arena.get<double>(Wq.size());
+    KFMM_HIP(hipMemcpy(D.per_mom_q, Wq.data(), Wq.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (dn && !D.per_fardn64) {
+    std::vector<double> Td = host_matmul(down(D.dc2de), far(), NC);
+    D.per_fardn64 = D.arena.get<double>(Td.size());
+    KFMM_HIP(hipMemcpy(D.per_fardn64, Td.data(), Td.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+}
+
 Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t n_src, const double* trg,
                   int64_t n_trg, const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, const fmm_opts& o,
                   hipStream_t s, const std::vector<double>& cells) {
@@ -1127,7 +1223,6 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   KFMM_REQUIRE(o.precision == KFMM_FP64 || o.precision == KFMM_FP32 || o.precision == KFMM_FP32_M2L_SPLIT16 ||
                    o.precision == KFMM_FP32_TRANS64,
                o.precision == KFMM_FP32_M2L_BF16 ? kBf16Withdrawn : "unknown precision");
-  KFMM_REQUIRE(cells.empty() || o.precision == KFMM_FP64, "periodic cells need KFMM_FP64");
   std::unique_ptr<Plan> P(new Plan());
   P->opts = o;
   P->periodic = !cells.empty();
@@ -1365,20 +1460,16 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   // periodic cells: the images beyond the 3 x 3 x 3 block act on each root through one operator, added
   // to the root's downward check potential like an M2L (unit half-width frame, so no per-box scale)
   if (P->periodic) {
-    DeviceOps& Dm = *P->ops;
-    {
-      std::lock_guard<std::mutex> lock(Dm.per_mutex);
-      if (!Dm.per_far64) {
-        std::vector<double> T = periodic_far_operator(p, P->el);
-        std::vector<double> Tp = pad_square(T, 3 * Dm.n_eq, NC);
-        Dm.per_far64 = Dm.arena.get<double>(Tp.size());
-        KFMM_HIP(hipMemcpy(Dm.per_far64, Tp.data(), Tp.size() * sizeof(double), hipMemcpyHostToDevice));
-      }
-    }
-    GemmCols c;
+    ensure_periodic_ops(*P->ops, p, P->el, P->f32t, !P->f32t && o.precision != KFMM_FP64 && P->comp != nullptr);
+    GemmCols c, cc;
     for (int b = t.level_start[0]; b < t.level_start[1]; ++b)
-      if (hs(b) && ht(b)) c.add(0, b, b);
+      if (hs(b) && ht(b)) {
+        c.add(0, b, b);
+        cc.add(0, b, (int)cc.op.size());  // into compact row i (check-potential form)
+      }
     P->job_per = upload_job(P->arena, c, s);
+    P->job_per_c = upload_job(P->arena, cc, s);
+    if (P->f32t) P->per_tmp_f = P->arena.get<float>(std::max<size_t>(1, cc.op.size()) * NC);
     // cell-mean constant of the displacement: roots with sources and targets, their sources in chunks
     std::vector<int> roots, coff = {0}, tb_, te_, cb, ce, cr;
     const int kChunk = 8192;
@@ -1406,6 +1497,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->per_chunk_e = upload_vec(P->arena, ce, s);
     P->per_chunk_root = upload_vec(P->arena, cr, s);
     P->per_part = P->arena.get<double>(6 * (size_t)std::max(1, P->per_n_chunks));
+    P->per_eqm = P->arena.get<double>(6 * (size_t)std::max(1, P->per_n_roots));
   }
   // W pairs and their output slots
   {
@@ -1702,6 +1794,20 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       gemm_f32(J2, D.fu2, GemmDims::Sq(NC), P.tmp_f, phi_up_f, kStore, s);
   }
   KFMM_HIP(hipGetLastError());
+  // periodic cells: the root's upward quantities are read before the M2L and the downward pass reuse their
+  // buffers -- the equivalent density's moments (cell-mean constant) and, with FP32 translations, the far
+  // images' check potential (T UC2UE) qhat_up, added back at the start of the downward pass
+  if (P.periodic && P.per_n_roots) {
+    if (P.f32t) {
+      hipLaunchKernelGGL(k_per_eqm<float>, dim3(P.per_n_roots), dim3(256), 0, s, P.per_root, D.per_mom_q,
+                         (const float*)P.q_f, NC, P.tv, P.per_eqm);
+      gemm_f32(P.job_per_c, D.per_farq32, GemmDims::Sq(NC), P.q_f, P.per_tmp_f, kStore, s);
+    } else {
+      hipLaunchKernelGGL(k_per_eqm<double>, dim3(P.per_n_roots), dim3(256), 0, s, P.per_root, D.per_mom_phi,
+                         (const double*)P.phi_up, NC, P.tv, P.per_eqm);
+    }
+    KFMM_HIP(hipGetLastError());
+  }
   // M2L into qhat.  qhat is FP64 in every precision; each box's M2L slots are summed in a fixed order,
   // so repeated products of one operator are bitwise identical (GMRES sees a fixed operator).
   mark(KFMM_PH_M2L_PREP);
@@ -1805,8 +1911,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       hipLaunchKernelGGL(k_add_rows<double>, dim3(P.n_x_boxes), dim3(reduce_block<double>(NC)), 0, s, P.x_boxes,
                          (const double*)P.qx, qhat, NC);
   }
-  // periodic cells (FP64 translations): the far images act on the roots
-  if (P.periodic && P.job_per.n_tiles)
+  // periodic cells, FP64 translations on qhat: the far images act on the roots
+  if (P.periodic && P.job_per.n_tiles && !P.f32t && !fused_down)
     gemm_f64(P.job_per, D.per_far64, GemmDims::Sq(NC), P.phi_up, qhat, kAdd, s);
   KFMM_HIP(hipGetLastError());
   mark(KFMM_PH_DOWN);
@@ -1830,6 +1936,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
         hipLaunchKernelGGL(k_add_rows<float>, dim3(P.n_x_boxes), dim3(reduce_block<float>(NC)), 0, s, P.x_boxes,
                            (const float*)P.qx_f, qhat_f, NC);
     }
+    if (P.periodic && P.per_n_roots)  // the far images' check potential of every root
+      hipLaunchKernelGGL(k_add_rows<float>, dim3(P.per_n_roots), dim3(reduce_block<float>(NC)), 0, s, P.per_root,
+                         (const float*)P.per_tmp_f, qhat_f, NC);
     for (size_t i = 0; i < P.dn_levels.size(); ++i) {
       if (split16 && big(P.dn_levels[i])) {  // split the parents' level, then qhat(child) += L2L_q qhat(parent)
         const int l = P.dn_lv[i], b0 = t.level_start[l - 1], b1 = t.level_start[l];
@@ -1860,6 +1969,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       const int NCr = P.comp->NCr;
       gemm_f64(P.job_dc2de, P.comp->DU64, GemmDims{NC, NCr, NCr, NC}, P.q_t, P.phi_dn, kStore, s);
       gemm_f64(P.job_dcx, D.dc2de, GemmDims::Sq(NC), P.qx, P.phi_dn, kAdd, s);
+      if (P.periodic && P.job_per.n_tiles)  // the far images straight onto the roots' downward densities
+        gemm_f64(P.job_per, D.per_fardn64, GemmDims::Sq(NC), P.phi_up, P.phi_dn, kAdd, s);
     } else {
       gemm_f64(P.job_dc2de, D.dc2de, GemmDims::Sq(NC), qhat, P.phi_dn, kStore, s);
     }
@@ -1883,8 +1994,7 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
                        P.per_chunk_e, P.tv, t.leaf_of_src, spos, P.has_nrm ? snrm : (const T*)nullptr, dens,
                        P.el.K - 2.0 * P.el.G / 3.0, P.el.G, P.per_part);
     hipLaunchKernelGGL(k_per_shift, dim3(P.per_n_roots), dim3(256), 0, s, P.per_root, P.per_chunk_off, P.per_trg_b,
-                       P.per_trg_e, P.per_part, P.tv, (const double*)P.phi_up, D.surf, n_eq, NC, 1.05, P.el.nu,
-                       P.el.G, out);
+                       P.per_trg_e, P.per_part, P.tv, (const double*)P.per_eqm, P.el.nu, P.el.G, out);
     KFMM_HIP(hipGetLastError());
   }
   mark(KFMM_N_PHASES);

@@ -40,7 +40,9 @@ struct Plan {
   // periodic cells: levels 0 and 1 take part in the translations, and job_per adds the far-image operator
   // to the root's downward check potential
   bool periodic = false;
-  GemmJob job_per;
+  GemmJob job_per, job_per_c;  // roots in place / into compact rows (FP32 translations: T UC2UE qhat_up)
+  float* per_tmp_f = nullptr;  // compact rows of the far images' check potential (FP32 translations)
+  double* per_eqm = nullptr;   // the equivalent density's second moments, 6 per root
   // periodic displacement: the cell-mean constant per root (second moments of the sources in chunks of
   // sources, then per root with the equivalent density), subtracted from the root's target rows
   int per_n_roots = 0, per_n_chunks = 0;

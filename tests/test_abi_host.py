@@ -79,7 +79,7 @@ def test_plan_argument_errors(lib):
 
 
 def test_periodic_plan_argument_errors(lib):
-    """fmm_plan_periodic: a NULL cell array and a precision other than FP64 are refused before any device call."""
+    """fmm_plan_periodic: a NULL cell array is refused before any device call."""
     from paper_1612_04082_amd import kfmm
     plan = ctypes.c_void_p()
     xyz = (ctypes.c_double * 3)(0.5, 0.5, 0.5)
@@ -91,11 +91,11 @@ def test_periodic_plan_argument_errors(lib):
         return lib.fmm_plan_periodic(ctypes.byref(plan), xyz, None, None, 1, None, 1, None, None, 0, c,
                                      ctypes.byref(opts), None)
 
-    assert call(None, kfmm.FmmOpts(**good)) == KFMM_E_ARG
-    assert last_error(lib) == "cells is NULL" and not plan.value
-    for prec in (kfmm.FP32, kfmm.FP32_M2L_SPLIT16, kfmm.FP32_TRANS64):
-        assert call(cells, kfmm.FmmOpts(**{**good, "precision": prec})) == KFMM_E_ARG
-        assert "periodic cells need KFMM_FP64" in last_error(lib)
+    for prec in (kfmm.FP64, kfmm.FP32, kfmm.FP32_M2L_SPLIT16):
+        assert call(None, kfmm.FmmOpts(**{**good, "precision": prec})) == KFMM_E_ARG
+        assert last_error(lib) == "cells is NULL" and not plan.value
+    assert call(cells, kfmm.FmmOpts(**{**good, "precision": 2})) == KFMM_E_ARG  # the withdrawn BF16 mode
+    assert "M2L_BF16 is withdrawn" in last_error(lib)
 
 
 def test_selftest_gemm_selector_errors(lib):

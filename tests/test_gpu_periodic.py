@@ -57,10 +57,15 @@ def _check(got, ref, kind, tol, label):
     assert err < tol
 
 
+_REF = {}
+PRECISIONS = {"fp64": (0, 0.0), "fp32": (1, 0.0), "fp32-comp": (1, 3e-7), "split16-comp": (3, 3e-7),
+              "trans64-comp": (4, 3e-7), "trans64": (4, 0.0)}
+
+
 @pytest.mark.parametrize("N,leaf,p", [(4000, 64, 8), (40, 64, 6), (600, 16, 6)])
 def test_periodic_matches_ewald(cuda, N, leaf, p):
     """Many levels (W and X lists, V lists at level 1 through the images), a tree that is only the root
-    (near field with the 26 images, far images through the root operator), and a shallow tree."""
+    (near field with the 26 images, far images through the root operator), and a shallow tree (FP64)."""
     from paper_1612_04082_amd import kfmm
     lo, L = np.array([-0.3, 0.2, 1.0]), 1.7
     src, nrm, w, a, b = _cloud(N, lo, L, seed=N)
@@ -76,6 +81,27 @@ def test_periodic_matches_ewald(cuda, N, leaf, p):
         got = plan.eval(kind, a=_t(a), b=_t(b)).cpu().numpy()
         ref = op.periodic(kind, trg, src, w, a=a, b=b, nrm=nrm, K=K, G=G, L=L)
         _check(got, ref, kind, tol, f"N={N}")
+    plan.close()
+
+
+@pytest.mark.parametrize("mode", [m for m in PRECISIONS if m != "fp64"])
+def test_periodic_precisions(cuda, mode):
+    """Every precision mode on the periodic tree (the far images in check-potential form with FP32
+    translations, straight onto the downward densities with FP64 translations and the compressed M2L),
+    at the free-space bound of p = 8, leaf <= 64."""
+    from paper_1612_04082_amd import kfmm
+    prec, tol_m2l = PRECISIONS[mode]
+    lo, L = np.array([-0.3, 0.2, 1.0]), 1.7
+    src, nrm, w, a, b = _cloud(4000, lo, L, seed=4000)
+    rng = np.random.default_rng(7)
+    trg = lo + rng.uniform(size=(300, 3)) * L
+    plan = kfmm.FmmPlan(_t(src), nrm=_t(nrm), w=_t(w), trg=_t(trg), K=K, G=G, p=8, leaf_max=64, precision=prec,
+                        m2l_tol=tol_m2l, cells=[(lo[0], lo[1], lo[2], L)])
+    for kind in (od.DISP, od.STRESS):
+        got = plan.eval(kind, a=_t(a), b=_t(b)).cpu().numpy()
+        if kind not in _REF:  # the same inputs for every mode
+            _REF[kind] = op.periodic(kind, trg, src, w, a=a, b=b, nrm=nrm, K=K, G=G, L=L)
+        _check(got, _REF[kind], kind, 1e-5, mode)
     plan.close()
 
 
