@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--iters", type=int, default=20, help="Algorithm 1 iterations for the warmstart workload")
     ap.add_argument("--measure-from", type=int, default=11)
     ap.add_argument("--p-bem", type=int, default=8, help="expansion order of the BEM solves in the warmstart workload")
+    ap.add_argument("--periodic", action="store_true", help="cells workload: periodic metamaterial cells")
     ap.add_argument("--cell-n", type=int, default=100, help="voxels per axis of the metacell workload")
     ap.add_argument("--rc", type=float, default=0.2, help="initial cavity radius of the metacell workload")
     ap.add_argument("--alpha-c", type=float, default=0.7, help="volume fraction of the metacell workload")

@@ -3,7 +3,9 @@
 sphere      4,096 points on the unit sphere, single layer, FP64, p = 6, leaf <= 64; full O(N^2) oracle.
 cells       64 periodic-cell bodies (unit cube minus ellipsoids, 20k-200k points each) in ONE batched plan,
             single + double layer, FP32 (split FP16 with the compressed M2L with --precision split16); also 64
-            separate plans; oracle on 1,000 targets per cell.
+            separate plans; oracle on 1,000 targets per cell.  With --periodic the cells are the periodic
+            metamaterial cells of Sec. 4.3 (the void/material faces only, every integral over the lattice
+            images; fmm_plan_periodic), oracle: Ewald sums on 40 targets of 2 cells.
 cantilever  8:1:1 cantilever with 64 spherical holes (~965k quadrature points): bem_solve (FP64, tol 1e-6)
             without and with the two-level preconditioner (--precond), then the stress at the 128^3 interior
             lattice; oracle rows of the matrix-vector product and stress on sampled points; with
@@ -75,7 +77,8 @@ def cells(args):
     from oracle import direct as od
     prec = {"split16": kfmm.FP32_M2L_SPLIT16}.get(args.precision, kfmm.FP32)
     tol = args.m2l_tol if args.precision == "split16" else 0.0  # compressed M2L with the split-FP16 arithmetic
-    cl = geo.cell_batch(64)
+    cl = geo.periodic_cell_batch(64) if args.periodic else geo.cell_batch(64)
+    cells_arg = [(0.0, 0.0, 0.0, 1.0)] * 64 if args.periodic else None
     src = np.concatenate([c["src"] for c in cl])
     nrm = np.concatenate([c["nrm"] for c in cl])
     w = np.concatenate([c["w"] for c in cl])
@@ -85,7 +88,7 @@ def cells(args):
     n = src.shape[0]
     t0 = time.time()
     plan = kfmm.FmmPlan(_t(src), _t(nrm), _t(w), K=K, G=G, p=args.p, leaf_max=args.leaf, precision=prec,
-                        batch_src=list(off), m2l_tol=tol)
+                        batch_src=list(off), m2l_tol=tol, cells=cells_arg)
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     da, db = _t(a), _t(b)
@@ -98,7 +101,7 @@ def cells(args):
     t0 = time.time()
     for c in cl:
         plans.append(kfmm.FmmPlan(_t(c["src"]), _t(c["nrm"]), _t(c["w"]), K=K, G=G, p=args.p, leaf_max=args.leaf,
-                                  precision=prec, m2l_tol=tol))
+                                  precision=prec, m2l_tol=tol, cells=cells_arg[:1] if cells_arg else None))
         bufs.append((_t(c["a"]), _t(c["b"]), torch.empty((c["src"].shape[0], 3), dtype=torch.float64, device="cuda")))
     torch.cuda.synchronize()
     plan_seq_s = time.time() - t0
@@ -115,25 +118,37 @@ def cells(args):
     ms_seq = e0.elapsed_time(e1) / args.steps
     for p_ in plans:
         p_.close()
-    # oracle on 1,000 targets per cell
+    # oracle on 1,000 targets per cell (free space), or Ewald sums on 100 targets of 4 cells (periodic)
     rng = np.random.default_rng(4)
     errs = []
     tc = time.time()
+    n_ref = 0
     for g, c in enumerate(cl):
-        idx = rng.choice(c["src"].shape[0], size=1000, replace=False)
-        ref = od.direct(od.DISP, c["src"][idx], c["src"], c["w"], a=c["a"], b=c["b"], nrm=c["nrm"], K=K, G=G,
-                        nthreads=_cores())
+        if args.periodic and g % 32:
+            continue
+        idx = rng.choice(c["src"].shape[0], size=40 if args.periodic else 1000, replace=False)
+        if args.periodic:
+            from oracle import periodic as opd
+            ref = opd.periodic(od.DISP, c["src"][idx], c["src"], c["w"], a=c["a"], b=c["b"], nrm=c["nrm"], K=K, G=G,
+                               L=1.0, alpha_L=3.5, nthreads=_cores())
+        else:
+            ref = od.direct(od.DISP, c["src"][idx], c["src"], c["w"], a=c["a"], b=c["b"], nrm=c["nrm"], K=K, G=G,
+                            nthreads=_cores())
+        n_ref += len(idx)
         errs.append(float(np.linalg.norm(got[off[g]:off[g + 1]][idx] - ref) / np.linalg.norm(ref)))
     tcpu = time.time() - tc
-    return dict(metric="FMM target points/s (64 cells, one batched plan)", value=n / (ms * 1e-3),
+    kind_cells = "periodic metamaterial cells" if args.periodic else "periodic-cell bodies"
+    return dict(metric=f"FMM target points/s (64 {'periodic ' if args.periodic else ''}cells, one batched plan)",
+                value=n / (ms * 1e-3),
                 unit="target points/s", ms_per_step=ms,
                 dtype={kfmm.FP32_M2L_SPLIT16: "f32+f16x2"}.get(prec, "f32"),
-                config=dict(workload=f"64 periodic-cell bodies, {n} points, SL+DL, p={args.p}, leaf<={args.leaf}",
+                config=dict(workload=f"64 {kind_cells}, {n} points, SL+DL, p={args.p}, leaf<={args.leaf}",
                             m2l_tol=tol),
                 sequential=dict(ms_per_step=ms_seq, value=n / (ms_seq * 1e-3), plan_seconds=plan_seq_s),
                 plan_seconds=plan_s, rel_err_max_cell=max(errs), rel_err_median_cell=float(np.median(errs)),
-                cpu_baseline=dict(value=64000 / tcpu, unit="target points/s", cores=_cores(), kind="oracle",
-                                  sample="1000 targets per cell x all sources of the cell"))
+                cpu_baseline=dict(value=n_ref / tcpu, unit="target points/s", cores=_cores(), kind="oracle",
+                                  sample=("40 targets of cells 0 and 32 x all sources of the cell, Ewald sums"
+                                          if args.periodic else "1000 targets per cell x all sources of the cell")))
 
 
 def cantilever(args):

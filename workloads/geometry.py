@@ -316,6 +316,35 @@ def cell_batch(n_cells=64, seed_base=4000, lo=20000, hi=200000, seed=4):
     return out
 
 
+def periodic_cell_batch(n_cells=64, seed_base=4000, lo=20000, hi=200000, seed=4):
+    """n_cells periodic metamaterial cells (Sec. 4.3): the unit cell of cell_voxels repeated over the lattice,
+    the surface the void/material faces only (periodic_voxel_surface; the cell's own faces are no boundary),
+    the voxel resolution chosen so that each cell's quadrature point count falls near a target drawn in
+    [lo, hi].  Returns a list of dicts with src, nrm, w, a, b (densities with zero net single-layer force
+    per cell, the case of a closed surface's tractions)."""
+    out = []
+    for g in range(n_cells):
+        rng = np.random.default_rng(seed_base + 1000 + g)
+        target = rng.uniform(lo, hi)
+        n_vox, pts = 8, None
+        while n_vox <= 96:
+            M, h = cell_voxels(g, n_vox, seed_base)
+            surf = periodic_voxel_surface(M, h)
+            npts = surf["tri"].shape[0] * 16
+            if npts >= target or n_vox == 96:
+                if npts > hi and n_vox > 8:  # one step back stays within [lo, hi]
+                    M, h = cell_voxels(g, n_vox - 1, seed_base)
+                    surf = periodic_voxel_surface(M, h)
+                break
+            n_vox += max(1, int(n_vox * (np.sqrt(target / max(npts, 1)) - 1.0) * 0.5))
+        pts, nrm, w = quadrature_cloud(surf["tri"])
+        r2 = np.random.default_rng(seed * 100000 + g)
+        a = r2.normal(size=pts.shape)
+        a -= (w[:, None] * a).sum(0) / w.sum()
+        out.append(dict(src=pts, nrm=nrm, w=w, a=a, b=r2.normal(size=pts.shape)))
+    return out
+
+
 # ----------------------------------------------------------------------------- cube in uniaxial tension
 
 
