@@ -70,8 +70,8 @@ def cpu_model():
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
 # profiles/m2l_split16_boxbeam_p8_leaf256.md.  Valid only for the kernel sources and the launch set-up (tile
 # widths, in fmm.hip) it was measured on.
-M2L_TRAFFIC = {"sources_sha256": "cb0f707df8030949bdefbf96ae6657ceaf84dba26d5a00496488491a8ada970d",
-               "fetch_kib": 210463.1 * 2.0, "write_kib": 202336.9 * 1.0}
+M2L_TRAFFIC = {"sources_sha256": "19fc3278bd72010c0573001e5227d31fdf940cd0ded3f40dd4ab7fc9407bcbdf",
+               "fetch_kib": 210321.5 * 2.0, "write_kib": 202339.5 * 1.0}
 M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
                "paper_1612_04082_amd/csrc/gemm.h", "paper_1612_04082_amd/csrc/fmm.hip")
 
