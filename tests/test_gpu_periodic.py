@@ -148,3 +148,35 @@ def test_periodic_rejects_points_outside_cell(cuda):
     src[7, 1] = 1.0  # the cell is [0, 1): its upper faces belong to the next image
     with pytest.raises(kfmm.KfmmError, match="outside its periodic cell"):
         kfmm.FmmPlan(src, K=K, G=G, p=4, precision=kfmm.FP64, cells=[(0.0, 0.0, 0.0, 1.0)])
+
+
+def test_periodic_edges_empty_cell_and_face_clusters(cuda):
+    """A batch whose middle geometry is empty, and a cell whose points sit on its lower faces and just below
+    its upper faces: those meet their own images across the faces at distances of 1e-6 of the side."""
+    from paper_1612_04082_amd import kfmm
+    rng = np.random.default_rng(31)
+    L = 1.0
+    n = 600
+    src = rng.uniform(size=(n, 3)) * L
+    src[: n // 3, 0] = 0.0                      # on the lower x face
+    src[n // 3: 2 * n // 3, 0] = L - 1e-6       # just below the upper x face (image at distance ~1e-6)
+    src[::7, 1] = 0.0
+    nrm = rng.normal(size=(n, 3))
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    w = rng.uniform(0.5, 1.5, size=n)
+    a = rng.normal(size=(n, 3))
+    a -= (w[:, None] * a).sum(0) / w.sum()
+    b = rng.normal(size=(n, 3))
+    other = _cloud(500, np.array([3.0, 0.0, 0.0]), 2.0, seed=5)
+    S = np.vstack([src, other[0]]); N_ = np.vstack([nrm, other[1]]); W = np.concatenate([w, other[2]])
+    A = np.vstack([a, other[3]]); B = np.vstack([b, other[4]])
+    cells = [(0.0, 0.0, 0.0, L), (-5.0, -5.0, -5.0, 1.0), (3.0, 0.0, 0.0, 2.0)]
+    plan = kfmm.FmmPlan(_t(S), nrm=_t(N_), w=_t(W), K=K, G=G, p=8, leaf_max=32, precision=kfmm.FP64,
+                        batch_src=[0, n, n, n + 500], cells=cells)
+    for kind in (od.DISP, od.STRESS):
+        got = plan.eval(kind, a=_t(A), b=_t(B)).cpu().numpy()
+        ref0 = op.periodic(kind, S[:n], S[:n], W[:n], a=A[:n], b=B[:n], nrm=N_[:n], K=K, G=G, L=L)
+        ref2 = op.periodic(kind, S[n:], S[n:], W[n:], a=A[n:], b=B[n:], nrm=N_[n:], K=K, G=G, L=2.0)
+        _check(got[:n], ref0, kind, 1e-5, "face clusters")
+        _check(got[n:], ref2, kind, 1e-5, "third cell")
+    plan.close()
