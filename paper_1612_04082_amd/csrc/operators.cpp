@@ -61,6 +61,20 @@ std::vector<double> cube_surface(int p) {
   return pts;
 }
 
+// Runs body(i) for i in [0, count) on up to 16 threads (contiguous ranges; each i is done once, by one thread,
+// so results do not depend on the thread count).
+template <typename F>
+static void parallel_for(int count, F body) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nth = std::max(1, std::min({count, 16, (int)(hw == 0 ? 1 : hw)}));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&, t] {
+      for (int i = count * t / nth; i < count * (t + 1) / nth; ++i) body(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
 // Dense U-kernel matrix, row-major (3 nx) x (3 ny): entry [3a+i][3b+j] = U_ij(x_a, y_b)  (eq. disp_1).
 static void kernel_matrix_U(const Elastic& e, const double* X, int nx, const double* Y, int ny, double* out) {
   const int ld = 3 * ny;
@@ -191,12 +205,13 @@ static std::vector<double> pinv_from_svd(const std::vector<double>& W, const std
       keep.push_back(j);
       ++rank;
     }
-  for (int i = 0; i < n; ++i)
+  parallel_for(n, [&](int i) {
     for (int k = 0; k < n; ++k) {
       double acc = 0;
       for (int j : keep) acc += V[(size_t)j * n + i] * W[(size_t)j * n + k] / (sig[j] * sig[j]);
       P[(size_t)i * n + k] = acc;
     }
+  });
   if (rank_out) *rank_out = rank;
   return P;
 }
@@ -226,17 +241,17 @@ static void pinv_factors(const std::vector<double>& W, const std::vector<double>
   }
 }
 
-// C = A B for n x n row-major FP64 matrices.
+// C = A B for n x n row-major FP64 matrices (rows in parallel; every entry summed in k order).
 static std::vector<double> matmul(const std::vector<double>& A, const std::vector<double>& B, int n) {
   std::vector<double> C((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) {
+  parallel_for(n, [&](int i) {
     double* c = &C[(size_t)i * n];
     for (int k = 0; k < n; ++k) {
       double a = A[(size_t)i * n + k];
       const double* b = &B[(size_t)k * n];
       for (int j = 0; j < n; ++j) c[j] += a * b[j];
     }
-  }
+  });
   return C;
 }
 
@@ -368,17 +383,22 @@ Operators build_operators(int p, const Elastic& e, double svd_eps) {
   // M2L for every index offset d in [-3,3]^3 with max |d_i| >= 2 (316 offsets)
   std::vector<double> dc = scaled(RC_DN, 0, 0, 0);
   op.m2l_index.assign(343, -1);
+  std::vector<int> offs;
   for (int dz = -3; dz <= 3; ++dz)
     for (int dy = -3; dy <= 3; ++dy)
       for (int dx = -3; dx <= 3; ++dx) {
         if (std::max(std::abs(dx), std::max(std::abs(dy), std::abs(dz))) < 2) continue;
         int idx = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
-        op.m2l_index[idx] = (int)op.m2l.size();
-        std::vector<double> se = scaled(RE_UP, 2.0 * dx, 2.0 * dy, 2.0 * dz);
-        std::vector<double> Km((size_t)n * n);
-        kernel_matrix_U(e, dc.data(), op.n_eq, se.data(), op.n_eq, Km.data());
-        op.m2l.push_back(std::move(Km));
+        op.m2l_index[idx] = (int)offs.size();
+        offs.push_back(idx);
       }
+  op.m2l.resize(offs.size());
+  parallel_for((int)offs.size(), [&](int o) {
+    const int idx = offs[o], dx = idx % 7 - 3, dy = (idx / 7) % 7 - 3, dz = idx / 49 - 3;
+    std::vector<double> se = scaled(RE_UP, 2.0 * dx, 2.0 * dy, 2.0 * dz);
+    op.m2l[o].resize((size_t)n * n);
+    kernel_matrix_U(e, dc.data(), op.n_eq, se.data(), op.n_eq, op.m2l[o].data());
+  });
   return op;
 }
 
