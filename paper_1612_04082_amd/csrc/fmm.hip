@@ -432,7 +432,7 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
   for (int j = 0; j < n; ++j)  // stored by columns; G is symmetric
     for (int i = 0; i < n; ++i) G[(size_t)i * n + j] = 0.5 * (hg[(size_t)j * NC + i] + hg[(size_t)i * NC + j]);
   std::vector<double> lam, vecs;
-  sym_eig_psd(G, n, lam, vecs);
+  sym_eig_psd_cached(G, n, "m2l_gram", lam, vecs);
   int r = 0;
   while (r < n && lam[r] > 0 && std::sqrt(lam[r] / lam[0]) > tol) ++r;
   r = std::max(r, 1);

@@ -255,29 +255,29 @@ static std::vector<double> matmul(const std::vector<double>& A, const std::vecto
   return C;
 }
 
-static std::string cache_path(int p, const Elastic& e, double eps) {
+static std::string cache_dir() {
   const char* dir = std::getenv("KFMM_CACHE_DIR");
-  std::string d;
-  if (dir && *dir) {
-    d = dir;
-  } else {
-    const char* home = std::getenv("HOME");
-    d = std::string(home ? home : "/tmp") + "/.cache/kfmm";
-  }
+  if (dir && *dir) return dir;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/kfmm";
+}
+
+static std::string cache_path(int p, const Elastic& e, double eps) {
+  const std::string d = cache_dir();
   char name[256];
   std::snprintf(name, sizeof(name), "/svd_uc_ue_p%d_nu%.17g_G%.17g_r1.05_2.95.bin", p, e.nu, e.G);
   (void)eps;  // the SVD does not depend on the cutoff
   return d + name;
 }
 
-// Cache file: n, then the SVD (W, V, sig) as one array of 2 n^2 + n doubles, then a checksum.
-static bool load_cache(const std::string& path, int n, std::vector<double>& P) {
+// Cache file: n, then one array of doubles (the SVD: W, V, sig, 2 n^2 + n values by default), then a checksum.
+static bool load_cache(const std::string& path, int n, std::vector<double>& P, size_t count = 0) {
   std::ifstream f(path, std::ios::binary);
   if (!f) return false;
   int nn = 0;
   f.read((char*)&nn, sizeof(int));
   if (nn != n) return false;
-  P.resize((size_t)2 * n * n + n);
+  P.resize(count ? count : (size_t)2 * n * n + n);
   f.read((char*)P.data(), sizeof(double) * P.size());
   uint64_t chk = 0, ref = 0;
   f.read((char*)&ref, sizeof(ref));
@@ -417,6 +417,31 @@ void sym_eig_psd(const std::vector<double>& A, int n, std::vector<double>& lambd
     lambda[k] = sig[order[k]];
     for (int i = 0; i < n; ++i) vecs[(size_t)k * n + i] = V[(size_t)order[k] * n + i];
   }
+}
+
+// sym_eig_psd with the result kept in the operator cache directory, keyed by a hash of the matrix's bits (the
+// same matrix gives the same file; any change of the input, a new file).
+void sym_eig_psd_cached(const std::vector<double>& A, int n, const char* tag, std::vector<double>& lambda,
+                        std::vector<double>& vecs) {
+  uint64_t h = 1469598103934665603ull;
+  for (double v : A) {
+    uint64_t u;
+    std::memcpy(&u, &v, 8);
+    h = (h ^ u) * 1099511628211ull;
+  }
+  char name[128];
+  std::snprintf(name, sizeof(name), "/eig_%s_n%d_%016llx.bin", tag, n, (unsigned long long)h);
+  const std::string path = cache_dir() + name;
+  std::vector<double> P;
+  if (load_cache(path, n, P, (size_t)n + (size_t)n * n)) {
+    lambda.assign(P.begin(), P.begin() + n);
+    vecs.assign(P.begin() + n, P.end());
+    return;
+  }
+  sym_eig_psd(A, n, lambda, vecs);
+  P = lambda;
+  P.insert(P.end(), vecs.begin(), vecs.end());
+  save_cache(path, n, P);
 }
 
 // Far-image operator of a periodic cell (Sec. 4.3: the multipole expansions are periodic, so the tree is

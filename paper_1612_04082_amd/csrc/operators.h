@@ -24,6 +24,9 @@ struct Operators {
 std::vector<double> cube_surface(int p);
 Operators build_operators(int p, const Elastic& e, double svd_eps);
 void sym_eig_psd(const std::vector<double>& A, int n, std::vector<double>& lambda, std::vector<double>& vecs);
+// The same, cached on disk with the operators (file name from a hash of A).
+void sym_eig_psd_cached(const std::vector<double>& A, int n, const char* tag, std::vector<double>& lambda,
+                        std::vector<double>& vecs);
 // Far-image operator of a periodic cell at unit half-width (cell side 2), n x n row-major: the downward check
 // potential of the root from the upward equivalent densities of every lattice image outside the 3 x 3 x 3
 // block around the cell (see operators.cpp).
