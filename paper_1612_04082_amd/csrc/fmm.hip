@@ -64,6 +64,10 @@ struct CompressedM2L {
   float* Ch3_scale = nullptr;   // power-of-two scale per operator
   uint16_t* U_h3 = nullptr;     // U32 split likewise (one operator)
   float* U_h3_scale = nullptr;
+  // U and fd1 U (two NC x NCr operators, split FP16): the downward check potential of a box with children,
+  // and the first pseudo-inverse factor already applied for a leaf (whose check potential nothing else reads)
+  uint16_t* UF_h3 = nullptr;
+  float* UF_h3_scale = nullptr;
 };
 
 struct DeviceOps {
@@ -86,6 +90,12 @@ struct DeviceOps {
   // factors fu1, fd1, made on first use
   uint16_t *m2mq_h3 = nullptr, *l2lq_h3 = nullptr, *fu1_h3 = nullptr, *fd1_h3 = nullptr;
   float *m2mq_h3_scale = nullptr, *l2lq_h3_scale = nullptr, *fu1_h3_scale = nullptr, *fd1_h3_scale = nullptr;
+  // fd1 and the transposed L2L_q in FP64, and the 16 operators [L2L_q | fd1 L2L_q] (FP32 and split FP16):
+  // an L2L into a leaf applies the first factor of its DC2DE at once (made on first use)
+  double *fd1_64 = nullptr, *l2lqT64 = nullptr;
+  float* l2lq_fold32 = nullptr;
+  uint16_t* l2lq_fold_h3 = nullptr;
+  float* l2lq_fold_h3_scale = nullptr;
   std::mutex h3_mutex;
   double* surf = nullptr;  // n_eq x 3
   std::vector<int> m2l_index;
@@ -169,6 +179,14 @@ static std::shared_ptr<DeviceOps> get_ops(int p, const Elastic& el, double eps, 
     d->fu1 = up32(pad_square(op.fu1, op.n, NC));
     d->fu2 = up32(pad_square(op.fu2, op.n, NC));
     d->fd1 = up32(pad_square(op.fd1, op.n, NC));
+    d->fd1_64 = up(pad_square(op.fd1, op.n, NC));
+    {
+      std::vector<double> lt = cat8(op.l2l_q), tr(lt.size());
+      for (int c = 0; c < 8; ++c)
+        for (int i = 0; i < NC; ++i)
+          for (int j = 0; j < NC; ++j) tr[((size_t)c * NC + j) * NC + i] = lt[((size_t)c * NC + i) * NC + j];
+      d->l2lqT64 = up(tr);
+    }
     d->fd2 = up32(pad_square(op.fd2, op.n, NC));
     d->vs32 = up32(pad_square(op.vs, op.n, NC));
     d->us32 = up32(pad_square(op.us, op.n, NC));
@@ -540,6 +558,58 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
   KFMM_HIP(hipStreamSynchronize(s));
   d.comp[tol] = c;
   return c;
+}
+
+// Operators of the folded downward pass (split FP16, compressed M2L): the 16 L2L operators [L2L_q | fd1 L2L_q]
+// and the two [U | fd1 U], products in FP64 on the device, rounded to FP32 and split; made once per device
+// and basis.
+static void ensure_fold_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(d.h3_mutex);
+  const int NC = d.NC;
+  const int64_t sq = (int64_t)NC * NC;
+  Arena tmp;
+  // fd1 applied to n NC-vectors stored as rows; row j of the result is fd1 times row j of the input
+  auto fd1_rows = [&](const double* rows, int n) {
+    GemmCols cols;
+    for (int j = 0; j < n; ++j) cols.add(0, j, j);
+    GemmJob job = upload_job(tmp, cols, s, kGemmBN);
+    double* Y = tmp.get<double>((size_t)n * NC);
+    gemm_f64(job, d.fd1_64, GemmDims::Sq(NC), rows, Y, kStore, s);
+    std::vector<double> h((size_t)n * NC);
+    KFMM_HIP(hipStreamSynchronize(s));
+    KFMM_HIP(hipMemcpy(h.data(), Y, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+    return h;
+  };
+  if (!d.l2lq_fold32) {
+    // rows of L2L_q[c]^T are its columns: row c NC + j of h is column j of fd1 L2L_q[c]
+    const std::vector<double> h = fd1_rows(d.l2lqT64, 8 * NC);
+    std::vector<float> f((size_t)8 * sq);
+    for (int c2 = 0; c2 < 8; ++c2)
+      for (int j = 0; j < NC; ++j)
+        for (int i = 0; i < NC; ++i)
+          f[(size_t)c2 * sq + (size_t)i * NC + j] = (float)h[((size_t)c2 * NC + j) * NC + i];
+    d.l2lq_fold32 = d.arena.get<float>((size_t)16 * sq);
+    KFMM_HIP(hipMemcpy(d.l2lq_fold32, d.l2lq32, sizeof(float) * 8 * sq, hipMemcpyDeviceToDevice));
+    KFMM_HIP(hipMemcpy(d.l2lq_fold32 + 8 * sq, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice));
+    d.l2lq_fold_h3 = d.arena.get<uint16_t>((size_t)16 * 2 * sq);
+    d.l2lq_fold_h3_scale = d.arena.get<float>(16);
+    split_h3(d.l2lq_fold32, 16, sq, sq, d.l2lq_fold_h3, d.l2lq_fold_h3_scale, s);
+  }
+  if (!c->UF_h3) {
+    const int NCr = c->NCr;
+    const int64_t len = (int64_t)NC * NCr;
+    const std::vector<double> h = fd1_rows(c->Ut64, NCr);  // row k: fd1 u_k (zero past the rank)
+    std::vector<float> f((size_t)len);
+    for (int k = 0; k < NCr; ++k)
+      for (int i = 0; i < NC; ++i) f[(size_t)i * NCr + k] = (float)h[(size_t)k * NC + i];
+    float* uf = tmp.get<float>((size_t)2 * len);
+    KFMM_HIP(hipMemcpy(uf, c->U32, sizeof(float) * len, hipMemcpyDeviceToDevice));
+    KFMM_HIP(hipMemcpy(uf + len, f.data(), sizeof(float) * len, hipMemcpyHostToDevice));
+    c->UF_h3 = d.arena.get<uint16_t>((size_t)2 * 2 * len);
+    c->UF_h3_scale = d.arena.get<float>(2);
+    split_h3(uf, 2, len, len, c->UF_h3, c->UF_h3_scale, s);
+  }
+  KFMM_HIP(hipStreamSynchronize(s));
 }
 
 // Split-FP16 copies of the M2L operators (dense, or the compressed C_o of c), made once per device.
@@ -1403,6 +1473,15 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     P->job_m2l = upload_job(P->arena, sc, s, m2l_cols);
     if (split16) {
       ensure_split_ops(*P->ops, P->comp.get(), s);
+      // a leaf's downward check potential is only ever multiplied by fd1, so that factor can ride on the
+      // products that form it, unless something else adds to it: X lists of a leaf, or a periodic root
+      // that is a leaf (its far images)
+      bool fold = P->comp != nullptr && D.NC <= 1024;
+      for (int b2 : x_boxes) fold = fold && !t.h_is_leaf[b2];
+      if (P->periodic)
+        for (int b2 = t.level_start[0]; b2 < t.level_start[1]; ++b2) fold = fold && !t.h_is_leaf[b2];
+      if (fold) ensure_fold_ops(*P->ops, P->comp.get(), s);
+      P->fold_fd1 = fold;
       P->phi_h3 = P->arena.get<uint16_t>((size_t)nb * 2 * slot_len);
       P->phi_h3_scale = P->arena.get<float>(std::max(nb, 1));
       // NC-wide split rows per box: check potentials for the translations, phi_up for the U^T projection
@@ -1435,8 +1514,8 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   {
     GemmCols c;
     for (int b = 0; b < nb; ++b)
-      if (t.h_level[b] >= lv0 && ht(b)) c.add(0, b, b);
-    P->job_dc2de = upload_job(P->arena, c, s, wide(c));
+      if (t.h_level[b] >= lv0 && ht(b)) c.add(P->fold_fd1 && t.h_is_leaf[b] ? 1 : 0, b, b);
+    P->job_dc2de = upload_job(P->arena, sorted_by_op(c), s, wide(c));
     if (P->f32t) {  // DC2DE at the leaves only: the downward pass carries check potentials
       GemmCols cl;
       for (int b : leaves_trg)
@@ -1455,7 +1534,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     for (int l = lv0 + 1; l <= t.depth; ++l) {
       GemmCols cl;
       for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b)
-        if (ht(b)) cl.add(octant(b), t.h_parent[b], b);
+        if (ht(b)) cl.add(octant(b) + (P->fold_fd1 && t.h_is_leaf[b] ? 8 : 0), t.h_parent[b], b);
       if (cl.op.empty()) continue;
       P->dn_levels.push_back(upload_job(P->arena, sorted_by_op(cl), s, wide(cl)));
       P->dn_lv.push_back(l);
@@ -1926,12 +2005,14 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   if (P.f32t) {
     // downward pass in FP32 on check potentials: qhat = U q~ + X rows (compressed), qhat(child) +=
     // L2L_q qhat(parent) level by level, then phi_dn = DC2DE qhat = fd2 (fd1 qhat) at the target leaves
-    // (split16: U, L2L_q and fd1 as split-FP16 products, their inputs split level by level)
+    // (split16: U, L2L_q and fd1 as split-FP16 products, their inputs split level by level; with fold_fd1
+    // the leaves' columns of the U and L2L products use fd1 U and fd1 L2L_q instead)
     if (fused_down) {
       const int NCr = P.comp->NCr;
       if (split16) {
         split_h3(P.q_t_f, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
-        gemm_h3(P.job_dc2de, P.comp->U_h3, P.comp->U_h3_scale, GemmDims{NC, NCr, 2 * NCr, NC}, P.phi_h3,
+        gemm_h3(P.job_dc2de, P.fold_fd1 ? P.comp->UF_h3 : P.comp->U_h3,
+                P.fold_fd1 ? P.comp->UF_h3_scale : P.comp->U_h3_scale, GemmDims{NC, NCr, 2 * NCr, NC}, P.phi_h3,
                 P.phi_h3_scale, qhat_f, kStore, s);
       } else {
         gemm_f32(P.job_dc2de, P.comp->U32, GemmDims{NC, NCr, NCr, NC}, P.q_t_f, qhat_f, kStore, s);
@@ -1947,25 +2028,32 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       if (split16 && big(P.dn_levels[i])) {  // split the parents' level, then qhat(child) += L2L_q qhat(parent)
         const int l = P.dn_lv[i], b0 = t.level_start[l - 1], b1 = t.level_start[l];
         split_h3(qhat_f + (size_t)b0 * NC, b1 - b0, NC, NC, xq + (size_t)b0 * 2 * NC, xq_scale + b0, s);
-        gemm_h3(P.dn_levels[i], D.l2lq_h3, D.l2lq_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, qhat_f,
-                kAdd, s);
+        gemm_h3(P.dn_levels[i], P.fold_fd1 ? D.l2lq_fold_h3 : D.l2lq_h3,
+                P.fold_fd1 ? D.l2lq_fold_h3_scale : D.l2lq_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale,
+                qhat_f, kAdd, s);
       } else {
-        gemm_f32(P.dn_levels[i], D.l2lq32, GemmDims::Sq(NC), qhat_f, qhat_f, kAdd, s);
+        gemm_f32(P.dn_levels[i], P.fold_fd1 ? D.l2lq_fold32 : D.l2lq32, GemmDims::Sq(NC), qhat_f, qhat_f, kAdd, s);
       }
     }
-    if (split16) {
-      split_h3(qhat_f, nb, NC, NC, xq, xq_scale, s);
-      gemm_h3(P.job_dn_leaf, D.fd1_h3, D.fd1_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, P.tmp_f, kStore,
-              s);
-    } else {
-      gemm_f32(P.job_dn_leaf, D.fd1, GemmDims::Sq(NC), qhat_f, P.tmp_f, kStore, s);
-    }
-    if (sig_split) {  // fd2 = us diag(inv_sig): 1/sigma in the split pass, us as split products
-      split_h3(P.tmp_f, nb, NC, NC, xq, xq_scale, s, D.inv_sig32);
+    if (P.fold_fd1) {  // the leaves' rows hold fd1 qhat: 1/sigma in the split pass, then us
+      split_h3(qhat_f, nb, NC, NC, xq, xq_scale, s, D.inv_sig32);
       gemm_h3(P.job_dn_leaf, D.us_h3, D.us_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, phi_dn_f, kStore,
               s);
     } else {
-      gemm_f32(P.job_dn_leaf, D.fd2, GemmDims::Sq(NC), P.tmp_f, phi_dn_f, kStore, s);
+      if (split16) {
+        split_h3(qhat_f, nb, NC, NC, xq, xq_scale, s);
+        gemm_h3(P.job_dn_leaf, D.fd1_h3, D.fd1_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, P.tmp_f,
+                kStore, s);
+      } else {
+        gemm_f32(P.job_dn_leaf, D.fd1, GemmDims::Sq(NC), qhat_f, P.tmp_f, kStore, s);
+      }
+      if (sig_split) {  // fd2 = us diag(inv_sig): 1/sigma in the split pass, us as split products
+        split_h3(P.tmp_f, nb, NC, NC, xq, xq_scale, s, D.inv_sig32);
+        gemm_h3(P.job_dn_leaf, D.us_h3, D.us_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, phi_dn_f,
+                kStore, s);
+      } else {
+        gemm_f32(P.job_dn_leaf, D.fd2, GemmDims::Sq(NC), P.tmp_f, phi_dn_f, kStore, s);
+      }
     }
   } else {
     // downward pass in FP64

@@ -34,6 +34,9 @@ struct Plan {
   // FP32 translations (KFMM_FP32, KFMM_FP32_M2L_SPLIT16): M2M and L2L on check potentials and factored
   // pseudo-inverses, in FP32 on FP32 buffers; otherwise the translations run in FP64
   bool f32t = false;
+  // split FP16 with the compressed M2L: U q~ and the L2L into a leaf carry the leaf's fd1 (the first factor of
+  // DC2DE), so a leaf's row of the downward pass holds fd1 qhat and no separate fd1 product runs
+  bool fold_fd1 = false;
   int64_t n_src = 0, n_trg = 0;
   int NC = 0, n_eq = 0;
   std::shared_ptr<DeviceOps> ops;
