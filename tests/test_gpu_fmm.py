@@ -135,6 +135,40 @@ def test_split16_m2l_matches_fp32(cuda, m2l_tol, p):
     assert e16 <= 1.02 * e32 + 1e-7
 
 
+@pytest.mark.parametrize("leaf", [64, 512])
+def test_split16_folded_and_unfolded_downward_pass(cuda, leaf):
+    """Split FP16 with the compressed M2L applies a leaf's fd1 (first DC2DE factor) inside the U and L2L
+    products that form its check potential, unless a leaf has an X list (then the check potential gets the X
+    sources as well and the separate fd1 product runs).  Leaves of at most 64 targets lose their X pairs to
+    the near field, so every leaf folds; leaves of up to 512 targets keep some.  Both forms against the FP32
+    evaluation of the same tree and against the oracle.  Adaptive input: half the points uniform in a cube,
+    half on a small sphere near one corner."""
+    from tests.fmm_cases import to_dev, K, G
+    from paper_1612_04082_amd import kfmm
+    rng = np.random.default_rng(leaf)
+    n = 8000
+    d = rng.normal(size=(n // 2, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    src = np.vstack([rng.uniform(size=(n // 2, 3)), 0.25 + 0.2 * d])
+    nrm = rng.normal(size=(n, 3))
+    nrm /= np.linalg.norm(nrm, axis=1)[:, None]
+    w, a, b = rng.uniform(0.5, 1.5, n), rng.normal(size=(n, 3)), rng.normal(size=(n, 3))
+    ref = run_oracle(src, nrm, w, a, b, od.DISP)
+    out = {}
+    for prec in (kfmm.FP32, kfmm.FP32_M2L_SPLIT16):
+        plan = kfmm.FmmPlan(to_dev(src), to_dev(nrm), to_dev(w), K=K, G=G, p=8, leaf_max=leaf, precision=prec,
+                            m2l_tol=3e-7)
+        out[prec] = plan.eval(od.DISP, to_dev(a), to_dev(b)).cpu().numpy()
+        leaf_x = bool((plan.target_lists() & 2).any())
+        plan.close()
+    assert leaf_x == (leaf == 512)
+    dd = rel_l2(out[kfmm.FP32_M2L_SPLIT16], out[kfmm.FP32])
+    e32, e16 = rel_l2(out[kfmm.FP32], ref), rel_l2(out[kfmm.FP32_M2L_SPLIT16], ref)
+    print(f"leaf {leaf} (leaf X lists: {leaf_x}): split16 vs fp32 {dd:.2e}, errors {e16:.2e} / {e32:.2e}")
+    assert dd < 1e-6
+    assert e16 <= 1.02 * e32 + 1e-7  # the fold adds no error (the method's own is 2.4e-5 on this cloud at p = 8)
+
+
 def test_profile_modes(cuda):
     """Phase timing (every phase in turn) and M2L-only timing leave the results bitwise unchanged."""
     from tests.fmm_cases import to_dev, K, G

@@ -64,8 +64,8 @@ PRECISIONS = {"fp64": (0, 0.0), "fp32": (1, 0.0), "fp32-comp": (1, 3e-7), "split
 
 @pytest.mark.parametrize("N,leaf,p", [(4000, 64, 8), (40, 64, 6), (600, 16, 6)])
 def test_periodic_matches_ewald(cuda, N, leaf, p):
-    """Many levels (W and X lists, V lists at level 1 through the images), a tree that is only the root
-    (near field with the 26 images, far images through the root operator), and a shallow tree (FP64)."""
+    """Many levels (W and X lists, V lists at level 1 through the images), few sources with many separate
+    targets (one level below the root), and a shallow tree (FP64)."""
     from paper_1612_04082_amd import kfmm
     lo, L = np.array([-0.3, 0.2, 1.0]), 1.7
     src, nrm, w, a, b = _cloud(N, lo, L, seed=N)
@@ -102,6 +102,22 @@ def test_periodic_precisions(cuda, mode):
         if kind not in _REF:  # the same inputs for every mode
             _REF[kind] = op.periodic(kind, trg, src, w, a=a, b=b, nrm=nrm, K=K, G=G, L=L)
         _check(got, _REF[kind], kind, 1e-5, mode)
+    plan.close()
+
+
+def test_periodic_one_box_tree_split16(cuda):
+    """A periodic tree that is only its root, in split FP16 with the compressed M2L: the root is a leaf whose
+    check potential receives the far images, so the downward pass keeps its separate fd1 product there."""
+    from paper_1612_04082_amd import kfmm
+    lo, L = np.array([-0.3, 0.2, 1.0]), 1.7
+    src, nrm, w, a, b = _cloud(40, lo, L, seed=40)
+    plan = kfmm.FmmPlan(_t(src), nrm=_t(nrm), w=_t(w), K=K, G=G, p=8, leaf_max=64, precision=3, m2l_tol=3e-7,
+                        cells=[(lo[0], lo[1], lo[2], L)])
+    assert plan.info()["n_box"] == 1  # 40 points, targets = sources
+    for kind in (od.DISP, od.STRESS):
+        got = plan.eval(kind, a=_t(a), b=_t(b)).cpu().numpy()
+        ref = op.periodic(kind, src, src, w, a=a, b=b, nrm=nrm, K=K, G=G, L=L)
+        _check(got, ref, kind, 1e-5, "one box split16")
     plan.close()
 
 
