@@ -36,7 +36,8 @@ namespace kfmm {
 
 // ------------------------------------------------------------------------ process-wide operator cache
 
-static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int tile_cols);
+static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int tile_cols = kGemmBN,
+                          const std::vector<int>* op_rank = nullptr);
 
 // Shared-basis compression of the M2L operators: K_o ~ U C_o U^T with one orthonormal basis U (n x r)
 // for every offset o.  U spans the dominant left singular space of [K_1 ... K_316]: the eigenvectors of
@@ -60,8 +61,15 @@ struct CompressedM2L {
   float* Mu_h3_scale = nullptr;
   float* Ut32 = nullptr;   // NCr x NC
   float* C32 = nullptr;    // 316 x NCr x NCr row-major
-  uint16_t* Ch3 = nullptr;      // C32 split into FP16 high / low parts (see split_h3), made on first use
-  float* Ch3_scale = nullptr;   // power-of-two scale per operator
+  // Per-offset rank (split FP16): C_o truncated to its leading r_o x r_o block (the basis is ordered by the
+  // singular values of all offsets together, and a far offset needs fewer of its vectors), r_o the smallest
+  // multiple of 32 whose dropped entries have a Frobenius norm below a third of the basis cutoff (absolute,
+  // like the cutoff itself).  Crk32 holds operator o in an NCr^2 slot as an r_o x r_o row-major block, the rest
+  // of the slot zero; the M2L tiles carry r_o (see k_gemm_h3).
+  std::vector<int> rank_o;  // per compact offset
+  float* Crk32 = nullptr;
+  uint16_t* Crk_h3 = nullptr;  // Crk32 split, made on first use
+  float* Crk_h3_scale = nullptr;
   uint16_t* U_h3 = nullptr;     // U32 split likewise (one operator)
   float* U_h3_scale = nullptr;
   // U and fd1 U (two NC x NCr operators, split FP16): the downward check potential of a box with children,
@@ -485,6 +493,39 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
     gemm_f64(j1, d.m2l64, GemmDims::Sq(NC), c->Ut64, T, kStore, s);
     gemm_f64(j2, c->Ut64, GemmDims{NCr, NC, NC, NCr}, T, C64, kStore, s);
   }
+  {  // per-offset ranks and the truncated operators
+    std::vector<double> hc((size_t)nops * NCr * NCr);
+    KFMM_HIP(hipStreamSynchronize(s));
+    KFMM_HIP(hipMemcpy(hc.data(), C64, sizeof(double) * hc.size(), hipMemcpyDeviceToHost));
+    const double drop2 = std::pow(tol / 3.0 * std::sqrt(lam[0]), 2);
+    c->rank_o.assign(nops, NCr);
+    std::vector<float> f((size_t)nops * NCr * NCr, 0.0f);
+    auto ranks = [&](int o0, int o1) {
+      for (int o = o0; o < o1; ++o) {
+        const double* C = hc.data() + (size_t)o * NCr * NCr;
+        double tot = 0;
+        for (size_t i = 0; i < (size_t)NCr * NCr; ++i) tot += C[i] * C[i];
+        int m = 64;
+        for (; m < NCr; m += 32) {
+          double kept = 0;
+          for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) kept += C[(size_t)i * NCr + j] * C[(size_t)i * NCr + j];
+          if (tot - kept <= drop2) break;
+        }
+        m = std::min(m, NCr);
+        c->rank_o[o] = m;
+        float* F = f.data() + (size_t)o * NCr * NCr;
+        for (int i = 0; i < m; ++i)
+          for (int j = 0; j < m; ++j) F[(size_t)i * m + j] = (float)C[(size_t)i * NCr + j];
+      }
+    };
+    const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nth; ++t) pool.emplace_back(ranks, nops * t / nth, nops * (t + 1) / nth);
+    for (auto& th : pool) th.join();
+    c->Crk32 = d.arena.get<float>(f.size());
+    KFMM_HIP(hipMemcpy(c->Crk32, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice));
+  }
   // DC2DE * U (columns k < r): rows k of Y = DC2DE u_k, transposed on the host
   {
     GemmCols cd;
@@ -631,7 +672,7 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     split_set(d.fd1, 1, sq, d.fd1_h3, d.fd1_h3_scale);
   }
   if (c) {
-    if (c->Ch3) {
+    if (c->Crk_h3) {
       KFMM_HIP(hipStreamSynchronize(s));
       return;
     }
@@ -639,9 +680,9 @@ static void ensure_split_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     split_set(c->Gv32, 1, (int64_t)c->NCr * d.NC, c->Gv_h3, c->Gv_h3_scale);
     split_set(c->Mu32, 1, (int64_t)c->NCr * d.NC, c->Mu_h3, c->Mu_h3_scale);
     const int64_t len = (int64_t)c->NCr * c->NCr;
-    c->Ch3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
-    c->Ch3_scale = d.arena.get<float>(nops);
-    split_h3(c->C32, nops, len, len, c->Ch3, c->Ch3_scale, s);
+    c->Crk_h3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
+    c->Crk_h3_scale = d.arena.get<float>(nops);
+    split_h3(c->Crk32, nops, len, len, c->Crk_h3, c->Crk_h3_scale, s);
   } else if (!d.m2l_h3) {
     const int64_t len = (int64_t)d.NC * d.NC;
     d.m2l_h3 = d.arena.get<uint16_t>((size_t)nops * 2 * len);
@@ -1163,7 +1204,8 @@ __global__ __launch_bounds__(256) void k_per_shift(const int* __restrict__ roots
 
 // ------------------------------------------------------------------------------------------ plan
 
-static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int tile_cols = kGemmBN) {
+static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int tile_cols,
+                          const std::vector<int>* op_rank) {
   GemmJob job;
   job.cols_per_tile = tile_cols;
   const int n = (int)cols.op.size();
@@ -1174,7 +1216,7 @@ static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int til
   while (i < n) {
     int j = i;
     while (j < n && cols.op[j] == cols.op[i] && j - i < tile_cols) ++j;
-    tiles.push_back(make_int4(cols.op[i], i, j - i, 0));
+    tiles.push_back(make_int4(cols.op[i], i, j - i, op_rank ? (*op_rank)[cols.op[i]] : 0));
     i = j;
   }
   job.n_tiles = (int)tiles.size();
@@ -1466,11 +1508,14 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
         KFMM_HIP(hipMemsetAsync(P->q_t, 0, sizeof(double) * nb * slot_len, s));
       }
     }
-    P->m2l_slots = P->arena.alloc(std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4));
+    const size_t slot_bytes = std::max<size_t>(1, (size_t)np_ * slot_len) * (o.precision == KFMM_FP64 ? 8 : 4);
+    P->m2l_slots = P->arena.alloc(slot_bytes);
+    KFMM_HIP(hipMemsetAsync(P->m2l_slots, 0, slot_bytes, s));  // rows past a pair's rank stay zero
     // column tiles: 128 (FP32 and split FP16; 160 x 128 workgroup tiles for the split-FP16 compressed
     // contraction when its rank is a multiple of 160), 64 otherwise
     const int m2l_cols = fp32m2l || split16 ? 2 * kGemmBN : kGemmBN;
-    P->job_m2l = upload_job(P->arena, sc, s, m2l_cols);
+    // split FP16 with the compressed M2L: every tile carries its offset's rank (k_gemm_h3)
+    P->job_m2l = upload_job(P->arena, sc, s, m2l_cols, split16 && P->comp ? &P->comp->rank_o : nullptr);
     if (split16) {
       ensure_split_ops(*P->ops, P->comp.get(), s);
       // a leaf's downward check potential is only ever multiplied by fd1, so that factor can ride on the
@@ -1938,8 +1983,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     if (split16) split_h3(P.phi_t, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
     mark(KFMM_PH_M2L);
     m2l_begin();
-    if (split16)
-      gemm_h3(P.job_m2l, C.Ch3, C.Ch3_scale, GemmDims{NCr, NCr, 2 * NCr, NCr}, P.phi_h3, P.phi_h3_scale,
+    if (split16)  // tiles of rank r_o: the leading r_o rows of each slot, contraction over r_o
+      gemm_h3(P.job_m2l, C.Crk_h3, C.Crk_h3_scale, GemmDims{NCr, NCr, 2 * NCr, NCr}, P.phi_h3, P.phi_h3_scale,
               (float*)P.m2l_slots, kStore, s);
     else
       gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
@@ -2179,15 +2224,27 @@ void plan_work(const Plan& P, int kind, bool sl, bool dl, double* flops, double*
     gemm(KFMM_PH_M2M, n, n, n_up_child, 8 * ob);
   }
   if (comp) gemm(KFMM_PH_M2L_PREP, r, n, n_up, ob);  // phi~ = U^T phi_up
-  flops[KFMM_PH_M2L] = 2.0 * r * r * (double)P.n_v_pairs;
-  bytes[KFMM_PH_M2L] = 316.0 * r * r * mb + (n_vsrc + n_vtrg) * r * mb;
+  if (comp && P.prec == KFMM_FP32_M2L_SPLIT16) {  // per-offset ranks: r_o^2 per pair and per operator
+    const CompressedM2L& C = *P.comp;
+    double f = 0, ob2 = 0;
+    for (size_t i = 0; i < t.h_v_off.size(); ++i) {
+      const double m = C.rank_o[P.ops->m2l_index[t.h_v_off[i]]];
+      f += 2.0 * m * m;
+    }
+    for (int m : C.rank_o) ob2 += (double)m * m * mb;
+    flops[KFMM_PH_M2L] = f;
+    bytes[KFMM_PH_M2L] = ob2 + (n_vsrc + n_vtrg) * r * mb;
+  } else {
+    flops[KFMM_PH_M2L] = 2.0 * r * r * (double)P.n_v_pairs;
+    bytes[KFMM_PH_M2L] = 316.0 * r * r * mb + (n_vsrc + n_vtrg) * r * mb;
+  }
   flops[KFMM_PH_S2L] = x_pts * neq * f_s2m;
   bytes[KFMM_PH_S2L] = x_pts * pt_bytes;
   if (comp) gemm(KFMM_PH_DOWN, n, r, n_vtrg, ob);  // qhat = U q~
   else if (!f32t) gemm(KFMM_PH_DOWN, n, n, n_dn, ob);  // DC2DE per box (FP64 translations)
   gemm(KFMM_PH_DOWN, n, n, n_dn_child, 8 * ob);       // L2L, parents into children
   if (f32t) {
-    gemm(KFMM_PH_DOWN, n, n, n_tleaf, ob);  // fd1
+    if (!P.fold_fd1) gemm(KFMM_PH_DOWN, n, n, n_tleaf, ob);  // fd1 (folded into U and L2L_q otherwise)
     gemm(KFMM_PH_DOWN, n, n, n_tleaf, ob);  // fd2
   }
   flops[KFMM_PH_NEAR] = (double)P.n_u_pairs * f_src;

@@ -31,7 +31,8 @@ inline int gemm_pad(int n) {
 struct GemmJob {  // device arrays describing one launch
   int n_tiles = 0;
   int cols_per_tile = 64;   // 64 or 128 (wide tiles: FP32 only)
-  int4* tiles = nullptr;    // {op, first column, column count, unused}
+  int4* tiles = nullptr;    // {op, first column, column count, rank}: rank 0 = the whole operator; a rank m
+                            // > 0 (split FP16, 128-column tiles) takes the leading m x m block (k_gemm_h3)
   int* in_idx = nullptr;    // per column: source box (X column)
   int* out_idx = nullptr;   // per column: destination box (Y column)
   double* scale = nullptr;  // per column factor or nullptr

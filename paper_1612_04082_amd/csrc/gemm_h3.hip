@@ -40,10 +40,16 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
   const int lid = xcd_logical_id();
   const int4 tile = tiles[lid / gridDim.y];
   const int r0 = (lid % gridDim.y) * BM;
+  // A tile of rank m (tile.w = m > 0, a multiple of 32; operators in M x K slots, square) multiplies the
+  // leading m x m block of its operator, stored row-major with rows of m values at the start of the slot and
+  // zeros after it: row blocks at or past m have nothing to do, a row block across m reads rows of zeros
+  // (inside the slot) and stores only its rows below m, and the contraction runs over m.
+  const int mr = tile.w > 0 ? tile.w : dm.M, kk = tile.w > 0 ? tile.w : dm.K;
+  if (r0 >= mr) return;  // the whole workgroup, before any barrier
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, g = lane >> 4;
-  const int rowq = dm.K / 4;  // 16-byte pieces per split row
-  const u32x4_t* Aop = A + ((size_t)tile.x * dm.M + r0) * rowq;
+  const int rowq = kk / 4;  // 16-byte pieces per split row
+  const u32x4_t* Aop = A + (size_t)tile.x * ((size_t)dm.M * dm.K / 4) + (size_t)r0 * rowq;
   const u32x4_t* xc[TN];
   bool ok[TN];
   int src[TN];
@@ -118,7 +124,7 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
       if (t + 2 < TM) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
     }
   };
-  const int ns = dm.K / 32;
+  const int ns = kk / 32;
   load(0);
   stash(0);
   __syncthreads();
@@ -139,6 +145,7 @@ __global__ __launch_bounds__(256) void k_gemm_h3(const u32x4_t* __restrict__ A, 
     float* ycol = Y + (size_t)out_idx[col] * dm.ldy + r0 + 4 * g;
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
+      if (r0 + 16 * t >= mr) break;  // rows past the tile's rank (16-row blocks: m is a multiple of 32)
       const float4_t v = (acc[t][u] * sa) * sc;  // scales applied one at a time (no product underflow)
       if (mode == kStore) {
         *(float4_t*)(ycol + t * 16) = v;

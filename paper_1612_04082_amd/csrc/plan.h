@@ -81,6 +81,7 @@ struct Plan {
   int *m2l_red_box = nullptr, *m2l_red_off = nullptr, *m2l_red_idx = nullptr;
   std::vector<UpLevel> up_levels;
   std::vector<GemmJob> dn_levels;
+
   std::vector<int> dn_lv;  // level of the children of each dn_levels job
   // per-box coefficient buffers (n_box x NC): FP64 translations
   double *q_up = nullptr, *phi_up = nullptr, *phi_dn = nullptr, *tmp = nullptr;
