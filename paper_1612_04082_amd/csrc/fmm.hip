@@ -1882,7 +1882,9 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   mark(KFMM_PH_M2M);
   for (const UpLevel& U : P.up_levels) {
     if (P.f32t) {  // qhat_up(parent) = sum_c M2M_q_c qhat_up(child); split16: parents' split rows too
-      if (split16 && big(U.job))
+      // (split16: every level as split products, the children's split rows already written by S2M and by the
+      // reduction of the level below)
+      if (split16)
         gemm_h3(U.job, D.m2mq_h3, D.m2mq_h3_scale, GemmDims{NC, NC, 2 * NC, NC}, xq, xq_scale, P.tmp_f, kStore, s);
       else
         gemm_f32(U.job, D.m2mq32, GemmDims::Sq(NC), P.q_f, P.tmp_f, kStore, s);

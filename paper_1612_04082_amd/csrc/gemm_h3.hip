@@ -370,7 +370,9 @@ void gemm_h3(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDi
     else
       launch_h3<6, 1>(job, A, a_scale, d, X, x_scale, Y, mode, s);
   } else {
-    if (nt * (d.M / 64) < 512)
+    if (nt * (d.M / 64) < 160)  // 32-row blocks: twice the workgroups (8 operators, 180 columns: 7.6 vs 9.5 us)
+      launch_h3k<2, 1, 2, 2>(job, A, a_scale, d, X, x_scale, Y, mode, s);
+    else if (nt * (d.M / 64) < 512)
       launch_h3k<4, 1, 2, 2>(job, A, a_scale, d, X, x_scale, Y, mode, s);
     else
       launch_h3<4, 1>(job, A, a_scale, d, X, x_scale, Y, mode, s);
