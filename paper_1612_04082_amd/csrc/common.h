@@ -75,6 +75,14 @@ __device__ __forceinline__ float rsqrt_t<float>(float x) { return __frsqrt_rn(x)
 template <>
 __device__ __forceinline__ double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 
+// 1/r, or 0 for a coincident pair (r2 = 0): every term of the pair kernels below carries a factor 1/r, so a
+// coincident pair then adds exact zeros and a loop over pairs needs no branch.
+template <typename T>
+__device__ __forceinline__ T rsqrt_or_zero(T r2) {
+  const T ir = rsqrt_t<T>(r2);
+  return r2 > T(0) ? ir : T(0);
+}
+
 // Displacement at a target from one source (d = source - target, r2 = |d|^2 > 0):
 //   v += U(d) wa + P(d, n) wb           (eq. disp_1, eq. disp_2 read with the leading minus)
 // The prefactors cU, cP are applied by the caller after the sum (they are common to all pairs).
@@ -118,10 +126,10 @@ __device__ __forceinline__ void disp_pair(T dx, T dy, T dz, T r2, const T* wa, c
 // expanded as v_i += t wa'_i + sc d_i - fp wb'_i - c2 n_i with t = (3-4nu)/r, fp = (1-2nu)(d.n)/r^3,
 // sc = (d.wa')/r^3 - 3 (d.n)(d.wb')/r^5 + (1-2nu)(n.wb')/r^3, c2 = (1-2nu)(d.wb')/r^3 (about 44 operations per
 // pair; separate U and P accumulators with the prefactors applied at the end take about 51).
+// With ir = 1/r given (0 for a coincident pair: no contribution).
 template <typename T, bool SL, bool DL>
-__device__ __forceinline__ void disp_pair_f(T dx, T dy, T dz, T r2, const T* wa, const T* wb, T nwb, T nx, T ny,
-                                            T nz, const KConst<T>& k, T* v) {
-  const T ir = rsqrt_t<T>(r2);
+__device__ __forceinline__ void disp_pair_f_ir(T dx, T dy, T dz, T ir, const T* wa, const T* wb, T nwb, T nx, T ny,
+                                               T nz, const KConst<T>& k, T* v) {
   const T ir2 = ir * ir, ir3 = ir2 * ir;
   T sc = T(0), t = T(0), fp = T(0), c2 = T(0);
   if (SL) {
@@ -146,6 +154,11 @@ __device__ __forceinline__ void disp_pair_f(T dx, T dy, T dz, T r2, const T* wa,
     if (DL) acc -= fp * wb[i] + c2 * n[i];
     v[i] = acc;
   }
+}
+template <typename T, bool SL, bool DL>
+__device__ __forceinline__ void disp_pair_f(T dx, T dy, T dz, T r2, const T* wa, const T* wb, T nwb, T nx, T ny,
+                                            T nz, const KConst<T>& k, T* v) {
+  disp_pair_f_ir<T, SL, DL>(dx, dy, dz, rsqrt_t<T>(r2), wa, wb, nwb, nx, ny, nz, k, v);
 }
 
 // Stress at a target from one source:  s_ij += D_kij wa_k + S_kij wb_k   (eq. stress_2 with 8 pi,

@@ -887,7 +887,22 @@ __global__ __launch_bounds__(256) void k_leaf_eval(
     // far-field points carry only a single-layer density (in sd[0..2])
     auto flush = [&](int n, bool near) {
       __syncthreads();
-      if (act) {
+      if (act && !near && KIND == 0) {
+        // L2T: each equivalent point read once for both targets, no branch (a target on the point, which the
+        // check radius rules out anyway, would add zeros; targets past nt are computed and never stored).
+        // The near field keeps its branches: alone it would run faster without them, but beside the main
+        // stream's matrix-core work the evaluation as a whole ran slower.
+        for (int j = sl; j < n; j += S) {
+          const T px = sp[j][0], py = sp[j][1], pz = sp[j][2];
+          const T wa[3] = {sd[j][0], sd[j][1], sd[j][2]};
+#pragma unroll
+          for (int q = 0; q < TPL; ++q) {
+            const T dx = px - x[q][0], dy = py - x[q][1], dz = pz - x[q][2];
+            const T ir = rsqrt_or_zero(dx * dx + dy * dy + dz * dz);
+            disp_pair_f_ir<T, true, false>(dx, dy, dz, ir, wa, wa, T(0), T(0), T(0), T(0), kc, aP[q]);
+          }
+        }
+      } else if (act) {
         for (int j = sl; j < n; j += S) {
           const T px = sp[j][0], py = sp[j][1], pz = sp[j][2];
 #pragma unroll
