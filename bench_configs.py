@@ -169,7 +169,7 @@ def cantilever(args):
         t0 = time.time()
         x, u, t, st = kfmm.bem_solve(dtri, dbc, dval, K=K, G=G, tol=1e-6, restart=200, max_iter=3000, p=8,
                                      leaf_max=128, precision=kfmm.FP64, svd_eps=args.svd_eps, allow_noconv=True,
-                                     precond=pcm)
+                                     precond=pcm, m2l_tol=args.bem_m2l_tol)
         torch.cuda.synchronize()
         solve_s = time.time() - t0
         solves["two-level" if pcm == kfmm.PC_TWO_LEVEL else "none"] = dict(
@@ -187,7 +187,7 @@ def cantilever(args):
     ref_rows = ob.matvec_rows(prob["tri"], prob["bc_type"], xs, rows, K, G, nthreads=_cores())
     t_rows = time.time() - tc
     gpu_full = kfmm.bem_matvec(dtri, dbc, dval, x=_t(xs), which=0, K=K, G=G, p=8, precision=kfmm.FP64,
-                               svd_eps=args.svd_eps or 1e-7).cpu().numpy()
+                               svd_eps=args.svd_eps or 1e-7, m2l_tol=args.bem_m2l_tol).cpu().numpy()
     gpu_rows = gpu_full[rows]
     matvec_err = float(np.linalg.norm(gpu_rows - ref_rows) / np.linalg.norm(ref_rows))
     # residual floor of the solution measured with the exact operator: product error eps times
@@ -196,7 +196,7 @@ def cantilever(args):
     xsol = x.cpu().numpy().copy()
     xsol[prob["bc_type"] == 0] /= scale_t  # solver units
     b_gpu = kfmm.bem_matvec(dtri, dbc, dval, which=1, K=K, G=G, p=8, precision=kfmm.FP64,
-                            svd_eps=args.svd_eps or 1e-7).cpu().numpy()
+                            svd_eps=args.svd_eps or 1e-7, m2l_tol=args.bem_m2l_tol).cpu().numpy()
     kx = float(np.linalg.norm(gpu_full) / np.linalg.norm(xs) * np.linalg.norm(xsol) / np.linalg.norm(b_gpu))
     residual = dict(norm_A_x_over_b=kx, product_err_random=matvec_err, floor_estimate=matvec_err * kx)
     if args.full_residual:
@@ -237,7 +237,8 @@ def cantilever(args):
     return dict(metric="BEM solve time (s), cantilever 8:1:1 with 64 holes", value=solve_s, unit="s",
                 higher_is_better=False, dtype="f64",
                 config=dict(workload=f"cantilever [0,32]x[0,4]^2, h=2/9, 64 holes: {T} elements, {16 * T} quadrature "
-                                     f"points, {3 * T} unknowns; GMRES(200) tol 1e-6, FMM p=8 leaf<=128 FP64",
+                                     f"points, {3 * T} unknowns; GMRES(200) tol 1e-6, FMM p=8 leaf<=128 FP64, "
+                                     f"m2l_tol {args.bem_m2l_tol:g}",
                             precond=args.precond),
                 svd_eps=args.svd_eps, gmres=solves,
                 matvec_rows_rel_err=matvec_err, oracle_rows_seconds=t_rows, residual_vs_exact=residual,

@@ -74,10 +74,13 @@ typedef struct {
   double svd_eps;     /* relative singular-value cutoff of the check-to-equivalent pseudo-inverse; 0 -> 1e-8 */
   int max_depth;      /* deepest octree level; 0 -> 16 */
   size_t mem_limit;   /* bytes of device memory the plan may use; 0 = no limit */
-  double m2l_tol;     /* KFMM_FP32, KFMM_FP32_M2L_SPLIT16, KFMM_FP32_TRANS64: > 0 compresses the M2L onto one
-                         shared basis, keeping the singular directions above m2l_tol (relative) of
-                         sum_o K_o K_o^T's square root, their count rounded up to the GEMM padding
-                         (fmm_info.m2l_rank); 0 = dense */
+  double m2l_tol;     /* > 0 compresses the M2L onto one shared basis, keeping the singular directions above
+                         m2l_tol (relative) of sum_o K_o K_o^T's square root, their count rounded up to the GEMM
+                         padding (fmm_info.m2l_rank); 0 = dense.  Every precision: KFMM_FP64 contracts in FP64
+                         (with FP64 translations), the others in FP32 or split FP16.  With KFMM_FP64 and
+                         KFMM_FP32_M2L_SPLIT16 each offset's operator is further cut to its leading r_o x r_o
+                         block, r_o the smallest multiple of 32 whose dropped part stays below m2l_tol / 3 in the
+                         same absolute scale */
 } fmm_opts;
 
 typedef struct kfmm_plan* kfmm_plan_t;

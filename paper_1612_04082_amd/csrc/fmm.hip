@@ -68,6 +68,8 @@ struct CompressedM2L {
   // of the slot zero; the M2L tiles carry r_o (see k_gemm_h3).
   std::vector<int> rank_o;  // per compact offset
   float* Crk32 = nullptr;
+  double* C64 = nullptr;     // 316 x NCr x NCr row-major, FP64
+  double* Crk64 = nullptr;   // the same truncated layout as Crk32 in FP64 (KFMM_FP64), made on first use
   uint16_t* Crk_h3 = nullptr;  // Crk32 split, made on first use
   float* Crk_h3_scale = nullptr;
   uint16_t* U_h3 = nullptr;     // U32 split likewise (one operator)
@@ -477,7 +479,7 @@ static std::shared_ptr<CompressedM2L> get_compressed(DeviceOps& d, double tol, h
   KFMM_HIP(hipMemcpy(c->Ut32, Ut32.data(), sizeof(float) * Ut32.size(), hipMemcpyHostToDevice));
   // T_o = K_o U (columns j < r), then C_o(:, j) = U^T T_o(:, j) written as row j of C_{-o}
   double* T = tmp.get<double>((size_t)nops * r * NC);
-  double* C64 = tmp.get<double>((size_t)nops * NCr * NCr);
+  double* C64 = c->C64 = d.arena.get<double>((size_t)nops * NCr * NCr);
   KFMM_HIP(hipMemsetAsync(C64, 0, sizeof(double) * nops * NCr * NCr, s));
   std::vector<int> neg(nops, -1);
   for (int k343 = 0; k343 < 343; ++k343)
@@ -651,6 +653,24 @@ static void ensure_fold_ops(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
     split_h3(uf, 2, len, len, c->UF_h3, c->UF_h3_scale, s);
   }
   KFMM_HIP(hipStreamSynchronize(s));
+}
+
+// The per-offset truncated operators in FP64 (KFMM_FP64 with the compressed M2L), made once per device and basis.
+static void ensure_rank64(DeviceOps& d, CompressedM2L* c, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(d.h3_mutex);
+  if (c->Crk64) return;
+  const int nops = 316, NCr = c->NCr;
+  const size_t sq = (size_t)NCr * NCr;
+  std::vector<double> hc((size_t)nops * sq), f((size_t)nops * sq, 0.0);
+  KFMM_HIP(hipStreamSynchronize(s));
+  KFMM_HIP(hipMemcpy(hc.data(), c->C64, sizeof(double) * hc.size(), hipMemcpyDeviceToHost));
+  for (int o = 0; o < nops; ++o) {
+    const int m = c->rank_o[o];
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) f[o * sq + (size_t)i * m + j] = hc[o * sq + (size_t)i * NCr + j];
+  }
+  c->Crk64 = d.arena.get<double>(f.size());
+  KFMM_HIP(hipMemcpy(c->Crk64, f.data(), sizeof(double) * f.size(), hipMemcpyHostToDevice));
 }
 
 // Split-FP16 copies of the M2L operators (dense, or the compressed C_o of c), made once per device.
@@ -1232,6 +1252,7 @@ static GemmJob upload_job(Arena& a, const GemmCols& cols, hipStream_t s, int til
     int j = i;
     while (j < n && cols.op[j] == cols.op[i] && j - i < tile_cols) ++j;
     tiles.push_back(make_int4(cols.op[i], i, j - i, op_rank ? (*op_rank)[cols.op[i]] : 0));
+    job.ranked = job.ranked || op_rank != nullptr;
     i = j;
   }
   job.n_tiles = (int)tiles.size();
@@ -1502,7 +1523,8 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     int slot_len = D.NC;
     const bool split16 = o.precision == KFMM_FP32_M2L_SPLIT16;
     const bool fp32m2l = o.precision == KFMM_FP32 || o.precision == KFMM_FP32_TRANS64;
-    if ((fp32m2l || split16) && o.m2l_tol > 0) {
+    const bool comp64 = o.precision == KFMM_FP64 && o.m2l_tol > 0;  // FP64 contractions on the basis
+    if ((fp32m2l || split16 || comp64) && o.m2l_tol > 0) {
       // compressed M2L: phi~ = U^T phi for every source box, r x r contractions per pair, and the downward
       // pass starts from q~ with DC2DE * U
       P->comp = get_compressed(*P->ops, o.m2l_tol, s);
@@ -1511,9 +1533,15 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
       for (int b2 = 0; b2 < nb; ++b2)
         if (t.h_src_e[b2] > t.h_src_b[b2]) cu.add(0, b2, b2);
       // split FP16: 64-column tiles (a few thousand boxes in 128-column tiles leave most compute units idle)
-      P->job_ut = upload_job(P->arena, cu, s, split16 ? kGemmBN : 2 * kGemmBN);
-      P->phi_t = P->arena.get<float>((size_t)nb * slot_len);
-      KFMM_HIP(hipMemsetAsync(P->phi_t, 0, sizeof(float) * nb * slot_len, s));  // boxes without sources
+      P->job_ut = upload_job(P->arena, cu, s, split16 || comp64 ? kGemmBN : 2 * kGemmBN);
+      if (comp64) {
+        P->phi_t64 = P->arena.get<double>((size_t)nb * slot_len);
+        KFMM_HIP(hipMemsetAsync(P->phi_t64, 0, sizeof(double) * nb * slot_len, s));
+        ensure_rank64(*P->ops, P->comp.get(), s);
+      } else {
+        P->phi_t = P->arena.get<float>((size_t)nb * slot_len);
+        KFMM_HIP(hipMemsetAsync(P->phi_t, 0, sizeof(float) * nb * slot_len, s));  // boxes without sources
+      }
       // rows of boxes without V lists stay zero: the downward pass applies DC2DE * U to every box
       if (P->f32t) {
         P->q_t_f = P->arena.get<float>((size_t)nb * slot_len);
@@ -1530,7 +1558,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
     // contraction when its rank is a multiple of 160), 64 otherwise
     const int m2l_cols = fp32m2l || split16 ? 2 * kGemmBN : kGemmBN;
     // split FP16 with the compressed M2L: every tile carries its offset's rank (k_gemm_h3)
-    P->job_m2l = upload_job(P->arena, sc, s, m2l_cols, split16 && P->comp ? &P->comp->rank_o : nullptr);
+    P->job_m2l = upload_job(P->arena, sc, s, m2l_cols, (split16 || comp64) && P->comp ? &P->comp->rank_o : nullptr);
     if (split16) {
       ensure_split_ops(*P->ops, P->comp.get(), s);
       // a leaf's downward check potential is only ever multiplied by fd1, so that factor can ride on the
@@ -1603,7 +1631,7 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   // periodic cells: the images beyond the 3 x 3 x 3 block act on each root through one operator, added
   // to the root's downward check potential like an M2L (unit half-width frame, so no per-box scale)
   if (P->periodic) {
-    ensure_periodic_ops(*P->ops, p, P->el, P->f32t, !P->f32t && o.precision != KFMM_FP64 && P->comp != nullptr);
+    ensure_periodic_ops(*P->ops, p, P->el, P->f32t, !P->f32t && P->comp != nullptr);
     GemmCols c, cc;
     for (int b = t.level_start[0]; b < t.level_start[1]; ++b)
       if (hs(b) && ht(b)) {
@@ -1959,7 +1987,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
   double* qhat = P.q_up;  // reuse: the S2M potentials are consumed (FP64 translations)
   float* qhat_f = P.q_f;  // the same with FP32 translations
   const bool fp32m2l = P.prec == KFMM_FP32 || P.prec == KFMM_FP32_TRANS64;
-  const bool fused_down = (fp32m2l || split16) && P.comp;  // DC2DE * U applied to q~ (no qhat)
+  const bool comp64 = P.prec == KFMM_FP64 && P.comp;          // FP64 contractions on the basis
+  const bool fused_down = (fp32m2l || split16 || comp64) && P.comp;  // DC2DE * U applied to q~ (no qhat)
   if (!fused_down) {
     if (P.f32t)
       hipLaunchKernelGGL(k_fill_zero<float>, dim3((unsigned)((nbc + 255) / 256)), dim3(256), 0, s, (int64_t)nbc,
@@ -1977,7 +2006,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     w_eval(side);
     KFMM_HIP(hipEventRecord(P.join_ev, side));
   }
-  if (P.prec == KFMM_FP64) {
+  if (P.prec == KFMM_FP64 && !comp64) {  // dense FP64 M2L: slots of NC values, tiles without a rank
+    KFMM_REQUIRE(!P.job_m2l.ranked, "internal: dense FP64 M2L with ranked tiles");
     mark(KFMM_PH_M2L);
     m2l_begin();
     gemm_f64(P.job_m2l, D.m2l64, GemmDims::Sq(NC), P.phi_up, (double*)P.m2l_slots, kStore, s);
@@ -1995,6 +2025,8 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
       gemm_h3(P.job_ut, C.Gv_h3, C.Gv_h3_scale, GemmDims{NCr, NC, 2 * NC, NCr}, xq, xq_scale, P.phi_t, kStore, s);
     else if (P.f32t)  // phi~ = U^T UC2UE qhat = G (fu1 qhat)
       gemm_f32(P.job_ut, C.G32, GemmDims{NCr, NC, NC, NCr}, P.tmp_f, P.phi_t, kStore, s);
+    else if (comp64)
+      gemm_f64(P.job_ut, C.Ut64, GemmDims{NCr, NC, NC, NCr}, P.phi_up, P.phi_t64, kStore, s);
     else
       gemm_f32(P.job_ut, C.Ut32, GemmDims{NCr, NC, NC, NCr}, (const float*)P.phi_up_lo, P.phi_t, kStore, s);
     if (split16) split_h3(P.phi_t, nb, NCr, NCr, P.phi_h3, P.phi_h3_scale, s);
@@ -2003,12 +2035,17 @@ static void eval_t(Plan& P, int kind, const double* a, const double* b, double* 
     if (split16)  // tiles of rank r_o: the leading r_o rows of each slot, contraction over r_o
       gemm_h3(P.job_m2l, C.Crk_h3, C.Crk_h3_scale, GemmDims{NCr, NCr, 2 * NCr, NCr}, P.phi_h3, P.phi_h3_scale,
               (float*)P.m2l_slots, kStore, s);
+    else if (comp64)  // the same in FP64
+      gemm_f64(P.job_m2l, C.Crk64, GemmDims::Sq(NCr), P.phi_t64, (double*)P.m2l_slots, kStore, s);
     else
       gemm_f32(P.job_m2l, C.C32, GemmDims::Sq(NCr), (const float*)P.phi_t, (float*)P.m2l_slots, kStore, s);
     m2l_end();
     mark(KFMM_PH_M2L_RED);
     if (P.m2l_red_n) {
-      if (P.f32t)
+      if (comp64)
+        hipLaunchKernelGGL((k_slot_reduce<double, double>), dim3(P.m2l_red_n), dim3(reduce_block<double>(NCr)), 0,
+                           s, P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const double*)P.m2l_slots, P.q_t, NCr);
+      else if (P.f32t)
         hipLaunchKernelGGL((k_slot_reduce<float, float>), dim3(P.m2l_red_n), dim3(reduce_block<float>(NCr)), 0, s,
                            P.m2l_red_box, P.m2l_red_off, P.m2l_red_idx, (const float*)P.m2l_slots, P.q_t_f, NCr);
       else
@@ -2241,7 +2278,7 @@ void plan_work(const Plan& P, int kind, bool sl, bool dl, double* flops, double*
     gemm(KFMM_PH_M2M, n, n, n_up_child, 8 * ob);
   }
   if (comp) gemm(KFMM_PH_M2L_PREP, r, n, n_up, ob);  // phi~ = U^T phi_up
-  if (comp && P.prec == KFMM_FP32_M2L_SPLIT16) {  // per-offset ranks: r_o^2 per pair and per operator
+  if (comp && (P.prec == KFMM_FP32_M2L_SPLIT16 || P.prec == KFMM_FP64)) {  // per-offset ranks: r_o^2 per pair
     const CompressedM2L& C = *P.comp;
     double f = 0, ob2 = 0;
     for (size_t i = 0; i < t.h_v_off.size(); ++i) {

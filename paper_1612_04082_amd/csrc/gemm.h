@@ -32,10 +32,11 @@ struct GemmJob {  // device arrays describing one launch
   int n_tiles = 0;
   int cols_per_tile = 64;   // 64 or 128 (wide tiles: FP32 only)
   int4* tiles = nullptr;    // {op, first column, column count, rank}: rank 0 = the whole operator; a rank m
-                            // > 0 (split FP16, 128-column tiles) takes the leading m x m block (k_gemm_h3)
+                            // > 0 takes the leading m x m block (k_gemm_h3 with 128-column tiles, k_gemm_f)
   int* in_idx = nullptr;    // per column: source box (X column)
   int* out_idx = nullptr;   // per column: destination box (Y column)
   double* scale = nullptr;  // per column factor or nullptr
+  bool ranked = false;      // some tile has a rank (split FP16: k_gemm_h3; FP64 / FP32: the tiled kernel)
 };
 
 // Host-side description: (op, in, out, scale) per column, grouped by op into tiles.

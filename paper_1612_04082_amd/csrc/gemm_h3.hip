@@ -347,6 +347,7 @@ void gemm_h3(const GemmJob& job, const uint16_t* A, const float* a_scale, GemmDi
              const float* x_scale, float* Y, int mode, hipStream_t s) {
   if (job.n_tiles == 0) return;
   KFMM_REQUIRE(job.cols_per_tile <= 2 * kGemmBN, "gemm_h3: at most 128 columns per tile");
+  KFMM_REQUIRE(!job.ranked || job.cols_per_tile > kGemmBN, "gemm_h3: tiles with a rank need 128-column tiles");
   KFMM_REQUIRE(d.K % 32 == 0 && d.K >= 64 && d.ldx % 8 == 0 && d.ldx >= 2 * d.K, "gemm_h3: bad K or ldx");
   if (mode == kStore) KFMM_REQUIRE(d.ldy % 4 == 0, "gemm_h3: ldy must be a multiple of 4 for vector stores");
   KFMM_REQUIRE(d.M % 96 == 0 || d.M % 64 == 0, "gemm_h3: M must be a multiple of 96 or 64");

@@ -59,6 +59,11 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
   const int lid = xcd_logical_id();
   const int4 tile = tiles[lid / gridDim.y];
   const int r0 = (lid % gridDim.y) * BM;
+  // a tile of rank m (tile.w = m > 0, a multiple of 32; square operators in M x K slots) multiplies the leading
+  // m x m block of its operator, stored row-major with rows of m values at the start of the slot and zeros
+  // after it (as in k_gemm_h3)
+  const int mr = tile.w > 0 ? tile.w : dm.M, kk = tile.w > 0 ? tile.w : dm.K;
+  if (r0 >= mr) return;  // the whole workgroup, before any barrier
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T* Aop = A + (size_t)tile.x * dm.M * dm.K;
   typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type vec_t;
@@ -71,7 +76,7 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
     for (int e = 0; e < A_VEC; ++e) {
       int lin = tid + 256 * e;  // vector index in the tile, row-major
       int row = lin / (BK / VA), kv = lin % (BK / VA);
-      ra[e] = *(const vec_t*)(Aop + (size_t)(r0 + row) * dm.K + k0 + kv * VA);
+      ra[e] = *(const vec_t*)(Aop + (size_t)(r0 + row) * kk + k0 + kv * VA);
     }
 #pragma unroll
     for (int e = 0; e < B_ELEMS / VA; ++e) {
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
       }
     }
   };
-  const int nk = dm.K / BK;
+  const int nk = kk / BK;
   load(0);
   stash(0);
   if constexpr (NBUF == 2) {
@@ -156,12 +161,14 @@ __global__ __launch_bounds__(256) void k_gemm_f(const T* __restrict__ A, GemmDim
     TY* ycol = Y + (size_t)out_idx[col] * dm.ldy + r0;
     const TY sc = scale ? (TY)scale[col] : TY(1);
 #pragma unroll
-    for (int t = 0; t < TM; ++t)
+    for (int t = 0; t < TM; ++t) {
+      if (r0 + 16 * t >= mr) break;  // rows past the tile's rank
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = sizeof(T) == 8 ? t * 16 + (lane >> 4) + 4 * v : t * 16 + 4 * (lane >> 4) + v;
         store_out(ycol + row, sc * (TY)acc[t][u][v], mode);
       }
+    }
   }
 }
 
@@ -280,6 +287,7 @@ inline void check_dims(const GemmDims& d) {
 // crossover, measured on translation-pass shapes (NC = 960, 1 or 8 operators, FP64 with 64-column and
 // FP32 with 128-column tiles), sits near 20k tile columns x row blocks.
 inline bool use_split_k(const GemmJob& job, const GemmDims& d, int kernel) {
+  if (job.ranked) return false;  // tiles of a given rank run on the tiled kernel only
   if (kernel != kGemmAuto) return kernel == kGemmSplitK;
   return (int64_t)job.n_tiles * job.cols_per_tile * d.M / 96 < 20480;
 }

@@ -77,6 +77,7 @@ struct Plan {
   float* phi_up_h3_scale = nullptr;
   // M2L: per-pair output slots (FP64 or FP32) and their fixed-order reduction per target box
   void* m2l_slots = nullptr;
+  double* phi_t64 = nullptr;  // KFMM_FP64 with the compressed M2L: phi~ = U^T phi_up per box
   int m2l_red_n = 0;
   int *m2l_red_box = nullptr, *m2l_red_off = nullptr, *m2l_red_idx = nullptr;
   std::vector<UpLevel> up_levels;

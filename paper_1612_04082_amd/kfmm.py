@@ -322,9 +322,10 @@ def _problem(tri, bc_type, bc_val, K, G, near_levels=0, near_radius=0.0, cell=No
 
 def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_iter=2000, x0=None, p=8,
               leaf_max=128, precision=FP32, svd_eps=0.0, want_full=True, allow_noconv=False, x0_alt=None,
-              precond=PC_NONE, pc_fine=0, pc_coarse=0, near_levels=0, near_radius=0.0, cell=None):
+              precond=PC_NONE, pc_fine=0, pc_coarse=0, near_levels=0, near_radius=0.0, cell=None, m2l_tol=0.0):
     """bem_solve on torch tensors: tri (T,3,3) f64, bc_type (T,3) int8, bc_val (T,3) f64, all on the GPU.
-    cell: None, or (x0, y0, z0, side) of a periodic cell (needs precision=FP64).
+    cell: None, or (x0, y0, z0, side) of a periodic cell (needs precision=FP64).  m2l_tol: the products' M2L
+    on the compressed basis (fmm_opts.m2l_tol; with FP64, FP64 contractions).
 
     Returns (x, u, t, stats) with x the unknowns (physical units) and u, t the full boundary data."""
     L = load_library()
@@ -332,7 +333,7 @@ def bem_solve(tri, bc_type, bc_val, K=None, G=1.0, tol=1e-6, restart=50, max_ite
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius, cell)
     alt = _dptr(x0_alt, "x0_alt", 3, int(tri.shape[0]))
-    opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0),
+    opts = BemOpts(tol, restart, max_iter, FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, m2l_tol),
                    alt.value if alt is not None else None, precond, pc_fine, pc_coarse)
     T = int(tri.shape[0])
     x = torch.empty((T, 3), dtype=torch.float64, device=tri.device)
@@ -368,13 +369,13 @@ def bem_precond_apply(tri, bc_type, bc_val, v, K=None, G=1.0, p=8, leaf_max=128,
 
 
 def bem_stress(tri, bc_type, bc_val, u, t, trg, K=None, G=1.0, p=8, leaf_max=128, precision=FP32, svd_eps=0.0,
-               cell=None):
-    """Interior stress (M,6) from boundary u, t (eq. stress_1) at trg (M,3); cell as in bem_solve."""
+               cell=None, m2l_tol=0.0):
+    """Interior stress (M,6) from boundary u, t (eq. stress_1) at trg (M,3); cell, m2l_tol as in bem_solve."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G, cell=cell)
-    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
+    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, m2l_tol)
     M = int(trg.shape[0])
     out = torch.empty((M, 6), dtype=torch.float64, device=trg.device)
     T = int(tri.shape[0])
@@ -398,13 +399,14 @@ def bem_quadrature(tri):
 
 
 def bem_matvec(tri, bc_type, bc_val, x=None, which=0, K=None, G=1.0, p=8, leaf_max=128, precision=FP32,
-               svd_eps=0.0, near_levels=0, near_radius=0.0, cell=None):
-    """y = A x (which=0, x in solver units) or the right-hand side B y (which=1); cell as in bem_solve."""
+               svd_eps=0.0, near_levels=0, near_radius=0.0, cell=None, m2l_tol=0.0):
+    """y = A x (which=0, x in solver units) or the right-hand side B y (which=1); cell, m2l_tol as in
+    bem_solve."""
     L = load_library()
     if K is None:
         K = moduli(G, 0.3)
     prob = _problem(tri, bc_type, bc_val, K, G, near_levels, near_radius, cell)
-    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, 0.0)
+    fo = FmmOpts(K, G, p, leaf_max, precision, svd_eps, 0, 0, m2l_tol)
     y = torch.empty((int(tri.shape[0]), 3), dtype=torch.float64, device=tri.device)
     check(L.bem_matvec(ctypes.byref(prob), ctypes.byref(fo), which, _dptr(x, "x", 3, int(tri.shape[0])),
                        _dptr(y, "y", 3), _stream()))

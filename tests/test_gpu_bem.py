@@ -74,29 +74,33 @@ def test_cube_tension_matches_lu_fp64(cuda, N):
     assert np.abs(u.cpu().numpy() - u_o).max() < 1e-4 * np.abs(u_o).max()
 
 
-@pytest.mark.parametrize("p_order", [8, 10])
-def test_matvec_matches_dense_operator(cuda, coarse_cantilever, p_order):
+@pytest.mark.parametrize("p_order,m2l_tol", [(8, 0.0), (10, 0.0), (8, 1e-8)])
+def test_matvec_matches_dense_operator(cuda, coarse_cantilever, p_order, m2l_tol):
     """bem_matvec (fast summation + local pass + free term) against the oracle's dense FP64 matrix, element by
     element, for random unknowns and for the right-hand side; the difference is the fast-summation error,
-    which falls with the expansion order (a mistake in the local correction or the self blocks would not)."""
+    which falls with the expansion order (a mistake in the local correction or the self blocks would not).
+    m2l_tol 1e-8: the M2L in FP64 on the compressed basis with per-offset ranks, at the dense bound."""
     from paper_1612_04082_amd import kfmm
     prob, sysm, _, _, _ = coarse_cantilever
     args = (dev(prob["tri"]), dev(prob["bc_type"], torch.int8), dev(prob["bc_val"]))
     rng = np.random.default_rng(21)
     xr = rng.normal(size=3 * sysm.T)
-    Ax = kfmm.bem_matvec(*args, x=dev(xr.reshape(-1, 3)), which=0, K=K, G=G, p=p_order, precision=0)
+    Ax = kfmm.bem_matvec(*args, x=dev(xr.reshape(-1, 3)), which=0, K=K, G=G, p=p_order, precision=0,
+                         m2l_tol=m2l_tol)
     Ax = Ax.cpu().numpy().reshape(-1)
     ref = sysm.A @ xr
     e2 = np.linalg.norm(Ax - ref) / np.linalg.norm(ref)
     einf = np.abs(Ax - ref).max() / np.abs(ref).max()
-    bb = kfmm.bem_matvec(*args, which=1, K=K, G=G, p=p_order, precision=0).cpu().numpy().reshape(-1)
+    bb = kfmm.bem_matvec(*args, which=1, K=K, G=G, p=p_order, precision=0, m2l_tol=m2l_tol)
+    bb = bb.cpu().numpy().reshape(-1)
     eb = np.linalg.norm(bb - sysm.b) / np.linalg.norm(sysm.b)
-    print(f"p={p_order}: A x rel err {e2:.2e} (max {einf:.2e}), b rel err {eb:.2e}")
+    print(f"p={p_order} m2l_tol {m2l_tol:.0e}: A x rel err {e2:.2e} (max {einf:.2e}), b rel err {eb:.2e}")
     bound = {8: 5e-6, 10: 1e-6}[p_order]
     assert e2 < bound and einf < 4 * bound and eb < bound
 
 
-def test_cantilever_converges_and_matches_oracle(cuda, coarse_cantilever):
+@pytest.mark.parametrize("m2l_tol", [0.0, 1e-8])
+def test_cantilever_converges_and_matches_oracle(cuda, coarse_cantilever, m2l_tol):
     """Mixed BVP on the slender cantilever.  The GPU residual (recomputed through bem_matvec) meets the
     tolerance.  Measured with the oracle's dense matrix the residual has a floor set by the product error:
     with A~ the fast operator and b~ its right-hand side,
@@ -111,12 +115,13 @@ def test_cantilever_converges_and_matches_oracle(cuda, coarse_cantilever):
     # FP64: the solution is ~1e4 times larger than ||b|| / ||A||, so FP32 products carry ~1e-3 relative
     # noise on this problem and GMRES stalls there; FP64 products converge like the dense oracle
     x, u, t, st = _solve(prob, tol=1e-6, restart=50, max_iter=2000, precision=0, p=8, leaf_max=128,
-                         precond=kfmm.PC_TWO_LEVEL)
+                         precond=kfmm.PC_TWO_LEVEL, m2l_tol=m2l_tol)
     args = (dev(prob["tri"]), dev(prob["bc_type"], torch.int8), dev(prob["bc_val"]))
     xs = x.cpu().numpy().reshape(-1).copy()
     xs[sysm.t_unknown] /= sysm.scale_t  # solver units
-    Ax = kfmm.bem_matvec(*args, x=dev(xs.reshape(-1, 3)), which=0, K=K, G=G, p=8, precision=0).cpu().numpy()
-    bb = kfmm.bem_matvec(*args, which=1, K=K, G=G, p=8, precision=0).cpu().numpy()
+    Ax = kfmm.bem_matvec(*args, x=dev(xs.reshape(-1, 3)), which=0, K=K, G=G, p=8, precision=0,
+                         m2l_tol=m2l_tol).cpu().numpy()
+    bb = kfmm.bem_matvec(*args, which=1, K=K, G=G, p=8, precision=0, m2l_tol=m2l_tol).cpu().numpy()
     Ax, bb = Ax.reshape(-1), bb.reshape(-1)
     bn = np.linalg.norm(sysm.b)
     res_gpu = np.linalg.norm(bb - Ax) / np.linalg.norm(bb)
@@ -124,7 +129,8 @@ def test_cantilever_converges_and_matches_oracle(cuda, coarse_cantilever):
     gap_A = np.linalg.norm(Ax - sysm.A @ xs) / bn
     gap_b = np.linalg.norm(bb - sysm.b) / bn
     xr = np.random.default_rng(22).normal(size=xs.size)
-    Axr = kfmm.bem_matvec(*args, x=dev(xr.reshape(-1, 3)), which=0, K=K, G=G, p=8, precision=0).cpu().numpy()
+    Axr = kfmm.bem_matvec(*args, x=dev(xr.reshape(-1, 3)), which=0, K=K, G=G, p=8, precision=0,
+                          m2l_tol=m2l_tol).cpu().numpy()
     Axr = Axr.reshape(-1)
     ref_r = sysm.A @ xr
     eps = np.linalg.norm(Axr - ref_r) / np.linalg.norm(ref_r)
@@ -132,7 +138,7 @@ def test_cantilever_converges_and_matches_oracle(cuda, coarse_cantilever):
     kx = normA * np.linalg.norm(xs) / bn
     floor = eps * kx
     err = np.linalg.norm(xs - x_lu) / np.linalg.norm(x_lu)
-    print(f"T={sysm.T}: iters {st['iters']} gpu rel_res {st['rel_res']:.2e} recomputed {res_gpu:.2e}; dense-matrix "
+    print(f"T={sysm.T} m2l_tol {m2l_tol:.0e}: iters {st['iters']} gpu rel_res {st['rel_res']:.2e} recomputed {res_gpu:.2e}; dense-matrix "
           f"residual {res_or:.2e} = product gap {gap_A:.2e} + rhs gap {gap_b:.2e} + ...; eps {eps:.2e} x "
           f"||A|| ||x|| / ||b|| {kx:.2e} = floor {floor:.2e}; |x - x_lu| / |x_lu| {err:.2e}")
     assert st["converged"] and st["rel_res"] <= 1e-6 and res_gpu < 2e-6

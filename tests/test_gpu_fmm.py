@@ -169,6 +169,34 @@ def test_split16_folded_and_unfolded_downward_pass(cuda, leaf):
     assert e16 <= 1.02 * e32 + 1e-7  # the fold adds no error (the method's own is 2.4e-5 on this cloud at p = 8)
 
 
+def test_fp64_compressed_m2l_matches_dense(cuda):
+    """KFMM_FP64 with m2l_tol 1e-8: FP64 contractions on the compressed basis (rank 716 of 888, padded to
+    768) with per-offset ranks, against the dense FP64 M2L and the oracle on the sphere at p = 8, both
+    layers, displacement and stress; the two forms differ by rounding through the pseudo-inverse (a few
+    1e-7), far below the method's error, and repeated products are the same bits."""
+    from tests.fmm_cases import to_dev, K, G
+    from paper_1612_04082_amd import kfmm
+    c = geo.sphere_cloud(4096, seed=1)
+    rng = np.random.default_rng(9)
+    b = rng.normal(size=c["src"].shape)
+    for kind in (od.DISP, od.STRESS):
+        ref = run_oracle(c["src"], c["nrm"], c["w"], c["a"], b, kind)
+        out = {}
+        for tol in (0.0, 1e-8):
+            plan = kfmm.FmmPlan(to_dev(c["src"]), to_dev(c["nrm"]), to_dev(c["w"]), K=K, G=G, p=8, leaf_max=64,
+                                precision=kfmm.FP64, m2l_tol=tol)
+            out[tol] = plan.eval(kind, to_dev(c["a"]), to_dev(b)).cpu().numpy()
+            again = plan.eval(kind, to_dev(c["a"]), to_dev(b)).cpu().numpy()
+            assert np.array_equal(out[tol], again)
+            if tol > 0:
+                assert plan.info()["m2l_rank"] == 768
+            plan.close()
+        d = rel_l2(out[1e-8], out[0.0])
+        e0, e1 = rel_l2(out[0.0], ref), rel_l2(out[1e-8], ref)
+        print(f"kind {kind}: compressed vs dense {d:.2e}, errors {e1:.2e} / {e0:.2e}")
+        assert d < 2e-6 and e1 <= 1.05 * e0 + 1e-7
+
+
 def test_profile_modes(cuda):
     """Phase timing (every phase in turn) and M2L-only timing leave the results bitwise unchanged."""
     from tests.fmm_cases import to_dev, K, G
