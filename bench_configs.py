@@ -253,7 +253,7 @@ def metacell(args):
     from paper_1612_04082_amd.alg1 import PeriodicCell
     n = args.cell_n
     M0 = geo.cavity_cell(n, args.rc)
-    cell = PeriodicCell(n, p=args.p_bem, leaf_max=128, tol=1e-6)
+    cell = PeriodicCell(n, p=args.p_bem, leaf_max=128, tol=1e-6, m2l_tol=args.bem_m2l_tol)
     cell.single_iteration(geo.cavity_cell(8, args.rc), args.alpha_c)  # operators of this p (first use)
     torch.cuda.synchronize()
     t0 = time.time()
@@ -265,7 +265,8 @@ def metacell(args):
     return dict(metric="periodic cell single-iteration time (s), 100^3 voxels", value=it_s, unit="s",
                 higher_is_better=False, dtype="f64",
                 config=dict(workload=f"periodic cell {n}^3 voxels, spherical cavity R_c={args.rc}, alpha_c={args.alpha_c}, "
-                                     f"hydrostatic stress, FMM p={args.p_bem} leaf<=128 FP64, GMRES tol 1e-6"),
+                                     f"hydrostatic stress, FMM p={args.p_bem} leaf<=128 FP64, m2l_tol "
+                                     f"{args.bem_m2l_tol:g}, GMRES tol 1e-6"),
                 initial=rec, result=dict(void_fraction=out["void_fraction"], K_eff=out["K_eff"], K_hs=out["K_hs"],
                                          K_eff_over_hs=out["K_eff"] / out["K_hs"], T=out["T"], gmres=out["gmres"],
                                          t_solve_s=out["t_solve_s"]),
@@ -279,7 +280,7 @@ def warmstart(args):
     pcm = kfmm.PC_NONE if args.precond == "none" else kfmm.PC_TWO_LEVEL
     rec = warm_start_study(M0, n_iter=args.iters, train_from=2, measure_from=args.measure_from, h=1.0, C=0.001,
                            tol_seq=1e-6, tol=1e-6, epochs=200, lr=1e-3, restart=200, p=args.p_bem, leaf_max=128,
-                           precision=kfmm.FP64, precond=pcm,
+                           precision=kfmm.FP64, precond=pcm, m2l_tol=args.bem_m2l_tol,
                            log=lambda r: (log.append(r), print(json.dumps(r), flush=True)))
     meas = [r for r in rec if "zero" in r]
     summ = {}
@@ -291,7 +292,8 @@ def warmstart(args):
     return dict(metric="BEM solve time learned vs plain (s per solve, mean over measured iterations)",
                 value=summ["net"]["seconds_mean"], unit="s", higher_is_better=False, dtype="f64",
                 config=dict(workload=f"Algorithm 1 on 120x15x15 voxels, C=0.001, tol 1e-6, GMRES(200), "
-                                     f"FMM p={args.p_bem} FP64", precond="none" if pcm == kfmm.PC_NONE else "two-level"),
+                                     f"FMM p={args.p_bem} FP64, m2l_tol {args.bem_m2l_tol:g}",
+                            precond="none" if pcm == kfmm.PC_NONE else "two-level"),
                 summary=summ, speedup_vs_zero=summ["zero"]["seconds_mean"] / summ["net"]["seconds_mean"],
                 speedup_vs_prev=summ["prev"]["seconds_mean"] / summ["net"]["seconds_mean"],
                 iterations=[dict(iter=r["iter"], alpha=r.get("alpha"), T=r["T"]) for r in rec])

@@ -60,7 +60,7 @@ class Problem:
 
 class Optimiser:
     def __init__(self, M0, h=1.0, load=(0.0, 0.0, -1.0), C=0.02, G=1.0, nu=0.3, tol=1e-8, restart=200, p=8,
-                 leaf_max=128, precision=0, max_iter=5000, precond=0):
+                 leaf_max=128, precision=0, max_iter=5000, precond=0, m2l_tol=0.0):
         from paper_1612_04082_amd import kfmm
         self.kfmm = kfmm
         self.M0 = np.asarray(M0, bool)
@@ -69,8 +69,8 @@ class Optimiser:
         self.K = kfmm.moduli(G, nu)
         self.E = 2 * G * (1 + nu)
         self.solve_kw = dict(K=self.K, G=G, tol=tol, restart=restart, p=p, leaf_max=leaf_max, precision=precision,
-                             max_iter=max_iter, precond=precond)
-        self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=precision)
+                             max_iter=max_iter, precond=precond, m2l_tol=m2l_tol)
+        self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=precision, m2l_tol=m2l_tol)
 
     def solve(self, prob, x0=None, x0_alt=None, **over):
         kw = dict(self.solve_kw)
@@ -254,7 +254,8 @@ class PeriodicCell:
     sym(u_e (x) n_e)] with the solution u on the faces (n_e out of the material, eps_h the matrix strain of
     s^h; a rigid translation of u drops out on closed surfaces), K_eff = <sigma>_kk / (3 tr eps_h)."""
 
-    def __init__(self, n, h=None, K=None, G=1.0, p=8, leaf_max=64, tol=1e-6, restart=100, max_iter=400):
+    def __init__(self, n, h=None, K=None, G=1.0, p=8, leaf_max=64, tol=1e-6, restart=100, max_iter=400,
+                 m2l_tol=0.0):
         from paper_1612_04082_amd import kfmm
         self.kfmm = kfmm
         self.n = int(n)
@@ -264,7 +265,8 @@ class PeriodicCell:
         self.K = kfmm.moduli(G, 0.3) if K is None else K
         self.cell = (0.0, 0.0, 0.0, self.L)
         self.sig_h = (1.0, 1.0, 1.0, 0.0, 0.0, 0.0)
-        self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=kfmm.FP64, cell=self.cell)
+        self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=kfmm.FP64, cell=self.cell,
+                           m2l_tol=m2l_tol)
         self.solve_kw = dict(self.fmm_kw, tol=tol, restart=restart, max_iter=max_iter)
 
     def _sync_time(self, t0):

@@ -59,7 +59,7 @@ def _check(got, ref, kind, tol, label):
 
 _REF = {}
 PRECISIONS = {"fp64": (0, 0.0), "fp32": (1, 0.0), "fp32-comp": (1, 3e-7), "split16-comp": (3, 3e-7),
-              "trans64-comp": (4, 3e-7), "trans64": (4, 0.0)}
+              "trans64-comp": (4, 3e-7), "trans64": (4, 0.0), "fp64-comp": (0, 1e-8)}
 
 
 @pytest.mark.parametrize("N,leaf,p", [(4000, 64, 8), (40, 64, 6), (600, 16, 6)])

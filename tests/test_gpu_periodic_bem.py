@@ -44,21 +44,24 @@ def cell(request):
     return _cell_problem(request.param)
 
 
-def test_periodic_matvec_and_rhs_rows(cuda, cell):
+@pytest.mark.parametrize("m2l_tol", [0.0, 1e-8])
+def test_periodic_matvec_and_rhs_rows(cuda, cell, m2l_tol):
+    """Rows of A x and of the right-hand side, with the dense FP64 M2L and with the compressed FP64 one (the
+    far images then reach the roots' downward densities through DC2DE T)."""
     from paper_1612_04082_amd import kfmm
     M, tri, bc_type, bc_val = cell
     T = tri.shape[0]
     rng = np.random.default_rng(1)
     x = rng.normal(size=(T, 3))
     rows = rng.choice(T, size=min(T, 120), replace=False)
-    kw = dict(K=K, G=G, p=8, leaf_max=64, precision=kfmm.FP64, cell=(0.0, 0.0, 0.0, 1.0))
+    kw = dict(K=K, G=G, p=8, leaf_max=64, precision=kfmm.FP64, cell=(0.0, 0.0, 0.0, 1.0), m2l_tol=m2l_tol)
     y = kfmm.bem_matvec(_t(tri), _t(bc_type, torch.int8), _t(bc_val), _t(x), which=0, **kw).cpu().numpy()
     ref = ob.matvec_rows(tri, bc_type, x, rows, K, G, cell_L=1.0)
     err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
     b = kfmm.bem_matvec(_t(tri), _t(bc_type, torch.int8), _t(bc_val), None, which=1, **kw).cpu().numpy()
     bref = ob.rhs_rows(tri, bc_type, bc_val, rows, K, G, cell_L=1.0)
     errb = np.linalg.norm(b[rows] - bref) / np.linalg.norm(bref)
-    print(f"T={T}: A x rows rel {err:.2e}, rhs rows rel {errb:.2e}")
+    print(f"T={T} m2l_tol {m2l_tol:.0e}: A x rows rel {err:.2e}, rhs rows rel {errb:.2e}")
     assert err < 1e-6 and errb < 1e-6
 
 
