@@ -120,12 +120,16 @@ def mean_edge(tri):
 NEAR_RADIUS = 1.5
 
 
-def near_pairs(tri, radius=NEAR_RADIUS):
+def near_pairs(tri, radius=NEAR_RADIUS, cell_L=None):
     """Pairs (t, e), t != e, whose collocation point lies within `radius` longest edges of triangle e:
     |c_t - c_e|^2 < radius^2 l_e^2, with squared distances summed as dx*dx + dy*dy + dz*dz and l_e^2 the
     largest squared edge of e (brute force over all pairs).  Sorted by t, then e.  Reading: the paper names
     'triangles close to the triangle with singularity' (Sec. 2.2) without a distance; at 1.5 edges the
-    16-point rule is within about 2e-6 of the exact block on voxel surfaces."""
+    16-point rule is within about 2e-6 of the exact block on voxel surfaces.
+
+    cell_L: the surface repeats with period cell_L (Sec. 4.3); the pairs are then (t, e, code) with e's image
+    shifted by cell_L (sx, sy, sz), s in {-1, 0, 1}^3, code = (sx+1) + 3 (sy+1) + 9 (sz+1), the image tested
+    as c_e + cell_L s (only the element itself at s = 0 is left out); sorted by t, e, code."""
     tri = np.asarray(tri, dtype=np.float64)
     cen = tri_geometry(tri)[0]
     l2 = np.zeros(tri.shape[0])
@@ -134,12 +138,28 @@ def near_pairs(tri, radius=NEAR_RADIUS):
         l2 = np.maximum(l2, d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2])
     thr = (radius * radius) * l2
     out = []
+    shifts = [(0, 0, 0)] if cell_L is None else [(sx, sy, sz) for sz in (-1, 0, 1) for sy in (-1, 0, 1)
+                                                   for sx in (-1, 0, 1)]
     for t in range(tri.shape[0]):
-        d = cen - cen[t]
-        d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
-        es = np.nonzero(d2 < thr)[0]
-        out.extend((t, e) for e in es if e != t)
-    return np.array(out, dtype=np.int64).reshape(-1, 2)
+        for sx, sy, sz in shifts:
+            code = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)
+            img = cen if cell_L is None else cen + cell_L * np.array([sx, sy, sz], dtype=np.float64)
+            d = img - cen[t]
+            d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+            es = np.nonzero(d2 < thr)[0]
+            if cell_L is None:
+                out.extend((t, e) for e in es if e != t)
+            else:
+                out.extend((t, e, code) for e in es if e != t or code != 13)
+    if cell_L is None:
+        return np.array(out, dtype=np.int64).reshape(-1, 2)
+    out = sorted(out)
+    return np.array(out, dtype=np.int64).reshape(-1, 3)
+
+
+def shift_of(code):
+    """(sx, sy, sz) of a shift code (sx+1) + 3 (sy+1) + 9 (sz+1)."""
+    return np.array([code % 3 - 1, (code // 3) % 3 - 1, code // 9 - 1], dtype=np.float64)
 
 
 class DenseBEM:
@@ -242,12 +262,14 @@ def gmres(matvec, b, x0=None, tol=1e-6, restart=50, max_iter=2000):
         x = x + V[:k].T @ y
 
 
-def _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L=None):
+def _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L=None, near_levels=0, near_radius=NEAR_RADIUS):
     """Rows of U(a) + P(b) + 1/2 b at the collocation points `rows`, element densities a_el, b_el (T x 3):
     the quadrature sum over every element's 16 points (coincident pair skipped), with the element's own
     quadrature terms replaced by its closed-form self block, plus the free term.  cell_L: the surface
     repeats with period cell_L (Sec. 4.3): the quadrature sum runs over every lattice image (oracle.periodic,
-    the k = 0 reading) and only the element's own n = 0 terms are replaced."""
+    the k = 0 reading) and only the element's own n = 0 terms are replaced.  near_levels > 0: the 16-point
+    terms of every near pair (near_pairs; with cell_L, of the near image) are replaced by the upsampled
+    blocks, as in DenseBEM."""
     qp, qn, qw, qe = quadrature(tri)
     cen = tri_geometry(tri)[0]
     rows = np.asarray(rows)
@@ -262,10 +284,23 @@ def _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L=None):
         own = od.direct(od.DISP, cen[r:r + 1], qp[sl], qw[sl], a=a_el[qe[sl]], b=b_el[qe[sl]], nrm=qn[sl], K=K, G=G)
         Us, Ps = self_integrals(tri[r], K, G)
         out[i] += -own[0] + Us @ a_el[r] + Ps @ b_el[r] + 0.5 * b_el[r]
+    if near_levels > 0:
+        pairs = near_pairs(tri, near_radius, cell_L)
+        pos = {int(r): i for i, r in enumerate(rows)}
+        sel = [k for k in range(pairs.shape[0]) if int(pairs[k, 0]) in pos]
+        for k in sel:
+            t, e = int(pairs[k, 0]), int(pairs[k, 1])
+            # the image of e shifted by cell_L s seen from c_t is e itself seen from c_t - cell_L s
+            x = cen[t] - (0.0 if cell_L is None else cell_L * shift_of(int(pairs[k, 2])))
+            Un, Pn = od.near_blocks(x[None, :], tri, np.array([[0, e]]), near_levels, K, G)
+            sl = slice(16 * e, 16 * e + 16)
+            q16 = od.direct(od.DISP, x[None, :], qp[sl], qw[sl], a=a_el[qe[sl]], b=b_el[qe[sl]], nrm=qn[sl], K=K,
+                            G=G)
+            out[pos[t]] += Un[0] @ a_el[e] + Pn[0] @ b_el[e] - q16[0]
     return out
 
 
-def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0, cell_L=None):
+def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0, cell_L=None, near_levels=0, near_radius=NEAR_RADIUS):
     """Rows of A x (eq. num2, solver units as in DenseBEM) by direct FP64 sums, for large meshes (cell_L: the
     periodic surface of a cell of that side, see _rows).
 
@@ -280,10 +315,10 @@ def matvec_rows(tri, bc_type, x, rows, K, G, nthreads=0, cell_L=None):
     t_unk = bc == 0
     a_el = np.where(t_unk, -scale_t * x, 0.0)   # -t for traction unknowns
     b_el = np.where(t_unk, 0.0, x)              #  u for displacement unknowns
-    return _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L)
+    return _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L, near_levels, near_radius)
 
 
-def rhs_rows(tri, bc_type, bc_val, rows, K, G, nthreads=0, cell_L=None):
+def rhs_rows(tri, bc_type, bc_val, rows, K, G, nthreads=0, cell_L=None, near_levels=0, near_radius=NEAR_RADIUS):
     """Rows of the right-hand side b = U t_known - P u_known - 1/2 u_known (eq. num2) by direct FP64 sums
     (cell_L as in matvec_rows)."""
     tri = np.ascontiguousarray(tri, dtype=np.float64)
@@ -293,4 +328,4 @@ def rhs_rows(tri, bc_type, bc_val, rows, K, G, nthreads=0, cell_L=None):
     u_known = bc == 0
     a_el = np.where(u_known, 0.0, y)    # t where the traction is prescribed
     b_el = np.where(u_known, -y, 0.0)   # -u where the displacement is prescribed
-    return _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L)
+    return _rows(tri, a_el, b_el, rows, K, G, nthreads, cell_L, near_levels, near_radius)
