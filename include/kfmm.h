@@ -234,8 +234,9 @@ typedef struct {
                              the pure traction problem with bc_val = -s^h n on every element: its solution is
                              the periodic fluctuation field (zero cell mean), added to s^h for the total
                              stress.  Every quadrature point and centroid must lie in [c, c + L)^3 (a
-                             face on an upper face of the cell is given on the lower one); near_levels must
-                             be 0 and precond KFMM_PC_NONE (both are built for free space). */
+                             face on an upper face of the cell is given on the lower one).  Near pairs then
+                             include the images of elements across the cell faces (c_e + L s, s in
+                             {-1, 0, 1}^3); precond must be KFMM_PC_NONE (its exact blocks are free-space). */
 } bem_problem;
 
 typedef struct {

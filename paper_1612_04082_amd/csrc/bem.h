@@ -22,9 +22,12 @@ inline std::vector<double> problem_cells(const bem_problem& p) {
 struct NearPairs {
   int64_t n = 0;
   int *off = nullptr, *idx = nullptr, *row = nullptr;
+  signed char* sh = nullptr;  // periodic surface: the image's shift code (sx+1)+3(sy+1)+9(sz+1) per pair
+  double cell_L = 0;          // side of the periodic cell, 0 in free space
 };
+// cell_L > 0: the surface repeats with that period; pairs with an element's images across the faces too
 NearPairs find_near_pairs(const double* tri, const double* cen, int64_t T, double radius, Arena& arena,
-                          hipStream_t s);
+                          hipStream_t s, double cell_L = 0);
 // dU, dP (n x 9 each): upsampled blocks (levels extra midpoint splits) minus the element's 16 quadrature points
 void near_blocks(const NearPairs& np, int levels, const double* tri, const double* cen, const double* qp,
                  const double* qn, const double* qw, const Elastic& el, double* dU, double* dP, hipStream_t s);

@@ -358,7 +358,7 @@ BemSystem::BemSystem(const bem_problem& p, const fmm_opts& fo, hipStream_t s) : 
   KFMM_HIP(hipGetLastError());
   near_levels = p.near_levels;
   if (near_levels > 0) {
-    near = find_near_pairs(tri, cen, T, p.near_radius > 0 ? p.near_radius : 1.5, arena, s);
+    near = find_near_pairs(tri, cen, T, p.near_radius > 0 ? p.near_radius : 1.5, arena, s, p.cell ? p.cell[3] : 0.0);
     near_dU = arena.get<double>((size_t)9 * std::max<int64_t>(near.n, 1));
     near_dP = arena.get<double>((size_t)9 * std::max<int64_t>(near.n, 1));
     near_blocks(near, near_levels, tri, cen, qp, qn, qw, el, near_dU, near_dP, s);

@@ -207,7 +207,6 @@ static void check_problem(const bem_problem* p) {
     KFMM_REQUIRE(std::isfinite(p->cell[0]) && std::isfinite(p->cell[1]) && std::isfinite(p->cell[2]) &&
                      std::isfinite(p->cell[3]) && p->cell[3] > 0,
                  "cell: finite lower corner and side > 0 required");
-    KFMM_REQUIRE(p->near_levels == 0, "near_levels must be 0 for a periodic cell");
   }
 }
 

@@ -6,6 +6,10 @@
 //    adjacent cell): centroids sorted by cell key, then per element the 27 neighbouring cells searched by
 //    binary search; each element's list is sorted by e.  Squared distances are summed as
 //    dx*dx + dy*dy + dz*dz without fused multiply-adds, so the decision matches a plain FP64 evaluation.
+//  * Periodic surface (a cell of side L): also the images c_e + L s, s in {-1, 0, 1}^3, are tested (the
+//    element itself only at s != 0), found by searching around c_t - L s; a pair keeps its shift code
+//    (sx+1) + 3 (sy+1) + 9 (sz+1), and a row is sorted by e, then code.  The blocks of an image are those of
+//    e seen from c_t - L s (translation invariance).
 //  * Per near pair the upsampled blocks: the triangle e split at its edge midpoints L + 1 times (children
 //    (v0, m01, m20), (m01, v1, m12), (m20, m12, v2), (m01, m12, m20)), the symmetric 4-point rule on each of
 //    the 4^(L+1) leaves (weights: leaf area x rule weight), leaves in the order of their base-4 index; minus
@@ -100,49 +104,65 @@ __device__ __forceinline__ int64_t lower_bound(const uint64_t* keys, int64_t n, 
 }
 
 // Pass 0 counts the near elements of each t into cnt[t]; pass 1 writes them at idx[off[t]...] (with the
-// row t in row[]) and sorts the row by e.
+// row t in row[] and, on a periodic surface of side L > 0, the shift code in sh[]) and sorts the row by e,
+// then code.
 __global__ void k_near_scan(int pass, const double* __restrict__ cen, const double* __restrict__ l2, int64_t T,
                             const double* __restrict__ bounds, double cs, double r2, const uint64_t* __restrict__ keys,
                             const int* __restrict__ sorted, int* __restrict__ cnt, const int* __restrict__ off,
-                            int* __restrict__ idx, int* __restrict__ row) {
+                            int* __restrict__ idx, int* __restrict__ row, double L, signed char* __restrict__ sh) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
-  const double cx = cen[3 * t], cy = cen[3 * t + 1], cz = cen[3 * t + 2];
-  const int64_t qx = cell_of(cx, bounds[0], cs), qy = cell_of(cy, bounds[1], cs), qz = cell_of(cz, bounds[2], cs);
   int n = 0;
   const int64_t base = pass ? off[t] : 0;
-  for (int64_t dx = -1; dx <= 1; ++dx)
-    for (int64_t dy = -1; dy <= 1; ++dy)
-      for (int64_t dz = -1; dz <= 1; ++dz) {
-        const int64_t ax = qx + dx, ay = qy + dy, az = qz + dz;
-        if (ax < 0 || ay < 0 || az < 0 || ax >= (1 << kCellBits) || ay >= (1 << kCellBits) || az >= (1 << kCellBits))
-          continue;
-        const uint64_t k = cell_key(ax, ay, az);
-        for (int64_t p = lower_bound(keys, T, k); p < T && keys[p] == k; ++p) {
-          const int e = sorted[p];
-          if (e == t) continue;
-          const double d2 = sq3(cen[3 * e] - cx, cen[3 * e + 1] - cy, cen[3 * e + 2] - cz);
-          if (d2 < __dmul_rn(r2, l2[e])) {
-            if (pass) {
-              idx[base + n] = e;
-              row[base + n] = (int)t;
+  const int s_lo = L > 0 ? -1 : 0, s_hi = L > 0 ? 1 : 0;
+  for (int sz = s_lo; sz <= s_hi; ++sz)
+    for (int sy = s_lo; sy <= s_hi; ++sy)
+      for (int sx = s_lo; sx <= s_hi; ++sx) {
+        const int code = (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1);
+        // cells searched around c_t - L s; the decision on (c_e + L s) - c_t, each sum rounded on its own
+        const double cx = cen[3 * t] - L * sx, cy = cen[3 * t + 1] - L * sy, cz = cen[3 * t + 2] - L * sz;
+        const double ox = L * sx, oy = L * sy, oz = L * sz;
+        const int64_t qx = cell_of(cx, bounds[0], cs), qy = cell_of(cy, bounds[1], cs), qz = cell_of(cz, bounds[2], cs);
+        for (int64_t dx = -1; dx <= 1; ++dx)
+          for (int64_t dy = -1; dy <= 1; ++dy)
+            for (int64_t dz = -1; dz <= 1; ++dz) {
+              const int64_t ax = qx + dx, ay = qy + dy, az = qz + dz;
+              if (ax < 0 || ay < 0 || az < 0 || ax >= (1 << kCellBits) || ay >= (1 << kCellBits) ||
+                  az >= (1 << kCellBits))
+                continue;
+              const uint64_t k = cell_key(ax, ay, az);
+              for (int64_t p = lower_bound(keys, T, k); p < T && keys[p] == k; ++p) {
+                const int e = sorted[p];
+                if (e == t && code == 13) continue;
+                const double d2 = sq3(__dsub_rn(__dadd_rn(cen[3 * e], ox), cen[3 * t]),
+                                      __dsub_rn(__dadd_rn(cen[3 * e + 1], oy), cen[3 * t + 1]),
+                                      __dsub_rn(__dadd_rn(cen[3 * e + 2], oz), cen[3 * t + 2]));
+                if (d2 < __dmul_rn(r2, l2[e])) {
+                  if (pass) {
+                    idx[base + n] = e;
+                    row[base + n] = (int)t;
+                    if (sh) sh[base + n] = (signed char)code;
+                  }
+                  ++n;
+                }
+              }
             }
-            ++n;
-          }
-        }
       }
   if (!pass) {
     cnt[t] = n;
     return;
   }
-  for (int a = 1; a < n; ++a) {  // insertion sort of the row by e
+  for (int a = 1; a < n; ++a) {  // insertion sort of the row by e, then code
     const int v = idx[base + a];
+    const signed char c = sh ? sh[base + a] : 0;
     int b = a - 1;
-    while (b >= 0 && idx[base + b] > v) {
+    while (b >= 0 && (idx[base + b] > v || (idx[base + b] == v && sh && sh[base + b] > c))) {
       idx[base + b + 1] = idx[base + b];
+      if (sh) sh[base + b + 1] = sh[base + b];
       --b;
     }
     idx[base + b + 1] = v;
+    if (sh) sh[base + b + 1] = c;
   }
 }
 
@@ -173,11 +193,14 @@ __global__ void k_near_blocks(int64_t n, const int* __restrict__ row, const int*
                               const double* __restrict__ tri, const double* __restrict__ cen,
                               const double* __restrict__ qp, const double* __restrict__ qn,
                               const double* __restrict__ qw, Elastic el, double* __restrict__ dU,
-                              double* __restrict__ dP) {
+                              double* __restrict__ dP, const signed char* __restrict__ sh, double L) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int64_t t = row[p], e = col[p];
-  const double* x = cen + 3 * t;
+  // an image shifted by L s is e seen from c_t - L s
+  const int code = sh ? sh[p] : 13;
+  const double x[3] = {cen[3 * t] - L * (code % 3 - 1), cen[3 * t + 1] - L * ((code / 3) % 3 - 1),
+                       cen[3 * t + 2] - L * (code / 9 - 1)};
   const double* v = tri + 9 * e;
   double e1[3], e2[3], nr[3];
   for (int d = 0; d < 3; ++d) {
@@ -247,9 +270,11 @@ __global__ void k_near_blocks(int64_t n, const int* __restrict__ row, const int*
 }  // namespace
 
 NearPairs find_near_pairs(const double* tri, const double* cen, int64_t T, double radius, Arena& arena,
-                          hipStream_t s) {
+                          hipStream_t s, double cell_L) {
   KFMM_REQUIRE(radius > 0 && radius < 16, "near_radius must be in (0, 16)");
+  KFMM_REQUIRE(cell_L >= 0, "near pairs: bad cell side");
   NearPairs np;
+  np.cell_L = cell_L;
   Arena scratch;
   double* l2 = arena.get<double>(T);
   hipLaunchKernelGGL(k_near_l2, dim3(nblk(T, 256)), dim3(256), 0, s, tri, T, l2);
@@ -272,7 +297,7 @@ NearPairs find_near_pairs(const double* tri, const double* cen, int64_t T, doubl
   int* cnt = scratch.get<int>(T);
   const double r2 = radius * radius;
   hipLaunchKernelGGL(k_near_scan, dim3(nblk(T, 128)), dim3(128), 0, s, 0, cen, l2, T, bounds, cs, r2, keys, sorted, cnt,
-                     (const int*)nullptr, (int*)nullptr, (int*)nullptr);
+                     (const int*)nullptr, (int*)nullptr, (int*)nullptr, cell_L, (signed char*)nullptr);
   KFMM_HIP(hipGetLastError());
   std::vector<int> hc(T);
   KFMM_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int) * T, hipMemcpyDeviceToHost, s));
@@ -287,8 +312,9 @@ NearPairs find_near_pairs(const double* tri, const double* cen, int64_t T, doubl
   KFMM_HIP(hipMemcpyAsync(np.off, ho.data(), sizeof(int) * (T + 1), hipMemcpyHostToDevice, s));
   np.idx = arena.get<int>(std::max<int64_t>(np.n, 1));
   np.row = arena.get<int>(std::max<int64_t>(np.n, 1));
+  if (cell_L > 0) np.sh = arena.get<signed char>(std::max<int64_t>(np.n, 1));
   hipLaunchKernelGGL(k_near_scan, dim3(nblk(T, 128)), dim3(128), 0, s, 1, cen, l2, T, bounds, cs, r2, keys, sorted, cnt,
-                     np.off, np.idx, np.row);
+                     np.off, np.idx, np.row, cell_L, np.sh);
   KFMM_HIP(hipGetLastError());
   KFMM_HIP(hipStreamSynchronize(s));  // scratch (keys, sorted) is released on return
   return np;
@@ -299,7 +325,7 @@ void near_blocks(const NearPairs& np, int levels, const double* tri, const doubl
   KFMM_REQUIRE(levels >= 1 && levels <= 5, "near_levels must be in [0, 5]");
   if (np.n == 0) return;
   hipLaunchKernelGGL(k_near_blocks, dim3(nblk(np.n, 64)), dim3(64), 0, s, np.n, np.row, np.idx, levels, tri, cen,
-                     qp, qn, qw, el, dU, dP);
+                     qp, qn, qw, el, dU, dP, (const signed char*)np.sh, np.cell_L);
   KFMM_HIP(hipGetLastError());
 }
 
