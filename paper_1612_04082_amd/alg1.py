@@ -255,7 +255,7 @@ class PeriodicCell:
     s^h; a rigid translation of u drops out on closed surfaces), K_eff = <sigma>_kk / (3 tr eps_h)."""
 
     def __init__(self, n, h=None, K=None, G=1.0, p=8, leaf_max=64, tol=1e-6, restart=100, max_iter=400,
-                 m2l_tol=0.0):
+                 m2l_tol=0.0, near_levels=0):
         from paper_1612_04082_amd import kfmm
         self.kfmm = kfmm
         self.n = int(n)
@@ -267,7 +267,7 @@ class PeriodicCell:
         self.sig_h = (1.0, 1.0, 1.0, 0.0, 0.0, 0.0)
         self.fmm_kw = dict(K=self.K, G=G, p=p, leaf_max=leaf_max, precision=kfmm.FP64, cell=self.cell,
                            m2l_tol=m2l_tol)
-        self.solve_kw = dict(self.fmm_kw, tol=tol, restart=restart, max_iter=max_iter)
+        self.solve_kw = dict(self.fmm_kw, tol=tol, restart=restart, max_iter=max_iter, near_levels=near_levels)
 
     def _sync_time(self, t0):
         torch.cuda.synchronize()

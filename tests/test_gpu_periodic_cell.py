@@ -12,11 +12,14 @@ from workloads import geometry as geo
 pytestmark = pytest.mark.gpu
 
 
-def test_single_iteration_cell(cuda):
+@pytest.mark.parametrize("near_levels", [0, 2])
+def test_single_iteration_cell(cuda, near_levels):
+    """One single-iteration step of the cell (Sec. 4.3), with the 16-point rule everywhere and with the
+    near-singular quadrature on the periodic surface."""
     from paper_1612_04082_amd.alg1 import PeriodicCell
     n = 16
     M0 = geo.cavity_cell(n, 0.3)
-    cell = PeriodicCell(n, p=6, tol=1e-6)
+    cell = PeriodicCell(n, p=6, tol=1e-6, near_levels=near_levels)
     new, rec = cell.single_iteration(M0, alpha_c=0.7)
     print({k: (round(v, 4) if isinstance(v, float) else v) for k, v in rec.items()})
     assert rec["converged"] and rec["gmres"] <= 60
