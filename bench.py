@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--m2l-tol", type=float, default=3e-7, help="shared-basis M2L compression cutoff (FP32); 0 = dense")
     ap.add_argument("--svd-eps", type=float, default=0.0, help="pseudo-inverse cutoff (0: library default)")
+    ap.add_argument("--stress-m2l-tol", type=float, default=1e-7,
+                    help="M2L compression cutoff of the cantilever's lattice stress (FP32 M2L; 0 = dense)")
     ap.add_argument("--bem-m2l-tol", type=float, default=1e-8,
                     help="M2L compression cutoff of the FP64 BEM products (cantilever, warmstart, metacell; 0 = dense)")
     ap.add_argument("--rows", type=int, default=2000, help="oracle sample for the cantilever workload")

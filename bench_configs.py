@@ -222,7 +222,7 @@ def cantilever(args):
         torch.cuda.synchronize()
         t0 = time.time()
         sig = kfmm.bem_stress(dtri, dbc, dval, u, t, dl, K=K, G=G, p=9, leaf_max=128,
-                              precision=kfmm.FP32_TRANS64)
+                              precision=kfmm.FP32_TRANS64, m2l_tol=args.stress_m2l_tol)
         torch.cuda.synchronize()
         stress_times.append(time.time() - t0)
     stress_s = stress_times[1]
@@ -242,7 +242,8 @@ def cantilever(args):
                             precond=args.precond),
                 svd_eps=args.svd_eps, gmres=solves,
                 matvec_rows_rel_err=matvec_err, oracle_rows_seconds=t_rows, residual_vs_exact=residual,
-                stress=dict(targets=int(lat.shape[0]), p=9, precision="fp32t64", seconds=stress_s,
+                stress=dict(targets=int(lat.shape[0]), p=9, precision="fp32t64", m2l_tol=args.stress_m2l_tol,
+                            seconds=stress_s,
                             seconds_first_call=stress_times[0], points_per_s=lat.shape[0] / stress_s,
                             rel_err=stress_err, oracle_seconds=t_sig),
                 cpu_baseline=dict(value=args.rows / t_sig, unit="stress target points/s", cores=_cores(),
