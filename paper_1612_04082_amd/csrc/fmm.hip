@@ -1442,7 +1442,20 @@ Plan* plan_create(const double* src, const double* nrm, const double* w, int64_t
   P->n_leaves_trg = (int)leaves_trg.size();
   P->n_x_boxes = (int)x_boxes.size();
   P->leaves_src = upload_vec(P->arena, leaves_src, s);
-  P->leaves_trg = upload_vec(P->arena, leaves_trg, s);
+  {
+    // the leaf passes run one workgroup per target leaf, in this order: leaves with the most near-field pairs
+    // first, so that a leaf beside a finely refined region (tens of U-list boxes) does not start last and
+    // hold the launch's tail (each leaf writes only its own targets, so the order leaves results unchanged)
+    std::vector<int64_t> work(nb, 0);
+    for (int b : leaves_trg)
+      for (int k = t.h_u_off[b]; k < t.h_u_off[b + 1]; ++k) {
+        const int A = t.h_u_idx[k];
+        work[b] += (int64_t)(t.h_trg_e[b] - t.h_trg_b[b]) * (t.h_src_e[A] - t.h_src_b[A]);
+      }
+    std::vector<int> by_work = leaves_trg;
+    std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) { return work[a] > work[b]; });
+    P->leaves_trg = upload_vec(P->arena, by_work, s);
+  }
   P->x_boxes = upload_vec(P->arena, x_boxes, s);
   auto half = [&](int b) { return std::ldexp(t.h_root_R[t.h_geom[b]], -t.h_level[b]); };
   // 128-column tiles once a launch has enough columns to fill the chip with them
