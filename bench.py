@@ -70,8 +70,8 @@ def cpu_model():
 # (KiB per dispatch) scaled by the same counters on a 1024 MiB copy (factors 2.0 and 1.0); the summary is in
 # profiles/m2l_split16_boxbeam_p8_leaf256.md.  Valid only for the kernel sources and the launch set-up (tile
 # widths, in fmm.hip) it was measured on.
-M2L_TRAFFIC = {"sources_sha256": "e790cc3f84176b09145c8f9894fc93ab0b505fb847c37a2f155873ee0d9406d2",
-               "fetch_kib": 152947.25 * 2.0, "write_kib": 172766.2 * 1.0}
+M2L_TRAFFIC = {"sources_sha256": "78cf899a0402fc685f47d45d84675d2037e3f7e00e630a5893eec5d68d18d4d9",
+               "fetch_kib": 153057.6 * 2.0, "write_kib": 172768.0 * 1.0}
 M2L_SOURCES = ("paper_1612_04082_amd/csrc/gemm_kernels.h", "paper_1612_04082_amd/csrc/gemm_h3.hip",
                "paper_1612_04082_amd/csrc/gemm.h", "paper_1612_04082_amd/csrc/fmm.hip")
 
