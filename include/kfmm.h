@@ -236,7 +236,9 @@ typedef struct {
                              stress.  Every quadrature point and centroid must lie in [c, c + L)^3 (a
                              face on an upper face of the cell is given on the lower one).  Near pairs then
                              include the images of elements across the cell faces (c_e + L s, s in
-                             {-1, 0, 1}^3); precond must be KFMM_PC_NONE (its exact blocks are free-space). */
+                             {-1, 0, 1}^3), so near_radius times the longest edge must be below L
+                             (KFMM_E_ARG otherwise); precond must be KFMM_PC_NONE (its exact blocks are
+                             free-space). */
 } bem_problem;
 
 typedef struct {

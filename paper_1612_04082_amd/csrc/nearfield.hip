@@ -286,6 +286,10 @@ NearPairs find_near_pairs(const double* tri, const double* cen, int64_t T, doubl
   KFMM_HIP(hipStreamSynchronize(s));
   // cells no smaller than the largest near distance (slightly enlarged against rounding in the cell index)
   double cs = radius * std::sqrt(hb[3]) * (1.0 + 1e-9);
+  // on a periodic surface only the 27 images around the cell are searched: every near distance must stay
+  // below the cell side
+  KFMM_REQUIRE(cell_L == 0 || cs < cell_L,
+               "near pairs: near_radius times the longest element edge must be below the periodic cell's side");
   if (!(cs > 0)) cs = 1.0;
   int64_t n_pad = 2048;
   while (n_pad < T) n_pad *= 2;

@@ -140,3 +140,9 @@ def test_periodic_near_singular_rows_and_solve(cuda, cell):
                                     near_levels=2, **kw)
     print(f"solve with near-singular quadrature: {st['iters']} steps, rel res {st['rel_res']:.2e}")
     assert st["converged"] and st["iters"] <= 40
+    # only the 27 images around the cell are searched: a near distance of a cell side or more is refused
+    l_max = max(np.linalg.norm(tri[:, i] - tri[:, (i + 1) % 3], axis=1).max() for i in range(3))
+    assert 12.0 * l_max >= 1.0
+    with pytest.raises(kfmm.KfmmError, match="periodic cell"):
+        kfmm.bem_matvec(_t(tri), _t(bc_type, torch.int8), _t(bc_val), _t(x), which=0, near_levels=2,
+                        near_radius=12.0, **kw)
