@@ -69,7 +69,8 @@ def test_plan_argument_errors(lib):
     for change, msg in ((dict(K=-1.0), "moduli"), (dict(G=float("nan")), "moduli"),
                         (dict(precision=9), "unknown precision"), (dict(precision=2), "M2L_BF16 is withdrawn"),
                         (dict(p=2), "p must be in"),
-                        (dict(m2l_tol=1.5), "m2l_tol"), (dict(leaf_max=-4), "negative leaf_max")):
+                        (dict(m2l_tol=1.5), "m2l_tol"), (dict(m2l_tol=-1e-8), "m2l_tol"),
+                        (dict(m2l_tol=float("nan")), "m2l_tol"), (dict(leaf_max=-4), "negative leaf_max")):
         opts = kfmm.FmmOpts(**{**good, **change})
         assert call(ctypes.byref(plan), ctypes.byref(opts)) == KFMM_E_ARG, change
         assert msg in last_error(lib), (change, last_error(lib))
