@@ -146,3 +146,34 @@ def test_periodic_near_singular_rows_and_solve(cuda, cell):
     with pytest.raises(kfmm.KfmmError, match="periodic cell"):
         kfmm.bem_matvec(_t(tri), _t(bc_type, torch.int8), _t(bc_val), _t(x), which=0, near_levels=2,
                         near_radius=12.0, **kw)
+
+
+def test_periodic_near_pairs_through_two_images(cuda):
+    """Near distances between half a cell side and a side (near_radius 6 on the 0.1-edge wrapping cavity):
+    one element pair can then be near through two images c_e + L s, and each image's block is corrected on
+    its own.  Rows of A x and the correction (rows with minus rows without) against the oracle's; the pairs
+    farther than 4.9 edges, among them every pair near through two images, carry 6e-7 of the correction, so
+    the correction's bound would show one left out."""
+    from collections import Counter
+    from paper_1612_04082_amd import kfmm
+    _, tri, bc_type, _ = _cell_problem((0.05, 0.5, 0.5))
+    T = tri.shape[0]
+    per_pair = Counter((int(t), int(e)) for t, e, _ in ob.near_pairs(tri, radius=6.0, cell_L=1.0))
+    twice = sum(1 for v in per_pair.values() if v == 2)
+    assert twice > 0
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(T, 3))
+    rows = rng.choice(T, size=40, replace=False)
+    kw = dict(K=K, G=G, p=8, leaf_max=64, precision=kfmm.FP64, cell=(0.0, 0.0, 0.0, 1.0))
+    y = kfmm.bem_matvec(_t(tri), _t(bc_type, torch.int8), _t(np.zeros((T, 3))), _t(x), which=0, near_levels=1,
+                        near_radius=6.0, **kw).cpu().numpy()
+    y0 = kfmm.bem_matvec(_t(tri), _t(bc_type, torch.int8), _t(np.zeros((T, 3))), _t(x), which=0,
+                         **kw).cpu().numpy()
+    ref = ob.matvec_rows(tri, bc_type, x, rows, K, G, cell_L=1.0, near_levels=1, near_radius=6.0)
+    ref0 = ob.matvec_rows(tri, bc_type, x, rows, K, G, cell_L=1.0)
+    err = np.linalg.norm(y[rows] - ref) / np.linalg.norm(ref)
+    dref = ref - ref0
+    errc = np.linalg.norm((y - y0)[rows] - dref) / np.linalg.norm(dref)
+    print(f"T={T}: {sum(per_pair.values())} near pairs, {twice} element pairs near through two images; "
+          f"A x rows rel {err:.2e}, correction rel {errc:.2e}")
+    assert err < 1e-6 and errc < 1e-9
