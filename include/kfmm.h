@@ -317,8 +317,9 @@ int bem_matvec(const bem_problem* prob, const fmm_opts* fmm, int which, const do
 
 /*
  * bem_near_pairs -- the near pairs of prob (near_radius as in bem_problem; near_levels is ignored; a periodic
- * cell is KFMM_E_ARG: pairs across the cell faces are not searched), sorted by collocation element t, then by
- * source element e.  *count (host) receives their number; pairs (device,
+ * cell is KFMM_E_ARG: the (t, e) rows carry no image shift, so this entry point serves free-space surfaces
+ * only, while the solver's own near pairs on a periodic surface include the images), sorted by collocation
+ * element t, then by source element e.  *count (host) receives their number; pairs (device,
  * 2 x count int32 as (t, e) rows) may be NULL to query the count, else it must hold *count_capacity pairs
  * (KFMM_E_ARG if fewer).  Synchronises the stream.
  */

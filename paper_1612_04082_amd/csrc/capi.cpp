@@ -218,7 +218,7 @@ extern "C" int bem_near_pairs(const bem_problem* prob, int64_t* count, int32_t* 
     KFMM_REQUIRE(std::isfinite(prob->near_radius) && prob->near_radius >= 0 && prob->near_radius < 16,
                  "near_radius must be in [0, 16)");
     KFMM_REQUIRE(count != nullptr, "count is NULL");
-    KFMM_REQUIRE(prob->cell == nullptr, "near pairs are not searched across the faces of a periodic cell");
+    KFMM_REQUIRE(prob->cell == nullptr, "bem_near_pairs serves free-space surfaces only (its rows carry no image shift)");
     hipStream_t s = (hipStream_t)stream;
     const int64_t T = prob->n_tri, NQ = 16 * T;
     Arena a;
