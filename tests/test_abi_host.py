@@ -194,3 +194,20 @@ def test_bem_entry_points_check_problem_and_options_first(lib):
     opts.precond = 7
     assert lib.bem_solve(ctypes.byref(prob), ctypes.byref(opts), None, ctypes.c_void_p(fake), None, None, None,
                          None) == KFMM_E_ARG and "preconditioner" in last_error(lib)
+    # periodic cells: the side must be finite and positive; the preconditioner and bem_near_pairs are free-space
+    for bad in ((0.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, -1.0), (float("nan"), 0.0, 0.0, 1.0),
+                (0.0, 0.0, 0.0, float("inf"))):
+        p = kfmm.BemProblem(10, fake, fake, fake, 2.0, 1.0, 0, 0.0, (ctypes.c_double * 4)(*bad))
+        rc = lib.bem_matvec(ctypes.byref(p), ctypes.byref(fo), 0, ctypes.c_void_p(fake), ctypes.c_void_p(fake), None)
+        assert rc == KFMM_E_ARG and "side > 0" in last_error(lib), (bad, last_error(lib))
+    cell = (ctypes.c_double * 4)(0.0, 0.0, 0.0, 1.0)
+    pc = kfmm.BemProblem(10, fake, fake, fake, 2.0, 1.0, 0, 0.0, cell)
+    count = ctypes.c_int64(0)
+    assert lib.bem_near_pairs(ctypes.byref(pc), ctypes.byref(count), None, 0, None) == KFMM_E_ARG
+    assert "free-space surfaces only" in last_error(lib)
+    opts.precond = kfmm.PC_TWO_LEVEL
+    assert lib.bem_solve(ctypes.byref(pc), ctypes.byref(opts), None, ctypes.c_void_p(fake), None, None, None,
+                         None) == KFMM_E_ARG and "cell must be NULL" in last_error(lib)
+    assert lib.bem_precond_apply(ctypes.byref(pc), ctypes.byref(opts), ctypes.c_void_p(fake),
+                                 ctypes.c_void_p(fake + 64), None, None) == KFMM_E_ARG
+    assert "cell must be NULL" in last_error(lib)
