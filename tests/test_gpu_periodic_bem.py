@@ -152,8 +152,9 @@ def test_periodic_near_pairs_through_two_images(cuda):
     """Near distances between half a cell side and a side (near_radius 6 on the 0.1-edge wrapping cavity):
     one element pair can then be near through two images c_e + L s, and each image's block is corrected on
     its own.  Rows of A x and the correction (rows with minus rows without) against the oracle's; the pairs
-    farther than 4.9 edges, among them every pair near through two images, carry 6e-7 of the correction, so
-    the correction's bound would show one left out."""
+    farther than 4.9 edges, among them every pair near through two images, carry 6e-7 of the correction
+    together, far above the correction's bound, so leaving them out would show.  Both sides decide each pair
+    on (c_e + L s) - c_t with the same roundings, ties on the voxel grid included."""
     from collections import Counter
     from paper_1612_04082_amd import kfmm
     _, tri, bc_type, _ = _cell_problem((0.05, 0.5, 0.5))

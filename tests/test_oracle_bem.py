@@ -346,19 +346,27 @@ def _periodic_surface():
     return geo.periodic_voxel_surface(M, 1.0 / 6.0)["tri"]
 
 
-def test_periodic_near_pairs_match_the_tiled_surface():
+@pytest.mark.parametrize("radius", [ob.NEAR_RADIUS, 4.1])
+def test_periodic_near_pairs_match_the_tiled_surface(radius):
     """Near pairs of a periodic surface (cell side 1) against the free-space near pairs of its 3 x 3 x 3 tiling:
-    the rows of the centre copy, each element of copy s mapped back to (e, code of s)."""
+    the rows of the centre copy, each element of copy s mapped back to (e, code of s).  At 4.1 edges of 1/6 the
+    near distance lies between half a side and a side, so some element pairs are near through two images.
+    (Not at 4 edges: centroid distances of exactly 2/3 exist on this voxel grid, and such ties are decided by
+    rounding, which differs between c_e + s and the centroid of the shifted vertices; with face centres as
+    vertices the centroids lie on a 1/36 grid, so squared centroid distances are multiples of 1/1296, and the
+    threshold at 4.1 edges is 605.16/1296.)"""
     tri = _periodic_surface()
     T = tri.shape[0]
     shifts = [(sx, sy, sz) for sz in (-1, 0, 1) for sy in (-1, 0, 1) for sx in (-1, 0, 1)]
     tiled = np.concatenate([tri + np.array(s, dtype=np.float64) for s in shifts])
-    free = ob.near_pairs(tiled)
+    free = ob.near_pairs(tiled, radius)
     centre = 13 * T
     want = sorted((int(t) - centre, int(e) % T, int(e) // T) for t, e in free if centre <= t < centre + T)
-    got = [tuple(int(v) for v in row) for row in ob.near_pairs(tri, cell_L=1.0)]
+    got = [tuple(int(v) for v in row) for row in ob.near_pairs(tri, radius, cell_L=1.0)]
     assert got == want
     assert any(c != 13 for _, _, c in got)  # pairs across the faces exist
+    twice = len(got) - len({(t, e) for t, e, _ in got})
+    assert (twice > 0) == (radius == 4.1)
 
 
 def test_periodic_near_block_is_the_shifted_element_seen_from_the_point():
