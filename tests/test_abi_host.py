@@ -211,3 +211,12 @@ def test_bem_entry_points_check_problem_and_options_first(lib):
     assert lib.bem_precond_apply(ctypes.byref(pc), ctypes.byref(opts), ctypes.c_void_p(fake),
                                  ctypes.c_void_p(fake + 64), None, None) == KFMM_E_ARG
     assert "cell must be NULL" in last_error(lib)
+
+
+def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
+    """No fallback path: with the built library absent the binding raises instead of computing anything."""
+    from paper_1612_04082_amd import kfmm
+    monkeypatch.setattr(kfmm, "_lib", None)
+    monkeypatch.setattr(kfmm, "LIB_PATH", str(tmp_path / "libkfmm.so"))
+    with pytest.raises(ImportError, match="not built"):
+        kfmm.load_library()
